@@ -1,0 +1,205 @@
+/*
+ * gmm.h -- C ABI of the MI355X (gfx950) Gaussian-mixture training library.
+ *
+ * The operations follow Sanderson & Curtin, arXiv:1707.09094:
+ *   gmm_global_stats   global diagonal covariance for the Mahalanobis k-means
+ *                      distance (Sec. 3.1, Eq. 20)
+ *   gmm_kmeans_iter    one k-means iteration: hard assignment (Sec. 3, Eq. 19),
+ *                      new means, dead-mean resurrection (Sec. 3.1), and the
+ *                      hand-off weights/variances (Sec. 3, Eqs. 5-7 with hard l)
+ *   gmm_em_iter        one EM iteration: E-step in the log domain (Sec. 2.2,
+ *                      Eqs. 15-18), responsibilities (Sec. 2, Eq. 3), M-step
+ *                      (Sec. 2, Eqs. 4-7; accumulator split of Sec. 2.1,
+ *                      Eqs. 8-14) and the variance floor (Sec. 2.2)
+ *   gmm_loglik         per-sample and mean log-likelihood (Sec. 4 API:
+ *                      log_p(X), avg_log_p(X))
+ *   gmm_assign         closest Gaussian per sample and its histogram
+ *                      (Sec. 4 API: assign, raw_hist)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every array argument is a DEVICE pointer owned by the caller; the
+ * library keeps no pointer after the call returns and allocates no device
+ * memory: scratch space comes from the caller's workspace `ws` of `ws_bytes`
+ * bytes (size it with gmm_workspace_bytes; 256-byte aligned).  All work is
+ * enqueued on `stream` (a hipStream_t; NULL = the null stream) and nothing
+ * synchronises with the host, so a sequence of calls can be captured into a
+ * graph.  Calls that share a workspace must be ordered on one stream.
+ *
+ * Layouts (one sample per column, Sec. 4 API).  X is D x N column-major FP32:
+ * element d of sample i is X[i*ldx + d], ldx >= D.  Parameters are FP32:
+ *   hefts[g]                       weights, g < G
+ *   means[g*D + d]                 column g = mean of Gaussian g
+ *   covs[g*D + d]                  diagonal covariances (cov = GMM_COV_DIAG)
+ *   covs[g*D*D + e*D + d]          full covariance of Gaussian g, column-major,
+ *                                  symmetric (cov = GMM_COV_FULL)
+ *
+ * Errors.  Argument errors (null required pointer, N < 1, D < 1, G < 1,
+ * ldx < D, unknown enum value, workspace too small, a shape outside the
+ * supported range) are detected on the host before anything is enqueued:
+ * the call returns GMM_EINVAL and writes nothing.  A failed launch returns
+ * GMM_EHIP.  Numerical failures are detected on the device and OR-ed into
+ * *dev_status (GMM_DEV_* bits; the call sets it to 0 first), which the caller
+ * reads after synchronising: a non-finite log-likelihood or parameter
+ * (GMM_DEV_NONFINITE: NaN/Inf in the data, or a covariance <= 0 on input --
+ * the failure mode named at the end of Sec. 2.2) and, for full covariances, a
+ * matrix that is not positive definite (GMM_DEV_NOTPD).  Outputs are then
+ * unspecified.
+ */
+#ifndef GMM_H
+#define GMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* host return codes */
+#define GMM_OK 0
+#define GMM_EINVAL (-1)
+#define GMM_EHIP (-2)
+
+/* device status bits */
+#define GMM_DEV_OK 0
+#define GMM_DEV_NONFINITE 1
+#define GMM_DEV_NOTPD 2
+
+/* covariance type (Sec. 4: diagonal covariances; full as in Eq. 2) */
+#define GMM_COV_DIAG 0
+#define GMM_COV_FULL 1
+
+/* k-means distance (Sec. 3.1 / learn() dist_mode) */
+#define GMM_DIST_EUCL 0
+#define GMM_DIST_MAHA 1
+
+/* assignment distance of gmm_assign (Sec. 4 API: eucl_dist / prob_dist) */
+#define GMM_ASSIGN_EUCL 0
+#define GMM_ASSIGN_PROB 1
+
+/* arithmetic of the log-density / distance contraction.
+ * GMM_PREC_FP32:   direct (x - mu)^2 form in FP32 on the vector ALUs.
+ * GMM_PREC_BF16X3: the expanded form x^2 * Lambda - 2 x * (Lambda mu) + const
+ *                  as a GEMM on the matrix cores with each FP32 operand split
+ *                  into two BF16 parts (hi*hi + hi*lo + lo*hi, FP32 accumulate);
+ *                  every sample's leading components (those within a fixed gap
+ *                  of the best, see gmm_em_iter) are recomputed in the FP32
+ *                  direct form, so the result carries FP32-path accuracy. */
+#define GMM_PREC_FP32 0
+#define GMM_PREC_BF16X3 1
+
+typedef void* gmm_stream_t; /* hipStream_t */
+
+/* Library version, (major << 16) | minor. */
+int gmm_version(void);
+
+/* Human-readable name of a host return code. */
+const char* gmm_status_string(int code);
+
+/* Bytes of workspace that every entry point below needs for a problem of N
+ * samples, D dimensions and G Gaussians with covariance type `cov` and
+ * precision `prec` (one size serves them all).  Returns 0 for arguments out of
+ * range. */
+size_t gmm_workspace_bytes(int64_t N, int32_t D, int32_t G, int32_t cov, int32_t prec);
+
+/* Global per-dimension mean and population variance (divide by N) of X, in
+ * FP64: the global diagonal covariance of the Mahalanobis k-means distance
+ * (Sec. 3.1, Eq. 20).  mean_out[D], var_out[D]: device FP64 outputs. */
+int gmm_global_stats(const float* X, int64_t N, int32_t D, int64_t ldx, double* mean_out,
+                     double* var_out, void* ws, size_t ws_bytes, gmm_stream_t stream);
+
+/* One k-means iteration (Sec. 3; Eq. 19 with Eq. 20's distance).
+ *   dist        GMM_DIST_EUCL: sum_d (x_d - mu_gd)^2;
+ *               GMM_DIST_MAHA: sum_d (x_d - mu_gd)^2 / max(gvar_d, var_floor).
+ *   gvar[D]     FP64 global variances (gmm_global_stats), required for MAHA,
+ *               ignored (may be NULL) for EUCL.
+ *   means[D*G]  in: current means; out: new means (average of the assigned
+ *               samples; dead means resurrected, see below).
+ *   dcovs[D*G]  out: max(mean squared deviation of the assigned samples about
+ *               the new mean, var_floor); 1 for a cluster with no samples.
+ *   hefts[G]    out: count_g / N.
+ *   counts[G]   out: int64 number of samples assigned to each mean.
+ *   assign[N]   out (may be NULL): index of the nearest input mean; the lowest
+ *               index wins exact ties.
+ *   inertia[1]  out: FP64 sum over samples of the distance to the nearest
+ *               INPUT mean.
+ *   n_recomputed[1]  out (may be NULL): samples whose two best FP32 (or BF16x3)
+ *               distances were closer than the arithmetic's error bound and
+ *               were re-decided in FP64.
+ * Dead means (Sec. 3.1): clusters with no samples, taken in increasing index,
+ * become a sample of the cluster with the largest remaining count (lowest
+ * index on ties; it needs at least 2), the k-th donation from a cluster taking
+ * its k-th lowest-index sample; each donation lowers the donor's remaining
+ * count by one.  A dead mean with no eligible donor is kept.
+ * prec: GMM_PREC_FP32 or GMM_PREC_BF16X3 (distance contraction). */
+int gmm_kmeans_iter(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int32_t dist,
+                    const double* gvar, float var_floor, float* means, float* dcovs,
+                    float* hefts, int64_t* counts, int32_t* assign, double* inertia,
+                    int32_t prec, int64_t* n_recomputed, int32_t* dev_status, void* ws,
+                    size_t ws_bytes, gmm_stream_t stream);
+
+/* One EM iteration (Sec. 2, Eqs. 3-7), parameters updated in place.
+ *   hefts[G], means[D*G], covs (D*G diag or D*D*G full): in/out.
+ *   var_floor   lower bound applied to every (diagonal) variance after the
+ *               update (Sec. 2.2); the input parameters are used as given.
+ *   mean_loglik[1]  out: FP64 mean log-likelihood of the INPUT parameters
+ *               (the E-step's by-product; EM makes successive values
+ *               non-decreasing).
+ *   n_recomputed[1] out (may be NULL): with GMM_PREC_BF16X3, number of
+ *               (sample, Gaussian) log-densities recomputed in the FP32
+ *               direct form (the best one of every sample plus every one
+ *               within 20 nats of it); 0 with GMM_PREC_FP32.
+ * A Gaussian whose responsibilities sum to exactly 0 gets weight 0 and keeps
+ * its mean and covariance.  Responsibilities below exp(-80) relative to the
+ * sample's best component are treated as 0.
+ * Full covariances (cov = GMM_COV_FULL): Cholesky factors and log-determinants
+ * in FP64; a factorisation that fails sets GMM_DEV_NOTPD. */
+int gmm_em_iter(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int32_t cov,
+                float* hefts, float* means, float* covs, float var_floor, int32_t prec,
+                double* mean_loglik, int64_t* n_recomputed, int32_t* dev_status, void* ws,
+                size_t ws_bytes, gmm_stream_t stream);
+
+/* Log-likelihood of X under the given parameters (Sec. 4 API).
+ *   mean_loglik[1]  out: FP64 average of log p(x_i | lambda)   (avg_log_p(X))
+ *   per_sample[N]   out (may be NULL): FP32 log p(x_i | lambda) (log_p(X)) */
+int gmm_loglik(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int32_t cov,
+               const float* hefts, const float* means, const float* covs, int32_t prec,
+               double* mean_loglik, float* per_sample, int32_t* dev_status, void* ws,
+               size_t ws_bytes, gmm_stream_t stream);
+
+/* Closest Gaussian per sample (Sec. 4 API assign / raw_hist), diagonal model.
+ *   mode        GMM_ASSIGN_EUCL: nearest mean in Euclidean distance;
+ *               GMM_ASSIGN_PROB: largest weighted log-likelihood
+ *               log w_g + log N(x | mu_g, Sigma_g).
+ *   assign[N]   out: int32 index (lowest index on exact ties).
+ *   hist[G]     out (may be NULL): int64 count of samples per Gaussian. */
+int gmm_assign(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int32_t mode,
+               const float* hefts, const float* means, const float* dcovs, int32_t* assign,
+               int64_t* hist, int32_t* dev_status, void* ws, size_t ws_bytes,
+               gmm_stream_t stream);
+
+/* ---- instrumentation -----------------------------------------------------
+ * When enabled, every launch of a data-pass kernel (one that reads all of X)
+ * is bracketed by a pair of HIP events recorded on the caller's stream, and
+ * the elapsed times are accumulated per kind.  For eager benchmarking only:
+ * keep it disabled while a stream is being captured into a graph. */
+#define GMM_PROF_EM 0        /* fused E-step + M-step map pass of gmm_em_iter */
+#define GMM_PROF_KM_ASSIGN 1 /* k-means assignment pass */
+#define GMM_PROF_KM_ACCUM 2  /* k-means accumulation pass */
+#define GMM_PROF_LOGLIK 3    /* gmm_loglik pass */
+#define GMM_PROF_STATS 4     /* gmm_global_stats passes */
+#define GMM_PROF_BATCHED 5   /* batched data passes */
+
+/* Enable (on != 0) or disable recording; either way the totals are reset. */
+int gmm_profile_enable(int on);
+
+/* Total milliseconds and number of launches recorded for `kind` since the last
+ * gmm_profile_enable; waits for the recorded events. */
+int gmm_profile_read(int32_t kind, double* ms_total, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMM_H */

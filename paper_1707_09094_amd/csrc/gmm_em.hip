@@ -1,0 +1,329 @@
+// gmm_em.hip -- EM iteration and log-likelihood for diagonal covariances,
+// generic kernels valid for every shape the API accepts.
+//
+// One EM iteration (Sec. 2, Eqs. 3-7) is three launches on one stream:
+//   k_pre_diag      per-component constants in FP64 (Sec. 2.2, Eq. 15):
+//                   s_gd = 1/sigma_gd, m_gd = mu_gd/sigma_gd (rounded to FP32)
+//                   and c_g = log w_g - 1/2 (D log 2pi + sum_d log sigma2_gd)
+//                   (kept as an FP32 hi/lo pair)
+//   k_estep_diag    sample tiles: log-densities a_gi = c_g - 1/2 sum_d
+//                   (x_di s_gd - m_gd)^2, max-shifted log-sum-exp per sample
+//                   (Eqs. 16-18), responsibilities (Eq. 3), and the map step of
+//                   Sec. 2.1 (Eqs. 9-11) into per-block FP64 partials.  The
+//                   moments are accumulated about the component's current mean
+//                   (y = x - mu_old): L, sum l*y, sum l*y^2, which makes the
+//                   one-pass covariance of Eq. 8 free of cancellation.
+//   k_fin_diag      reduce step (Eqs. 12-14) over the block partials in a fixed
+//                   order, Eq. 5 weights, Eq. 6 means, Eq. 7 variances about the
+//                   new mean, the variance floor, and the mean log-likelihood.
+#include "gmm_internal.hpp"
+
+namespace gmm {
+
+namespace {
+
+constexpr int kNT = 256;
+
+__global__ void k_init(int32_t* dev_status, int64_t* n_recomputed, int64_t* counters) {
+  if (threadIdx.x == 0) {
+    if (dev_status) *dev_status = 0;
+    if (n_recomputed) *n_recomputed = 0;
+  }
+  if (threadIdx.x < 8) counters[threadIdx.x] = 0;
+}
+
+// One workgroup per component g.
+__global__ void __launch_bounds__(kNT) k_pre_diag(const float* __restrict__ hefts,
+                                                  const float* __restrict__ means,
+                                                  const float* __restrict__ covs, int D, int G,
+                                                  float* __restrict__ s_out,
+                                                  float* __restrict__ m_out,
+                                                  float* __restrict__ c_out,
+                                                  double* __restrict__ c64_out,
+                                                  double* __restrict__ lam64_out) {
+  __shared__ double sh[kNT];
+  const int g = blockIdx.x;
+  double ld = 0.0;
+  for (int d = threadIdx.x; d < D; d += kNT) {
+    const double v = (double)covs[(size_t)g * D + d];
+    const double mu = (double)means[(size_t)g * D + d];
+    const double lam = 1.0 / v;
+    const double s = sqrt(lam);
+    s_out[(size_t)d * G + g] = (float)s;
+    m_out[(size_t)d * G + g] = (float)(mu * s);
+    lam64_out[(size_t)g * D + d] = lam;
+    ld += log(v);
+  }
+  const double logdet = block_sum_d<kNT>(ld, sh);
+  if (threadIdx.x == 0) {
+    const double c = log((double)hefts[g]) - 0.5 * ((double)D * kLog2Pi + logdet);
+    const float hi = (float)c;
+    c_out[g] = hi;  // -inf for a zero weight: that component gets l = 0
+    c_out[G + g] = isfinite(c) ? (float)(c - (double)hi) : 0.0f;
+    c64_out[g] = c;
+  }
+}
+
+// E-step (+ optional M-step map) over the block's contiguous sample range.
+// LDS: xs[T][D] samples, as[T][G] log-densities then responsibilities,
+// lse[T].  T is chosen on the host so the tile fits in LDS.
+template <bool MSTEP>
+__global__ void __launch_bounds__(kNT) k_estep_diag(
+    const float* __restrict__ X, int64_t N, int D, int64_t ldx, int G, int T, int64_t chunk,
+    const float* __restrict__ sT, const float* __restrict__ mT, const float* __restrict__ cc,
+    const double* __restrict__ c64, const double* __restrict__ lam64,
+    const float* __restrict__ means, double* __restrict__ part, double* __restrict__ ll_part,
+    float* __restrict__ per_sample, int32_t* __restrict__ dev_status) {
+  extern __shared__ float lds[];
+  float* xs = lds;                  // [T][D]
+  float* as = xs + (size_t)T * D;   // [T][G]
+  double* lse = (double*)(as + (size_t)T * G + ((T * G) & 1));  // [T]
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wid = tid / kWave;
+  const int nw = kNT / kWave;
+  const int b = blockIdx.x;
+  const int64_t i0 = (int64_t)b * chunk;
+  const int64_t i1 = min(N, i0 + chunk);
+  const int P = 2 * D + 1;
+  double* pb = part + (size_t)b * G * P;
+  if (tid == 0) bad = 0;
+  if (MSTEP)
+    for (int p = tid; p < G * P; p += kNT) pb[p] = 0.0;
+  double llacc = 0.0;  // thread 0 only
+  __syncthreads();
+
+  for (int64_t t0 = i0; t0 < i1; t0 += T) {
+    const int nt = (int)min((int64_t)T, i1 - t0);
+    for (int p = tid; p < nt * D; p += kNT) {
+      const int t = p / D, d = p - t * D;
+      xs[p] = X[(t0 + t) * ldx + d];
+    }
+    __syncthreads();
+    // a_gi: one (sample, component) pair per thread iteration.
+    for (int p = tid; p < nt * G; p += kNT) {
+      const int t = p / G, g = p - t * G;
+      const float* x = xs + (size_t)t * D;
+      float acc = 0.0f;
+      for (int d = 0; d < D; ++d) {
+        const float u = fmaf(x[d], sT[(size_t)d * G + g], -mT[(size_t)d * G + g]);
+        acc = fmaf(u, u, acc);
+      }
+      as[p] = (cc[g] - 0.5f * acc) + cc[G + g];
+    }
+    __syncthreads();
+    // One wave per sample: the FP32 values screen the components; the best
+    // one and every one within kNearGap nats of it are recomputed in FP64
+    // (a_g = c_g - 1/2 sum_d (x_d - mu_gd)^2 / sigma2_gd, Eq. 15), and the
+    // sample's log-sum-exp (Eqs. 16-18) is assembled in FP64 from those plus
+    // the FP32 values of the rest (each below exp(-30) of the best).
+    for (int t = wid; t < nt; t += nw) {
+      float* a = as + (size_t)t * G;
+      const float* x = xs + (size_t)t * D;
+      float mx = -INFINITY;
+      for (int g = lane; g < G; g += kWave) mx = fmaxf(mx, a[g]);
+      mx = wave_max(mx);
+      const double M = (double)mx;
+      // bit c of nearbits: component c*64 + lane is in the near set; its
+      // entry of a[] then holds (a64 - M) instead of the FP32 value
+      unsigned long long nearbits = 0;
+      for (int c = 0, g0 = 0; g0 < G; ++c, g0 += kWave) {
+        const int g = g0 + lane;
+        const bool near = g < G && a[g] >= mx - kNearGap;
+        if (near) nearbits |= 1ull << c;
+        unsigned long long msk = __ballot(near);
+        while (msk) {
+          const int j = __ffsll((long long)msk) - 1;
+          msk &= msk - 1;
+          const int gg = g0 + j;
+          double q = 0.0;
+          for (int d = lane; d < D; d += kWave) {
+            const double u = (double)x[d] - (double)means[(size_t)gg * D + d];
+            q += u * u * lam64[(size_t)gg * D + d];
+          }
+          q = wave_sum_d(q);
+          if (lane == j) a[gg] = (float)(c64[gg] - 0.5 * q - M);
+        }
+      }
+      double sm = 0.0;
+      for (int c = 0, g0 = 0; g0 < G; ++c, g0 += kWave) {
+        const int g = g0 + lane;
+        if (g < G) {
+          const float v = ((nearbits >> c) & 1ull) ? a[g] : a[g] - mx;
+          sm += (double)__expf(v);
+        }
+      }
+      sm = wave_sum_d(sm);
+      const double l = M + log(sm);
+      if (MSTEP) {
+        const float dl = (float)(l - M);
+        for (int c = 0, g0 = 0; g0 < G; ++c, g0 += kWave) {
+          const int g = g0 + lane;
+          if (g < G) {
+            const float z = (((nearbits >> c) & 1ull) ? a[g] : a[g] - mx) - dl;
+            a[g] = z >= -kRespCut ? __expf(z) : 0.0f;
+          }
+        }
+      }
+      if (lane == 0) {
+        lse[t] = l;
+        if (!isfinite(l)) bad = 1;
+        if (per_sample) per_sample[t0 + t] = (float)l;
+      }
+    }
+    __syncthreads();
+    if (tid == 0)
+      for (int t = 0; t < nt; ++t) llacc += lse[t];
+    if (MSTEP) {
+      // map step (Eqs. 9-11) about the current mean: thread owns pairs (g, d).
+      for (int p = tid; p < G * D; p += kNT) {
+        const int g = p / D, d = p - g * D;
+        const float mu = means[(size_t)g * D + d];
+        double s1 = 0.0, s2 = 0.0, sl = 0.0;
+        for (int t = 0; t < nt; ++t) {
+          const float r = as[(size_t)t * G + g];
+          if (r != 0.0f) {
+            const double y = (double)(xs[(size_t)t * D + d] - mu);
+            const double ry = (double)r * y;
+            s1 += ry;
+            s2 += ry * y;
+            sl += (double)r;
+          }
+        }
+        double* q = pb + (size_t)g * P;
+        q[1 + d] += s1;
+        q[1 + D + d] += s2;
+        if (d == 0) q[0] += sl;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    ll_part[b] = llacc;
+    if (bad) atomicOr(dev_status, GMM_DEV_NONFINITE);
+  }
+}
+
+// Reduce step: one workgroup per component.  Thread j sums column j of the
+// partials over blocks 0..nb-1 in order.
+__global__ void __launch_bounds__(kNT) k_fin_diag(const double* __restrict__ part, int nb, int64_t N,
+                                                  int D, int G, float var_floor,
+                                                  float* __restrict__ hefts,
+                                                  float* __restrict__ means,
+                                                  float* __restrict__ covs,
+                                                  const double* __restrict__ ll_part,
+                                                  double* __restrict__ mean_loglik,
+                                                  int32_t* __restrict__ dev_status) {
+  extern __shared__ double tot[];  // [P]
+  __shared__ int bad;
+  const int g = blockIdx.x;
+  const int P = 2 * D + 1;
+  if (threadIdx.x == 0) bad = 0;
+  for (int j = threadIdx.x; j < P; j += kNT) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[((size_t)b * G + g) * P + j];
+    tot[j] = s;
+  }
+  __syncthreads();
+  const double L = tot[0];
+  if (threadIdx.x == 0) {
+    const float w = (float)(L / (double)N);  // Eq. 5
+    hefts[g] = w;
+    if (!isfinite(w)) bad = 1;
+  }
+  if (L > 0.0) {
+    for (int d = threadIdx.x; d < D; d += kNT) {
+      const double dm = tot[1 + d] / L;                  // Eq. 6, relative to mu_old
+      const double mu = (double)means[(size_t)g * D + d] + dm;
+      double v = tot[1 + D + d] / L - dm * dm;           // Eq. 7 about the new mean
+      v = v > 0.0 ? v : 0.0;
+      v = v > (double)var_floor ? v : (double)var_floor;  // floor, Sec. 2.2
+      means[(size_t)g * D + d] = (float)mu;
+      covs[(size_t)g * D + d] = (float)v;
+      if (!isfinite(mu) || !isfinite(v)) bad = 1;
+    }
+  }
+  if (g == 0 && threadIdx.x == 0 && mean_loglik) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += ll_part[b];
+    *mean_loglik = s / (double)N;
+    if (!isfinite(s)) bad = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && bad) atomicOr(dev_status, GMM_DEV_NONFINITE);
+}
+
+__global__ void k_ll_finish(const double* __restrict__ ll_part, int nb, int64_t N,
+                            double* __restrict__ mean_loglik, int32_t* __restrict__ dev_status) {
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += ll_part[b];
+    *mean_loglik = s / (double)N;
+    if (!isfinite(s)) atomicOr(dev_status, GMM_DEV_NONFINITE);
+  }
+}
+
+int tile_rows(int D, int G) {
+  int T = 64;
+  while (T > 1 && (size_t)T * (D + G + 2) * sizeof(float) > 60 * 1024) T >>= 1;
+  return T;
+}
+
+}  // namespace
+
+hipError_t launch_pre_diag(const float* hefts, const float* means, const float* covs, int D,
+                           int G, const Workspace& w, hipStream_t st) {
+  hipLaunchKernelGGL(k_pre_diag, dim3(G), dim3(kNT), 0, st, hefts, means, covs, D, G, w.s, w.m,
+                     w.c, w.c64, w.lamg64);
+  return hipGetLastError();
+}
+
+hipError_t launch_em_diag(const float* X, int64_t N, int D, int64_t ldx, int G, float* hefts,
+                          float* means, float* covs, float var_floor, int prec,
+                          double* mean_loglik, int64_t* n_recomputed, int32_t* dev_status,
+                          const Workspace& w, hipStream_t st) {
+  (void)prec;
+  const int T = tile_rows(D, G);
+  const int nb = partial_blocks(N, 4 * T);
+  int64_t chunk = (N + nb - 1) / nb;
+  const size_t lds = sizeof(float) * ((size_t)T * (D + G) + 1) + sizeof(double) * T;
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, dev_status, n_recomputed, w.counters);
+  hipLaunchKernelGGL(k_pre_diag, dim3(G), dim3(kNT), 0, st, hefts, means, covs, D, G, w.s, w.m,
+                     w.c, w.c64, w.lamg64);
+  {
+    ProfScope ps(kProfEM, st);
+    hipLaunchKernelGGL(k_estep_diag<true>, dim3(nb), dim3(kNT), lds, st, X, N, D, ldx, G, T,
+                       chunk, w.s, w.m, w.c, w.c64, w.lamg64, means, w.partials, w.scalars, nullptr,
+                       dev_status);
+  }
+  hipLaunchKernelGGL(k_fin_diag, dim3(G), dim3(kNT), sizeof(double) * (2 * D + 1), st, w.partials,
+                     nb, N, D, G, var_floor, hefts, means, covs, w.scalars, mean_loglik,
+                     dev_status);
+  return hipGetLastError();
+}
+
+hipError_t launch_loglik_diag(const float* X, int64_t N, int D, int64_t ldx, int G,
+                              const float* hefts, const float* means, const float* covs, int prec,
+                              double* mean_loglik, float* per_sample, int32_t* dev_status,
+                              const Workspace& w, hipStream_t st) {
+  (void)prec;
+  const int T = tile_rows(D, G);
+  const int nb = partial_blocks(N, 4 * T);
+  int64_t chunk = (N + nb - 1) / nb;
+  const size_t lds = sizeof(float) * ((size_t)T * (D + G) + 1) + sizeof(double) * T;
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, dev_status, nullptr, w.counters);
+  hipLaunchKernelGGL(k_pre_diag, dim3(G), dim3(kNT), 0, st, hefts, means, covs, D, G, w.s, w.m,
+                     w.c, w.c64, w.lamg64);
+  {
+    ProfScope ps(kProfLoglik, st);
+    hipLaunchKernelGGL(k_estep_diag<false>, dim3(nb), dim3(kNT), lds, st, X, N, D, ldx, G, T,
+                       chunk, w.s, w.m, w.c, w.c64, w.lamg64, means, w.partials, w.scalars,
+                       per_sample, dev_status);
+  }
+  hipLaunchKernelGGL(k_ll_finish, dim3(1), dim3(64), 0, st, w.scalars, nb, N, mean_loglik,
+                     dev_status);
+  return hipGetLastError();
+}
+
+}  // namespace gmm

@@ -1,0 +1,210 @@
+// gmm_internal.hpp -- shared definitions of the gfx950 GMM library (not part of
+// the public ABI; see include/gmm.h for that).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/gmm.h"
+
+namespace gmm {
+
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kMaxBlocks = 512;      // E/M grid: 2 workgroups per CU on 256 CUs
+constexpr float kRespCut = 80.0f;    // responsibilities below exp(-80) of the best are 0
+// Every sample's best component and all components within this many nats of it
+// have their log-density recomputed in FP64 from the FP32 parameters.
+constexpr float kNearGap = 30.0f;
+constexpr double kLog2Pi = 1.8378770664093454835606594728112353;
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Number of workgroups of the per-block-partial kernels (E/M, k-means
+// accumulation, global statistics).  A function of N only, so a given problem
+// always reduces in the same order.
+inline int partial_blocks(int64_t N, int64_t per_block_min) {
+  int64_t b = (N + per_block_min - 1) / per_block_min;
+  if (b < 1) b = 1;
+  if (b > kMaxBlocks) b = kMaxBlocks;
+  return (int)b;
+}
+
+// Values stored per (block, component) in the FP64 partials.
+inline int partial_width(int D, int cov) {
+  return cov == GMM_COV_FULL ? 1 + D + D * (D + 1) / 2 : 2 * D + 1;
+}
+
+// Carving of the caller's workspace.  Every region is 256-byte aligned.
+struct Workspace {
+  // per-component constants of the E-step (see em precompute kernels)
+  float* s;        // diag: [D][G] 1/sigma (d-major)      full: unused
+  float* m;        // diag: [D][G] mu/sigma                full: unused
+  float* c;        // [2][G] log w - 1/2 (D log 2pi + log|Sigma|), split hi/lo
+  float* W;        // full: [G][D][D] inverse Cholesky factor (row-major lower)
+  uint16_t* Bhi;   // BF16X3 expanded weights [G][K] hi part
+  uint16_t* Blo;   // BF16X3 expanded weights [G][K] lo part
+  float* cexp;     // BF16X3: [2][G] constant of the expanded form, hi/lo
+  double* c64;     // [G] log w - 1/2 (D log 2pi + log|Sigma|) in FP64
+  double* lamg64;  // diag: [G][D] 1/sigma2 in FP64
+  double* W64;     // full: [G][D][D] inverse Cholesky factor in FP64 (row-major lower)
+  double* partials;   // [B][G][P]
+  double* scalars;    // [4][B] per-block FP64 sums (log-likelihood / inertia)
+  int32_t* assign;    // [N] k-means assignment scratch
+  double* lam64;      // [D] k-means distance weights (FP64)
+  float* lam32;       // [D] the same rounded to FP32
+  int64_t* counters;  // [8] device counters
+  size_t bytes;
+};
+
+inline int kexp_K(int D) { return ((2 * D + 31) / 32) * 32; }  // expanded-form depth, padded
+
+inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Workspace* w) {
+  size_t off = 0;
+  auto take = [&](size_t n) {
+    size_t o = off;
+    off = align_up(off + n);
+    return o;
+  };
+  const int B = kMaxBlocks;
+  const int P = partial_width(D, cov);
+  const int K = kexp_K(D);
+  size_t o_s = take(sizeof(float) * (size_t)D * G);
+  size_t o_m = take(sizeof(float) * (size_t)D * G);
+  size_t o_c = take(sizeof(float) * 2 * (size_t)G);
+  size_t o_W = take(cov == GMM_COV_FULL ? sizeof(float) * (size_t)D * D * G : 0);
+  size_t o_bh = take(sizeof(uint16_t) * (size_t)K * G);
+  size_t o_bl = take(sizeof(uint16_t) * (size_t)K * G);
+  size_t o_ce = take(sizeof(float) * 2 * (size_t)G);
+  size_t o_c64 = take(sizeof(double) * (size_t)G);
+  size_t o_lg = take(sizeof(double) * (size_t)G * D);
+  size_t o_w64 = take(cov == GMM_COV_FULL ? sizeof(double) * (size_t)D * D * G : 0);
+  size_t o_p = take(sizeof(double) * (size_t)B * G * P);
+  size_t o_sc = take(sizeof(double) * 4 * (size_t)B);
+  size_t o_a = take(sizeof(int32_t) * (size_t)N);
+  size_t o_l64 = take(sizeof(double) * (size_t)D);
+  size_t o_l32 = take(sizeof(float) * (size_t)D);
+  size_t o_ct = take(sizeof(int64_t) * 8);
+  w->bytes = off;
+  if (!base) return true;
+  if (avail < off) return false;
+  char* b = (char*)base;
+  w->s = (float*)(b + o_s);
+  w->m = (float*)(b + o_m);
+  w->c = (float*)(b + o_c);
+  w->W = (float*)(b + o_W);
+  w->Bhi = (uint16_t*)(b + o_bh);
+  w->Blo = (uint16_t*)(b + o_bl);
+  w->cexp = (float*)(b + o_ce);
+  w->c64 = (double*)(b + o_c64);
+  w->lamg64 = (double*)(b + o_lg);
+  w->W64 = (double*)(b + o_w64);
+  w->partials = (double*)(b + o_p);
+  w->scalars = (double*)(b + o_sc);
+  w->assign = (int32_t*)(b + o_a);
+  w->lam64 = (double*)(b + o_l64);
+  w->lam32 = (float*)(b + o_l32);
+  w->counters = (int64_t*)(b + o_ct);
+  return true;
+}
+
+// ---- device helpers -------------------------------------------------------
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Fixed-order FP64 block reduction (tree over LDS).  All threads must call it;
+// returns the sum in thread 0 (others get an unspecified value).
+template <int NT>
+__device__ __forceinline__ double block_sum_d(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// ---- optional event timing of the data-pass kernels (gmm_profile.hip) ------
+
+constexpr int kProfKinds = 8;
+enum ProfKind {
+  kProfEM = GMM_PROF_EM,
+  kProfKmAssign = GMM_PROF_KM_ASSIGN,
+  kProfKmAccum = GMM_PROF_KM_ACCUM,
+  kProfLoglik = GMM_PROF_LOGLIK,
+  kProfStats = GMM_PROF_STATS,
+  kProfBatched = GMM_PROF_BATCHED,
+};
+
+// Records an event pair around its lifetime when profiling is on.
+class ProfScope {
+ public:
+  ProfScope(int kind, hipStream_t st);
+  ~ProfScope();
+
+ private:
+  int kind_;
+  hipStream_t st_;
+  hipEvent_t a_, b_;
+};
+
+// ---- launchers (defined in the kernel sources) ----------------------------
+
+hipError_t launch_global_stats(const float* X, int64_t N, int D, int64_t ldx, double* mean,
+                               double* var, const Workspace& w, hipStream_t st);
+
+hipError_t launch_pre_diag(const float* hefts, const float* means, const float* covs, int D,
+                           int G, const Workspace& w, hipStream_t st);
+
+hipError_t launch_em_diag(const float* X, int64_t N, int D, int64_t ldx, int G, float* hefts,
+                          float* means, float* covs, float var_floor, int prec,
+                          double* mean_loglik, int64_t* n_recomputed, int32_t* dev_status,
+                          const Workspace& w, hipStream_t st);
+
+hipError_t launch_loglik_diag(const float* X, int64_t N, int D, int64_t ldx, int G,
+                              const float* hefts, const float* means, const float* covs, int prec,
+                              double* mean_loglik, float* per_sample, int32_t* dev_status,
+                              const Workspace& w, hipStream_t st);
+
+hipError_t launch_em_full(const float* X, int64_t N, int D, int64_t ldx, int G, float* hefts,
+                          float* means, float* covs, float var_floor, double* mean_loglik,
+                          int64_t* n_recomputed, int32_t* dev_status, const Workspace& w,
+                          hipStream_t st);
+
+hipError_t launch_loglik_full(const float* X, int64_t N, int D, int64_t ldx, int G,
+                              const float* hefts, const float* means, const float* covs,
+                              double* mean_loglik, float* per_sample, int32_t* dev_status,
+                              const Workspace& w, hipStream_t st);
+
+hipError_t launch_kmeans(const float* X, int64_t N, int D, int64_t ldx, int G, int dist,
+                         const double* gvar, float var_floor, float* means, float* dcovs,
+                         float* hefts, int64_t* counts, int32_t* assign, double* inertia,
+                         int prec, int64_t* n_recomputed, int32_t* dev_status, const Workspace& w,
+                         hipStream_t st);
+
+hipError_t launch_assign(const float* X, int64_t N, int D, int64_t ldx, int G, int mode,
+                         const float* hefts, const float* means, const float* dcovs,
+                         int32_t* assign, int64_t* hist, int32_t* dev_status, const Workspace& w,
+                         hipStream_t st);
+
+}  // namespace gmm

@@ -1,0 +1,453 @@
+// gmm_kmeans.hip -- one k-means iteration (Sec. 3) and the assign() query of
+// the Sec. 4 API, generic kernels for every accepted shape.
+//
+// Launch sequence of gmm_kmeans_iter:
+//   k_km_pre        per-dimension distance weights lam_d: 1 (Euclidean) or
+//                   1/max(global variance, floor) (Mahalanobis, Sec. 3.1
+//                   Eq. 20), in FP64 and rounded to FP32
+//   k_km_assign     hard assignment (Sec. 3, Eq. 19): FP32 direct-form
+//                   distances, lowest index on ties; when the two best FP32
+//                   distances are within twice their rounding-error bound the
+//                   sample is re-decided in FP64, so the result is the FP64
+//                   argmin.  The distance to the chosen mean is re-evaluated in
+//                   FP64 for the inertia.
+//   k_km_accum      map step of Sec. 2.1 with hard l (Eqs. 9-11): per-block
+//                   FP64 count, sum (x - mu_old), sum (x - mu_old)^2
+//   k_km_fin        reduce step (Eqs. 12-14): new means, hand-off variances and
+//                   weights (Sec. 3, Eqs. 5-7 with hard l), counts, inertia
+//   k_km_resurrect  dead-mean resurrection (Sec. 3.1), a single workgroup that
+//                   does nothing unless some cluster is empty
+#include "gmm_internal.hpp"
+
+namespace gmm {
+
+namespace {
+
+constexpr int kNT = 256;
+constexpr int kRT = 1024;  // resurrection workgroup
+constexpr float kU32 = 5.9604645e-08f;  // 2^-24
+
+__global__ void k_km_init(int32_t* dev_status, int64_t* n_recomputed) {
+  if (threadIdx.x == 0) {
+    *dev_status = 0;
+    if (n_recomputed) *n_recomputed = 0;
+  }
+}
+
+__global__ void k_km_pre(const double* __restrict__ gvar, int D, float var_floor, int dist,
+                         double* __restrict__ lam64, float* __restrict__ lam32) {
+  for (int d = threadIdx.x + blockIdx.x * blockDim.x; d < D; d += blockDim.x * gridDim.x) {
+    double l = 1.0;
+    if (dist == GMM_DIST_MAHA) {
+      double v = gvar[d];
+      v = v > (double)var_floor ? v : (double)var_floor;
+      l = 1.0 / v;
+    }
+    lam64[d] = l;
+    lam32[d] = (float)l;
+  }
+}
+
+// FP64 distance sum_d lam_d (x_d - mu_d)^2 of one sample to one mean.
+__device__ __forceinline__ double dist64(const float* __restrict__ x, const float* __restrict__ mu,
+                                         const double* __restrict__ lam, int D) {
+  double s = 0.0;
+  for (int d = 0; d < D; ++d) {
+    const double t = (double)x[d] - (double)mu[d];
+    s += lam[d] * t * t;
+  }
+  return s;
+}
+
+// One thread per sample (strided over the block's contiguous range).
+// The FP32 sum of D non-negative terms, each with relative error <= 3u
+// (difference, product, lam rounding), is within gamma = (D + 4) u of the
+// exact value; the computed argmin is then provably the exact one when
+// d2 - d1 > gamma (d1 + d2).  Twice that margin triggers the FP64 re-decision.
+__global__ void __launch_bounds__(kNT) k_km_assign(
+    const float* __restrict__ X, int64_t N, int D, int64_t ldx, int G, int64_t chunk,
+    const float* __restrict__ means, const float* __restrict__ lam32,
+    const double* __restrict__ lam64, int32_t* __restrict__ assign,
+    double* __restrict__ inertia_part, int64_t* __restrict__ n_recomputed,
+    int32_t* __restrict__ dev_status) {
+  __shared__ double sh[kNT];
+  __shared__ int bad;
+  const int b = blockIdx.x;
+  const int64_t i0 = (int64_t)b * chunk;
+  const int64_t i1 = min(N, i0 + chunk);
+  const float gamma = 2.0f * (float)(D + 4) * kU32;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  double acc = 0.0;
+  long long nrec = 0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kNT) {
+    const float* x = X + i * ldx;
+    float d1 = INFINITY, d2 = INFINITY;
+    int arg = 0;
+    for (int g = 0; g < G; ++g) {
+      const float* mu = means + (size_t)g * D;
+      float s = 0.0f;
+      for (int d = 0; d < D; ++d) {
+        const float t = x[d] - mu[d];
+        s = fmaf(lam32[d] * t, t, s);
+      }
+      if (s < d1) {
+        d2 = d1;
+        d1 = s;
+        arg = g;
+      } else if (s < d2) {
+        d2 = s;
+      }
+    }
+    double best;
+    if (G > 1 && !(d2 - d1 > gamma * (d1 + d2))) {
+      // near tie (or non-finite): decide in FP64, first minimum wins
+      ++nrec;
+      best = INFINITY;
+      arg = 0;
+      for (int g = 0; g < G; ++g) {
+        const double s = dist64(x, means + (size_t)g * D, lam64, D);
+        if (s < best) {
+          best = s;
+          arg = g;
+        }
+      }
+    } else {
+      best = dist64(x, means + (size_t)arg * D, lam64, D);
+    }
+    if (!isfinite(best)) bad = 1;
+    assign[i] = arg;
+    acc += best;
+  }
+  const double tot = block_sum_d<kNT>(acc, sh);
+  if (nrec) atomicAdd((unsigned long long*)n_recomputed, (unsigned long long)nrec);
+  if (threadIdx.x == 0) {
+    inertia_part[b] = tot;
+    if (bad) atomicOr(dev_status, GMM_DEV_NONFINITE);
+  }
+}
+
+// Per-block FP64 partials [G][2D+1]: count, sum y, sum y^2 with y = x - mu_old.
+// Thread t owns dimensions t, t+256, ...; samples are visited in order.
+__global__ void __launch_bounds__(kNT) k_km_accum(const float* __restrict__ X, int64_t N, int D,
+                                                  int64_t ldx, int G, int64_t chunk,
+                                                  const float* __restrict__ means,
+                                                  const int32_t* __restrict__ assign,
+                                                  double* __restrict__ part) {
+  const int b = blockIdx.x;
+  const int P = 2 * D + 1;
+  double* pb = part + (size_t)b * G * P;
+  for (int p = threadIdx.x; p < G * P; p += kNT) pb[p] = 0.0;
+  __syncthreads();
+  const int64_t i0 = (int64_t)b * chunk;
+  const int64_t i1 = min(N, i0 + chunk);
+  for (int64_t i = i0; i < i1; ++i) {
+    const int g = assign[i];
+    double* q = pb + (size_t)g * P;
+    if (threadIdx.x == 0) q[0] += 1.0;
+    for (int d = threadIdx.x; d < D; d += kNT) {
+      const double y = (double)X[i * ldx + d] - (double)means[(size_t)g * D + d];
+      q[1 + d] += y;
+      q[1 + D + d] += y * y;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kNT) k_km_fin(const double* __restrict__ part, int nb, int64_t N,
+                                                int D, int G, float var_floor,
+                                                float* __restrict__ means,
+                                                float* __restrict__ dcovs,
+                                                float* __restrict__ hefts,
+                                                int64_t* __restrict__ counts,
+                                                const double* __restrict__ inertia_part,
+                                                int nbi, double* __restrict__ inertia,
+                                                int32_t* __restrict__ dev_status) {
+  extern __shared__ double tot[];
+  const int g = blockIdx.x;
+  const int P = 2 * D + 1;
+  for (int j = threadIdx.x; j < P; j += kNT) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[((size_t)b * G + g) * P + j];
+    tot[j] = s;
+  }
+  __syncthreads();
+  const double c = tot[0];
+  if (threadIdx.x == 0) {
+    counts[g] = (int64_t)c;
+    hefts[g] = (float)(c / (double)N);
+  }
+  for (int d = threadIdx.x; d < D; d += kNT) {
+    if (c > 0.0) {
+      const double dm = tot[1 + d] / c;
+      double v = tot[1 + D + d] / c - dm * dm;
+      v = v > 0.0 ? v : 0.0;
+      v = v > (double)var_floor ? v : (double)var_floor;
+      means[(size_t)g * D + d] = (float)((double)means[(size_t)g * D + d] + dm);
+      dcovs[(size_t)g * D + d] = (float)v;
+    } else {
+      dcovs[(size_t)g * D + d] = 1.0f;
+    }
+  }
+  if (g == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nbi; ++b) s += inertia_part[b];
+    *inertia = s;
+    if (!isfinite(s)) atomicOr(dev_status, GMM_DEV_NONFINITE);
+  }
+}
+
+// Dead-mean resurrection (Sec. 3.1), one workgroup.  rem/taken live in the
+// (now free) partials area.
+__global__ void __launch_bounds__(kRT) k_km_resurrect(const float* __restrict__ X, int64_t N,
+                                                      int D, int64_t ldx, int G,
+                                                      const int64_t* __restrict__ counts,
+                                                      const int32_t* __restrict__ assign,
+                                                      float* __restrict__ means,
+                                                      int64_t* __restrict__ scratch) {
+  __shared__ int any_dead;
+  __shared__ long long s_val[kRT];
+  __shared__ int s_idx[kRT];
+  __shared__ long long s_cnt[kRT];
+  __shared__ long long s_pick;
+  const int tid = threadIdx.x;
+  if (tid == 0) any_dead = 0;
+  __syncthreads();
+  for (int g = tid; g < G; g += kRT)
+    if (counts[g] == 0) any_dead = 1;
+  __syncthreads();
+  if (!any_dead) return;
+  int64_t* rem = scratch;
+  int64_t* taken = scratch + G;
+  for (int g = tid; g < G; g += kRT) {
+    rem[g] = counts[g];
+    taken[g] = 0;
+  }
+  __syncthreads();
+  const int64_t slice = (N + kRT - 1) / kRT;
+  for (int g = 0; g < G; ++g) {
+    if (counts[g] != 0) continue;  // uniform across the workgroup
+    // donor: largest remaining count, lowest index on ties
+    long long bv = -1;
+    int bi = 0;
+    for (int k = tid; k < G; k += kRT)
+      if ((long long)rem[k] > bv) {
+        bv = rem[k];
+        bi = k;
+      }
+    s_val[tid] = bv;
+    s_idx[tid] = bi;
+    __syncthreads();
+    for (int s = kRT / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        const long long ov = s_val[tid + s];
+        const int oi = s_idx[tid + s];
+        if (ov > s_val[tid] || (ov == s_val[tid] && oi < s_idx[tid])) {
+          s_val[tid] = ov;
+          s_idx[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const long long rq = s_val[0];
+    const int q = s_idx[0];
+    __syncthreads();
+    if (rq < 2) continue;
+    const long long want = taken[q];
+    // the want-th (0-based) sample assigned to q, in index order
+    const int64_t a0 = (int64_t)tid * slice, a1 = min(N, a0 + slice);
+    long long cnt = 0;
+    for (int64_t i = a0; i < a1; ++i) cnt += (assign[i] == q);
+    s_cnt[tid] = cnt;
+    if (tid == 0) s_pick = -1;
+    __syncthreads();
+    if (tid == 0) {
+      long long run = 0;
+      for (int t = 0; t < kRT; ++t) {
+        if (want < run + s_cnt[t]) {
+          s_cnt[0] = t;          // owner thread
+          s_val[0] = want - run;  // rank inside its slice
+          break;
+        }
+        run += s_cnt[t];
+      }
+    }
+    __syncthreads();
+    const int owner = (int)s_cnt[0];
+    if (tid == owner) {
+      long long k = s_val[0];
+      for (int64_t i = a0; i < a1; ++i)
+        if (assign[i] == q) {
+          if (k == 0) {
+            s_pick = i;
+            break;
+          }
+          --k;
+        }
+    }
+    __syncthreads();
+    const long long pick = s_pick;
+    if (pick >= 0) {
+      for (int d = tid; d < D; d += kRT) means[(size_t)g * D + d] = X[pick * ldx + d];
+      if (tid == 0) {
+        taken[q] += 1;
+        rem[q] -= 1;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---- assign() query (Sec. 4 API) ------------------------------------------
+
+// Euclidean: same FP32 + FP64 re-decision scheme as k_km_assign with lam = 1.
+// Probabilistic: a_g = c_g - 1/2 sum_d (x s - m)^2 from the EM constants, with
+// an FP64 re-decision when the best two are within a conservative bound.
+__global__ void __launch_bounds__(kNT) k_assign(const float* __restrict__ X, int64_t N, int D,
+                                                int64_t ldx, int G, int mode,
+                                                const float* __restrict__ hefts,
+                                                const float* __restrict__ means,
+                                                const float* __restrict__ dcovs,
+                                                const float* __restrict__ sT,
+                                                const float* __restrict__ mT,
+                                                const float* __restrict__ cc,
+                                                int32_t* __restrict__ assign,
+                                                unsigned long long* __restrict__ hist,
+                                                int32_t* __restrict__ dev_status) {
+  const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (i >= N) return;
+  const float* x = X + i * ldx;
+  int arg = 0;
+  if (mode == GMM_ASSIGN_EUCL) {
+    const float gamma = 2.0f * (float)(D + 4) * kU32;
+    float d1 = INFINITY, d2 = INFINITY;
+    for (int g = 0; g < G; ++g) {
+      float s = 0.0f;
+      for (int d = 0; d < D; ++d) {
+        const float t = x[d] - means[(size_t)g * D + d];
+        s = fmaf(t, t, s);
+      }
+      if (s < d1) {
+        d2 = d1;
+        d1 = s;
+        arg = g;
+      } else if (s < d2) {
+        d2 = s;
+      }
+    }
+    if (G > 1 && !(d2 - d1 > gamma * (d1 + d2))) {
+      double best = INFINITY;
+      arg = 0;
+      for (int g = 0; g < G; ++g) {
+        double s = 0.0;
+        for (int d = 0; d < D; ++d) {
+          const double t = (double)x[d] - (double)means[(size_t)g * D + d];
+          s += t * t;
+        }
+        if (s < best) {
+          best = s;
+          arg = g;
+        }
+      }
+      if (!isfinite(best)) atomicOr(dev_status, GMM_DEV_NONFINITE);
+    }
+  } else {
+    float a1 = -INFINITY, a2 = -INFINITY, mag = 0.0f;
+    for (int g = 0; g < G; ++g) {
+      float acc = 0.0f;
+      for (int d = 0; d < D; ++d) {
+        const float u = fmaf(x[d], sT[(size_t)d * G + g], -mT[(size_t)d * G + g]);
+        acc = fmaf(u, u, acc);
+      }
+      const float a = (cc[g] - 0.5f * acc) + cc[G + g];
+      if (a > a1) {
+        a2 = a1;
+        a1 = a;
+        arg = g;
+      } else if (a > a2) {
+        a2 = a;
+      }
+      mag = fmaxf(mag, fabsf(cc[g]) + 0.5f * acc);
+    }
+    // |error| of each FP32 a_g is below ~ (D + 8) u (|c_g| + sum u^2 / 2)
+    // plus the rounding of m_gd (|m| u per term); 8x that bound re-decides.
+    const float tol = 8.0f * (float)(D + 8) * kU32 * (mag + 1.0f);
+    if (G > 1 && !(a1 - a2 > tol)) {
+      double best = -INFINITY;
+      arg = 0;
+      for (int g = 0; g < G; ++g) {
+        double ld = 0.0, q = 0.0;
+        for (int d = 0; d < D; ++d) {
+          const double v = (double)dcovs[(size_t)g * D + d];
+          const double t = (double)x[d] - (double)means[(size_t)g * D + d];
+          ld += log(v);
+          q += t * t / v;
+        }
+        const double a = log((double)hefts[g]) - 0.5 * ((double)D * kLog2Pi + ld) - 0.5 * q;
+        if (a > best) {
+          best = a;
+          arg = g;
+        }
+      }
+      if (!isfinite(best)) atomicOr(dev_status, GMM_DEV_NONFINITE);
+    }
+  }
+  assign[i] = arg;
+  if (hist) atomicAdd(hist + arg, 1ull);
+}
+
+__global__ void k_zero_i64(int64_t* p, int n, int32_t* dev_status) {
+  for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) p[i] = 0;
+  if (dev_status && blockIdx.x == 0 && threadIdx.x == 0) *dev_status = 0;
+}
+
+}  // namespace
+
+hipError_t launch_kmeans(const float* X, int64_t N, int D, int64_t ldx, int G, int dist,
+                         const double* gvar, float var_floor, float* means, float* dcovs,
+                         float* hefts, int64_t* counts, int32_t* assign, double* inertia,
+                         int prec, int64_t* n_recomputed, int32_t* dev_status, const Workspace& w,
+                         hipStream_t st) {
+  (void)prec;
+  int32_t* asg = assign ? assign : w.assign;
+  const int nb = partial_blocks(N, 256);
+  const int64_t chunk = (N + nb - 1) / nb;
+  hipLaunchKernelGGL(k_km_init, dim3(1), dim3(64), 0, st, dev_status, n_recomputed);
+  hipLaunchKernelGGL(k_km_pre, dim3((D + 255) / 256), dim3(256), 0, st, gvar, D, var_floor, dist,
+                     w.lam64, w.lam32);
+  {
+    ProfScope ps(kProfKmAssign, st);
+    hipLaunchKernelGGL(k_km_assign, dim3(nb), dim3(kNT), 0, st, X, N, D, ldx, G, chunk, means,
+                       w.lam32, w.lam64, asg, w.scalars,
+                       n_recomputed ? n_recomputed : w.counters, dev_status);
+  }
+  {
+    ProfScope ps(kProfKmAccum, st);
+    hipLaunchKernelGGL(k_km_accum, dim3(nb), dim3(kNT), 0, st, X, N, D, ldx, G, chunk, means,
+                       asg, w.partials);
+  }
+  hipLaunchKernelGGL(k_km_fin, dim3(G), dim3(kNT), sizeof(double) * (2 * D + 1), st, w.partials,
+                     nb, N, D, G, var_floor, means, dcovs, hefts, counts, w.scalars, nb, inertia,
+                     dev_status);
+  hipLaunchKernelGGL(k_km_resurrect, dim3(1), dim3(kRT), 0, st, X, N, D, ldx, G, counts, asg,
+                     means, (int64_t*)w.partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_assign(const float* X, int64_t N, int D, int64_t ldx, int G, int mode,
+                         const float* hefts, const float* means, const float* dcovs,
+                         int32_t* assign, int64_t* hist, int32_t* dev_status, const Workspace& w,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(256), 0, st, hist ? hist : w.counters,
+                     hist ? G : 8, dev_status);
+  if (mode == GMM_ASSIGN_PROB) {
+    hipError_t e = launch_pre_diag(hefts, means, dcovs, D, G, w, st);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t nblk = (N + kNT - 1) / kNT;
+  hipLaunchKernelGGL(k_assign, dim3((unsigned)nblk), dim3(kNT), 0, st, X, N, D, ldx, G, mode,
+                     hefts, means, dcovs, w.s, w.m, w.c, assign, (unsigned long long*)hist,
+                     dev_status);
+  return hipGetLastError();
+}
+
+}  // namespace gmm

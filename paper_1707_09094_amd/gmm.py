@@ -1,0 +1,237 @@
+"""Python binding of the C ABI in include/gmm.h (libgmm.so, built in-tree).
+
+Argument marshalling only: every function checks the torch tensors it is given
+(device, dtype, shape, contiguity), passes their device pointers and the
+current HIP stream to the C entry point of the same name, and raises
+``GmmError`` on a non-zero return code.  All arithmetic runs in the HIP
+kernels; there is no fallback: if the library is missing, importing the
+binding's functions raises.
+
+Shapes: X is a float32 (N, D) tensor whose rows are samples (the paper's
+D x N column-major data matrix); a row stride >= D is allowed.  means and
+diagonal covariances are (G, D) float32 (row g = column g of the paper's
+matrices), full covariances (G, D, D), hefts (G,).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgmm.so")
+HEADER = os.path.join(HERE, "..", "include", "gmm.h")
+
+GMM_OK, GMM_EINVAL, GMM_EHIP = 0, -1, -2
+GMM_DEV_OK, GMM_DEV_NONFINITE, GMM_DEV_NOTPD = 0, 1, 2
+COV_DIAG, COV_FULL = 0, 1
+DIST_EUCL, DIST_MAHA = 0, 1
+ASSIGN_EUCL, ASSIGN_PROB = 0, 1
+PREC_FP32, PREC_BF16X3 = 0, 1
+
+
+class GmmError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__(f"{fn} failed with code {code} ({_status_string(code)})")
+        self.code = code
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_f32 = ctypes.c_float
+_sz = ctypes.c_size_t
+
+_SIGS = {
+    "gmm_version": ([], _i32),
+    "gmm_status_string": ([_i32], ctypes.c_char_p),
+    "gmm_workspace_bytes": ([_i64, _i32, _i32, _i32, _i32], _sz),
+    "gmm_global_stats": ([_vp, _i64, _i32, _i64, _vp, _vp, _vp, _sz, _vp], _i32),
+    "gmm_kmeans_iter": ([_vp, _i64, _i32, _i64, _i32, _i32, _vp, _f32, _vp, _vp, _vp, _vp, _vp,
+                         _vp, _i32, _vp, _vp, _vp, _sz, _vp], _i32),
+    "gmm_em_iter": ([_vp, _i64, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _f32, _i32, _vp, _vp, _vp,
+                     _vp, _sz, _vp], _i32),
+    "gmm_loglik": ([_vp, _i64, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp,
+                    _sz, _vp], _i32),
+    "gmm_assign": ([_vp, _i64, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
+                    _vp], _i32),
+    "gmm_profile_enable": ([_i32], _i32),
+    "gmm_profile_read": ([_i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)], _i32),
+}
+
+PROF_EM, PROF_KM_ASSIGN, PROF_KM_ACCUM, PROF_LOGLIK, PROF_STATS, PROF_BATCHED = range(6)
+
+_lib = None
+
+
+def library():
+    """Load libgmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not found: build it first (__graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def header_functions():
+    """Names of the functions declared in include/gmm.h."""
+    with open(HEADER) as f:
+        txt = f.read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gmm_[a-z0-9_]+)\s*\(", txt)))
+
+
+def _status_string(code):
+    try:
+        return library().gmm_status_string(int(code)).decode()
+    except Exception:
+        return "?"
+
+
+def _check(fn, rc):
+    if rc != GMM_OK:
+        raise GmmError(fn, rc)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, dtype, shape=None, name="tensor", optional=False):
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _xptr(X):
+    if not isinstance(X, torch.Tensor) or not X.is_cuda or X.dtype != torch.float32 or X.dim() != 2:
+        raise ValueError("X must be a float32 (N, D) device tensor")
+    N, D = X.shape
+    ldx = X.stride(0) if N > 1 else D
+    if (D > 1 and X.stride(1) != 1) or ldx < D:
+        raise ValueError("X rows must be contiguous samples with row stride >= D")
+    return ctypes.c_void_p(X.data_ptr()), int(N), int(D), int(ldx)
+
+
+def gmm_workspace_bytes(N, D, G, cov=COV_DIAG, prec=PREC_FP32):
+    return int(library().gmm_workspace_bytes(int(N), int(D), int(G), int(cov), int(prec)))
+
+
+def workspace(N, D, G, cov=COV_DIAG, prec=PREC_FP32, device="cuda"):
+    """A device byte buffer large enough for every entry point at this shape."""
+    n = gmm_workspace_bytes(N, D, G, cov, prec)
+    if n == 0:
+        raise GmmError("gmm_workspace_bytes", GMM_EINVAL)
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def _ws(ws):
+    if ws is None or ws.dtype != torch.uint8 or not ws.is_cuda:
+        raise ValueError("ws must be a uint8 device tensor from workspace()")
+    return ctypes.c_void_p(ws.data_ptr()), int(ws.numel())
+
+
+def gmm_global_stats(X, mean_out, var_out, ws, stream=None):
+    xp, N, D, ldx = _xptr(X)
+    wp, wn = _ws(ws)
+    rc = library().gmm_global_stats(xp, N, D, ldx, _ptr(mean_out, torch.float64, (D,), "mean_out"),
+                                    _ptr(var_out, torch.float64, (D,), "var_out"), wp, wn,
+                                    _stream(stream))
+    _check("gmm_global_stats", rc)
+
+
+def gmm_kmeans_iter(X, dist, gvar, var_floor, means, dcovs, hefts, counts, assign, inertia, prec,
+                    n_recomputed, dev_status, ws, stream=None):
+    xp, N, D, ldx = _xptr(X)
+    G = means.shape[0]
+    wp, wn = _ws(ws)
+    rc = library().gmm_kmeans_iter(
+        xp, N, D, ldx, G, int(dist), _ptr(gvar, torch.float64, (D,), "gvar", optional=True),
+        float(var_floor), _ptr(means, torch.float32, (G, D), "means"),
+        _ptr(dcovs, torch.float32, (G, D), "dcovs"), _ptr(hefts, torch.float32, (G,), "hefts"),
+        _ptr(counts, torch.int64, (G,), "counts"),
+        _ptr(assign, torch.int32, (N,), "assign", optional=True),
+        _ptr(inertia, torch.float64, (1,), "inertia"), int(prec),
+        _ptr(n_recomputed, torch.int64, (1,), "n_recomputed", optional=True),
+        _ptr(dev_status, torch.int32, (1,), "dev_status"), wp, wn, _stream(stream))
+    _check("gmm_kmeans_iter", rc)
+
+
+def _covshape(cov, G, D):
+    return (G, D, D) if cov == COV_FULL else (G, D)
+
+
+def gmm_em_iter(X, cov, hefts, means, covs, var_floor, prec, mean_loglik, n_recomputed,
+                dev_status, ws, stream=None):
+    xp, N, D, ldx = _xptr(X)
+    G = means.shape[0]
+    wp, wn = _ws(ws)
+    rc = library().gmm_em_iter(
+        xp, N, D, ldx, G, int(cov), _ptr(hefts, torch.float32, (G,), "hefts"),
+        _ptr(means, torch.float32, (G, D), "means"),
+        _ptr(covs, torch.float32, _covshape(cov, G, D), "covs"), float(var_floor), int(prec),
+        _ptr(mean_loglik, torch.float64, (1,), "mean_loglik"),
+        _ptr(n_recomputed, torch.int64, (1,), "n_recomputed", optional=True),
+        _ptr(dev_status, torch.int32, (1,), "dev_status"), wp, wn, _stream(stream))
+    _check("gmm_em_iter", rc)
+
+
+def gmm_loglik(X, cov, hefts, means, covs, prec, mean_loglik, per_sample, dev_status, ws,
+               stream=None):
+    xp, N, D, ldx = _xptr(X)
+    G = means.shape[0]
+    wp, wn = _ws(ws)
+    rc = library().gmm_loglik(
+        xp, N, D, ldx, G, int(cov), _ptr(hefts, torch.float32, (G,), "hefts"),
+        _ptr(means, torch.float32, (G, D), "means"),
+        _ptr(covs, torch.float32, _covshape(cov, G, D), "covs"), int(prec),
+        _ptr(mean_loglik, torch.float64, (1,), "mean_loglik"),
+        _ptr(per_sample, torch.float32, (N,), "per_sample", optional=True),
+        _ptr(dev_status, torch.int32, (1,), "dev_status"), wp, wn, _stream(stream))
+    _check("gmm_loglik", rc)
+
+
+def gmm_assign(X, mode, hefts, means, dcovs, assign, hist, dev_status, ws, stream=None):
+    xp, N, D, ldx = _xptr(X)
+    G = means.shape[0]
+    wp, wn = _ws(ws)
+    rc = library().gmm_assign(
+        xp, N, D, ldx, G, int(mode), _ptr(hefts, torch.float32, (G,), "hefts", optional=True),
+        _ptr(means, torch.float32, (G, D), "means"),
+        _ptr(dcovs, torch.float32, (G, D), "dcovs", optional=True),
+        _ptr(assign, torch.int32, (N,), "assign"),
+        _ptr(hist, torch.int64, (G,), "hist", optional=True),
+        _ptr(dev_status, torch.int32, (1,), "dev_status"), wp, wn, _stream(stream))
+    _check("gmm_assign", rc)
+
+
+def gmm_profile_enable(on=True):
+    _check("gmm_profile_enable", library().gmm_profile_enable(1 if on else 0))
+
+
+def gmm_profile_read(kind):
+    """(total milliseconds, launches) recorded for a kernel kind."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check("gmm_profile_read", library().gmm_profile_read(int(kind), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value

@@ -1,0 +1,47 @@
+"""Comparison helpers for GPU-vs-oracle parity (relative-error definitions of
+the per-step parity bar)."""
+import numpy as np
+
+PARAM_TOL = 1e-5    # weights, means, variances
+LOGLIK_TOL = 1e-6   # mean log-likelihood
+
+
+def rel_weights(w_gpu, w_ref, N):
+    w_ref = np.asarray(w_ref, dtype=np.float64)
+    return np.abs(np.asarray(w_gpu, np.float64) - w_ref) / np.maximum(w_ref, 1.0 / N)
+
+
+def rel_means(mu_gpu, mu_ref, var_ref):
+    mu_ref = np.asarray(mu_ref, np.float64)
+    scale = np.maximum(np.abs(mu_ref), np.sqrt(np.asarray(var_ref, np.float64)))
+    return np.abs(np.asarray(mu_gpu, np.float64) - mu_ref) / scale
+
+
+def rel_vars(v_gpu, v_ref):
+    v_ref = np.asarray(v_ref, np.float64)
+    return np.abs(np.asarray(v_gpu, np.float64) - v_ref) / v_ref
+
+
+def rel_full_cov(S_gpu, S_ref):
+    S_ref = np.asarray(S_ref, np.float64)
+    d = np.sqrt(np.einsum("gii->gi", S_ref))
+    scale = d[:, :, None] * d[:, None, :]
+    return np.abs(np.asarray(S_gpu, np.float64) - S_ref) / scale
+
+
+def check_em(gpu, ref, N, live=None, tol=PARAM_TOL, ll_tol=LOGLIK_TOL, full=False):
+    """gpu: dict hefts/means/covs/loglik; ref: oracle EMResult.  Components whose
+    oracle L_g < 1 are exempt for means/covariances."""
+    if live is None:
+        live = ref.L >= 1.0
+    ew = rel_weights(gpu["hefts"], ref.hefts, N).max()
+    em = rel_means(gpu["means"][live], ref.means[live],
+                   np.einsum("gii->gi", ref.covs[live]) if full else ref.covs[live]).max(initial=0)
+    if full:
+        ev = rel_full_cov(gpu["covs"][live], ref.covs[live]).max(initial=0)
+    else:
+        ev = rel_vars(gpu["covs"][live], ref.covs[live]).max(initial=0)
+    el = abs(gpu["loglik"] - ref.mean_loglik) / abs(ref.mean_loglik)
+    msg = f"weights {ew:.2e} means {em:.2e} covs {ev:.2e} loglik {el:.2e}"
+    assert ew <= tol and em <= tol and ev <= tol and el <= ll_tol, msg
+    return dict(weights=ew, means=em, covs=ev, loglik=el)

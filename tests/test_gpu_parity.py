@@ -1,0 +1,325 @@
+"""GPU parity: the HIP path through the C ABI vs the FP64 oracle, element by
+element on the same seeded inputs (same FP32 parameters into both, one
+iteration), plus edge cases, error paths and run-to-run determinism."""
+import numpy as np
+import pytest
+
+from paper_1707_09094_amd import synth
+from tests.parity import check_em, rel_means, rel_vars, rel_weights
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def G_():
+    from paper_1707_09094_amd import gmm
+    gmm.library()
+    return gmm
+
+
+def _t(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype)
+
+
+def gpu_em_step(gmm, X, w, mu, var, floor, prec=0, full=False, ws=None):
+    N, D = X.shape
+    G = len(w)
+    cov = gmm.COV_FULL if full else gmm.COV_DIAG
+    Xd = _t(X)
+    h, m, c = _t(w), _t(mu), _t(var)
+    ll = torch.zeros(1, dtype=torch.float64, device=DEV)
+    nrec = torch.zeros(1, dtype=torch.int64, device=DEV)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    if ws is None:
+        ws = gmm.workspace(N, D, G, cov, prec, DEV)
+    gmm.gmm_em_iter(Xd, cov, h, m, c, floor, prec, ll, nrec, st, ws)
+    torch.cuda.synchronize()
+    return dict(hefts=h.cpu().numpy(), means=m.cpu().numpy(), covs=c.cpu().numpy(),
+                loglik=float(ll.item()), nrec=int(nrec.item()), status=int(st.item()))
+
+
+def gpu_kmeans_step(gmm, X, mu, dist, floor, gvar=None, prec=0):
+    N, D = X.shape
+    G = mu.shape[0]
+    Xd = _t(X)
+    m = _t(mu)
+    dc = torch.zeros(G, D, device=DEV)
+    h = torch.zeros(G, device=DEV)
+    cnt = torch.zeros(G, dtype=torch.int64, device=DEV)
+    asg = torch.zeros(N, dtype=torch.int32, device=DEV)
+    inr = torch.zeros(1, dtype=torch.float64, device=DEV)
+    nrec = torch.zeros(1, dtype=torch.int64, device=DEV)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    ws = gmm.workspace(N, D, G, gmm.COV_DIAG, prec, DEV)
+    gv = None if gvar is None else _t(gvar, torch.float64)
+    gmm.gmm_kmeans_iter(Xd, dist, gv, floor, m, dc, h, cnt, asg, inr, prec, nrec, st, ws)
+    torch.cuda.synchronize()
+    return dict(means=m.cpu().numpy(), dcovs=dc.cpu().numpy(), hefts=h.cpu().numpy(),
+                counts=cnt.cpu().numpy(), assign=asg.cpu().numpy(), inertia=float(inr.item()),
+                nrec=int(nrec.item()), status=int(st.item()))
+
+
+def _params(seed, D, G, X=None):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w, mu, var = synth.random_params(rng, D, G)
+    if X is not None:  # means near data so components own samples
+        mu = X[rng.choice(len(X), G, replace=False)].astype(np.float32)
+    return w, mu, var
+
+
+# ---------------------------------------------------------------- global stats
+@pytest.mark.parametrize("N,D", [(1, 3), (10_000, 4), (50_001, 100), (777, 1)])
+def test_global_stats(G_, oracle, N, D):
+    rng = np.random.Generator(np.random.PCG64(N + D))
+    X = (rng.normal(size=(N, D)) * rng.uniform(0.1, 10, D) + rng.normal(size=D) * 50).astype(np.float32)
+    m = torch.zeros(D, dtype=torch.float64, device=DEV)
+    v = torch.zeros(D, dtype=torch.float64, device=DEV)
+    ws = G_.workspace(N, D, 1, device=DEV)
+    G_.gmm_global_stats(_t(X), m, v, ws)
+    rm, rv = oracle.global_stats(X)
+    np.testing.assert_allclose(m.cpu().numpy(), rm, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(v.cpu().numpy(), rv, rtol=1e-10, atol=1e-300)
+
+
+# ---------------------------------------------------------------- EM, diagonal
+EM_CASES = [
+    # (N, D, G) spanning several tiles, ragged tails and the degenerate shapes
+    (10_000, 4, 4),
+    (1, 3, 2),
+    (5, 2, 3),
+    (63, 17, 5),
+    (1000, 1, 3),
+    (3001, 128, 7),
+    (20_000, 100, 100),
+    (4097, 64, 40),
+]
+
+
+@pytest.mark.parametrize("N,D,G", EM_CASES)
+def test_em_step_diag_fp32(G_, oracle, N, D, G):
+    X, _ = synth.diag_gmm(1000 + N + D, D, max(G, 2), N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
+    w, mu, var = _params(N * 7 + G, D, G, X if N >= G else None)
+    floor = 1e-10
+    gpu = gpu_em_step(G_, X, w, mu, var, floor)
+    assert gpu["status"] == 0
+    ref = oracle.em_iter(X, w, mu, var, floor)
+    check_em(gpu, ref, N)
+
+
+def test_em_step_config1_and_trajectory(G_, oracle):
+    """Config 1 (D=4, G=4, N=1e4): 10 Mahalanobis k-means + 10 EM iterations;
+    every step compared with the oracle fed the same FP32 inputs, and the
+    trajectories' log-likelihood non-decreasing."""
+    X, _ = synth.config1()
+    N, D = X.shape
+    G = 4
+    _, gv = oracle.global_stats(X)
+    lam = oracle.maha_lambda(gv, 1e-10)
+    mu = synth.static_subset(X, G)
+    for _ in range(10):
+        gk = gpu_kmeans_step(G_, X, mu, 1, 1e-10, gvar=gv)
+        rk = oracle.kmeans_iter(X, mu, lam, 1e-10)
+        ok = rk.gap >= 1e-6
+        assert np.array_equal(gk["assign"][ok], rk.assign[ok])
+        mu = gk["means"]
+    w, var = gk["hefts"], gk["dcovs"]
+    prev = -np.inf
+    for _ in range(10):
+        gpu = gpu_em_step(G_, X, w, mu, var, 1e-10)
+        ref = oracle.em_iter(X, w, mu, var, 1e-10)
+        check_em(gpu, ref, N)
+        assert gpu["loglik"] >= prev - 1e-6 * abs(gpu["loglik"])
+        prev = gpu["loglik"]
+        w, mu, var = gpu["hefts"], gpu["means"], gpu["covs"]
+
+
+def test_em_single_component_closed_form(G_):
+    """N_G = 1 (Eqs. 5-7 with l = 1): sample mean and population variance."""
+    rng = np.random.Generator(np.random.PCG64(3))
+    X = (rng.normal(size=(5000, 6)) * 2 + 3).astype(np.float32)
+    gpu = gpu_em_step(G_, X, np.ones(1, np.float32), np.zeros((1, 6), np.float32),
+                      np.ones((1, 6), np.float32), 1e-10)
+    X64 = X.astype(np.float64)
+    assert abs(gpu["hefts"][0] - 1.0) <= 1e-6
+    np.testing.assert_allclose(gpu["means"][0], X64.mean(0), rtol=1e-5)
+    np.testing.assert_allclose(gpu["covs"][0], X64.var(0), rtol=1e-5)
+
+
+def test_em_floor_and_zero_weight(G_, oracle):
+    """Constant dimension -> variance exactly the floor; a zero-weight component
+    gets no responsibility, weight 0, and keeps its parameters."""
+    rng = np.random.Generator(np.random.PCG64(4))
+    X = rng.normal(size=(3000, 3)).astype(np.float32)
+    X[:, 2] = 1.25
+    w = np.array([0.5, 0.5, 0.0], np.float32)
+    mu = np.array([[-1, 0, 1.25], [1, 0, 1.25], [5, 5, 5]], np.float32)
+    var = np.ones((3, 3), np.float32)
+    gpu = gpu_em_step(G_, X, w, mu, var, 1e-3)
+    ref = oracle.em_iter(X, w, mu, var, 1e-3)
+    assert gpu["covs"][0, 2] == np.float32(1e-3) and gpu["covs"][1, 2] == np.float32(1e-3)
+    assert gpu["hefts"][2] == 0.0
+    np.testing.assert_array_equal(gpu["means"][2], mu[2])
+    check_em(gpu, ref, len(X))
+
+
+def test_em_nan_sets_status(G_):
+    X = np.ones((100, 3), np.float32)
+    X[17, 1] = np.nan
+    gpu = gpu_em_step(G_, X, np.ones(1, np.float32), np.zeros((1, 3), np.float32),
+                      np.ones((1, 3), np.float32), 1e-6)
+    assert gpu["status"] & 1
+
+
+def test_em_nonpositive_variance_sets_status(G_):
+    X = np.zeros((50, 2), np.float32)
+    gpu = gpu_em_step(G_, X, np.ones(2, np.float32) / 2, np.zeros((2, 2), np.float32),
+                      np.array([[1, 1], [1, 0]], np.float32), 1e-6)
+    assert gpu["status"] & 1
+
+
+def test_em_deterministic(G_):
+    X, _ = synth.diag_gmm(55, 32, 16, 30_000, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
+    w, mu, var = _params(5, 32, 16, X)
+    a = gpu_em_step(G_, X, w, mu, var, 1e-10)
+    b = gpu_em_step(G_, X, w, mu, var, 1e-10)
+    for k in ("hefts", "means", "covs"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["loglik"] == b["loglik"]
+
+
+def test_em_row_stride(G_, oracle):
+    """X with a row stride larger than D (ldx > D)."""
+    X, _ = synth.diag_gmm(56, 5, 3, 2000, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
+    w, mu, var = _params(6, 5, 3, X)
+    wide = np.zeros((2000, 8), np.float32)
+    wide[:, :5] = X
+    Xd = _t(wide)[:, :5]
+    cov = G_.COV_DIAG
+    h, m, c = _t(w), _t(mu), _t(var)
+    ll = torch.zeros(1, dtype=torch.float64, device=DEV)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    ws = G_.workspace(2000, 5, 3, cov, 0, DEV)
+    G_.gmm_em_iter(Xd, cov, h, m, c, 1e-10, 0, ll, None, st, ws)
+    gpu = dict(hefts=h.cpu().numpy(), means=m.cpu().numpy(), covs=c.cpu().numpy(),
+               loglik=float(ll.item()))
+    check_em(gpu, oracle.em_iter(X, w, mu, var, 1e-10), 2000)
+
+
+# ---------------------------------------------------------------- loglik
+@pytest.mark.parametrize("N,D,G", [(10_000, 4, 4), (777, 33, 9), (1, 2, 1)])
+def test_loglik_diag(G_, oracle, N, D, G):
+    X, _ = synth.diag_gmm(77 + N, D, max(G, 2), N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
+    w, mu, var = _params(8, D, G, X if N >= G else None)
+    ll = torch.zeros(1, dtype=torch.float64, device=DEV)
+    ps = torch.zeros(N, device=DEV)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    ws = G_.workspace(N, D, G, device=DEV)
+    G_.gmm_loglik(_t(X), 0, _t(w), _t(mu), _t(var), 0, ll, ps, st, ws)
+    ref, rps = oracle.loglik(X, w, mu, var, per_sample=True)
+    assert abs(ll.item() - ref) <= 1e-6 * abs(ref)
+    np.testing.assert_allclose(ps.cpu().numpy(), rps, rtol=2e-6, atol=2e-5)
+
+
+# ---------------------------------------------------------------- k-means
+@pytest.mark.parametrize("N,D,G,maha", [(10_000, 4, 4, True), (20_000, 100, 100, True),
+                                        (999, 3, 7, False), (1, 2, 1, False), (4, 2, 9, False)])
+def test_kmeans_step(G_, oracle, N, D, G, maha):
+    X, _ = synth.diag_gmm(300 + N, D, max(G, 2), N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
+    mu = synth.static_subset(X, G) if N >= G else np.concatenate(
+        [X, np.full((G - N, D), 100.0, np.float32)])
+    gv = oracle.global_stats(X)[1] if maha else None
+    lam = oracle.maha_lambda(gv, 1e-10) if maha else np.ones(D)
+    gk = gpu_kmeans_step(G_, X, mu, 1 if maha else 0, 1e-10, gvar=gv)
+    rk = oracle.kmeans_iter(X, mu, lam, 1e-10)
+    assert gk["status"] == 0
+    ok = rk.gap >= 1e-6
+    assert np.array_equal(gk["assign"][ok], rk.assign[ok])
+    assert np.abs(gk["counts"] - rk.counts).sum() <= 2 * (~ok).sum()
+    assert abs(gk["inertia"] - rk.inertia) <= 1e-9 * abs(rk.inertia) + 1e-12
+    if ok.all():
+        np.testing.assert_array_equal(gk["counts"], rk.counts)
+        live = rk.counts > 0
+        assert rel_means(gk["means"][live], rk.means[live], rk.dcovs[live]).max() <= 1e-5
+        assert rel_vars(gk["dcovs"][live], rk.dcovs[live]).max() <= 1e-5
+        assert rel_weights(gk["hefts"], rk.hefts, N).max() <= 1e-6
+        np.testing.assert_array_equal(gk["means"][~live], rk.means[~live].astype(np.float32))
+
+
+def test_kmeans_resurrection_golden(G_):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "resurrection_1d.json")) as f:
+        gd = json.load(f)
+    X = np.array(gd["X"], np.float32)[:, None]
+    mu = np.array(gd["means_in"], np.float32)[:, None]
+    gk = gpu_kmeans_step(G_, X, mu, 0, gd["var_floor"])
+    assert list(gk["assign"]) == gd["assign"]
+    assert list(gk["counts"]) == gd["counts"]
+    np.testing.assert_allclose(gk["means"][:, 0], gd["means_out"], rtol=1e-7)
+    np.testing.assert_allclose(gk["dcovs"][:, 0], gd["dcovs_out"], rtol=1e-6)
+    np.testing.assert_allclose(gk["hefts"], gd["hefts_out"], rtol=1e-7)
+    assert abs(gk["inertia"] - gd["inertia"]) <= 1e-9 * gd["inertia"]
+
+
+def test_kmeans_duplicate_means_tie(G_):
+    X = np.array([[0.0, 0.0], [1.0, 1.0], [5.0, 5.0]], np.float32)
+    mu = np.array([[5.0, 5.0], [0.5, 0.5], [0.5, 0.5]], np.float32)
+    gk = gpu_kmeans_step(G_, X, mu, 0, 1e-10)
+    assert list(gk["assign"]) == [1, 1, 0]
+    assert gk["nrec"] >= 2
+
+
+# ---------------------------------------------------------------- assign()
+@pytest.mark.parametrize("mode", [0, 1])
+def test_assign_and_hist(G_, oracle, mode):
+    X, _ = synth.diag_gmm(91, 6, 5, 5000, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
+    w, mu, var = _params(9, 6, 5, X)
+    asg = torch.zeros(5000, dtype=torch.int32, device=DEV)
+    hist = torch.zeros(5, dtype=torch.int64, device=DEV)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    ws = G_.workspace(5000, 6, 5, device=DEV)
+    G_.gmm_assign(_t(X), mode, _t(w), _t(mu), _t(var), asg, hist, st, ws)
+    ref = oracle.assign(X, w, mu, var, mode)
+    assert np.array_equal(asg.cpu().numpy(), ref)
+    assert np.array_equal(hist.cpu().numpy(), np.bincount(ref, minlength=5))
+
+
+# ---------------------------------------------------------------- errors
+def test_binding_raises_on_invalid(G_):
+    X = torch.zeros(10, 3, device=DEV)
+    ws = G_.workspace(10, 3, 2, device=DEV)
+    h = torch.zeros(2, device=DEV)
+    m = torch.zeros(2, 3, device=DEV)
+    c = torch.ones(2, 3, device=DEV)
+    ll = torch.zeros(1, dtype=torch.float64, device=DEV)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    with pytest.raises(G_.GmmError):
+        G_.gmm_em_iter(X, 0, h, m, c, -1.0, 0, ll, None, st, ws)  # negative floor
+    with pytest.raises(G_.GmmError):
+        G_.gmm_em_iter(X, 0, h, m, c, 0.0, 0, ll, None, st, ws[:64])  # workspace too small
+
+
+# ---------------------------------------------------------------- full covariance
+@pytest.mark.parametrize("N,D,G", [(5000, 4, 3), (3000, 32, 8), (257, 7, 2)])
+def test_em_step_full(G_, oracle, N, D, G):
+    X, truth = synth.full_gmm(500 + D, D, G, N)
+    rng = np.random.Generator(np.random.PCG64(D))
+    w = rng.dirichlet(np.ones(G)).astype(np.float32)
+    mu = X[rng.choice(N, G, replace=False)].astype(np.float32)
+    S = truth.covs.astype(np.float32)
+    S = (S + np.transpose(S, (0, 2, 1))) / 2
+    gpu = gpu_em_step(G_, X, w, mu, S, 1e-6, full=True)
+    assert gpu["status"] == 0
+    ref = oracle.em_iter(X, w, mu, S, 1e-6, full=True)
+    check_em(gpu, ref, N, full=True)
+
+
+def test_full_not_pd_sets_status(G_):
+    X = np.zeros((20, 2), np.float32)
+    S = np.array([[[1.0, 2.0], [2.0, 1.0]]], np.float32)
+    gpu = gpu_em_step(G_, X, np.ones(1, np.float32), np.zeros((1, 2), np.float32), S, 1e-6,
+                      full=True)
+    assert gpu["status"] & 2
