@@ -283,7 +283,15 @@ hipError_t launch_em_diag(const float* X, int64_t N, int D, int64_t ldx, int G, 
                           float* means, float* covs, float var_floor, int prec,
                           double* mean_loglik, int64_t* n_recomputed, int32_t* dev_status,
                           const Workspace& w, hipStream_t st) {
-  (void)prec;
+  if (em_fast_supported(D, G, prec)) {
+    int nb = 0;
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, dev_status, n_recomputed, w.counters);
+    hipError_t e = launch_em_fast(X, N, D, ldx, G, hefts, means, covs, prec, true, n_recomputed,
+                                  nullptr, dev_status, w, st, &nb);
+    if (e != hipSuccess) return e;
+    return launch_fin_welford(nb, N, D, G, var_floor, hefts, means, covs, mean_loglik,
+                              dev_status, w, st);
+  }
   const int T = tile_rows(D, G);
   const int nb = partial_blocks(N, 4 * T);
   int64_t chunk = (N + nb - 1) / nb;
@@ -307,7 +315,16 @@ hipError_t launch_loglik_diag(const float* X, int64_t N, int D, int64_t ldx, int
                               const float* hefts, const float* means, const float* covs, int prec,
                               double* mean_loglik, float* per_sample, int32_t* dev_status,
                               const Workspace& w, hipStream_t st) {
-  (void)prec;
+  if (em_fast_supported(D, G, prec)) {
+    int nb = 0;
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, dev_status, nullptr, w.counters);
+    hipError_t e = launch_em_fast(X, N, D, ldx, G, hefts, means, covs, prec, false, nullptr,
+                                  per_sample, dev_status, w, st, &nb);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ll_finish, dim3(1), dim3(64), 0, st, w.scalars, nb, N, mean_loglik,
+                       dev_status);
+    return hipGetLastError();
+  }
   const int T = tile_rows(D, G);
   const int nb = partial_blocks(N, 4 * T);
   int64_t chunk = (N + nb - 1) / nb;

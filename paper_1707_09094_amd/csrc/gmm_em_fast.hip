@@ -1,0 +1,765 @@
+// gmm_em_fast.hip -- one-pass EM kernel for diagonal covariances with up to
+// 128 Gaussians and 128 dimensions (the shapes of the D=100/G=100 and batched
+// D=40 workloads).  Shapes outside that envelope use the generic kernels of
+// gmm_em.hip.
+//
+// Workgroup of 8 waves, persistent over a contiguous range of samples, tiles of
+// T = 32 samples.  Per tile:
+//   1. the tile's samples are staged in LDS (xf[n][d]);
+//   2. screening: FP32 log-densities a_gn of every (component, sample) pair,
+//      either
+//        FORM_FP32   direct form c_g - 1/2 sum_d (x_d s_gd - m_gd)^2 on the
+//                    vector ALUs (s = 1/sigma, m = mu/sigma, staged in LDS), or
+//        FORM_BF16X3 expanded form c'_g + sum_k A_gk B_kn with
+//                    A_g = [Lambda_g mu_g ; -1/2 Lambda_g] and B_n = [x_n ; x_n^2]
+//                    (Sec. 2.2 Eq. 15 expanded) on the matrix cores,
+//                    v_mfma_f32_16x16x32_bf16 with both operands split into
+//                    BF16 hi + lo and the three products hi*hi, hi*lo, lo*hi
+//                    accumulated in FP32;
+//   3. per sample, the best FP32 value M_n and the near set {g: a_gn >= M_n - 30}.
+//      Near (sample, component) pairs are recomputed by 8-lane groups: in FP64
+//      from the FP32 parameters when the sample has two or more near
+//      components (their relative values decide shared responsibilities), in
+//      the FP32 direct form when it has one (BF16X3 only: that value sets the
+//      sample's log-likelihood);
+//   4. log-sum-exp per sample (Eqs. 16-18) summed in FP64, responsibilities
+//      (Eq. 3); responsibilities below exp(-80) are 0;
+//   5. the map step of Sec. 2.1 (Eqs. 9-11) in a weighted Welford form (West's
+//      update) on the deviations y = x - mu_old from the current mean: wave w
+//      owns components g = w, w+8, ...; lane owns dimensions d = lane, lane+64;
+//      for every sample with a non-zero responsibility r, in sample order,
+//        L' = L + r, delta = y - m, m += delta r / L', Q += delta^2 r L / L'
+//      (the first sample sets m = y exactly).  m is the block's weighted mean of
+//      y and Q its weighted sum of squared deviations from it; neither update
+//      subtracts two large accumulated sums, so the one-pass covariance of
+//      Eq. 8 loses nothing to cancellation (one sample gives Q = 0 exactly).
+//      Blocks are combined in fixed order by the pairwise update of (L, m, Q)
+//      in FP64 (k_fin_welford).
+#include "gmm_internal.hpp"
+
+namespace gmm {
+
+namespace {
+
+constexpr int kNW = 8;            // waves per workgroup
+constexpr int kThreads = kNW * kWave;
+constexpr int kT = 32;            // samples per tile
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+struct FastArgs {
+  const float* X;
+  int64_t N;
+  int64_t ldx;
+  int64_t chunk;
+  int D, G, KS;             // KS: number of 32-deep k-steps of the expanded form
+  const float* prm;         // [2][G][D+1]: s then m
+  const float* cc;          // [2][G] direct-form constant, hi/lo
+  const float* cexp;        // [2][G] expanded-form constant, hi/lo
+  const bf16x8* Whi;        // [RB][KS][64] fragments of A (hi)
+  const bf16x8* Wlo;        // same, lo part
+  const double* c64;        // [G]
+  const double* lam64;      // [G][D]
+  const float* means;       // [G][D] current means (centre of the moments)
+  double* part;             // [nb][G][2D+1]
+  double* ll_part;          // [nb]
+  float* per_sample;        // [N] or null
+  int32_t* dev_status;
+  int64_t* n_rec;           // or null
+};
+
+// LDS layout.  FP32 form: the direct-form parameters are staged (ps, pm) and
+// the moment accumulators live in registers.  BF16X3 form: the B fragments
+// (bhi, blo) and the FP32 moment accumulators acc[G][2D+1] live in LDS.
+struct Lds {
+  float* ps;        // [G][D+1]   (FP32 form)
+  float* pm;        // [G][D+1]   (FP32 form)
+  float* xf;        // [T][D+1]
+  float* as;        // [G][T]
+  bf16x8* bhi;      // [KS][2][64] (BF16X3 form)
+  bf16x8* blo;
+  float* acc;       // [G][2D+1]  (BF16X3 form)
+  float* pmax;      // [NW][T]
+  double* psum;     // [NW][T]
+  uint32_t* nbits;  // [T][4]
+  int* ncnt;        // [T]
+  int* pcount;      // [1]
+  uint16_t* plist;  // [T*G]
+};
+
+template <typename F>
+__host__ __device__ inline size_t lds_walk(int D, int G, int KS, int form, F&& at) {
+  size_t w = 0;
+  auto put = [&](int which, size_t words, size_t align_words) {
+    w = (w + align_words - 1) / align_words * align_words;
+    at(which, w);
+    w += words;
+  };
+  const bool bf = form == GMM_PREC_BF16X3;
+  put(0, bf ? 0 : (size_t)G * (D + 1), 1);
+  put(1, bf ? 0 : (size_t)G * (D + 1), 1);
+  put(2, (size_t)kT * (D + 1), 1);
+  put(3, (size_t)G * kT, 1);
+  put(4, bf ? (size_t)KS * 2 * 64 * 4 : 0, 4);
+  put(5, bf ? (size_t)KS * 2 * 64 * 4 : 0, 4);
+  put(6, bf ? (size_t)G * (2 * D + 1) : 0, 1);
+  put(7, kNW * kT, 1);
+  put(8, 2 * kNW * kT, 2);
+  put(9, kT * 4, 1);
+  put(10, kT, 1);
+  put(11, 1, 1);
+  put(12, ((size_t)kT * G + 1) / 2, 1);
+  return w;
+}
+
+__host__ __device__ inline size_t fast_lds_bytes(int D, int G, int KS, int form) {
+  return lds_walk(D, G, KS, form, [](int, size_t) {}) * 4 + 64;
+}
+
+__device__ inline Lds carve_lds(char* base, int D, int G, int KS, int form) {
+  Lds L;
+  float* f = (float*)base;
+  lds_walk(D, G, KS, form, [&](int which, size_t off) {
+    switch (which) {
+      case 0: L.ps = f + off; break;
+      case 1: L.pm = f + off; break;
+      case 2: L.xf = f + off; break;
+      case 3: L.as = f + off; break;
+      case 4: L.bhi = (bf16x8*)(f + off); break;
+      case 5: L.blo = (bf16x8*)(f + off); break;
+      case 6: L.acc = f + off; break;
+      case 7: L.pmax = f + off; break;
+      case 8: L.psum = (double*)(f + off); break;
+      case 9: L.nbits = (uint32_t*)(f + off); break;
+      case 10: L.ncnt = (int*)(f + off); break;
+      case 11: L.pcount = (int*)(f + off); break;
+      default: L.plist = (uint16_t*)(f + off); break;
+    }
+  });
+  return L;
+}
+
+__device__ __forceinline__ float group8_sum(float v) {
+  v += __shfl_xor(v, 1, kWave);
+  v += __shfl_xor(v, 2, kWave);
+  v += __shfl_xor(v, 4, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double group8_sum_d(double v) {
+  v += __shfl_xor(v, 1, kWave);
+  v += __shfl_xor(v, 2, kWave);
+  v += __shfl_xor(v, 4, kWave);
+  return v;
+}
+
+template <int FORM, int CPW, int DPL, bool MSTEP>
+__global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const int D = a.D, G = a.G, KS = a.KS;
+  const int DP = D + 1;
+  const Lds L = carve_lds(lds_raw, D, G, KS, FORM);
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int w = tid / kWave;
+  const int b = blockIdx.x;
+  const int64_t i0 = (int64_t)b * a.chunk;
+  const int64_t i1 = min(a.N, i0 + a.chunk);
+
+  constexpr bool ACCLDS = FORM == GMM_PREC_BF16X3;
+  const int P = 2 * D + 1;
+  if (!ACCLDS) {  // stage the direct-form parameters (ps and pm are adjacent)
+    for (int p = tid; p < G * DP; p += kThreads) {
+      L.ps[p] = a.prm[p];
+      L.pm[p] = a.prm[(size_t)G * DP + p];
+    }
+  } else if (MSTEP) {
+    for (int p = tid; p < G * P; p += kThreads) L.acc[p] = 0.0f;
+  }
+
+  // expanded-form weights of this wave's row block, kept in registers
+  constexpr int KSMAX = 8;
+  bf16x8 whi[KSMAX], wlo[KSMAX];
+  const int RB = (G + 15) / 16;
+  if (FORM == GMM_PREC_BF16X3 && w < RB) {
+#pragma unroll
+    for (int ks = 0; ks < KSMAX; ++ks)
+      if (ks < KS) {
+        whi[ks] = a.Whi[((size_t)w * KS + ks) * 64 + lane];
+        wlo[ks] = a.Wlo[((size_t)w * KS + ks) * 64 + lane];
+      }
+  }
+
+  // moment accumulators: component g = w + 8c, dimension d = lane + 64j
+  float S1[CPW][DPL], S2[CPW][DPL], Lc[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    Lc[c] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+      S1[c][j] = 0.0f;
+      S2[c][j] = 0.0f;
+    }
+  }
+  double llacc = 0.0;  // lanes < kT of wave 0: samples n = lane of every tile
+  int bad = 0;
+  long long nrec = 0;
+
+  for (int64_t t0 = i0; t0 < i1; t0 += kT) {
+    const int nt = (int)min((int64_t)kT, i1 - t0);
+    // 1. stage samples (zeros past the tail)
+    for (int p = tid; p < kT * D; p += kThreads) {
+      const int n = p / D, d = p - n * D;
+      L.xf[n * DP + d] = n < nt ? a.X[(t0 + n) * a.ldx + d] : 0.0f;
+    }
+    if (tid < kT) {
+      L.ncnt[tid] = 0;
+      L.nbits[tid * 4 + 0] = L.nbits[tid * 4 + 1] = L.nbits[tid * 4 + 2] = L.nbits[tid * 4 + 3] = 0u;
+    }
+    if (tid == 0) *L.pcount = 0;
+    __syncthreads();
+
+    // 2. screening
+    if (FORM == GMM_PREC_BF16X3) {
+      // B fragments: element i of lane l in k-step ks, column block cb is
+      // feature k = 32 ks + 8 (l/16) + i of sample n = 16 cb + l%16.
+      for (int p = tid; p < KS * 2 * 64; p += kThreads) {
+        const int l = p & 63, cb = (p >> 6) & 1, ks = p >> 7;
+        const int n = 16 * cb + (l & 15);
+        bf16x8 hi, lo;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int k = 32 * ks + 8 * (l >> 4) + i;
+          float v = 0.0f;
+          if (k < D) {
+            v = L.xf[n * DP + k];
+          } else if (k < 2 * D) {
+            const float x = L.xf[n * DP + k - D];
+            v = x * x;
+          }
+          const __bf16 h = (__bf16)v;
+          hi[i] = h;
+          lo[i] = (__bf16)(v - (float)h);
+        }
+        L.bhi[p] = hi;
+        L.blo[p] = lo;
+      }
+      __syncthreads();
+      if (w < RB) {
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int ks = 0; ks < KSMAX; ++ks)
+            if (ks < KS) {
+              const bf16x8 bh = L.bhi[(ks * 2 + cb) * 64 + lane];
+              const bf16x8 bl = L.blo[(ks * 2 + cb) * 64 + lane];
+              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wlo[ks], bh, acc, 0, 0, 0);
+              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(whi[ks], bl, acc, 0, 0, 0);
+              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(whi[ks], bh, acc, 0, 0, 0);
+            }
+          const int n = 16 * cb + (lane & 15);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int g = 16 * w + 4 * (lane >> 4) + j;
+            if (g < G) L.as[g * kT + n] = (acc[j] + a.cexp[g]) + a.cexp[G + g];
+          }
+        }
+      }
+    } else {
+      // direct form: thread owns component g = lane + 64 (w & 1) and samples
+      // n = 8 (w >> 1) .. + 7
+      const int g = lane + kWave * (w & 1);
+      const int n0 = 8 * (w >> 1);
+      if (g < G) {
+        float acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
+        const float* sg = L.ps + g * DP;
+        const float* mg = L.pm + g * DP;
+        for (int d = 0; d < D; ++d) {
+          const float s = sg[d], m = mg[d];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const float u = fmaf(L.xf[(n0 + q) * DP + d], s, -m);
+            acc[q] = fmaf(u, u, acc[q]);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) L.as[g * kT + n0 + q] = (a.cc[g] - 0.5f * acc[q]) + a.cc[G + g];
+      }
+    }
+    __syncthreads();
+
+    // 3a. per-sample maximum: wave w scans components g = w + 8c; lane n = lane%32,
+    // half = lane/32 takes every other one
+    const int n = lane & (kT - 1);
+    const int half = lane >> 5;
+    {
+      float mx = -INFINITY;
+      for (int g = w + kNW * half; g < G; g += 2 * kNW) mx = fmaxf(mx, L.as[g * kT + n]);
+      mx = fmaxf(mx, __shfl_xor(mx, 32, kWave));
+      if (half == 0) L.pmax[w * kT + n] = mx;
+    }
+    __syncthreads();
+    float M = -INFINITY;
+#pragma unroll
+    for (int q = 0; q < kNW; ++q) M = fmaxf(M, L.pmax[q * kT + n]);
+    // 3b. near pairs
+    if (n < nt) {
+      for (int g = w + kNW * half; g < G; g += 2 * kNW) {
+        if (L.as[g * kT + n] >= M - kNearGap) {
+          const int slot = atomicAdd(L.pcount, 1);
+          L.plist[slot] = (uint16_t)((n << 8) | g);
+          atomicAdd(&L.ncnt[n], 1);
+          atomicOr(&L.nbits[n * 4 + (g >> 5)], 1u << (g & 31));
+        }
+      }
+    }
+    __syncthreads();
+    // 3c. recompute near pairs, one 8-lane group per pair
+    {
+      const int np = *L.pcount;
+      const int grp = tid >> 3, gl = tid & 7;
+      for (int p = grp; p < np; p += kThreads / 8) {
+        const int code = L.plist[p];
+        const int pn = code >> 8, g = code & 255;
+        const float* x = L.xf + pn * DP;
+        float Mp = -INFINITY;
+#pragma unroll
+        for (int q = 0; q < kNW; ++q) Mp = fmaxf(Mp, L.pmax[q * kT + pn]);
+        if (L.ncnt[pn] >= 2) {
+          const float* mu_g = a.means + (size_t)g * D;
+          const double* lg = a.lam64 + (size_t)g * D;
+          double q = 0.0;
+          for (int d = gl; d < D; d += 8) {
+            const double u = (double)x[d] - (double)mu_g[d];
+            q += u * u * lg[d];
+          }
+          q = group8_sum_d(q);
+          if (gl == 0) L.as[g * kT + pn] = (float)(a.c64[g] - 0.5 * q - (double)Mp);
+          if (gl == 0) ++nrec;
+        } else if (FORM == GMM_PREC_BF16X3) {
+          const float* sg = a.prm + (size_t)g * DP;
+          const float* mg = a.prm + (size_t)G * DP + (size_t)g * DP;
+          float q = 0.0f;
+          for (int d = gl; d < D; d += 8) {
+            const float u = fmaf(x[d], sg[d], -mg[d]);
+            q = fmaf(u, u, q);
+          }
+          q = group8_sum(q);
+          if (gl == 0) {
+            const double av = ((double)a.cc[g] + (double)a.cc[G + g]) - 0.5 * (double)q;
+            L.as[g * kT + pn] = (float)(av - (double)Mp);
+            ++nrec;
+          }
+        } else {
+          // FP32 form, single near component: the screening value is already
+          // the direct form; store it relative to the maximum
+          if (gl == 0) L.as[g * kT + pn] = L.as[g * kT + pn] - Mp;
+        }
+      }
+    }
+    __syncthreads();
+    // 4. log-sum-exp: entries of near pairs now hold a - M_n, the rest a32
+    {
+      double s = 0.0;
+      for (int g = w + kNW * half; g < G; g += 2 * kNW) {
+        const bool near = (L.nbits[n * 4 + (g >> 5)] >> (g & 31)) & 1u;
+        const float v = L.as[g * kT + n];
+        s += (double)__expf(near ? v : v - M);
+      }
+      s += __shfl_xor(s, 32, kWave);
+      if (half == 0) L.psum[w * kT + n] = s;
+    }
+    __syncthreads();
+    double tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < kNW; ++q) tot += L.psum[q * kT + n];
+    const double lse = (double)M + log(tot);
+    if (w == 0 && half == 0 && n < nt) {
+      llacc += lse;
+      if (!isfinite(lse)) bad = 1;
+      if (a.per_sample) a.per_sample[t0 + n] = (float)lse;
+    }
+    if (MSTEP) {
+      const float dl = (float)(lse - (double)M);
+      for (int g = w + kNW * half; g < G; g += 2 * kNW) {
+        const bool near = (L.nbits[n * 4 + (g >> 5)] >> (g & 31)) & 1u;
+        const float v = L.as[g * kT + n];
+        const float z = (near ? v : v - M) - dl;
+        L.as[g * kT + n] = (n < nt && z >= -kRespCut) ? __expf(z) : 0.0f;
+      }
+      // 5. moments of this wave's components (written above by this wave only)
+      if (ACCLDS) {
+        for (int g = w; g < G; g += kNW) {
+          const float r_l = lane < kT ? L.as[g * kT + lane] : 0.0f;
+          unsigned long long msk = __ballot(r_l != 0.0f);
+          if (!msk) continue;
+          float mu[2];
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const int d = lane + kWave * j;
+            mu[j] = d < D ? a.means[(size_t)g * D + d] : 0.0f;
+          }
+          float* ag = L.acc + (size_t)g * P;
+          float Lg = ag[0];
+          while (msk) {
+            const int nn = __ffsll((long long)msk) - 1;
+            msk &= msk - 1;
+            const float r = L.as[g * kT + nn];
+            const float Lo = Lg;
+            const float Ln = Lo + r;
+            const float inv = r / Ln;
+            const float w2 = inv * Lo;
+            Lg = Ln;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              const int d = lane + kWave * j;
+              if (d < D) {
+                const float y = L.xf[nn * DP + d] - mu[j];
+                if (Lo == 0.0f) {
+                  ag[1 + d] = y;
+                } else {
+                  const float m0 = ag[1 + d];
+                  const float dl = y - m0;
+                  ag[1 + d] = fmaf(inv, dl, m0);
+                  ag[1 + D + d] = fmaf(w2 * dl, dl, ag[1 + D + d]);
+                }
+              }
+            }
+          }
+          if (lane == 0) ag[0] = Lg;
+        }
+      } else
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int g = w + kNW * c;
+        if (g < G) {
+          const float r_l = lane < kT ? L.as[g * kT + lane] : 0.0f;
+          unsigned long long msk = __ballot(r_l != 0.0f);
+          float mu[DPL];
+#pragma unroll
+          for (int j = 0; j < DPL; ++j) {
+            const int d = lane + kWave * j;
+            mu[j] = (msk && d < D) ? a.means[(size_t)g * D + d] : 0.0f;
+          }
+          while (msk) {
+            const int nn = __ffsll((long long)msk) - 1;
+            msk &= msk - 1;
+            const float r = L.as[g * kT + nn];
+            const float Lo = Lc[c];
+            const float Ln = Lo + r;
+            const float inv = r / Ln;
+            const float w2 = inv * Lo;
+            Lc[c] = Ln;
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) {
+              const int d = lane + kWave * j;
+              if (d < D) {
+                const float y = L.xf[nn * DP + d] - mu[j];
+                if (Lo == 0.0f) {
+                  S1[c][j] = y;
+                } else {
+                  const float dl = y - S1[c][j];
+                  S1[c][j] = fmaf(inv, dl, S1[c][j]);
+                  S2[c][j] = fmaf(w2 * dl, dl, S2[c][j]);
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // block partials in FP64
+  if (MSTEP && ACCLDS) {
+    __syncthreads();
+    double* pb = a.part + (size_t)b * G * P;
+    for (int p = tid; p < G * P; p += kThreads) pb[p] = (double)L.acc[p];
+  } else if (MSTEP) {
+    double* pb = a.part + (size_t)b * G * P;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int g = w + kNW * c;
+      if (g < G) {
+        if (lane == 0) pb[(size_t)g * P] = (double)Lc[c];
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) {
+          const int d = lane + kWave * j;
+          if (d < D) {
+            pb[(size_t)g * P + 1 + d] = (double)S1[c][j];
+            pb[(size_t)g * P + 1 + D + d] = (double)S2[c][j];
+          }
+        }
+      }
+    }
+  }
+  // log-likelihood: lanes 0..31 of wave 0, fixed-order tree
+  if (w == 0) {
+    double v = lane < kT ? llacc : 0.0;
+    v = wave_sum_d(v);
+    if (lane == 0) a.ll_part[b] = v;
+  }
+  if (bad) atomicOr(a.dev_status, GMM_DEV_NONFINITE);
+  if (a.n_rec) {
+    long long v = nrec;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    if (lane == 0 && v) atomicAdd((unsigned long long*)a.n_rec, (unsigned long long)v);
+  }
+}
+
+// Per-component constants of the fast kernel.  One workgroup per component.
+__global__ void __launch_bounds__(256) k_pre_fast(const float* __restrict__ hefts,
+                                                  const float* __restrict__ means,
+                                                  const float* __restrict__ covs, int D, int G,
+                                                  int KS, float* __restrict__ prm,
+                                                  float* __restrict__ cc,
+                                                  float* __restrict__ cexp,
+                                                  bf16x8* __restrict__ Whi,
+                                                  bf16x8* __restrict__ Wlo,
+                                                  double* __restrict__ c64,
+                                                  double* __restrict__ lam64) {
+  __shared__ double sh[256];
+  const int g = blockIdx.x;
+  const int DP = D + 1;
+  double ld = 0.0, q = 0.0;
+  for (int d = threadIdx.x; d < D; d += 256) {
+    const double v = (double)covs[(size_t)g * D + d];
+    const double mu = (double)means[(size_t)g * D + d];
+    const double lam = 1.0 / v;
+    const double s = sqrt(lam);
+    prm[(size_t)g * DP + d] = (float)s;
+    prm[(size_t)G * DP + (size_t)g * DP + d] = (float)(mu * s);
+    lam64[(size_t)g * D + d] = lam;
+    ld += log(v);
+    q += lam * mu * mu;
+  }
+  if (threadIdx.x == 0) {
+    prm[(size_t)g * DP + D] = 0.0f;
+    prm[(size_t)G * DP + (size_t)g * DP + D] = 0.0f;
+  }
+  const double logdet = block_sum_d<256>(ld, sh);
+  const double quad = block_sum_d<256>(q, sh);
+  if (threadIdx.x == 0) {
+    const double c = log((double)hefts[g]) - 0.5 * ((double)D * kLog2Pi + logdet);
+    const float hi = (float)c;
+    cc[g] = hi;
+    cc[G + g] = isfinite(c) ? (float)(c - (double)hi) : 0.0f;
+    c64[g] = c;
+    const double ce = c - 0.5 * quad;
+    const float ehi = (float)ce;
+    cexp[g] = ehi;
+    cexp[G + g] = isfinite(ce) ? (float)(ce - (double)ehi) : 0.0f;
+  }
+  // fragments of A row g: A_gk = lam mu (k < D), -lam/2 (D <= k < 2D), 0 beyond
+  const int rb = g >> 4, row = g & 15;
+  for (int e = threadIdx.x; e < KS * 4 * 8; e += 256) {
+    const int ks = e / 32, r = e - ks * 32, lq = r >> 3, i = r & 7;
+    const int k = 32 * ks + 8 * lq + i;
+    float v = 0.0f;
+    if (k < D) {
+      const double lam = 1.0 / (double)covs[(size_t)g * D + k];
+      v = (float)(lam * (double)means[(size_t)g * D + k]);
+    } else if (k < 2 * D) {
+      v = (float)(-0.5 / (double)covs[(size_t)g * D + k - D]);
+    }
+    const __bf16 h = (__bf16)v;
+    const __bf16 l = (__bf16)(v - (float)h);
+    const int lanei = 16 * lq + row;
+    const size_t idx = ((size_t)rb * KS + ks) * 64 + lanei;
+    ((__bf16*)(Whi + idx))[i] = h;
+    ((__bf16*)(Wlo + idx))[i] = l;
+  }
+}
+
+// Rows of the last row block past G get zero weights.
+__global__ void k_zero_pad_rows(bf16x8* Whi, bf16x8* Wlo, int G, int KS) {
+  const int RB = (G + 15) / 16;
+  const int rb = RB - 1;
+  for (int e = threadIdx.x; e < KS * 64; e += blockDim.x) {
+    const int ks = e / 64, l = e - ks * 64;
+    const int g = 16 * rb + (l & 15);
+    if (g >= G) {
+      const size_t idx = ((size_t)rb * KS + ks) * 64 + l;
+      bf16x8 z;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) z[i] = (__bf16)0.0f;
+      Whi[idx] = z;
+      Wlo[idx] = z;
+    }
+  }
+}
+
+// Reduce step for the Welford partials [nb][G][1 + 2D] = (L, m, Q), m being
+// the weighted mean of x - mu_old: one
+// workgroup per component, thread per dimension, blocks combined in order by
+// L = La + Lb, m = ma + (mb - ma) Lb / L, Q = Qa + Qb + (mb - ma)^2 La Lb / L.
+// Then Eq. 5 (w = L/N), Eq. 6 (mu = mu_old + m), Eq. 7 (sigma2 = Q/L) and the
+// floor.
+__global__ void __launch_bounds__(256) k_fin_welford(const double* __restrict__ part, int nb,
+                                                     int64_t N, int D, int G, float var_floor,
+                                                     float* __restrict__ hefts,
+                                                     float* __restrict__ means,
+                                                     float* __restrict__ covs,
+                                                     const double* __restrict__ ll_part,
+                                                     double* __restrict__ mean_loglik,
+                                                     int32_t* __restrict__ dev_status) {
+  __shared__ int bad;
+  const int g = blockIdx.x;
+  const int P = 2 * D + 1;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  double Ltot = 0.0;
+  for (int b = 0; b < nb; ++b) Ltot += part[((size_t)b * G + g) * P];
+  for (int d = threadIdx.x; d < D; d += 256) {
+    double L = 0.0, m = 0.0, Q = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      const double* q = part + ((size_t)b * G + g) * P;
+      const double Lb = q[0];
+      if (Lb == 0.0) continue;
+      const double mb = q[1 + d], Qb = q[1 + D + d];
+      if (L == 0.0) {
+        L = Lb;
+        m = mb;
+        Q = Qb;
+      } else {
+        const double Ln = L + Lb;
+        const double dl = mb - m;
+        m += dl * (Lb / Ln);
+        Q += Qb + dl * dl * (L * Lb / Ln);
+        L = Ln;
+      }
+    }
+    if (L > 0.0) {
+      double v = Q / L;
+      v = v > 0.0 ? v : 0.0;
+      v = v > (double)var_floor ? v : (double)var_floor;
+      means[(size_t)g * D + d] = (float)((double)means[(size_t)g * D + d] + m);
+      covs[(size_t)g * D + d] = (float)v;
+      if (!isfinite(m) || !isfinite(v)) bad = 1;
+    }
+  }
+  if (threadIdx.x == 0) {
+    const float w = (float)(Ltot / (double)N);
+    hefts[g] = w;
+    if (!isfinite(w)) bad = 1;
+  }
+  if (g == 0 && threadIdx.x == 0 && mean_loglik) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += ll_part[b];
+    *mean_loglik = s / (double)N;
+    if (!isfinite(s)) bad = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && bad) atomicOr(dev_status, GMM_DEV_NONFINITE);
+}
+
+template <int FORM, int CPW, int DPL, bool MSTEP>
+void launch_one(const FastArgs& a, int nb, size_t lds, hipStream_t st) {
+  auto kern = k_em_fast<FORM, CPW, DPL, MSTEP>;
+  static bool attr_set = false;  // benign race: setting the attribute twice is harmless
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), lds, st, a);
+}
+
+template <int FORM, bool MSTEP>
+void dispatch_cpw(const FastArgs& a, int nb, size_t lds, hipStream_t st) {
+  if constexpr (FORM == GMM_PREC_BF16X3) {
+    launch_one<FORM, 1, 1, MSTEP>(a, nb, lds, st);
+  } else {
+  const int cpw = (a.G + kNW - 1) / kNW;
+  const int dpl = (a.D + kWave - 1) / kWave;
+  if (dpl == 1) {
+    if (cpw <= 2) launch_one<FORM, 2, 1, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 4) launch_one<FORM, 4, 1, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 8) launch_one<FORM, 8, 1, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 13) launch_one<FORM, 13, 1, MSTEP>(a, nb, lds, st);
+    else launch_one<FORM, 16, 1, MSTEP>(a, nb, lds, st);
+  } else {
+    if (cpw <= 2) launch_one<FORM, 2, 2, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 4) launch_one<FORM, 4, 2, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 8) launch_one<FORM, 8, 2, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 13) launch_one<FORM, 13, 2, MSTEP>(a, nb, lds, st);
+    else launch_one<FORM, 16, 2, MSTEP>(a, nb, lds, st);
+  }
+  }
+}
+
+}  // namespace
+
+bool em_fast_supported(int D, int G, int prec) {
+  if (D < 1 || D > 128 || G < 1 || G > 128) return false;
+  const int KS = (2 * D + 31) / 32;
+  return fast_lds_bytes(D, G, KS, prec) <= 160 * 1024;
+}
+
+int em_fast_blocks(int64_t N) {
+  int64_t b = (N + kT * 4 - 1) / (kT * 4);
+  if (b < 1) b = 1;
+  if (b > 256) b = 256;
+  return (int)b;
+}
+
+hipError_t launch_em_fast(const float* X, int64_t N, int D, int64_t ldx, int G, const float* hefts,
+                          const float* means, const float* covs, int prec, bool mstep,
+                          int64_t* n_recomputed, float* per_sample, int32_t* dev_status,
+                          const Workspace& w, hipStream_t st, int* nb_out) {
+  const int KS = (2 * D + 31) / 32;
+  const int nb = em_fast_blocks(N);
+  FastArgs a;
+  a.X = X;
+  a.N = N;
+  a.ldx = ldx;
+  a.chunk = ((N + nb - 1) / nb + kT - 1) / kT * kT;
+  a.D = D;
+  a.G = G;
+  a.KS = KS;
+  a.prm = w.prm;
+  a.cc = w.c;
+  a.cexp = w.cexp;
+  a.Whi = (const bf16x8*)w.Bhi;
+  a.Wlo = (const bf16x8*)w.Blo;
+  a.c64 = w.c64;
+  a.lam64 = w.lamg64;
+  a.means = means;
+  a.part = w.partials;
+  a.ll_part = w.scalars;
+  a.per_sample = per_sample;
+  a.dev_status = dev_status;
+  a.n_rec = n_recomputed;
+  hipLaunchKernelGGL(k_pre_fast, dim3(G), dim3(256), 0, st, hefts, means, covs, D, G, KS, w.prm,
+                     w.c, w.cexp, (bf16x8*)w.Bhi, (bf16x8*)w.Blo, w.c64, w.lamg64);
+  if (G % 16) hipLaunchKernelGGL(k_zero_pad_rows, dim3(1), dim3(256), 0, st, (bf16x8*)w.Bhi,
+                                 (bf16x8*)w.Blo, G, KS);
+  const size_t lds = fast_lds_bytes(D, G, KS, prec);
+  {
+    ProfScope ps(mstep ? kProfEM : kProfLoglik, st);
+    if (prec == GMM_PREC_BF16X3) {
+      if (mstep) dispatch_cpw<GMM_PREC_BF16X3, true>(a, nb, lds, st);
+      else dispatch_cpw<GMM_PREC_BF16X3, false>(a, nb, lds, st);
+    } else {
+      if (mstep) dispatch_cpw<GMM_PREC_FP32, true>(a, nb, lds, st);
+      else dispatch_cpw<GMM_PREC_FP32, false>(a, nb, lds, st);
+    }
+  }
+  *nb_out = nb;
+  return hipGetLastError();
+}
+
+hipError_t launch_fin_welford(int nb, int64_t N, int D, int G, float var_floor, float* hefts,
+                              float* means, float* covs, double* mean_loglik, int32_t* dev_status,
+                              const Workspace& w, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_welford, dim3(G), dim3(256), 0, st, w.partials, nb, N, D, G,
+                     var_floor, hefts, means, covs, w.scalars, mean_loglik, dev_status);
+  return hipGetLastError();
+}
+
+}  // namespace gmm

@@ -42,6 +42,7 @@ struct Workspace {
   float* m;        // diag: [D][G] mu/sigma                full: unused
   float* c;        // [2][G] log w - 1/2 (D log 2pi + log|Sigma|), split hi/lo
   float* W;        // full: [G][D][D] inverse Cholesky factor (row-major lower)
+  float* prm;      // fast diag kernel: [2][G][D+1] 1/sigma then mu/sigma
   uint16_t* Bhi;   // BF16X3 expanded weights [G][K] hi part
   uint16_t* Blo;   // BF16X3 expanded weights [G][K] lo part
   float* cexp;     // BF16X3: [2][G] constant of the expanded form, hi/lo
@@ -73,8 +74,10 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   size_t o_m = take(sizeof(float) * (size_t)D * G);
   size_t o_c = take(sizeof(float) * 2 * (size_t)G);
   size_t o_W = take(cov == GMM_COV_FULL ? sizeof(float) * (size_t)D * D * G : 0);
-  size_t o_bh = take(sizeof(uint16_t) * (size_t)K * G);
-  size_t o_bl = take(sizeof(uint16_t) * (size_t)K * G);
+  const size_t GP = ((size_t)G + 15) / 16 * 16;
+  size_t o_prm = take(sizeof(float) * 2 * (size_t)G * (D + 1));
+  size_t o_bh = take(sizeof(uint16_t) * (size_t)K * GP);
+  size_t o_bl = take(sizeof(uint16_t) * (size_t)K * GP);
   size_t o_ce = take(sizeof(float) * 2 * (size_t)G);
   size_t o_c64 = take(sizeof(double) * (size_t)G);
   size_t o_lg = take(sizeof(double) * (size_t)G * D);
@@ -93,6 +96,7 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   w->m = (float*)(b + o_m);
   w->c = (float*)(b + o_c);
   w->W = (float*)(b + o_W);
+  w->prm = (float*)(b + o_prm);
   w->Bhi = (uint16_t*)(b + o_bh);
   w->Blo = (uint16_t*)(b + o_bl);
   w->cexp = (float*)(b + o_ce);
@@ -175,6 +179,16 @@ hipError_t launch_global_stats(const float* X, int64_t N, int D, int64_t ldx, do
 
 hipError_t launch_pre_diag(const float* hefts, const float* means, const float* covs, int D,
                            int G, const Workspace& w, hipStream_t st);
+
+bool em_fast_supported(int D, int G, int prec);
+hipError_t launch_em_fast(const float* X, int64_t N, int D, int64_t ldx, int G, const float* hefts,
+                          const float* means, const float* covs, int prec, bool mstep,
+                          int64_t* n_recomputed, float* per_sample, int32_t* dev_status,
+                          const Workspace& w, hipStream_t st, int* nb_out);
+
+hipError_t launch_fin_welford(int nb, int64_t N, int D, int G, float var_floor, float* hefts,
+                              float* means, float* covs, double* mean_loglik, int32_t* dev_status,
+                              const Workspace& w, hipStream_t st);
 
 hipError_t launch_em_diag(const float* X, int64_t N, int D, int64_t ldx, int G, float* hefts,
                           float* means, float* covs, float var_floor, int prec,

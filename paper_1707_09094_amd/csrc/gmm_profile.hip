@@ -34,12 +34,12 @@ ProfScope::ProfScope(int kind, hipStream_t st) : kind_(kind), st_(st), a_(nullpt
     a_ = b_ = nullptr;
     return;
   }
-  hipEventRecord(a_, st_);
+  (void)hipEventRecord(a_, st_);
 }
 
 ProfScope::~ProfScope() {
   if (!a_) return;
-  hipEventRecord(b_, st_);
+  (void)hipEventRecord(b_, st_);
   std::lock_guard<std::mutex> lk(g_mu);
   g_pending.push_back({kind_, a_, b_});
 }
@@ -52,8 +52,8 @@ static void drain_locked() {
       g_ms[r.kind] += ms;
       g_n[r.kind] += 1;
     }
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
   g_pending.clear();
 }

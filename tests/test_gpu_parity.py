@@ -86,7 +86,8 @@ def test_global_stats(G_, oracle, N, D):
 
 # ---------------------------------------------------------------- EM, diagonal
 EM_CASES = [
-    # (N, D, G) spanning several tiles, ragged tails and the degenerate shapes
+    # (N, D, G) spanning several tiles, ragged tails and the degenerate shapes;
+    # the last three fall outside the one-pass kernel's envelope (G or D > 128)
     (10_000, 4, 4),
     (1, 3, 2),
     (5, 2, 3),
@@ -95,18 +96,42 @@ EM_CASES = [
     (3001, 128, 7),
     (20_000, 100, 100),
     (4097, 64, 40),
+    (2000, 40, 128),
+    (1500, 200, 5),
+    (2500, 8, 150),
 ]
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
 @pytest.mark.parametrize("N,D,G", EM_CASES)
-def test_em_step_diag_fp32(G_, oracle, N, D, G):
+def test_em_step_diag(G_, oracle, N, D, G, prec):
     X, _ = synth.diag_gmm(1000 + N + D, D, max(G, 2), N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
     w, mu, var = _params(N * 7 + G, D, G, X if N >= G else None)
     floor = 1e-10
-    gpu = gpu_em_step(G_, X, w, mu, var, floor)
+    gpu = gpu_em_step(G_, X, w, mu, var, floor, prec=prec)
     assert gpu["status"] == 0
     ref = oracle.em_iter(X, w, mu, var, floor)
     check_em(gpu, ref, N)
+
+
+@pytest.mark.parametrize("N,D,G", [(200_000, 100, 100), (50_000, 40, 64)])
+def test_em_forms_agree_on_fitted_model(G_, oracle, N, D, G):
+    """From a k-means hand-off (the realistic regime: most samples have one
+    near component), both arithmetic forms match the oracle and each other."""
+    X, _ = synth.diag_gmm(4242 + D, D, G, N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
+    _, gv = oracle.global_stats(X)
+    mu = synth.static_subset(X, G)
+    for _ in range(3):
+        gk = gpu_kmeans_step(G_, X, mu, 1, 1e-10, gvar=gv)
+        mu = gk["means"]
+    w, var = gk["hefts"], gk["dcovs"]
+    ref = oracle.em_iter(X, w, mu, var, 1e-10)
+    a = gpu_em_step(G_, X, w, mu, var, 1e-10, prec=0)
+    b = gpu_em_step(G_, X, w, mu, var, 1e-10, prec=1)
+    check_em(a, ref, N)
+    check_em(b, ref, N)
+    assert abs(a["loglik"] - b["loglik"]) <= 1e-7 * abs(a["loglik"])
+    assert b["nrec"] >= N  # every sample's best component is recomputed
 
 
 def test_em_step_config1_and_trajectory(G_, oracle):
@@ -180,11 +205,12 @@ def test_em_nonpositive_variance_sets_status(G_):
     assert gpu["status"] & 1
 
 
-def test_em_deterministic(G_):
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
+def test_em_deterministic(G_, prec):
     X, _ = synth.diag_gmm(55, 32, 16, 30_000, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
     w, mu, var = _params(5, 32, 16, X)
-    a = gpu_em_step(G_, X, w, mu, var, 1e-10)
-    b = gpu_em_step(G_, X, w, mu, var, 1e-10)
+    a = gpu_em_step(G_, X, w, mu, var, 1e-10, prec=prec)
+    b = gpu_em_step(G_, X, w, mu, var, 1e-10, prec=prec)
     for k in ("hefts", "means", "covs"):
         assert np.array_equal(a[k], b[k]), k
     assert a["loglik"] == b["loglik"]
@@ -209,15 +235,17 @@ def test_em_row_stride(G_, oracle):
 
 
 # ---------------------------------------------------------------- loglik
-@pytest.mark.parametrize("N,D,G", [(10_000, 4, 4), (777, 33, 9), (1, 2, 1)])
-def test_loglik_diag(G_, oracle, N, D, G):
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
+@pytest.mark.parametrize("N,D,G", [(10_000, 4, 4), (777, 33, 9), (1, 2, 1), (3000, 100, 100),
+                                   (900, 150, 3)])
+def test_loglik_diag(G_, oracle, N, D, G, prec):
     X, _ = synth.diag_gmm(77 + N, D, max(G, 2), N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
     w, mu, var = _params(8, D, G, X if N >= G else None)
     ll = torch.zeros(1, dtype=torch.float64, device=DEV)
     ps = torch.zeros(N, device=DEV)
     st = torch.zeros(1, dtype=torch.int32, device=DEV)
     ws = G_.workspace(N, D, G, device=DEV)
-    G_.gmm_loglik(_t(X), 0, _t(w), _t(mu), _t(var), 0, ll, ps, st, ws)
+    G_.gmm_loglik(_t(X), 0, _t(w), _t(mu), _t(var), prec, ll, ps, st, ws)
     ref, rps = oracle.loglik(X, w, mu, var, per_sample=True)
     assert abs(ll.item() - ref) <= 1e-6 * abs(ref)
     np.testing.assert_allclose(ps.cpu().numpy(), rps, rtol=2e-6, atol=2e-5)
