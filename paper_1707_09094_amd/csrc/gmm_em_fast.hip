@@ -4,7 +4,8 @@
 // gmm_em.hip.
 //
 // Workgroup of 8 waves, persistent over a contiguous range of samples, tiles of
-// T = 32 samples.  Per tile:
+// T = 32 samples; the next tile is loaded into registers (all loads issued at
+// once) while the current one is processed.  Per tile:
 //   1. the tile's samples are staged in LDS (xf[n][d]);
 //   2. screening: FP32 log-densities a_gn of every (component, sample) pair,
 //      either
@@ -26,7 +27,8 @@
 //      (Eq. 3); responsibilities below exp(-80) are 0;
 //   5. the map step of Sec. 2.1 (Eqs. 9-11) in a weighted Welford form (West's
 //      update) on the deviations y = x - mu_old from the current mean: wave w
-//      owns components g = w, w+8, ...; lane owns dimensions d = lane, lane+64;
+//      owns components g = w, w+8, ...; lane owns dimensions d = lane, lane+64
+//      (the old means sit in LDS for the FP32 form, in registers for BF16X3);
 //      for every sample with a non-zero responsibility r, in sample order,
 //        L' = L + r, delta = y - m, m += delta r / L', Q += delta^2 r L / L'
 //      (the first sample sets m = y exactly).  m is the block's weighted mean of
@@ -44,6 +46,7 @@ namespace {
 constexpr int kNW = 8;            // waves per workgroup
 constexpr int kThreads = kNW * kWave;
 constexpr int kT = 32;            // samples per tile
+constexpr int kPF = 8;            // prefetch registers per thread: kT * 128 / kThreads
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
@@ -75,11 +78,12 @@ struct FastArgs {
 struct Lds {
   float* ps;        // [G][D+1]   (FP32 form)
   float* pm;        // [G][D+1]   (FP32 form)
-  float* xf;        // [T][D+1]
+  float* xf;        // [T][D]
   float* as;        // [G][T]
   bf16x8* bhi;      // [KS][2][64] (BF16X3 form)
   bf16x8* blo;
   float* acc;       // [G][2D+1]  (BF16X3 form)
+  float* mu;        // [G][D]     (FP32 form) current means
   float* pmax;      // [NW][T]
   double* psum;     // [NW][T]
   uint32_t* nbits;  // [T][4]
@@ -99,7 +103,7 @@ __host__ __device__ inline size_t lds_walk(int D, int G, int KS, int form, F&& a
   const bool bf = form == GMM_PREC_BF16X3;
   put(0, bf ? 0 : (size_t)G * (D + 1), 1);
   put(1, bf ? 0 : (size_t)G * (D + 1), 1);
-  put(2, (size_t)kT * (D + 1), 1);
+  put(2, (size_t)kT * D, 4);
   put(3, (size_t)G * kT, 1);
   put(4, bf ? (size_t)KS * 2 * 64 * 4 : 0, 4);
   put(5, bf ? (size_t)KS * 2 * 64 * 4 : 0, 4);
@@ -110,6 +114,7 @@ __host__ __device__ inline size_t lds_walk(int D, int G, int KS, int form, F&& a
   put(10, kT, 1);
   put(11, 1, 1);
   put(12, ((size_t)kT * G + 1) / 2, 1);
+  put(13, bf ? 0 : (size_t)G * D, 1);
   return w;
 }
 
@@ -134,7 +139,8 @@ __device__ inline Lds carve_lds(char* base, int D, int G, int KS, int form) {
       case 9: L.nbits = (uint32_t*)(f + off); break;
       case 10: L.ncnt = (int*)(f + off); break;
       case 11: L.pcount = (int*)(f + off); break;
-      default: L.plist = (uint16_t*)(f + off); break;
+      case 12: L.plist = (uint16_t*)(f + off); break;
+      default: L.mu = f + off; break;
     }
   });
   return L;
@@ -154,6 +160,33 @@ __device__ __forceinline__ double group8_sum_d(double v) {
   return v;
 }
 
+// Global -> register load of one tile: element p = tid + 512 i of the tile's
+// nt x D block (row-major); every load of the tile is issued before any use.
+__device__ __forceinline__ void tile_prefetch(const FastArgs& a, int64_t t0, int nt, int tid,
+                                              float (&pf)[kPF]) {
+  const int D = a.D;
+  const int tot = nt * D;
+  if (a.ldx == D) {
+    const float* src = a.X + t0 * D;
+#pragma unroll
+    for (int i = 0; i < kPF; ++i) {
+      const int p = tid + kThreads * i;
+      pf[i] = p < tot ? src[p] : 0.0f;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kPF; ++i) {
+      const int p = tid + kThreads * i;
+      float v = 0.0f;
+      if (p < tot) {
+        const int n = p / D, d = p - n * D;
+        v = a.X[(t0 + n) * a.ldx + d];
+      }
+      pf[i] = v;
+    }
+  }
+}
+
 template <int FORM, int CPW, int DPL, bool MSTEP>
 __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds_raw[];
@@ -169,11 +202,13 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
 
   constexpr bool ACCLDS = FORM == GMM_PREC_BF16X3;
   const int P = 2 * D + 1;
-  if (!ACCLDS) {  // stage the direct-form parameters (ps and pm are adjacent)
+  if (!ACCLDS) {  // stage the direct-form parameters and the current means
     for (int p = tid; p < G * DP; p += kThreads) {
       L.ps[p] = a.prm[p];
       L.pm[p] = a.prm[(size_t)G * DP + p];
     }
+    if (MSTEP)
+      for (int p = tid; p < G * D; p += kThreads) L.mu[p] = a.means[p];
   } else if (MSTEP) {
     for (int p = tid; p < G * P; p += kThreads) L.acc[p] = 0.0f;
   }
@@ -191,10 +226,14 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
       }
   }
 
-  // moment accumulators: component g = w + 8c, dimension d = lane + 64j
-  float S1[CPW][DPL], S2[CPW][DPL], Lc[CPW];
+  // Welford accumulators (FP32 form) of component g = w + 8c, dimension
+  // d = lane + 64j; the BF16X3 form keeps them in LDS and only the current
+  // means of its components in registers
+  constexpr int CA = ACCLDS ? 1 : CPW;
+  constexpr int CM = ACCLDS ? CPW : 1;
+  float S1[CA][DPL], S2[CA][DPL], Lc[CA], mur[CM][DPL];
 #pragma unroll
-  for (int c = 0; c < CPW; ++c) {
+  for (int c = 0; c < CA; ++c) {
     Lc[c] = 0.0f;
 #pragma unroll
     for (int j = 0; j < DPL; ++j) {
@@ -202,17 +241,32 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
       S2[c][j] = 0.0f;
     }
   }
+#pragma unroll
+  for (int c = 0; c < CM; ++c) {
+    const int g = w + kNW * c;
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+      const int d = lane + kWave * j;
+      mur[c][j] = (ACCLDS && MSTEP && g < G && d < D) ? a.means[(size_t)g * D + d] : 0.0f;
+    }
+  }
   double llacc = 0.0;  // lanes < kT of wave 0: samples n = lane of every tile
   int bad = 0;
   long long nrec = 0;
 
+  float pf[kPF];
+  if (i0 < i1) tile_prefetch(a, i0, (int)min((int64_t)kT, i1 - i0), tid, pf);
+
   for (int64_t t0 = i0; t0 < i1; t0 += kT) {
     const int nt = (int)min((int64_t)kT, i1 - t0);
-    // 1. stage samples (zeros past the tail)
-    for (int p = tid; p < kT * D; p += kThreads) {
-      const int n = p / D, d = p - n * D;
-      L.xf[n * DP + d] = n < nt ? a.X[(t0 + n) * a.ldx + d] : 0.0f;
+    // 1. samples loaded last iteration -> LDS (zeros past the tail); the next
+    // tile's loads are issued right after
+#pragma unroll
+    for (int i = 0; i < kPF; ++i) {
+      const int p = tid + kThreads * i;
+      if (p < kT * D) L.xf[p] = pf[i];
     }
+    if (t0 + kT < i1) tile_prefetch(a, t0 + kT, (int)min((int64_t)kT, i1 - t0 - kT), tid, pf);
     if (tid < kT) {
       L.ncnt[tid] = 0;
       L.nbits[tid * 4 + 0] = L.nbits[tid * 4 + 1] = L.nbits[tid * 4 + 2] = L.nbits[tid * 4 + 3] = 0u;
@@ -233,9 +287,9 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
           const int k = 32 * ks + 8 * (l >> 4) + i;
           float v = 0.0f;
           if (k < D) {
-            v = L.xf[n * DP + k];
+            v = L.xf[n * D + k];
           } else if (k < 2 * D) {
-            const float x = L.xf[n * DP + k - D];
+            const float x = L.xf[n * D + k - D];
             v = x * x;
           }
           const __bf16 h = (__bf16)v;
@@ -282,7 +336,7 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
           const float s = sg[d], m = mg[d];
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
-            const float u = fmaf(L.xf[(n0 + q) * DP + d], s, -m);
+            const float u = fmaf(L.xf[(n0 + q) * D + d], s, -m);
             acc[q] = fmaf(u, u, acc[q]);
           }
         }
@@ -325,7 +379,7 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
       for (int p = grp; p < np; p += kThreads / 8) {
         const int code = L.plist[p];
         const int pn = code >> 8, g = code & 255;
-        const float* x = L.xf + pn * DP;
+        const float* x = L.xf + pn * D;
         float Mp = -INFINITY;
 #pragma unroll
         for (int q = 0; q < kNW; ++q) Mp = fmaxf(Mp, L.pmax[q * kT + pn]);
@@ -344,9 +398,13 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
           const float* sg = a.prm + (size_t)g * DP;
           const float* mg = a.prm + (size_t)G * DP + (size_t)g * DP;
           float q = 0.0f;
-          for (int d = gl; d < D; d += 8) {
-            const float u = fmaf(x[d], sg[d], -mg[d]);
-            q = fmaf(u, u, q);
+#pragma unroll 8
+          for (int i = 0; i < 16; ++i) {
+            const int d = gl + 8 * i;
+            if (d < D) {
+              const float u = fmaf(x[d], sg[d], -mg[d]);
+              q = fmaf(u, u, q);
+            }
           }
           q = group8_sum(q);
           if (gl == 0) {
@@ -393,16 +451,13 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
       }
       // 5. moments of this wave's components (written above by this wave only)
       if (ACCLDS) {
-        for (int g = w; g < G; g += kNW) {
+#pragma unroll
+        for (int c = 0; c < CM; ++c) {
+          const int g = w + kNW * c;
+          if (g >= G) continue;
           const float r_l = lane < kT ? L.as[g * kT + lane] : 0.0f;
           unsigned long long msk = __ballot(r_l != 0.0f);
           if (!msk) continue;
-          float mu[2];
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            const int d = lane + kWave * j;
-            mu[j] = d < D ? a.means[(size_t)g * D + d] : 0.0f;
-          }
           float* ag = L.acc + (size_t)g * P;
           float Lg = ag[0];
           while (msk) {
@@ -415,10 +470,10 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
             const float w2 = inv * Lo;
             Lg = Ln;
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
+            for (int j = 0; j < DPL; ++j) {
               const int d = lane + kWave * j;
               if (d < D) {
-                const float y = L.xf[nn * DP + d] - mu[j];
+                const float y = L.xf[nn * D + d] - mur[c][j];
                 if (Lo == 0.0f) {
                   ag[1 + d] = y;
                 } else {
@@ -434,17 +489,11 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
         }
       } else
 #pragma unroll
-      for (int c = 0; c < CPW; ++c) {
+      for (int c = 0; c < CA; ++c) {
         const int g = w + kNW * c;
         if (g < G) {
           const float r_l = lane < kT ? L.as[g * kT + lane] : 0.0f;
           unsigned long long msk = __ballot(r_l != 0.0f);
-          float mu[DPL];
-#pragma unroll
-          for (int j = 0; j < DPL; ++j) {
-            const int d = lane + kWave * j;
-            mu[j] = (msk && d < D) ? a.means[(size_t)g * D + d] : 0.0f;
-          }
           while (msk) {
             const int nn = __ffsll((long long)msk) - 1;
             msk &= msk - 1;
@@ -458,7 +507,7 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
             for (int j = 0; j < DPL; ++j) {
               const int d = lane + kWave * j;
               if (d < D) {
-                const float y = L.xf[nn * DP + d] - mu[j];
+                const float y = L.xf[nn * D + d] - L.mu[g * D + d];
                 if (Lo == 0.0f) {
                   S1[c][j] = y;
                 } else {
@@ -483,7 +532,7 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
   } else if (MSTEP) {
     double* pb = a.part + (size_t)b * G * P;
 #pragma unroll
-    for (int c = 0; c < CPW; ++c) {
+    for (int c = 0; c < CA; ++c) {
       const int g = w + kNW * c;
       if (g < G) {
         if (lane == 0) pb[(size_t)g * P] = (double)Lc[c];
@@ -672,9 +721,7 @@ void launch_one(const FastArgs& a, int nb, size_t lds, hipStream_t st) {
 
 template <int FORM, bool MSTEP>
 void dispatch_cpw(const FastArgs& a, int nb, size_t lds, hipStream_t st) {
-  if constexpr (FORM == GMM_PREC_BF16X3) {
-    launch_one<FORM, 1, 1, MSTEP>(a, nb, lds, st);
-  } else {
+  {
   const int cpw = (a.G + kNW - 1) / kNW;
   const int dpl = (a.D + kWave - 1) / kWave;
   if (dpl == 1) {
