@@ -210,6 +210,13 @@ hipError_t launch_loglik_full(const float* X, int64_t N, int D, int64_t ldx, int
                               double* mean_loglik, float* per_sample, int32_t* dev_status,
                               const Workspace& w, hipStream_t st);
 
+bool km_fast_supported(int D, int G);
+hipError_t launch_kmeans_fast(const float* X, int64_t N, int D, int64_t ldx, int G, int dist,
+                              const double* gvar, float var_floor, float* means, float* dcovs,
+                              float* hefts, int64_t* counts, int32_t* assign, double* inertia,
+                              int64_t* n_recomputed, int32_t* dev_status, const Workspace& w,
+                              hipStream_t st);
+
 hipError_t launch_kmeans(const float* X, int64_t N, int D, int64_t ldx, int G, int dist,
                          const double* gvar, float var_floor, float* means, float* dcovs,
                          float* hefts, int64_t* counts, int32_t* assign, double* inertia,

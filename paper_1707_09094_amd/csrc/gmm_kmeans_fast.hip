@@ -1,0 +1,516 @@
+// gmm_kmeans_fast.hip -- one-pass k-means iteration for D <= 128 dimensions
+// and G <= 128 means (larger shapes use the generic kernels of
+// gmm_kmeans.hip).
+//
+// Workgroup of 8 waves, persistent over a contiguous sample range, tiles of 32
+// samples (next tile prefetched into registers).  Per tile:
+//   1. distances (Sec. 3 Eq. 19 with the Eq. 20 weights) in FP32:
+//        d_gn = sum_d u^2,  u = fma(x_d, s_d, -m_gd),  s_d = sqrt(lam_d),
+//        m_gd = mu_gd s_d
+//      thread per (mean, 8 samples);
+//   2. per sample the best and second-best distance (lowest index on ties).
+//      With e = 2^-24, every FP32 distance is within
+//        bound(d) = 2 e ((D + 6) d + 2 sqrt(d) max_g |m_g|)
+//      of sum_d s_d^2 (x_d - mu_gd)^2, so when d2 - d1 <= bound(d1) +
+//      bound(d2) the sample is re-decided in FP64 over all means (first
+//      minimum wins); the counted samples are reported as n_recomputed;
+//   3. FP64 distance of each sample to its chosen mean (inertia), 8 lanes per
+//      sample;
+//   4. map step of Sec. 2.1 with l in {0,1}: wave w owns means g = w, w+8, ...;
+//      for its samples, in sample order, the weighted-Welford update (West) of
+//      (count, mean of y, sum of squared deviations) with y = x - mu_old.
+#include "gmm_internal.hpp"
+
+namespace gmm {
+
+namespace {
+
+constexpr int kNW = 8;
+constexpr int kThreads = kNW * kWave;
+constexpr int kT = 32;
+constexpr int kPF = 8;
+constexpr float kE32 = 5.9604645e-08f;
+
+struct KmArgs {
+  const float* X;
+  int64_t N;
+  int64_t ldx;
+  int64_t chunk;
+  int D, G;
+  const float* means;   // [G][D]
+  const float* mprm;    // [G][D+1]: m_gd = mu_gd s_d
+  const float* sd;      // [D]: s_d
+  const double* lam64;  // [D]
+  const float* mnorm;   // [1]: max_g |m_g|
+  int32_t* assign;      // [N]
+  double* part;         // [nb][G][2D+1]
+  double* in_part;      // [nb]
+  int64_t* n_rec;
+  int32_t* dev_status;
+};
+
+template <typename F>
+__host__ __device__ inline size_t km_lds_walk(int D, int G, F&& at) {
+  size_t w = 0;
+  auto put = [&](int which, size_t words, size_t align_words) {
+    w = (w + align_words - 1) / align_words * align_words;
+    at(which, w);
+    w += words;
+  };
+  put(0, (size_t)G * D, 1);        // mu
+  put(1, (size_t)G * (D + 1), 1);  // m
+  put(2, D, 1);                    // s
+  put(3, 2 * (size_t)D, 2);        // lam64
+  put(4, (size_t)kT * D, 4);       // xf
+  put(5, (size_t)G * kT, 1);       // dist
+  put(6, kNW * kT, 1);             // pbest
+  put(7, kNW * kT, 1);             // psec
+  put(8, kNW * kT, 1);             // parg
+  put(9, kT, 1);                   // arg
+  put(10, 2 * kT, 2);              // dist64 of the chosen mean
+  return w;
+}
+
+__host__ __device__ inline size_t km_lds_bytes(int D, int G) {
+  return km_lds_walk(D, G, [](int, size_t) {}) * 4 + 64;
+}
+
+template <int CPW, int DPL>
+__global__ void __launch_bounds__(kThreads) k_km_fast(KmArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const int D = a.D, G = a.G;
+  const int DP = D + 1;
+  float *mu, *mm, *sv, *xf, *dist, *pbest, *psec;
+  double *l64, *d64;
+  int *parg, *arg;
+  {
+    float* f = (float*)lds_raw;
+    km_lds_walk(D, G, [&](int which, size_t off) {
+      switch (which) {
+        case 0: mu = f + off; break;
+        case 1: mm = f + off; break;
+        case 2: sv = f + off; break;
+        case 3: l64 = (double*)(f + off); break;
+        case 4: xf = f + off; break;
+        case 5: dist = f + off; break;
+        case 6: pbest = f + off; break;
+        case 7: psec = f + off; break;
+        case 8: parg = (int*)(f + off); break;
+        case 9: arg = (int*)(f + off); break;
+        default: d64 = (double*)(f + off); break;
+      }
+    });
+  }
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int w = tid / kWave;
+  const int b = blockIdx.x;
+  const int64_t i0 = (int64_t)b * a.chunk;
+  const int64_t i1 = min(a.N, i0 + a.chunk);
+  const int P = 2 * D + 1;
+
+  for (int p = tid; p < G * D; p += kThreads) mu[p] = a.means[p];
+  for (int p = tid; p < G * DP; p += kThreads) mm[p] = a.mprm[p];
+  for (int p = tid; p < D; p += kThreads) {
+    sv[p] = a.sd[p];
+    l64[p] = a.lam64[p];
+  }
+  const float mnorm = *a.mnorm;
+
+  float Lc[CPW], S1[CPW][DPL], S2[CPW][DPL];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    Lc[c] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) S1[c][j] = S2[c][j] = 0.0f;
+  }
+  double inacc = 0.0;  // wave 0, lane n < kT: sample n of every tile
+  int bad = 0;
+  long long nrec = 0;
+
+  float pf[kPF];
+  auto prefetch = [&](int64_t t0, int nt) {
+    const int tot = nt * D;
+    if (a.ldx == D) {
+      const float* src = a.X + t0 * D;
+#pragma unroll
+      for (int i = 0; i < kPF; ++i) {
+        const int p = tid + kThreads * i;
+        pf[i] = p < tot ? src[p] : 0.0f;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kPF; ++i) {
+        const int p = tid + kThreads * i;
+        float v = 0.0f;
+        if (p < tot) {
+          const int n = p / D, d = p - n * D;
+          v = a.X[(t0 + n) * a.ldx + d];
+        }
+        pf[i] = v;
+      }
+    }
+  };
+  if (i0 < i1) prefetch(i0, (int)min((int64_t)kT, i1 - i0));
+  __syncthreads();
+
+  for (int64_t t0 = i0; t0 < i1; t0 += kT) {
+    const int nt = (int)min((int64_t)kT, i1 - t0);
+#pragma unroll
+    for (int i = 0; i < kPF; ++i) {
+      const int p = tid + kThreads * i;
+      if (p < kT * D) xf[p] = pf[i];
+    }
+    if (t0 + kT < i1) prefetch(t0 + kT, (int)min((int64_t)kT, i1 - t0 - kT));
+    __syncthreads();
+
+    // 1. distances: thread owns mean g = lane + 64 (w & 1), samples 8 (w >> 1) + q
+    {
+      const int g = lane + kWave * (w & 1);
+      const int n0 = 8 * (w >> 1);
+      if (g < G) {
+        float acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
+        const float* mg = mm + g * DP;
+        for (int d = 0; d < D; ++d) {
+          const float s = sv[d], m = mg[d];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const float u = fmaf(xf[(n0 + q) * D + d], s, -m);
+            acc[q] = fmaf(u, u, acc[q]);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) dist[g * kT + n0 + q] = acc[q];
+      }
+    }
+    __syncthreads();
+
+    // 2. best / second best; lanes 0..31 = samples, lanes 32..63 repeat them
+    const int n = lane & (kT - 1);
+    {
+      float b1 = INFINITY, b2 = INFINITY;
+      int ag = G;  // "none" sorts after every real index
+      for (int g = w; g < G; g += kNW) {
+        const float v = dist[g * kT + n];
+        if (v < b1) {
+          b2 = b1;
+          b1 = v;
+          ag = g;
+        } else if (v < b2) {
+          b2 = v;
+        }
+      }
+      if (lane < kT) {
+        pbest[w * kT + n] = b1;
+        psec[w * kT + n] = b2;
+        parg[w * kT + n] = ag;
+      }
+    }
+    __syncthreads();
+    if (w == 0 && lane < kT) {
+      float d1 = INFINITY, d2 = INFINITY;
+      int ag = G;
+#pragma unroll
+      for (int q = 0; q < kNW; ++q) {
+        const float v = pbest[q * kT + n];
+        const int gq = parg[q * kT + n];
+        if (v < d1 || (v == d1 && gq < ag)) {
+          d2 = fminf(d2, d1);
+          d1 = v;
+          ag = gq;
+        } else {
+          d2 = fminf(d2, v);
+        }
+        d2 = fminf(d2, psec[q * kT + n]);
+      }
+      if (n < nt) {
+        const float bnd1 = 2.0f * kE32 * ((float)(D + 6) * d1 + 2.0f * sqrtf(d1) * mnorm);
+        const float bnd2 = 2.0f * kE32 * ((float)(D + 6) * d2 + 2.0f * sqrtf(d2) * mnorm);
+        if (G > 1 && !(d2 - d1 > 2.0f * (bnd1 + bnd2))) {
+          // near tie or non-finite value: decide in FP64, first minimum wins
+          ++nrec;
+          const float* x = xf + n * D;
+          double best = INFINITY;
+          ag = 0;
+          for (int g = 0; g < G; ++g) {
+            double s = 0.0;
+            for (int d = 0; d < D; ++d) {
+              const double t = (double)x[d] - (double)mu[g * D + d];
+              s += l64[d] * t * t;
+            }
+            if (s < best) {
+              best = s;
+              ag = g;
+            }
+          }
+          if (!(best < INFINITY)) {
+            bad = 1;
+            ag = 0;
+          }
+        }
+        a.assign[t0 + n] = ag;
+      } else {
+        ag = -1;
+      }
+      arg[n] = ag;
+    }
+    __syncthreads();
+
+    // 3. FP64 distance to the chosen mean: 8 lanes per sample (waves 0..3)
+    if (tid < kT * 8) {
+      const int s = tid >> 3, gl = tid & 7;
+      const int g = arg[s];
+      double q = 0.0;
+      if (g >= 0) {
+        const float* x = xf + s * D;
+        const float* m = mu + g * D;
+        for (int d = gl; d < D; d += 8) {
+          const double t = (double)x[d] - (double)m[d];
+          q += l64[d] * t * t;
+        }
+      }
+      q += __shfl_xor(q, 1, kWave);
+      q += __shfl_xor(q, 2, kWave);
+      q += __shfl_xor(q, 4, kWave);
+      if (gl == 0) d64[s] = q;
+    }
+    __syncthreads();
+    if (w == 0 && lane < nt) {
+      inacc += d64[lane];
+      if (!isfinite(d64[lane])) bad = 1;
+    }
+
+    // 4. map step, one-hot responsibilities
+    {
+      const int an = lane < kT ? arg[lane] : -1;
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int g = w + kNW * c;
+        if (g < G) {
+          unsigned long long msk = __ballot(an == g);
+          while (msk) {
+            const int nn = __ffsll((long long)msk) - 1;
+            msk &= msk - 1;
+            const float Lo = Lc[c];
+            const float Ln = Lo + 1.0f;
+            const float inv = 1.0f / Ln;
+            const float w2 = Lo * inv;
+            Lc[c] = Ln;
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) {
+              const int d = lane + kWave * j;
+              if (d < D) {
+                const float y = xf[nn * D + d] - mu[g * D + d];
+                if (Lo == 0.0f) {
+                  S1[c][j] = y;
+                } else {
+                  const float dy = y - S1[c][j];
+                  S1[c][j] = fmaf(inv, dy, S1[c][j]);
+                  S2[c][j] = fmaf(w2 * dy, dy, S2[c][j]);
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  double* pb = a.part + (size_t)b * G * P;
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int g = w + kNW * c;
+    if (g < G) {
+      if (lane == 0) pb[(size_t)g * P] = (double)Lc[c];
+#pragma unroll
+      for (int j = 0; j < DPL; ++j) {
+        const int d = lane + kWave * j;
+        if (d < D) {
+          pb[(size_t)g * P + 1 + d] = (double)S1[c][j];
+          pb[(size_t)g * P + 1 + D + d] = (double)S2[c][j];
+        }
+      }
+    }
+  }
+  if (w == 0) {
+    const double v = wave_sum_d(lane < kT ? inacc : 0.0);
+    if (lane == 0) a.in_part[b] = v;
+  }
+  if (bad) atomicOr(a.dev_status, GMM_DEV_NONFINITE);
+  if (w == 0) {
+    long long v = nrec;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    if (lane == 0 && v) atomicAdd((unsigned long long*)a.n_rec, (unsigned long long)v);
+  }
+}
+
+// lam_d, s_d = sqrt(lam_d), m_gd = mu_gd s_d and max_g |m_g| (one workgroup).
+__global__ void __launch_bounds__(256) k_km_pre_fast(const double* __restrict__ gvar, int D,
+                                                     int G, float var_floor, int dist,
+                                                     const float* __restrict__ means,
+                                                     double* __restrict__ lam64,
+                                                     float* __restrict__ sd,
+                                                     float* __restrict__ mprm,
+                                                     float* __restrict__ mnorm) {
+  __shared__ float red[256];
+  for (int d = threadIdx.x; d < D; d += 256) {
+    double l = 1.0;
+    if (dist == GMM_DIST_MAHA) {
+      double v = gvar[d];
+      v = v > (double)var_floor ? v : (double)var_floor;
+      l = 1.0 / v;
+    }
+    lam64[d] = l;
+    sd[d] = (float)sqrt(l);
+  }
+  __syncthreads();
+  float mx = 0.0f;
+  for (int g = threadIdx.x; g < G; g += 256) {
+    double q = 0.0;
+    for (int d = 0; d < D; ++d) {
+      const float m = (float)((double)means[(size_t)g * D + d] * (double)sd[d]);
+      mprm[(size_t)g * (D + 1) + d] = m;
+      q += (double)m * (double)m;
+    }
+    mprm[(size_t)g * (D + 1) + D] = 0.0f;
+    mx = fmaxf(mx, (float)sqrt(q) * 1.0000002f);
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *mnorm = red[0];
+}
+
+// Reduce step of the k-means map: pairwise (count, mean, M2) combination in
+// block order, new means, hand-off variances/weights, counts, inertia.
+__global__ void __launch_bounds__(256) k_km_fin_fast(const double* __restrict__ part, int nb,
+                                                     int64_t N, int D, int G, float var_floor,
+                                                     float* __restrict__ means,
+                                                     float* __restrict__ dcovs,
+                                                     float* __restrict__ hefts,
+                                                     int64_t* __restrict__ counts,
+                                                     const double* __restrict__ in_part,
+                                                     double* __restrict__ inertia,
+                                                     int32_t* __restrict__ dev_status) {
+  const int g = blockIdx.x;
+  const int P = 2 * D + 1;
+  double Ltot = 0.0;
+  for (int b = 0; b < nb; ++b) Ltot += part[((size_t)b * G + g) * P];
+  for (int d = threadIdx.x; d < D; d += 256) {
+    double L = 0.0, m = 0.0, Q = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      const double* q = part + ((size_t)b * G + g) * P;
+      const double Lb = q[0];
+      if (Lb == 0.0) continue;
+      const double mb = q[1 + d], Qb = q[1 + D + d];
+      if (L == 0.0) {
+        L = Lb;
+        m = mb;
+        Q = Qb;
+      } else {
+        const double Ln = L + Lb;
+        const double dl = mb - m;
+        m += dl * (Lb / Ln);
+        Q += Qb + dl * dl * (L * Lb / Ln);
+        L = Ln;
+      }
+    }
+    if (L > 0.0) {
+      double v = Q / L;
+      v = v > 0.0 ? v : 0.0;
+      v = v > (double)var_floor ? v : (double)var_floor;
+      means[(size_t)g * D + d] = (float)((double)means[(size_t)g * D + d] + m);
+      dcovs[(size_t)g * D + d] = (float)v;
+    } else {
+      dcovs[(size_t)g * D + d] = 1.0f;
+    }
+  }
+  if (threadIdx.x == 0) {
+    counts[g] = (int64_t)Ltot;
+    hefts[g] = (float)(Ltot / (double)N);
+  }
+  if (g == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += in_part[b];
+    *inertia = s;
+    if (!isfinite(s)) atomicOr(dev_status, GMM_DEV_NONFINITE);
+  }
+}
+
+template <int CPW, int DPL>
+void km_launch_one(const KmArgs& a, int nb, size_t lds, hipStream_t st) {
+  auto kern = k_km_fast<CPW, DPL>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), lds, st, a);
+}
+
+}  // namespace
+
+bool km_fast_supported(int D, int G) {
+  if (D < 1 || D > 128 || G < 1 || G > 128) return false;
+  return km_lds_bytes(D, G) <= 160 * 1024;
+}
+
+hipError_t launch_kmeans_fast(const float* X, int64_t N, int D, int64_t ldx, int G, int dist,
+                              const double* gvar, float var_floor, float* means, float* dcovs,
+                              float* hefts, int64_t* counts, int32_t* assign, double* inertia,
+                              int64_t* n_recomputed, int32_t* dev_status, const Workspace& w,
+                              hipStream_t st) {
+  int64_t nb64 = (N + 2 * kT - 1) / (2 * kT);
+  if (nb64 < 1) nb64 = 1;
+  if (nb64 > 256) nb64 = 256;
+  const int nb = (int)nb64;
+  KmArgs a;
+  a.X = X;
+  a.N = N;
+  a.ldx = ldx;
+  a.chunk = ((N + nb - 1) / nb + kT - 1) / kT * kT;
+  a.D = D;
+  a.G = G;
+  a.means = means;
+  a.mprm = w.prm;
+  a.sd = w.lam32;
+  a.lam64 = w.lam64;
+  a.mnorm = w.c;
+  a.assign = assign;
+  a.part = w.partials;
+  a.in_part = w.scalars;
+  a.n_rec = n_recomputed;
+  a.dev_status = dev_status;
+  hipLaunchKernelGGL(k_km_pre_fast, dim3(1), dim3(256), 0, st, gvar, D, G, var_floor, dist, means,
+                     w.lam64, w.lam32, w.prm, w.c);
+  const size_t lds = km_lds_bytes(D, G);
+  {
+    ProfScope ps(kProfKmAssign, st);
+    const int cpw = (G + kNW - 1) / kNW;
+    if (D <= 64) {
+      if (cpw <= 2) km_launch_one<2, 1>(a, nb, lds, st);
+      else if (cpw <= 4) km_launch_one<4, 1>(a, nb, lds, st);
+      else if (cpw <= 8) km_launch_one<8, 1>(a, nb, lds, st);
+      else if (cpw <= 13) km_launch_one<13, 1>(a, nb, lds, st);
+      else km_launch_one<16, 1>(a, nb, lds, st);
+    } else {
+      if (cpw <= 2) km_launch_one<2, 2>(a, nb, lds, st);
+      else if (cpw <= 4) km_launch_one<4, 2>(a, nb, lds, st);
+      else if (cpw <= 8) km_launch_one<8, 2>(a, nb, lds, st);
+      else if (cpw <= 13) km_launch_one<13, 2>(a, nb, lds, st);
+      else km_launch_one<16, 2>(a, nb, lds, st);
+    }
+  }
+  hipLaunchKernelGGL(k_km_fin_fast, dim3(G), dim3(256), 0, st, w.partials, nb, N, D, G, var_floor,
+                     means, dcovs, hefts, counts, w.scalars, inertia, dev_status);
+  return hipGetLastError();
+}
+
+}  // namespace gmm

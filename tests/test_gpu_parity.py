@@ -253,7 +253,9 @@ def test_loglik_diag(G_, oracle, N, D, G, prec):
 
 # ---------------------------------------------------------------- k-means
 @pytest.mark.parametrize("N,D,G,maha", [(10_000, 4, 4, True), (20_000, 100, 100, True),
-                                        (999, 3, 7, False), (1, 2, 1, False), (4, 2, 9, False)])
+                                        (999, 3, 7, False), (1, 2, 1, False), (4, 2, 9, False),
+                                        (3000, 40, 128, True), (2000, 150, 6, True),
+                                        (2500, 8, 160, False), (777, 1, 5, True)])
 def test_kmeans_step(G_, oracle, N, D, G, maha):
     X, _ = synth.diag_gmm(300 + N, D, max(G, 2), N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
     mu = synth.static_subset(X, G) if N >= G else np.concatenate(
