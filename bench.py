@@ -48,6 +48,23 @@ def em_flops(N, D, G):
     return 8.0 * N * G * D
 
 
+def measured_traffic(kernel_src, key_sha="source_sha16", key_f="fetch_bytes", key_w="write_bytes"):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_em_diag_D100_G100_N1e6.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, kernel_src), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if rec.get(key_sha) != sha:
+        return None
+    return rec[key_f] + rec[key_w]
+
+
 def cpu_baseline(X, hefts, means, dcovs):
     """One EM iteration of the FP64 oracle over the full data set on the host."""
     from oracle import oracle
@@ -130,7 +147,13 @@ def main():
     step_ms = [s.elapsed_time(e) for s, _, e in marks]
     em_phase_ms = [k.elapsed_time(e) for _, k, e in marks]
     if args.profile_only:
-        print(json.dumps({"profile_only": True, "ms_per_step": float(np.mean(step_ms))}))
+        # calibration for HBM byte counters: one plain device copy of 256 MiB
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_only": True, "ms_per_step": float(np.mean(step_ms)),
+                          "copy_bytes_each_way": src.numel() * 4}))
         return
 
     em_iter_s = EM_ITERS * len(em_phase_ms) / (sum(em_phase_ms) / 1e3)
@@ -173,9 +196,11 @@ def main():
     else:
         peak = FP32_VALU_PEAK_TF
         bound = "alu"
+    traffic = measured_traffic("paper_1707_09094_amd/csrc/gmm_em_fast.hip") if N == N_ else None
     roof = {"bound": bound, "achieved": round(achieved_tf, 3), "peak": round(peak, 2),
-            "unit": "TFLOP/s", "frac": round(achieved_tf / peak, 4), "traffic": None,
-            "kernel": "k_estep_diag (fused E-step + M-step map)",
+            "unit": "TFLOP/s", "frac": round(achieved_tf / peak, 4),
+            "traffic": None if traffic is None else round(traffic),
+            "kernel": "k_em_fast (fused E-step + M-step map)",
             "kernel_ms": round(em_kernel_ms, 4), "launches": em_launches}
 
     out = {
