@@ -15,6 +15,8 @@
  *                      log_p(X), avg_log_p(X))
  *   gmm_assign         closest Gaussian per sample and its histogram
  *                      (Sec. 4 API: assign, raw_hist)
+ *   gmm_*_batched      the same operations for many independent models per
+ *                      launch
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -65,6 +67,7 @@ extern "C" {
 #define GMM_DEV_OK 0
 #define GMM_DEV_NONFINITE 1
 #define GMM_DEV_NOTPD 2
+#define GMM_DEV_BADDESC 4   /* batched: descriptor disagrees with Ns/Gs; model skipped */
 
 /* covariance type (Sec. 4: diagonal covariances; full as in Eq. 2) */
 #define GMM_COV_DIAG 0
@@ -178,6 +181,70 @@ int gmm_assign(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int
                const float* hefts, const float* means, const float* dcovs, int32_t* assign,
                int64_t* hist, int32_t* dev_status, void* ws, size_t ws_bytes,
                gmm_stream_t stream);
+
+/* ---- many independent diagonal models in one launch sequence --------------
+ * The batch is described by an array of n_models descriptors in DEVICE
+ * memory.  All models share D (<= 128) and the arithmetic form; each has its
+ * own N >= 1 and 1 <= G <= 128.  The host arrays Ns[n_models] and
+ * Gs[n_models] must repeat the descriptors' N and G: the host uses them to
+ * size the launch and the workspace, the device uses the descriptors.
+ * Per model the arithmetic is that of the single-model call (gmm_em_iter /
+ * gmm_loglik / gmm_kmeans_iter with ldx = D); only the cut of the samples
+ * into partial sums differs, so k-means assignments and counts are identical
+ * and the floating-point results agree to rounding.  The calls below
+ * enqueue a fixed number of kernels whatever n_models is and copy nothing
+ * from the host, so a sequence of them can be captured into a graph.
+ * `chunk` is the number of samples per work item (a positive multiple of
+ * 32, typically from gmm_batched_autotune); every model's samples are cut
+ * into consecutive items and a persistent grid processes all items of all
+ * models in one launch. */
+typedef struct {
+  const float* X;       /* D x N column-major (ld = D) */
+  int64_t N;
+  int32_t G;
+  int32_t reserved;     /* 0 */
+  float* hefts;         /* [G] EM: in/out; k-means: out */
+  float* means;         /* [D*G] in/out */
+  float* covs;          /* [D*G] EM: diagonal covariances in/out; k-means: hand-off dcovs out */
+  int64_t* counts;      /* [G] k-means: out (required) */
+  int32_t* assign;      /* [N] k-means: out (required) */
+  double* loglik;       /* [1] EM / loglik: mean log-likelihood of the input parameters, or NULL */
+  double* inertia;      /* [1] k-means: inertia under the input means, or NULL */
+  const double* gvar;   /* [D] k-means with GMM_DIST_MAHA: global variances (required) */
+  int32_t* dev_status;  /* [1] out (required) */
+} gmm_model_desc;
+
+/* Workspace bytes for a batch (any of the batched calls, any chunk >= `chunk`). */
+size_t gmm_batched_workspace_bytes(int32_t n_models, const int64_t* Ns, const int32_t* Gs,
+                                   int32_t D, int32_t chunk);
+
+/* One EM iteration of every model (gmm_em_iter semantics, diagonal). */
+int gmm_em_iter_batched(const gmm_model_desc* models, int32_t n_models, const int64_t* Ns,
+                        const int32_t* Gs, int32_t D, float var_floor, int32_t prec,
+                        int32_t chunk, void* ws, size_t ws_bytes, gmm_stream_t stream);
+
+/* Mean log-likelihood of every model (gmm_loglik semantics, diagonal). */
+int gmm_loglik_batched(const gmm_model_desc* models, int32_t n_models, const int64_t* Ns,
+                       const int32_t* Gs, int32_t D, int32_t prec, int32_t chunk, void* ws,
+                       size_t ws_bytes, gmm_stream_t stream);
+
+/* One k-means iteration of every model (gmm_kmeans_iter semantics). */
+int gmm_kmeans_iter_batched(const gmm_model_desc* models, int32_t n_models, const int64_t* Ns,
+                            const int32_t* Gs, int32_t D, int32_t dist, float var_floor,
+                            int32_t chunk, void* ws, size_t ws_bytes, gmm_stream_t stream);
+
+/* Per-model global mean and population variance (gmm_global_stats of each
+ * model's X): mean_out and var_out are DEVICE arrays [n_models][D]. */
+int gmm_global_stats_batched(const gmm_model_desc* models, int32_t n_models, int32_t D,
+                             double* mean_out, double* var_out, gmm_stream_t stream);
+
+/* Chooses `chunk` for a batch: times gmm_loglik_batched (which leaves the
+ * models unchanged) for each candidate chunk in {1024, 2048, 4096, 8192,
+ * 16384} (those the workspace can hold) and writes the fastest to *best_chunk.
+ * Synchronises with the host; not for use under graph capture. */
+int gmm_batched_autotune(const gmm_model_desc* models, int32_t n_models, const int64_t* Ns,
+                         const int32_t* Gs, int32_t D, int32_t prec, void* ws, size_t ws_bytes,
+                         gmm_stream_t stream, int32_t* best_chunk);
 
 /* ---- instrumentation -----------------------------------------------------
  * When enabled, every launch of a data-pass kernel (one that reads all of X)

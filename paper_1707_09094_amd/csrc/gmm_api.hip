@@ -134,4 +134,148 @@ int gmm_assign(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int
                                  dev_status, w, (hipStream_t)stream));
 }
 
+// ---- many models -----------------------------------------------------------
+
+}  // extern "C"
+
+static_assert(sizeof(gmm_model_desc) == 96, "gmm_model_desc layout is part of the ABI");
+
+namespace {
+
+bool batch_shape_ok(const gmm_model_desc* models, int32_t n_models, const int64_t* Ns,
+                    const int32_t* Gs, int32_t D, int32_t chunk, int* Gmax) {
+  if (!models || !Ns || !Gs || n_models < 1 || D < 1 || D > kBatchMaxD) return false;
+  if (chunk < 32 || chunk % 32 != 0) return false;
+  int gm = 0;
+  for (int m = 0; m < n_models; ++m) {
+    if (Ns[m] < 1 || Ns[m] > ((int64_t)1 << 40) || Gs[m] < 1 || Gs[m] > kBatchMaxG) return false;
+    gm = Gs[m] > gm ? Gs[m] : gm;
+  }
+  *Gmax = gm;
+  return true;
+}
+
+bool batch_ws(void* ws, size_t ws_bytes, int32_t n_models, const int64_t* Ns, int D, int Gmax,
+              int32_t chunk, BatchWorkspace* bw, int* n_items) {
+  if (!ws || ((uintptr_t)ws) % 256 != 0) return false;
+  const int cap = batch_item_count(n_models, Ns, chunk);
+  if (cap < 1) return false;
+  *n_items = cap;
+  return carve_batched(ws, ws_bytes, n_models, D, Gmax, cap, bw);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gmm_batched_workspace_bytes(int32_t n_models, const int64_t* Ns, const int32_t* Gs,
+                                   int32_t D, int32_t chunk) {
+  int Gmax = 0;
+  if (!batch_shape_ok((const gmm_model_desc*)1, n_models, Ns, Gs, D, chunk, &Gmax)) return 0;
+  const int cap = batch_item_count(n_models, Ns, chunk);
+  if (cap < 1) return 0;
+  BatchWorkspace bw;
+  carve_batched(nullptr, 0, n_models, D, Gmax, cap, &bw);
+  return bw.bytes;
+}
+
+static int em_batched_common(const gmm_model_desc* models, int32_t n_models, const int64_t* Ns,
+                             const int32_t* Gs, int32_t D, float var_floor, int32_t prec,
+                             int32_t chunk, void* ws, size_t ws_bytes, gmm_stream_t stream,
+                             bool mstep) {
+  int Gmax = 0, n_items = 0;
+  if (!batch_shape_ok(models, n_models, Ns, Gs, D, chunk, &Gmax)) return GMM_EINVAL;
+  if (prec != GMM_PREC_FP32 && prec != GMM_PREC_BF16X3) return GMM_EINVAL;
+  if (!(var_floor >= 0.0f)) return GMM_EINVAL;
+  if (!em_fast_supported(D, Gmax, prec)) return GMM_EINVAL;
+  BatchWorkspace bw;
+  if (!batch_ws(ws, ws_bytes, n_models, Ns, D, Gmax, chunk, &bw, &n_items)) return GMM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_batch_plan(models, n_models, chunk, bw, st);
+  if (e == hipSuccess)
+    e = launch_em_batched(models, n_models, n_items, D, var_floor, prec, mstep, bw, st);
+  return status_of(e);
+}
+
+int gmm_em_iter_batched(const gmm_model_desc* models, int32_t n_models, const int64_t* Ns,
+                        const int32_t* Gs, int32_t D, float var_floor, int32_t prec,
+                        int32_t chunk, void* ws, size_t ws_bytes, gmm_stream_t stream) {
+  return em_batched_common(models, n_models, Ns, Gs, D, var_floor, prec, chunk, ws, ws_bytes,
+                           stream, true);
+}
+
+int gmm_loglik_batched(const gmm_model_desc* models, int32_t n_models, const int64_t* Ns,
+                       const int32_t* Gs, int32_t D, int32_t prec, int32_t chunk, void* ws,
+                       size_t ws_bytes, gmm_stream_t stream) {
+  return em_batched_common(models, n_models, Ns, Gs, D, 0.0f, prec, chunk, ws, ws_bytes, stream,
+                           false);
+}
+
+int gmm_kmeans_iter_batched(const gmm_model_desc* models, int32_t n_models, const int64_t* Ns,
+                            const int32_t* Gs, int32_t D, int32_t dist, float var_floor,
+                            int32_t chunk, void* ws, size_t ws_bytes, gmm_stream_t stream) {
+  int Gmax = 0, n_items = 0;
+  if (!batch_shape_ok(models, n_models, Ns, Gs, D, chunk, &Gmax)) return GMM_EINVAL;
+  if (dist != GMM_DIST_EUCL && dist != GMM_DIST_MAHA) return GMM_EINVAL;
+  if (!(var_floor >= 0.0f)) return GMM_EINVAL;
+  if (!km_fast_supported(D, Gmax)) return GMM_EINVAL;
+  BatchWorkspace bw;
+  if (!batch_ws(ws, ws_bytes, n_models, Ns, D, Gmax, chunk, &bw, &n_items)) return GMM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_batch_plan(models, n_models, chunk, bw, st);
+  if (e == hipSuccess)
+    e = launch_kmeans_batched(models, n_models, n_items, D, dist, var_floor, bw, st);
+  return status_of(e);
+}
+
+int gmm_global_stats_batched(const gmm_model_desc* models, int32_t n_models, int32_t D,
+                             double* mean_out, double* var_out, gmm_stream_t stream) {
+  if (!models || n_models < 1 || D < 1 || D > kBatchMaxD || !mean_out || !var_out)
+    return GMM_EINVAL;
+  return status_of(
+      launch_global_stats_batched(models, n_models, D, mean_out, var_out, (hipStream_t)stream));
+}
+
+int gmm_batched_autotune(const gmm_model_desc* models, int32_t n_models, const int64_t* Ns,
+                         const int32_t* Gs, int32_t D, int32_t prec, void* ws, size_t ws_bytes,
+                         gmm_stream_t stream, int32_t* best_chunk) {
+  if (!best_chunk) return GMM_EINVAL;
+  static const int32_t cand[] = {1024, 2048, 4096, 8192, 16384};
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return GMM_EHIP;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return GMM_EHIP;
+  }
+  float best = 0.0f;
+  int32_t pick = 0;
+  int rc = GMM_OK;
+  for (int32_t c : cand) {
+    if (ws_bytes < gmm_batched_workspace_bytes(n_models, Ns, Gs, D, c)) continue;
+    rc = gmm_loglik_batched(models, n_models, Ns, Gs, D, prec, c, ws, ws_bytes, stream);
+    if (rc != GMM_OK) break;
+    float ms = 0.0f;
+    if (hipEventRecord(a, st) != hipSuccess) { rc = GMM_EHIP; break; }
+    for (int r = 0; r < 2 && rc == GMM_OK; ++r)
+      rc = gmm_loglik_batched(models, n_models, Ns, Gs, D, prec, c, ws, ws_bytes, stream);
+    if (rc != GMM_OK) break;
+    if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+      rc = GMM_EHIP;
+      break;
+    }
+    if (pick == 0 || ms < best) {
+      best = ms;
+      pick = c;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc != GMM_OK) return rc;
+  if (pick == 0) return GMM_EINVAL;
+  *best_chunk = pick;
+  return GMM_OK;
+}
+
 }  // extern "C"

@@ -1,0 +1,75 @@
+// gmm_batched.hip -- shared pieces of the many-model entry points: the
+// on-device work list (a model's samples cut into consecutive items of
+// `chunk` samples, models in index order) and per-model status reset.
+// Building the list on the device keeps an iteration free of host copies,
+// so a sequence of batched calls can be captured into a graph.
+#include "gmm_internal.hpp"
+
+namespace gmm {
+
+namespace {
+
+// One workgroup.  mitems[m] = (first item, item count); items in model order.
+// A model whose descriptor is unusable gets no items; if the descriptors ask
+// for more items than the host sized (`cap`), no model gets any.
+__global__ void __launch_bounds__(1024) k_batch_plan(const gmm_model_desc* models, int n_models,
+                                                     int Gmax, int64_t chunk, int cap,
+                                                     BatchItemDev* items, int2* mitems,
+                                                     int* n_items) {
+  __shared__ int part_sum[1024];
+  __shared__ int overflow;
+  const int tid = threadIdx.x;
+  // per-thread contiguous block of models
+  const int per = (n_models + 1023) / 1024;
+  const int m0 = min(n_models, tid * per), m1 = min(n_models, m0 + per);
+  int64_t local = 0;
+  for (int m = m0; m < m1; ++m)
+    if (batch_desc_ok(models[m], Gmax)) local += (models[m].N + chunk - 1) / chunk;
+  part_sum[tid] = (int)min(local, (int64_t)cap + 1);
+  __syncthreads();
+  if (tid == 0) {
+    int64_t run = 0;
+    for (int t = 0; t < 1024; ++t) {
+      const int v = part_sum[t];
+      part_sum[t] = (int)min(run, (int64_t)cap);
+      run += v;
+    }
+    overflow = run > cap;
+    *n_items = run > cap ? 0 : (int)run;
+  }
+  __syncthreads();
+  int first = part_sum[tid];
+  for (int m = m0; m < m1; ++m) {
+    const gmm_model_desc& md = models[m];
+    const bool ok = batch_desc_ok(md, Gmax) && !overflow;
+    const int cnt = ok ? (int)((md.N + chunk - 1) / chunk) : 0;
+    mitems[m] = make_int2(first, cnt);
+    for (int k = 0; k < cnt; ++k) {
+      BatchItemDev it;
+      it.model = m;
+      it.first_of_model = first;
+      it.i0 = (int64_t)k * chunk;
+      it.i1 = min(md.N, (int64_t)(k + 1) * chunk);
+      items[first + k] = it;
+    }
+    if (md.dev_status) *md.dev_status = ok ? 0 : GMM_DEV_BADDESC;
+    first += cnt;
+  }
+}
+
+}  // namespace
+
+int batch_item_count(int32_t n_models, const int64_t* Ns, int64_t chunk) {
+  int64_t tot = 0;
+  for (int m = 0; m < n_models; ++m) tot += (Ns[m] + chunk - 1) / chunk;
+  return tot > INT32_MAX ? -1 : (int)tot;
+}
+
+hipError_t launch_batch_plan(const gmm_model_desc* models, int n_models, int64_t chunk,
+                             const BatchWorkspace& bw, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, st, models, n_models, bw.Gmax, chunk,
+                     bw.cap, bw.items, bw.mitems, bw.n_items);
+  return hipGetLastError();
+}
+
+}  // namespace gmm

@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(kNT) k_pre_diag(const float* __restrict__ heft
                                                   double* __restrict__ lam64_out) {
   __shared__ double sh[kNT];
   const int g = blockIdx.x;
-  double ld = 0.0;
+  double ld = 0.0, qm = 0.0;
   for (int d = threadIdx.x; d < D; d += kNT) {
     const double v = (double)covs[(size_t)g * D + d];
     const double mu = (double)means[(size_t)g * D + d];
@@ -53,9 +53,12 @@ __global__ void __launch_bounds__(kNT) k_pre_diag(const float* __restrict__ heft
     m_out[(size_t)d * G + g] = (float)(mu * s);
     lam64_out[(size_t)g * D + d] = lam;
     ld += log(v);
+    qm += lam * mu * mu;
   }
   const double logdet = block_sum_d<kNT>(ld, sh);
+  const double quad = block_sum_d<kNT>(qm, sh);
   if (threadIdx.x == 0) {
+    c_out[2 * G + g] = isfinite(quad) ? (float)(1.0001 * quad) : INFINITY;  // Q_g, error bounds
     const double c = log((double)hefts[g]) - 0.5 * ((double)D * kLog2Pi + logdet);
     const float hi = (float)c;
     c_out[g] = hi;  // -inf for a zero weight: that component gets l = 0
@@ -113,16 +116,18 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
       as[p] = (cc[g] - 0.5f * acc) + cc[G + g];
     }
     __syncthreads();
-    // One wave per sample: the FP32 values screen the components; the best
-    // one and every one within kNearGap nats of it are recomputed in FP64
-    // (a_g = c_g - 1/2 sum_d (x_d - mu_gd)^2 / sigma2_gd, Eq. 15), and the
-    // sample's log-sum-exp (Eqs. 16-18) is assembled in FP64 from those plus
-    // the FP32 values of the rest (each below exp(-30) of the best).
+    // One wave per sample: the FP32 values screen the components; every one
+    // that, widened by its rounding-error bound, could come within kNearGap
+    // nats of the best is recomputed in FP64 (a_g = c_g - 1/2 sum_d (x_d -
+    // mu_gd)^2 / sigma2_gd, Eq. 15), and the sample's log-sum-exp (Eqs. 16-18)
+    // is assembled in FP64 from those plus the FP32 values of the rest.  mx
+    // is max_g (a_g - err_g), a lower bound of the exact maximum.
     for (int t = wid; t < nt; t += nw) {
       float* a = as + (size_t)t * G;
       const float* x = xs + (size_t)t * D;
       float mx = -INFINITY;
-      for (int g = lane; g < G; g += kWave) mx = fmaxf(mx, a[g]);
+      for (int g = lane; g < G; g += kWave)
+        mx = fmaxf(mx, a[g] - err_direct(2.0f * (cc[g] - a[g]), cc[2 * G + g], cc[g], D));
       mx = wave_max(mx);
       const double M = (double)mx;
       // bit c of nearbits: component c*64 + lane is in the near set; its
@@ -130,7 +135,9 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
       unsigned long long nearbits = 0;
       for (int c = 0, g0 = 0; g0 < G; ++c, g0 += kWave) {
         const int g = g0 + lane;
-        const bool near = g < G && a[g] >= mx - kNearGap;
+        const bool near =
+            g < G &&
+            a[g] + err_direct(2.0f * (cc[g] - a[g]), cc[2 * G + g], cc[g], D) >= mx - kNearGap;
         if (near) nearbits |= 1ull << c;
         unsigned long long msk = __ballot(near);
         while (msk) {
@@ -146,22 +153,30 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
           if (lane == j) a[gg] = (float)(c64[gg] - 0.5 * q - M);
         }
       }
+      // reference: M + dn, dn the largest recomputed (a64 - M)
+      float dn = -INFINITY;
+      for (int c = 0, g0 = 0; g0 < G; ++c, g0 += kWave) {
+        const int g = g0 + lane;
+        if (g < G && ((nearbits >> c) & 1ull)) dn = fmaxf(dn, a[g]);
+      }
+      dn = wave_max(dn);
+      dn = dn > -INFINITY ? dn : 0.0f;
       double sm = 0.0;
       for (int c = 0, g0 = 0; g0 < G; ++c, g0 += kWave) {
         const int g = g0 + lane;
         if (g < G) {
-          const float v = ((nearbits >> c) & 1ull) ? a[g] : a[g] - mx;
+          const float v = ((nearbits >> c) & 1ull) ? a[g] - dn : (a[g] - mx) - dn;
           sm += (double)__expf(v);
         }
       }
       sm = wave_sum_d(sm);
-      const double l = M + log(sm);
+      const double l = (M + (double)dn) + log(sm);
       if (MSTEP) {
-        const float dl = (float)(l - M);
+        const float dl = (float)log(sm);
         for (int c = 0, g0 = 0; g0 < G; ++c, g0 += kWave) {
           const int g = g0 + lane;
           if (g < G) {
-            const float z = (((nearbits >> c) & 1ull) ? a[g] : a[g] - mx) - dl;
+            const float z = (((nearbits >> c) & 1ull) ? a[g] - dn : (a[g] - mx) - dn) - dl;
             a[g] = z >= -kRespCut ? __expf(z) : 0.0f;
           }
         }

@@ -90,6 +90,8 @@ struct Lds {
   int* ncnt;        // [T]
   int* pcount;      // [1]
   uint16_t* plist;  // [T*G]
+  float* cq;        // [2][G] c_g (hi) and Q_g = sum_d lam mu^2, for the error bounds
+  int* dmax;        // [T] max over the near set of (a - M_lo), order-mapped
 };
 
 template <typename F>
@@ -115,6 +117,8 @@ __host__ __device__ inline size_t lds_walk(int D, int G, int KS, int form, F&& a
   put(11, 1, 1);
   put(12, ((size_t)kT * G + 1) / 2, 1);
   put(13, bf ? 0 : (size_t)G * D, 1);
+  put(14, (size_t)2 * G, 1);
+  put(15, kT, 1);
   return w;
 }
 
@@ -140,7 +144,9 @@ __device__ inline Lds carve_lds(char* base, int D, int G, int KS, int form) {
       case 10: L.ncnt = (int*)(f + off); break;
       case 11: L.pcount = (int*)(f + off); break;
       case 12: L.plist = (uint16_t*)(f + off); break;
-      default: L.mu = f + off; break;
+      case 13: L.mu = f + off; break;
+      case 14: L.cq = f + off; break;
+      default: L.dmax = (int*)(f + off); break;
     }
   });
   return L;
@@ -187,21 +193,32 @@ __device__ __forceinline__ void tile_prefetch(const FastArgs& a, int64_t t0, int
   }
 }
 
+// The tile loop over samples [i0, i1) of one model; partials go to slot b.
 template <int FORM, int CPW, int DPL, bool MSTEP>
-__global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
-  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+__device__ __forceinline__ void em_range(const FastArgs& a, int64_t i0, int64_t i1, int b,
+                                         char* lds_raw) {
   const int D = a.D, G = a.G, KS = a.KS;
   const int DP = D + 1;
   const Lds L = carve_lds(lds_raw, D, G, KS, FORM);
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int w = tid / kWave;
-  const int b = blockIdx.x;
-  const int64_t i0 = (int64_t)b * a.chunk;
-  const int64_t i1 = min(a.N, i0 + a.chunk);
 
   constexpr bool ACCLDS = FORM == GMM_PREC_BF16X3;
   const int P = 2 * D + 1;
+  for (int g = tid; g < G; g += kThreads) {
+    const float c = a.cc[g];
+    const float Q = 2.0f * ((c + a.cc[G + g]) - (a.cexp[g] + a.cexp[G + g]));
+    L.cq[g] = c;
+    L.cq[G + g] = isfinite(Q) ? 1.0001f * fmaxf(Q, 0.0f) : 0.0f;
+  }
+  const float ecoef = err_expanded_coef(KS);
+  // rounding-error bound (nats) of a screening value v of component g
+  auto scr_err = [&](float v, int g) -> float {
+    const float c = L.cq[g], Q = L.cq[G + g];
+    const float q = 2.0f * (c - v);
+    return FORM == GMM_PREC_BF16X3 ? err_expanded(q, Q, c, ecoef) : err_direct(q, Q, c, D);
+  };
   if (!ACCLDS) {  // stage the direct-form parameters and the current means
     for (int p = tid; p < G * DP; p += kThreads) {
       L.ps[p] = a.prm[p];
@@ -269,6 +286,7 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
     if (t0 + kT < i1) tile_prefetch(a, t0 + kT, (int)min((int64_t)kT, i1 - t0 - kT), tid, pf);
     if (tid < kT) {
       L.ncnt[tid] = 0;
+      L.dmax[tid] = f2ord(-INFINITY);
       L.nbits[tid * 4 + 0] = L.nbits[tid * 4 + 1] = L.nbits[tid * 4 + 2] = L.nbits[tid * 4 + 3] = 0u;
     }
     if (tid == 0) *L.pcount = 0;
@@ -346,13 +364,17 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
     }
     __syncthreads();
 
-    // 3a. per-sample maximum: wave w scans components g = w + 8c; lane n = lane%32,
-    // half = lane/32 takes every other one
+    // 3a. per-sample M_lo = max_g (v_g - err_g), a lower bound of the exact
+    // maximum: wave w scans components g = w + 8c; lane n = lane%32, half =
+    // lane/32 takes every other one
     const int n = lane & (kT - 1);
     const int half = lane >> 5;
     {
       float mx = -INFINITY;
-      for (int g = w + kNW * half; g < G; g += 2 * kNW) mx = fmaxf(mx, L.as[g * kT + n]);
+      for (int g = w + kNW * half; g < G; g += 2 * kNW) {
+        const float v = L.as[g * kT + n];
+        mx = fmaxf(mx, v - scr_err(v, g));
+      }
       mx = fmaxf(mx, __shfl_xor(mx, 32, kWave));
       if (half == 0) L.pmax[w * kT + n] = mx;
     }
@@ -360,10 +382,11 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
     float M = -INFINITY;
 #pragma unroll
     for (int q = 0; q < kNW; ++q) M = fmaxf(M, L.pmax[q * kT + n]);
-    // 3b. near pairs
+    // 3b. near pairs: those whose value could come within kNearGap of the maximum
     if (n < nt) {
       for (int g = w + kNW * half; g < G; g += 2 * kNW) {
-        if (L.as[g * kT + n] >= M - kNearGap) {
+        const float v = L.as[g * kT + n];
+        if (v + scr_err(v, g) >= M - kNearGap) {
           const int slot = atomicAdd(L.pcount, 1);
           L.plist[slot] = (uint16_t)((n << 8) | g);
           atomicAdd(&L.ncnt[n], 1);
@@ -372,7 +395,10 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
       }
     }
     __syncthreads();
-    // 3c. recompute near pairs, one 8-lane group per pair
+    // 3c. recompute near pairs, one 8-lane group per pair: FP64 when the sample
+    // has two or more, else the FP32 direct form if its bound is below
+    // kExactTol (FP64 otherwise).  Entries then hold a - M_lo; dmax[n] gets
+    // their maximum.
     {
       const int np = *L.pcount;
       const int grp = tid >> 3, gl = tid & 7;
@@ -383,7 +409,33 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
         float Mp = -INFINITY;
 #pragma unroll
         for (int q = 0; q < kNW; ++q) Mp = fmaxf(Mp, L.pmax[q * kT + pn]);
-        if (L.ncnt[pn] >= 2) {
+        bool exact64 = L.ncnt[pn] >= 2;
+        double val = 0.0;
+        if (!exact64) {
+          float q32;
+          if (FORM == GMM_PREC_BF16X3) {
+            const float* sg = a.prm + (size_t)g * DP;
+            const float* mg = a.prm + (size_t)G * DP + (size_t)g * DP;
+            float q = 0.0f;
+#pragma unroll 8
+            for (int i = 0; i < 16; ++i) {
+              const int d = gl + 8 * i;
+              if (d < D) {
+                const float u = fmaf(x[d], sg[d], -mg[d]);
+                q = fmaf(u, u, q);
+              }
+            }
+            q32 = group8_sum(q);
+            val = ((double)a.cc[g] + (double)a.cc[G + g]) - 0.5 * (double)q32;
+          } else {
+            // the screening value is already the direct form
+            const float v = L.as[g * kT + pn];
+            q32 = 2.0f * (L.cq[g] - v);
+            val = (double)v;
+          }
+          exact64 = !(err_direct(q32, L.cq[G + g], L.cq[g], D) <= kExactTol);
+        }
+        if (exact64) {
           const float* mu_g = a.means + (size_t)g * D;
           const double* lg = a.lam64 + (size_t)g * D;
           double q = 0.0;
@@ -392,41 +444,27 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
             q += u * u * lg[d];
           }
           q = group8_sum_d(q);
-          if (gl == 0) L.as[g * kT + pn] = (float)(a.c64[g] - 0.5 * q - (double)Mp);
-          if (gl == 0) ++nrec;
-        } else if (FORM == GMM_PREC_BF16X3) {
-          const float* sg = a.prm + (size_t)g * DP;
-          const float* mg = a.prm + (size_t)G * DP + (size_t)g * DP;
-          float q = 0.0f;
-#pragma unroll 8
-          for (int i = 0; i < 16; ++i) {
-            const int d = gl + 8 * i;
-            if (d < D) {
-              const float u = fmaf(x[d], sg[d], -mg[d]);
-              q = fmaf(u, u, q);
-            }
-          }
-          q = group8_sum(q);
-          if (gl == 0) {
-            const double av = ((double)a.cc[g] + (double)a.cc[G + g]) - 0.5 * (double)q;
-            L.as[g * kT + pn] = (float)(av - (double)Mp);
-            ++nrec;
-          }
-        } else {
-          // FP32 form, single near component: the screening value is already
-          // the direct form; store it relative to the maximum
-          if (gl == 0) L.as[g * kT + pn] = L.as[g * kT + pn] - Mp;
+          val = a.c64[g] - 0.5 * q;
+        }
+        if (gl == 0) {
+          const float rel = (float)(val - (double)Mp);
+          L.as[g * kT + pn] = rel;
+          atomicMax(&L.dmax[pn], f2ord(rel));
+          if (exact64 || FORM == GMM_PREC_BF16X3) ++nrec;
         }
       }
     }
     __syncthreads();
-    // 4. log-sum-exp: entries of near pairs now hold a - M_n, the rest a32
+    // 4. log-sum-exp about M_lo + dmax: entries of near pairs hold a - M_lo,
+    // the rest the screening value (each at least kNearGap below the maximum)
+    float Dn = ord2f(L.dmax[n]);
+    Dn = Dn > -INFINITY ? Dn : 0.0f;  // padding samples have no near pair
     {
       double s = 0.0;
       for (int g = w + kNW * half; g < G; g += 2 * kNW) {
         const bool near = (L.nbits[n * 4 + (g >> 5)] >> (g & 31)) & 1u;
         const float v = L.as[g * kT + n];
-        s += (double)__expf(near ? v : v - M);
+        s += (double)__expf(near ? v - Dn : (v - M) - Dn);
       }
       s += __shfl_xor(s, 32, kWave);
       if (half == 0) L.psum[w * kT + n] = s;
@@ -435,18 +473,18 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
     double tot = 0.0;
 #pragma unroll
     for (int q = 0; q < kNW; ++q) tot += L.psum[q * kT + n];
-    const double lse = (double)M + log(tot);
+    const double lse = ((double)M + (double)Dn) + log(tot);
     if (w == 0 && half == 0 && n < nt) {
       llacc += lse;
       if (!isfinite(lse)) bad = 1;
       if (a.per_sample) a.per_sample[t0 + n] = (float)lse;
     }
     if (MSTEP) {
-      const float dl = (float)(lse - (double)M);
+      const float dl = (float)log(tot);
       for (int g = w + kNW * half; g < G; g += 2 * kNW) {
         const bool near = (L.nbits[n * 4 + (g >> 5)] >> (g & 31)) & 1u;
         const float v = L.as[g * kT + n];
-        const float z = (near ? v : v - M) - dl;
+        const float z = (near ? v - Dn : (v - M) - Dn) - dl;
         L.as[g * kT + n] = (n < nt && z >= -kRespCut) ? __expf(z) : 0.0f;
       }
       // 5. moments of this wave's components (written above by this wave only)
@@ -561,19 +599,73 @@ __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
   }
 }
 
-// Per-component constants of the fast kernel.  One workgroup per component.
-__global__ void __launch_bounds__(256) k_pre_fast(const float* __restrict__ hefts,
-                                                  const float* __restrict__ means,
-                                                  const float* __restrict__ covs, int D, int G,
-                                                  int KS, float* __restrict__ prm,
-                                                  float* __restrict__ cc,
-                                                  float* __restrict__ cexp,
-                                                  bf16x8* __restrict__ Whi,
-                                                  bf16x8* __restrict__ Wlo,
-                                                  double* __restrict__ c64,
-                                                  double* __restrict__ lam64) {
+template <int FORM, int CPW, int DPL, bool MSTEP>
+__global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const int b = blockIdx.x;
+  const int64_t i0 = (int64_t)b * a.chunk;
+  const int64_t i1 = min(a.N, i0 + a.chunk);
+  em_range<FORM, CPW, DPL, MSTEP>(a, i0, i1, b, lds_raw);
+}
+
+// ---- many models ----------------------------------------------------------
+
+// Per-model constants live at model * stride in each of these regions.
+struct BatchConst {
+  float* prm;      // stride 2 * Gmax * (D+1)
+  float* cc;       // stride 2 * Gmax
+  float* cexp;     // stride 2 * Gmax
+  bf16x8* Whi;     // stride RBmax * KS * 64
+  bf16x8* Wlo;
+  double* c64;     // stride Gmax
+  double* lam64;   // stride Gmax * D
+  int Gmax, RBmax, KS;
+};
+
+template <int FORM, int CPW, int DPL, bool MSTEP>
+__global__ void __launch_bounds__(kThreads) k_em_fast_batched(FastArgs base,
+                                                              const gmm_model_desc* models,
+                                                              const BatchItemDev* items,
+                                                              const int* n_items, BatchConst bc) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const int ni = *n_items;
+  const int D = base.D;
+  const int P = 2 * D + 1;
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    const BatchItemDev item = items[it];
+    const gmm_model_desc& m = models[item.model];
+    FastArgs a = base;
+    const size_t mi = (size_t)item.model;
+    a.X = m.X;
+    a.N = m.N;
+    a.ldx = D;
+    a.G = m.G;
+    a.prm = bc.prm + mi * 2 * bc.Gmax * (D + 1);
+    a.cc = bc.cc + mi * 2 * bc.Gmax;
+    a.cexp = bc.cexp + mi * 2 * bc.Gmax;
+    a.Whi = bc.Whi + mi * bc.RBmax * bc.KS * 64;
+    a.Wlo = bc.Wlo + mi * bc.RBmax * bc.KS * 64;
+    a.c64 = bc.c64 + mi * bc.Gmax;
+    a.lam64 = bc.lam64 + mi * bc.Gmax * D;
+    a.means = m.means;
+    a.part = base.part + (size_t)it * bc.Gmax * P;
+    a.ll_part = base.ll_part + it;
+    a.per_sample = nullptr;
+    a.dev_status = m.dev_status;
+    a.n_rec = nullptr;
+    em_range<FORM, CPW, DPL, MSTEP>(a, item.i0, item.i1, 0, lds_raw);
+    __syncthreads();
+  }
+}
+
+// Per-component constants of the fast kernel for component g (one workgroup).
+__device__ void pre_component(const float* __restrict__ hefts, const float* __restrict__ means,
+                              const float* __restrict__ covs, int D, int G, int KS, int g,
+                              float* __restrict__ prm, float* __restrict__ cc,
+                              float* __restrict__ cexp, bf16x8* __restrict__ Whi,
+                              bf16x8* __restrict__ Wlo, double* __restrict__ c64,
+                              double* __restrict__ lam64) {
   __shared__ double sh[256];
-  const int g = blockIdx.x;
   const int DP = D + 1;
   double ld = 0.0, q = 0.0;
   for (int d = threadIdx.x; d < D; d += 256) {
@@ -623,6 +715,52 @@ __global__ void __launch_bounds__(256) k_pre_fast(const float* __restrict__ heft
     ((__bf16*)(Whi + idx))[i] = h;
     ((__bf16*)(Wlo + idx))[i] = l;
   }
+}
+
+// Zero A fragments for row g (a padding row of the last row block).
+__device__ void zero_component_rows(bf16x8* Whi, bf16x8* Wlo, int KS, int g) {
+  const int rb = g >> 4, row = g & 15;
+  for (int e = threadIdx.x; e < KS * 4; e += 256) {
+    const int ks = e / 4, lq = e & 3;
+    const size_t idx = ((size_t)rb * KS + ks) * 64 + 16 * lq + row;
+    bf16x8 z;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) z[i] = (__bf16)0.0f;
+    Whi[idx] = z;
+    Wlo[idx] = z;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_pre_fast(const float* __restrict__ hefts,
+                                                  const float* __restrict__ means,
+                                                  const float* __restrict__ covs, int D, int G,
+                                                  int KS, float* __restrict__ prm,
+                                                  float* __restrict__ cc,
+                                                  float* __restrict__ cexp,
+                                                  bf16x8* __restrict__ Whi,
+                                                  bf16x8* __restrict__ Wlo,
+                                                  double* __restrict__ c64,
+                                                  double* __restrict__ lam64) {
+  pre_component(hefts, means, covs, D, G, KS, blockIdx.x, prm, cc, cexp, Whi, Wlo, c64, lam64);
+}
+
+// grid (16 * RBmax, n_models): component g of model blockIdx.y.
+__global__ void __launch_bounds__(256) k_pre_fast_batched(const gmm_model_desc* models, int D,
+                                                          BatchConst bc) {
+  const int mi = blockIdx.y;
+  const gmm_model_desc& m = models[mi];
+  if (!batch_desc_ok(m, bc.Gmax)) return;
+  const int G = m.G;
+  const int g = blockIdx.x;
+  bf16x8* Whi = bc.Whi + (size_t)mi * bc.RBmax * bc.KS * 64;
+  bf16x8* Wlo = bc.Wlo + (size_t)mi * bc.RBmax * bc.KS * 64;
+  if (g >= G) {
+    if (g < 16 * ((G + 15) / 16)) zero_component_rows(Whi, Wlo, bc.KS, g);
+    return;
+  }
+  pre_component(m.hefts, m.means, m.covs, D, G, bc.KS, g, bc.prm + (size_t)mi * 2 * bc.Gmax * (D + 1),
+                bc.cc + (size_t)mi * 2 * bc.Gmax, bc.cexp + (size_t)mi * 2 * bc.Gmax, Whi, Wlo,
+                bc.c64 + (size_t)mi * bc.Gmax, bc.lam64 + (size_t)mi * bc.Gmax * D);
 }
 
 // Rows of the last row block past G get zero weights.
@@ -705,6 +843,71 @@ __global__ void __launch_bounds__(256) k_fin_welford(const double* __restrict__ 
   }
   __syncthreads();
   if (threadIdx.x == 0 && bad) atomicOr(dev_status, GMM_DEV_NONFINITE);
+}
+
+// Reduce step of the batched form: grid (Gmax, n_models); block (g, m)
+// combines model m's items in order (same arithmetic as k_fin_welford).
+__global__ void __launch_bounds__(256) k_fin_welford_batched(const gmm_model_desc* models,
+                                                             const int2* mitems, int D, int Gmax,
+                                                             float var_floor,
+                                                             const double* __restrict__ part,
+                                                             const double* __restrict__ ll_part,
+                                                             int mstep) {
+  __shared__ int bad;
+  const int mi = blockIdx.y;
+  const gmm_model_desc& m = models[mi];
+  const int g = blockIdx.x;
+  const int first = mitems[mi].x, cnt = mitems[mi].y;
+  if (cnt == 0 || g >= m.G) return;
+  const int P = 2 * D + 1;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  if (mstep) {
+    double Ltot = 0.0;
+    for (int k = 0; k < cnt; ++k) Ltot += part[((size_t)(first + k) * Gmax + g) * P];
+    for (int d = threadIdx.x; d < D; d += 256) {
+      double L = 0.0, mu = 0.0, Q = 0.0;
+      for (int k = 0; k < cnt; ++k) {
+        const double* q = part + ((size_t)(first + k) * Gmax + g) * P;
+        const double Lb = q[0];
+        if (Lb == 0.0) continue;
+        const double mb = q[1 + d], Qb = q[1 + D + d];
+        if (L == 0.0) {
+          L = Lb;
+          mu = mb;
+          Q = Qb;
+        } else {
+          const double Ln = L + Lb;
+          const double dl = mb - mu;
+          mu += dl * (Lb / Ln);
+          Q += Qb + dl * dl * (L * Lb / Ln);
+          L = Ln;
+        }
+      }
+      if (L > 0.0) {
+        double v = Q / L;
+        v = v > 0.0 ? v : 0.0;
+        v = v > (double)var_floor ? v : (double)var_floor;
+        const double mn = (double)m.means[(size_t)g * D + d] + mu;
+        m.means[(size_t)g * D + d] = (float)mn;
+        m.covs[(size_t)g * D + d] = (float)v;
+        if (!isfinite(mn) || !isfinite(v)) bad = 1;
+      }
+    }
+    if (threadIdx.x == 0) {
+      const float w = (float)(Ltot / (double)m.N);
+      m.hefts[g] = w;
+      if (!isfinite(w)) bad = 1;
+    }
+  }
+  if (g == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < cnt; ++k) s += ll_part[first + k];
+    if (m.loglik) *m.loglik = s / (double)m.N;
+    if (!isfinite(s)) bad = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && bad) atomicOr(m.dev_status, GMM_DEV_NONFINITE);
 }
 
 template <int FORM, int CPW, int DPL, bool MSTEP>
@@ -806,6 +1009,83 @@ hipError_t launch_fin_welford(int nb, int64_t N, int D, int G, float var_floor, 
                               const Workspace& w, hipStream_t st) {
   hipLaunchKernelGGL(k_fin_welford, dim3(G), dim3(256), 0, st, w.partials, nb, N, D, G,
                      var_floor, hefts, means, covs, w.scalars, mean_loglik, dev_status);
+  return hipGetLastError();
+}
+
+namespace {
+
+template <int FORM, bool MSTEP, int CPW, int DPL>
+void launch_batched_one(const FastArgs& base, const gmm_model_desc* models, const BatchWorkspace& bw,
+                        const BatchConst& bc, int grid, size_t lds, hipStream_t st) {
+  auto kern = k_em_fast_batched<FORM, CPW, DPL, MSTEP>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, st, base, models, bw.items,
+                     bw.n_items, bc);
+}
+
+template <int FORM, bool MSTEP>
+void dispatch_batched(const FastArgs& base, const gmm_model_desc* models, const BatchWorkspace& bw,
+                      const BatchConst& bc, int grid, size_t lds, hipStream_t st) {
+  const int cpw = (bw.Gmax + kNW - 1) / kNW;
+  if (bw.D <= 64) {
+    if (cpw <= 2) launch_batched_one<FORM, MSTEP, 2, 1>(base, models, bw, bc, grid, lds, st);
+    else if (cpw <= 4) launch_batched_one<FORM, MSTEP, 4, 1>(base, models, bw, bc, grid, lds, st);
+    else if (cpw <= 8) launch_batched_one<FORM, MSTEP, 8, 1>(base, models, bw, bc, grid, lds, st);
+    else launch_batched_one<FORM, MSTEP, 16, 1>(base, models, bw, bc, grid, lds, st);
+  } else {
+    if (cpw <= 2) launch_batched_one<FORM, MSTEP, 2, 2>(base, models, bw, bc, grid, lds, st);
+    else if (cpw <= 4) launch_batched_one<FORM, MSTEP, 4, 2>(base, models, bw, bc, grid, lds, st);
+    else if (cpw <= 8) launch_batched_one<FORM, MSTEP, 8, 2>(base, models, bw, bc, grid, lds, st);
+    else launch_batched_one<FORM, MSTEP, 16, 2>(base, models, bw, bc, grid, lds, st);
+  }
+}
+
+}  // namespace
+
+bool em_batched_supported(int D, int Gmax, int prec) {
+  return em_fast_supported(D, Gmax, prec);
+}
+
+hipError_t launch_em_batched(const gmm_model_desc* models, int n_models, int n_items_host, int D,
+                             float var_floor, int prec, bool mstep, const BatchWorkspace& bw,
+                             hipStream_t st) {
+  BatchConst bc;
+  bc.prm = bw.prm;
+  bc.cc = bw.cc;
+  bc.cexp = bw.cexp;
+  bc.Whi = (bf16x8*)bw.Whi;
+  bc.Wlo = (bf16x8*)bw.Wlo;
+  bc.c64 = bw.c64;
+  bc.lam64 = bw.lam64;
+  bc.Gmax = bw.Gmax;
+  bc.RBmax = bw.RBmax;
+  bc.KS = bw.KS;
+  FastArgs base{};
+  base.D = D;
+  base.KS = bw.KS;
+  base.part = bw.partials;
+  base.ll_part = bw.sparts;
+  hipLaunchKernelGGL(k_pre_fast_batched, dim3(16 * bw.RBmax, n_models), dim3(256), 0, st, models,
+                     D, bc);
+  const size_t lds = fast_lds_bytes(D, bw.Gmax, bw.KS, prec);
+  const int grid = n_items_host < 256 ? (n_items_host < 1 ? 1 : n_items_host) : 256;
+  {
+    ProfScope ps(kProfBatched, st);
+    if (prec == GMM_PREC_BF16X3) {
+      if (mstep) dispatch_batched<GMM_PREC_BF16X3, true>(base, models, bw, bc, grid, lds, st);
+      else dispatch_batched<GMM_PREC_BF16X3, false>(base, models, bw, bc, grid, lds, st);
+    } else {
+      if (mstep) dispatch_batched<GMM_PREC_FP32, true>(base, models, bw, bc, grid, lds, st);
+      else dispatch_batched<GMM_PREC_FP32, false>(base, models, bw, bc, grid, lds, st);
+    }
+  }
+  hipLaunchKernelGGL(k_fin_welford_batched, dim3(bw.Gmax, n_models), dim3(256), 0, st, models,
+                     bw.mitems, D, bw.Gmax, var_floor, bw.partials, bw.sparts, mstep ? 1 : 0);
   return hipGetLastError();
 }
 

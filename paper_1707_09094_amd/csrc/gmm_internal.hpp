@@ -13,10 +13,46 @@ namespace gmm {
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kMaxBlocks = 512;      // E/M grid: 2 workgroups per CU on 256 CUs
 constexpr float kRespCut = 80.0f;    // responsibilities below exp(-80) of the best are 0
-// Every sample's best component and all components within this many nats of it
-// have their log-density recomputed in FP64 from the FP32 parameters.
+// Near set of a sample: every component whose screened log-density, widened by
+// its rounding-error bound, comes within this many nats of the largest
+// guaranteed lower bound.  Those are recomputed exactly (FP64 from the FP32
+// parameters, or FP32 direct form where its bound is below kExactTol).
 constexpr float kNearGap = 30.0f;
+constexpr float kExactTol = 1e-3f;
 constexpr double kLog2Pi = 1.8378770664093454835606594728112353;
+
+// ---- rounding-error bounds of the FP32 screening values --------------------
+// a_g(x) = c_g - q/2, q = sum_d lam_gd (x_d - mu_gd)^2, Q_g = sum_d lam_gd mu_gd^2.
+// Direct form: u_d = fma(x_d, s_gd, -m_gd) with s = sqrt(lam), m = mu s each
+// rounded once, so |du_d| <= 2^-24 (|u_d| + sqrt(lam_d)(|x_d| + |mu_d|)); with
+// (|x|+|mu|)^2 <= 2 (x-mu)^2 + 8 mu^2, Cauchy-Schwarz and D sequential FMAs,
+// |dq| <= 2^-24 ((2 + D) q + 2 sqrt(q (2q + 8Q))); adding c (hi + lo) and
+// forming c - q/2 rounds twice more.  q is taken from the screened value, whose
+// own error is covered by the 1% margin.
+__device__ __forceinline__ float err_direct(float q, float Q, float c, int D) {
+  q = fmaxf(q, 0.0f);
+  const float t = 2.0f * sqrtf(q * (2.0f * q + 8.0f * Q));
+  return 1.01f * (0x1p-25f * ((2.0f + (float)D) * q + t) + 0x1p-23f * (fabsf(c) + 0.5f * q));
+}
+
+// Expanded form in BF16x3 (A = [lam mu; -lam/2], B = [x; x^2], hi/lo split):
+// each product is off by <= 3 2^-16 |A||B|, the FP32 accumulation of 3*32*KS
+// terms by <= 96 KS 2^-24 sum|A||B|, and sum|A||B| <= (1 + sqrt 2)(q + Q);
+// adding cexp = c - Q/2 (hi + lo) rounds twice more.
+__device__ __forceinline__ float err_expanded_coef(int KS) {
+  return 1.02f * 2.4142136f * (3.0f * 0x1p-16f + 96.0f * (float)KS * 0x1p-24f + 0x1p-23f);
+}
+__device__ __forceinline__ float err_expanded(float q, float Q, float c, float coef) {
+  q = fmaxf(q, 0.0f);
+  return coef * (q + Q) + 1.01f * 0x1p-23f * (fabsf(c) + 0.5f * Q);
+}
+
+// Order-preserving map float <-> int (for integer atomicMax in LDS).
+__device__ __forceinline__ int f2ord(float f) {
+  const int i = __float_as_int(f);
+  return i >= 0 ? i : i ^ 0x7FFFFFFF;
+}
+__device__ __forceinline__ float ord2f(int i) { return __int_as_float(i >= 0 ? i : i ^ 0x7FFFFFFF); }
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
@@ -40,7 +76,7 @@ struct Workspace {
   // per-component constants of the E-step (see em precompute kernels)
   float* s;        // diag: [D][G] 1/sigma (d-major)      full: unused
   float* m;        // diag: [D][G] mu/sigma                full: unused
-  float* c;        // [2][G] log w - 1/2 (D log 2pi + log|Sigma|), split hi/lo
+  float* c;        // [3][G] log w - 1/2 (D log 2pi + log|Sigma|), split hi/lo; Q_g
   float* W;        // full: [G][D][D] inverse Cholesky factor (row-major lower)
   float* prm;      // fast diag kernel: [2][G][D+1] 1/sigma then mu/sigma
   uint16_t* Bhi;   // BF16X3 expanded weights [G][K] hi part
@@ -72,7 +108,7 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   const int K = kexp_K(D);
   size_t o_s = take(sizeof(float) * (size_t)D * G);
   size_t o_m = take(sizeof(float) * (size_t)D * G);
-  size_t o_c = take(sizeof(float) * 2 * (size_t)G);
+  size_t o_c = take(sizeof(float) * 3 * (size_t)G);
   size_t o_W = take(cov == GMM_COV_FULL ? sizeof(float) * (size_t)D * D * G : 0);
   const size_t GP = ((size_t)G + 15) / 16 * 16;
   size_t o_prm = take(sizeof(float) * 2 * (size_t)G * (D + 1));
@@ -111,6 +147,120 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   w->counters = (int64_t*)(b + o_ct);
   return true;
 }
+
+// ---- many-model (batched) workspace ---------------------------------------
+
+struct BatchItemDev {
+  int32_t model;
+  int32_t first_of_model;
+  int64_t i0, i1;
+};
+
+constexpr int kBatchMaxD = 128;
+constexpr int kBatchMaxG = 128;
+
+// A descriptor the batched kernels may use: the host sized the launch and the
+// workspace from Ns/Gs, so a model outside that envelope is skipped (its
+// status gets GMM_DEV_BADDESC from the plan kernel) rather than overrun it.
+__device__ inline bool batch_desc_ok(const gmm_model_desc& m, int Gmax) {
+  return m.N >= 1 && m.G >= 1 && m.G <= Gmax && m.X != nullptr;
+}
+
+struct BatchWorkspace {
+  int n_models, D, Gmax, RBmax, KS, cap;  // cap: item capacity
+  BatchItemDev* items;
+  int2* mitems;
+  int* n_items;
+  // EM constants (stride per model)
+  float* prm;      // 2 * Gmax * (D+1)
+  float* cc;       // 2 * Gmax
+  float* cexp;     // 2 * Gmax
+  void* Whi;       // RBmax * KS * 64 * 16 bytes
+  void* Wlo;
+  double* c64;     // Gmax
+  double* lam64;   // Gmax * D
+  // k-means constants (stride per model)
+  float* kmprm;    // Gmax * (D+1)
+  float* ksd;      // D
+  double* klam64;  // D
+  float* kmnorm;   // 1
+  int64_t* kscratch;  // 2 * Gmax (resurrection)
+  double* partials;   // cap * Gmax * (2D+1)
+  double* sparts;     // cap
+  size_t bytes;
+};
+
+inline bool carve_batched(void* base, size_t avail, int n_models, int D, int Gmax, int cap,
+                          BatchWorkspace* w) {
+  size_t off = 0;
+  auto take = [&](size_t n) {
+    size_t o = off;
+    off = align_up(off + n);
+    return o;
+  };
+  const size_t M = (size_t)n_models;
+  const int RBmax = (Gmax + 15) / 16;
+  const int KS = (2 * D + 31) / 32;
+  const size_t o_it = take(sizeof(BatchItemDev) * (size_t)cap);
+  const size_t o_mi = take(sizeof(int2) * M);
+  const size_t o_ni = take(sizeof(int) * 4);
+  const size_t o_prm = take(sizeof(float) * M * 2 * Gmax * (D + 1));
+  const size_t o_cc = take(sizeof(float) * M * 2 * Gmax);
+  const size_t o_ce = take(sizeof(float) * M * 2 * Gmax);
+  const size_t o_wh = take(M * RBmax * KS * 64 * 16);
+  const size_t o_wl = take(M * RBmax * KS * 64 * 16);
+  const size_t o_c64 = take(sizeof(double) * M * Gmax);
+  const size_t o_l64 = take(sizeof(double) * M * Gmax * D);
+  const size_t o_kp = take(sizeof(float) * M * Gmax * (D + 1));
+  const size_t o_ks = take(sizeof(float) * M * D);
+  const size_t o_kl = take(sizeof(double) * M * D);
+  const size_t o_kn = take(sizeof(float) * M);
+  const size_t o_kx = take(sizeof(int64_t) * M * 2 * Gmax);
+  const size_t o_p = take(sizeof(double) * (size_t)cap * Gmax * (2 * D + 1));
+  const size_t o_sp = take(sizeof(double) * (size_t)cap);
+  w->n_models = n_models;
+  w->D = D;
+  w->Gmax = Gmax;
+  w->RBmax = RBmax;
+  w->KS = KS;
+  w->cap = cap;
+  w->bytes = off;
+  if (!base) return true;
+  if (avail < off) return false;
+  char* b = (char*)base;
+  w->items = (BatchItemDev*)(b + o_it);
+  w->mitems = (int2*)(b + o_mi);
+  w->n_items = (int*)(b + o_ni);
+  w->prm = (float*)(b + o_prm);
+  w->cc = (float*)(b + o_cc);
+  w->cexp = (float*)(b + o_ce);
+  w->Whi = b + o_wh;
+  w->Wlo = b + o_wl;
+  w->c64 = (double*)(b + o_c64);
+  w->lam64 = (double*)(b + o_l64);
+  w->kmprm = (float*)(b + o_kp);
+  w->ksd = (float*)(b + o_ks);
+  w->klam64 = (double*)(b + o_kl);
+  w->kmnorm = (float*)(b + o_kn);
+  w->kscratch = (int64_t*)(b + o_kx);
+  w->partials = (double*)(b + o_p);
+  w->sparts = (double*)(b + o_sp);
+  return true;
+}
+
+int batch_item_count(int32_t n_models, const int64_t* Ns, int64_t chunk);
+hipError_t launch_batch_plan(const gmm_model_desc* models, int n_models, int64_t chunk,
+                             const BatchWorkspace& bw, hipStream_t st);
+bool em_fast_supported(int D, int G, int prec);
+bool km_fast_supported(int D, int G);
+hipError_t launch_em_batched(const gmm_model_desc* models, int n_models, int n_items_host, int D,
+                             float var_floor, int prec, bool mstep, const BatchWorkspace& bw,
+                             hipStream_t st);
+hipError_t launch_kmeans_batched(const gmm_model_desc* models, int n_models, int n_items_host,
+                                 int D, int dist, float var_floor, const BatchWorkspace& bw,
+                                 hipStream_t st);
+hipError_t launch_global_stats_batched(const gmm_model_desc* models, int n_models, int D,
+                                       double* mean_out, double* var_out, hipStream_t st);
 
 // ---- device helpers -------------------------------------------------------
 

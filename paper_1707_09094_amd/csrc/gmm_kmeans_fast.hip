@@ -76,8 +76,8 @@ __host__ __device__ inline size_t km_lds_bytes(int D, int G) {
 }
 
 template <int CPW, int DPL>
-__global__ void __launch_bounds__(kThreads) k_km_fast(KmArgs a) {
-  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+__device__ __forceinline__ void km_range(const KmArgs& a, int64_t i0, int64_t i1, int b,
+                                         char* lds_raw) {
   const int D = a.D, G = a.G;
   const int DP = D + 1;
   float *mu, *mm, *sv, *xf, *dist, *pbest, *psec;
@@ -104,9 +104,6 @@ __global__ void __launch_bounds__(kThreads) k_km_fast(KmArgs a) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int w = tid / kWave;
-  const int b = blockIdx.x;
-  const int64_t i0 = (int64_t)b * a.chunk;
-  const int64_t i1 = min(a.N, i0 + a.chunk);
   const int P = 2 * D + 1;
 
   for (int p = tid; p < G * D; p += kThreads) mu[p] = a.means[p];
@@ -340,21 +337,62 @@ __global__ void __launch_bounds__(kThreads) k_km_fast(KmArgs a) {
     if (lane == 0) a.in_part[b] = v;
   }
   if (bad) atomicOr(a.dev_status, GMM_DEV_NONFINITE);
-  if (w == 0) {
+  if (w == 0 && a.n_rec) {
     long long v = nrec;
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
     if (lane == 0 && v) atomicAdd((unsigned long long*)a.n_rec, (unsigned long long)v);
   }
 }
 
+template <int CPW, int DPL>
+__global__ void __launch_bounds__(kThreads) k_km_fast(KmArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const int b = blockIdx.x;
+  const int64_t i0 = (int64_t)b * a.chunk;
+  const int64_t i1 = min(a.N, i0 + a.chunk);
+  km_range<CPW, DPL>(a, i0, i1, b, lds_raw);
+}
+
+// Batched: persistent grid over the work items; per-model constants at
+// model * stride in the batched workspace.
+template <int CPW, int DPL>
+__global__ void __launch_bounds__(kThreads) k_km_fast_batched(KmArgs base,
+                                                              const gmm_model_desc* models,
+                                                              const BatchItemDev* items,
+                                                              const int* n_items, int Gmax) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const int ni = *n_items;
+  const int D = base.D;
+  const int P = 2 * D + 1;
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    const BatchItemDev item = items[it];
+    const gmm_model_desc& m = models[item.model];
+    const size_t mi = (size_t)item.model;
+    KmArgs a = base;
+    a.X = m.X;
+    a.N = m.N;
+    a.ldx = D;
+    a.G = m.G;
+    a.means = m.means;
+    a.mprm = base.mprm + mi * Gmax * (D + 1);
+    a.sd = base.sd + mi * D;
+    a.lam64 = base.lam64 + mi * D;
+    a.mnorm = base.mnorm + mi;
+    a.assign = m.assign;
+    a.part = base.part + (size_t)it * Gmax * P;
+    a.in_part = base.in_part + it;
+    a.n_rec = nullptr;
+    a.dev_status = m.dev_status;
+    km_range<CPW, DPL>(a, item.i0, item.i1, 0, lds_raw);
+    __syncthreads();
+  }
+}
+
 // lam_d, s_d = sqrt(lam_d), m_gd = mu_gd s_d and max_g |m_g| (one workgroup).
-__global__ void __launch_bounds__(256) k_km_pre_fast(const double* __restrict__ gvar, int D,
-                                                     int G, float var_floor, int dist,
-                                                     const float* __restrict__ means,
-                                                     double* __restrict__ lam64,
-                                                     float* __restrict__ sd,
-                                                     float* __restrict__ mprm,
-                                                     float* __restrict__ mnorm) {
+__device__ void km_pre(const double* __restrict__ gvar, int D, int G, float var_floor, int dist,
+                       const float* __restrict__ means, double* __restrict__ lam64,
+                       float* __restrict__ sd, float* __restrict__ mprm,
+                       float* __restrict__ mnorm) {
   __shared__ float red[256];
   for (int d = threadIdx.x; d < D; d += 256) {
     double l = 1.0;
@@ -385,6 +423,29 @@ __global__ void __launch_bounds__(256) k_km_pre_fast(const double* __restrict__ 
     __syncthreads();
   }
   if (threadIdx.x == 0) *mnorm = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_km_pre_fast(const double* __restrict__ gvar, int D,
+                                                     int G, float var_floor, int dist,
+                                                     const float* __restrict__ means,
+                                                     double* __restrict__ lam64,
+                                                     float* __restrict__ sd,
+                                                     float* __restrict__ mprm,
+                                                     float* __restrict__ mnorm) {
+  km_pre(gvar, D, G, var_floor, dist, means, lam64, sd, mprm, mnorm);
+}
+
+// one workgroup per model
+__global__ void __launch_bounds__(256) k_km_pre_batched(const gmm_model_desc* models, int D,
+                                                        int Gmax, float var_floor, int dist,
+                                                        double* lam64, float* sd, float* mprm,
+                                                        float* mnorm) {
+  const int mi = blockIdx.x;
+  const gmm_model_desc& m = models[mi];
+  if (!batch_desc_ok(m, Gmax)) return;
+  if (threadIdx.x == 0 && m.inertia) *m.inertia = 0.0;
+  km_pre(m.gvar, D, m.G, var_floor, dist, m.means, lam64 + (size_t)mi * D, sd + (size_t)mi * D,
+         mprm + (size_t)mi * Gmax * (D + 1), mnorm + mi);
 }
 
 // Reduce step of the k-means map: pairwise (count, mean, M2) combination in
@@ -441,6 +502,191 @@ __global__ void __launch_bounds__(256) k_km_fin_fast(const double* __restrict__ 
     *inertia = s;
     if (!isfinite(s)) atomicOr(dev_status, GMM_DEV_NONFINITE);
   }
+}
+
+__global__ void __launch_bounds__(256) k_km_fin_batched(const gmm_model_desc* models,
+                                                        const int2* mitems, int D, int Gmax,
+                                                        float var_floor,
+                                                        const double* __restrict__ part,
+                                                        const double* __restrict__ in_part) {
+  const int mi = blockIdx.y;
+  const gmm_model_desc& m = models[mi];
+  const int g = blockIdx.x;
+  const int first = mitems[mi].x, cnt = mitems[mi].y;
+  if (cnt == 0 || g >= m.G) return;
+  const int P = 2 * D + 1;
+  double Ltot = 0.0;
+  for (int k = 0; k < cnt; ++k) Ltot += part[((size_t)(first + k) * Gmax + g) * P];
+  for (int d = threadIdx.x; d < D; d += 256) {
+    double L = 0.0, mu = 0.0, Q = 0.0;
+    for (int k = 0; k < cnt; ++k) {
+      const double* q = part + ((size_t)(first + k) * Gmax + g) * P;
+      const double Lb = q[0];
+      if (Lb == 0.0) continue;
+      const double mb = q[1 + d], Qb = q[1 + D + d];
+      if (L == 0.0) {
+        L = Lb;
+        mu = mb;
+        Q = Qb;
+      } else {
+        const double Ln = L + Lb;
+        const double dl = mb - mu;
+        mu += dl * (Lb / Ln);
+        Q += Qb + dl * dl * (L * Lb / Ln);
+        L = Ln;
+      }
+    }
+    if (L > 0.0) {
+      double v = Q / L;
+      v = v > 0.0 ? v : 0.0;
+      v = v > (double)var_floor ? v : (double)var_floor;
+      m.means[(size_t)g * D + d] = (float)((double)m.means[(size_t)g * D + d] + mu);
+      m.covs[(size_t)g * D + d] = (float)v;
+    } else {
+      m.covs[(size_t)g * D + d] = 1.0f;
+    }
+  }
+  if (threadIdx.x == 0) {
+    m.counts[g] = (int64_t)Ltot;
+    m.hefts[g] = (float)(Ltot / (double)m.N);
+  }
+  if (g == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < cnt; ++k) s += in_part[first + k];
+    if (m.inertia) *m.inertia = s;
+    if (!isfinite(s)) atomicOr(m.dev_status, GMM_DEV_NONFINITE);
+  }
+}
+
+// Dead-mean resurrection per model (one workgroup of 256 per model; same rule
+// as the single-model kernel of gmm_kmeans.hip).
+__global__ void __launch_bounds__(256) k_km_resurrect_batched(const gmm_model_desc* models,
+                                                              int D, int Gmax,
+                                                              int64_t* scratch) {
+  constexpr int NT = 256;
+  __shared__ int any_dead;
+  __shared__ long long s_val[NT];
+  __shared__ int s_idx[NT];
+  __shared__ long long s_cnt[NT];
+  __shared__ long long s_pick;
+  const int mi = blockIdx.x;
+  const gmm_model_desc& m = models[mi];
+  if (!batch_desc_ok(m, Gmax)) return;
+  const int G = m.G;
+  const int64_t N = m.N;
+  const int tid = threadIdx.x;
+  if (tid == 0) any_dead = 0;
+  __syncthreads();
+  for (int g = tid; g < G; g += NT)
+    if (m.counts[g] == 0) any_dead = 1;
+  __syncthreads();
+  if (!any_dead) return;
+  int64_t* rem = scratch + (size_t)mi * 2 * Gmax;
+  int64_t* taken = rem + Gmax;
+  for (int g = tid; g < G; g += NT) {
+    rem[g] = m.counts[g];
+    taken[g] = 0;
+  }
+  __syncthreads();
+  const int64_t slice = (N + NT - 1) / NT;
+  for (int g = 0; g < G; ++g) {
+    if (m.counts[g] != 0) continue;
+    long long bv = -1;
+    int bi = 0;
+    for (int k = tid; k < G; k += NT)
+      if ((long long)rem[k] > bv) {
+        bv = rem[k];
+        bi = k;
+      }
+    s_val[tid] = bv;
+    s_idx[tid] = bi;
+    __syncthreads();
+    for (int sft = NT / 2; sft > 0; sft >>= 1) {
+      if (tid < sft) {
+        const long long ov = s_val[tid + sft];
+        const int oi = s_idx[tid + sft];
+        if (ov > s_val[tid] || (ov == s_val[tid] && oi < s_idx[tid])) {
+          s_val[tid] = ov;
+          s_idx[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const long long rq = s_val[0];
+    const int q = s_idx[0];
+    __syncthreads();
+    if (rq < 2) continue;
+    const long long want = taken[q];
+    const int64_t a0 = (int64_t)tid * slice, a1 = min(N, a0 + slice);
+    long long cnt = 0;
+    for (int64_t i = a0; i < a1; ++i) cnt += (m.assign[i] == q);
+    s_cnt[tid] = cnt;
+    if (tid == 0) s_pick = -1;
+    __syncthreads();
+    if (tid == 0) {
+      long long run = 0;
+      for (int t = 0; t < NT; ++t) {
+        if (want < run + s_cnt[t]) {
+          s_cnt[0] = t;
+          s_val[0] = want - run;
+          break;
+        }
+        run += s_cnt[t];
+      }
+    }
+    __syncthreads();
+    const int owner = (int)s_cnt[0];
+    if (tid == owner) {
+      long long k = s_val[0];
+      for (int64_t i = a0; i < a1; ++i)
+        if (m.assign[i] == q) {
+          if (k == 0) {
+            s_pick = i;
+            break;
+          }
+          --k;
+        }
+    }
+    __syncthreads();
+    const long long pick = s_pick;
+    if (pick >= 0) {
+      for (int d = tid; d < D; d += NT) m.means[(size_t)g * D + d] = m.X[pick * D + d];
+      if (tid == 0) {
+        taken[q] += 1;
+        rem[q] -= 1;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Per-model global mean / population variance, two FP64 passes, one
+// workgroup per model (thread per dimension, samples in order).
+__global__ void __launch_bounds__(256) k_gstats_batched(const gmm_model_desc* models, int D,
+                                                        double* mean_out, double* var_out) {
+  const int mi = blockIdx.x;
+  const gmm_model_desc& m = models[mi];
+  if (m.N < 1 || m.X == nullptr) {
+    if (threadIdx.x == 0 && m.dev_status) *m.dev_status = GMM_DEV_BADDESC;
+    return;
+  }
+  for (int d = threadIdx.x; d < D; d += 256) {
+    double s = 0.0;
+    for (int64_t i = 0; i < m.N; ++i) s += (double)m.X[i * D + d];
+    const double mean = s / (double)m.N;
+    double q = 0.0;
+    for (int64_t i = 0; i < m.N; ++i) {
+      const double t = (double)m.X[i * D + d] - mean;
+      q += t * t;
+    }
+    mean_out[(size_t)mi * D + d] = mean;
+    var_out[(size_t)mi * D + d] = q / (double)m.N;
+  }
+}
+
+__global__ void k_zero_status_batched(const gmm_model_desc* models, int n_models) {
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n_models; m += gridDim.x * blockDim.x)
+    *models[m].dev_status = 0;
 }
 
 template <int CPW, int DPL>
@@ -510,6 +756,68 @@ hipError_t launch_kmeans_fast(const float* X, int64_t N, int D, int64_t ldx, int
   }
   hipLaunchKernelGGL(k_km_fin_fast, dim3(G), dim3(256), 0, st, w.partials, nb, N, D, G, var_floor,
                      means, dcovs, hefts, counts, w.scalars, inertia, dev_status);
+  return hipGetLastError();
+}
+
+namespace {
+
+template <int CPW, int DPL>
+void km_launch_batched_one(const KmArgs& base, const gmm_model_desc* models,
+                           const BatchWorkspace& bw, int grid, size_t lds, hipStream_t st) {
+  auto kern = k_km_fast_batched<CPW, DPL>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, st, base, models, bw.items,
+                     bw.n_items, bw.Gmax);
+}
+
+}  // namespace
+
+hipError_t launch_kmeans_batched(const gmm_model_desc* models, int n_models, int n_items_host,
+                                 int D, int dist, float var_floor, const BatchWorkspace& bw,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_km_pre_batched, dim3(n_models), dim3(256), 0, st, models, D, bw.Gmax,
+                     var_floor, dist, bw.klam64, bw.ksd, bw.kmprm, bw.kmnorm);
+  KmArgs base{};
+  base.D = D;
+  base.mprm = bw.kmprm;
+  base.sd = bw.ksd;
+  base.lam64 = bw.klam64;
+  base.mnorm = bw.kmnorm;
+  base.part = bw.partials;
+  base.in_part = bw.sparts;
+  const size_t lds = km_lds_bytes(D, bw.Gmax);
+  const int grid = n_items_host < 256 ? (n_items_host < 1 ? 1 : n_items_host) : 256;
+  {
+    ProfScope ps(kProfBatched, st);
+    const int cpw = (bw.Gmax + kNW - 1) / kNW;
+    if (D <= 64) {
+      if (cpw <= 2) km_launch_batched_one<2, 1>(base, models, bw, grid, lds, st);
+      else if (cpw <= 4) km_launch_batched_one<4, 1>(base, models, bw, grid, lds, st);
+      else if (cpw <= 8) km_launch_batched_one<8, 1>(base, models, bw, grid, lds, st);
+      else km_launch_batched_one<16, 1>(base, models, bw, grid, lds, st);
+    } else {
+      if (cpw <= 2) km_launch_batched_one<2, 2>(base, models, bw, grid, lds, st);
+      else if (cpw <= 4) km_launch_batched_one<4, 2>(base, models, bw, grid, lds, st);
+      else if (cpw <= 8) km_launch_batched_one<8, 2>(base, models, bw, grid, lds, st);
+      else km_launch_batched_one<16, 2>(base, models, bw, grid, lds, st);
+    }
+  }
+  hipLaunchKernelGGL(k_km_fin_batched, dim3(bw.Gmax, n_models), dim3(256), 0, st, models,
+                     bw.mitems, D, bw.Gmax, var_floor, bw.partials, bw.sparts);
+  hipLaunchKernelGGL(k_km_resurrect_batched, dim3(n_models), dim3(256), 0, st, models, D, bw.Gmax,
+                     bw.kscratch);
+  return hipGetLastError();
+}
+
+hipError_t launch_global_stats_batched(const gmm_model_desc* models, int n_models, int D,
+                                       double* mean_out, double* var_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gstats_batched, dim3(n_models), dim3(256), 0, st, models, D, mean_out,
+                     var_out);
   return hipGetLastError();
 }
 

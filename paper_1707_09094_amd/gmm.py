@@ -235,3 +235,159 @@ def gmm_profile_read(kind):
     n = ctypes.c_int64(0)
     _check("gmm_profile_read", library().gmm_profile_read(int(kind), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+# ---- many models (gmm_*_batched) ---------------------------------------------
+
+class _Desc(ctypes.Structure):
+    """Mirror of gmm_model_desc (96 bytes, 8-byte aligned)."""
+    _fields_ = [("X", _vp), ("N", _i64), ("G", _i32), ("reserved", _i32), ("hefts", _vp),
+                ("means", _vp), ("covs", _vp), ("counts", _vp), ("assign", _vp),
+                ("loglik", _vp), ("inertia", _vp), ("gvar", _vp), ("dev_status", _vp)]
+
+
+assert ctypes.sizeof(_Desc) == 96
+
+_SIGS.update({
+    "gmm_batched_workspace_bytes": ([_i32, _vp, _vp, _i32, _i32], _sz),
+    "gmm_em_iter_batched": ([_vp, _i32, _vp, _vp, _i32, _f32, _i32, _i32, _vp, _sz, _vp], _i32),
+    "gmm_loglik_batched": ([_vp, _i32, _vp, _vp, _i32, _i32, _i32, _vp, _sz, _vp], _i32),
+    "gmm_kmeans_iter_batched": ([_vp, _i32, _vp, _vp, _i32, _i32, _f32, _i32, _vp, _sz, _vp],
+                                _i32),
+    "gmm_global_stats_batched": ([_vp, _i32, _i32, _vp, _vp, _vp], _i32),
+    "gmm_batched_autotune": ([_vp, _i32, _vp, _vp, _i32, _i32, _vp, _sz, _vp,
+                              ctypes.POINTER(_i32)], _i32),
+})
+
+
+class ModelBatch:
+    """Many independent diagonal models sharing D, stored flat on the device.
+
+    ``Xs`` is a list of contiguous float32 (N_m, D) device tensors (kept
+    referenced: the descriptors point into them) and ``Gs`` the component
+    counts.  Parameters of model m are views into flat arrays:
+    ``hefts[m]`` (G_m,), ``means[m]`` / ``covs[m]`` (G_m, D), ``counts[m]``
+    (G_m,) int64, ``assign[m]`` (N_m,) int32; per-model scalars are the rows
+    of ``loglik``, ``inertia`` (float64) and ``dev_status`` (int32); ``gvar``
+    is (n_models, D) float64.  The descriptor array is built once; the
+    tensors never move, so batched calls on it can be captured into a graph.
+    """
+
+    def __init__(self, Xs, Gs, device="cuda"):
+        if len(Xs) != len(Gs) or not Xs:
+            raise ValueError("need one G per model and at least one model")
+        D = int(Xs[0].shape[1])
+        for X in Xs:
+            if (X.dtype != torch.float32 or X.dim() != 2 or X.shape[1] != D
+                    or not X.is_contiguous() or not X.is_cuda or X.shape[0] < 1):
+                raise ValueError("every X must be a contiguous float32 (N>=1, D) device tensor")
+        self.D = D
+        self.n_models = len(Xs)
+        self.Xs = list(Xs)
+        self.Ns = [int(X.shape[0]) for X in Xs]
+        self.Gs = [int(g) for g in Gs]
+        self.Gmax = max(self.Gs)
+        g_off = [0]
+        for g in self.Gs:
+            g_off.append(g_off[-1] + g)
+        n_off = [0]
+        for n in self.Ns:
+            n_off.append(n_off[-1] + n)
+        self.g_off, self.n_off = g_off, n_off
+        kw = dict(device=device)
+        self.hefts_flat = torch.zeros(g_off[-1], dtype=torch.float32, **kw)
+        self.means_flat = torch.zeros(g_off[-1], D, dtype=torch.float32, **kw)
+        self.covs_flat = torch.ones(g_off[-1], D, dtype=torch.float32, **kw)
+        self.counts_flat = torch.zeros(g_off[-1], dtype=torch.int64, **kw)
+        self.assign_flat = torch.zeros(n_off[-1], dtype=torch.int32, **kw)
+        self.loglik = torch.zeros(self.n_models, dtype=torch.float64, **kw)
+        self.inertia = torch.zeros(self.n_models, dtype=torch.float64, **kw)
+        self.gvar = torch.ones(self.n_models, D, dtype=torch.float64, **kw)
+        self.gmean = torch.zeros(self.n_models, D, dtype=torch.float64, **kw)
+        self.dev_status = torch.zeros(self.n_models, dtype=torch.int32, **kw)
+        sl = lambda t, m, off: t[off[m]:off[m + 1]]
+        self.hefts = [sl(self.hefts_flat, m, g_off) for m in range(self.n_models)]
+        self.means = [sl(self.means_flat, m, g_off) for m in range(self.n_models)]
+        self.covs = [sl(self.covs_flat, m, g_off) for m in range(self.n_models)]
+        self.counts = [sl(self.counts_flat, m, g_off) for m in range(self.n_models)]
+        self.assign = [sl(self.assign_flat, m, n_off) for m in range(self.n_models)]
+        arr = (_Desc * self.n_models)()
+        e64, e32 = 8, 4
+        for m in range(self.n_models):
+            d = arr[m]
+            d.X = self.Xs[m].data_ptr()
+            d.N = self.Ns[m]
+            d.G = self.Gs[m]
+            d.reserved = 0
+            d.hefts = self.hefts_flat.data_ptr() + e32 * g_off[m]
+            d.means = self.means_flat.data_ptr() + e32 * D * g_off[m]
+            d.covs = self.covs_flat.data_ptr() + e32 * D * g_off[m]
+            d.counts = self.counts_flat.data_ptr() + e64 * g_off[m]
+            d.assign = self.assign_flat.data_ptr() + e32 * n_off[m]
+            d.loglik = self.loglik.data_ptr() + e64 * m
+            d.inertia = self.inertia.data_ptr() + e64 * m
+            d.gvar = self.gvar.data_ptr() + e64 * D * m
+            d.dev_status = self.dev_status.data_ptr() + e32 * m
+        host = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
+        self.desc = host.to(device)
+        self._Ns = (_i64 * self.n_models)(*self.Ns)
+        self._Gs = (_i32 * self.n_models)(*self.Gs)
+
+    def _args(self):
+        return ctypes.c_void_p(self.desc.data_ptr()), self.n_models, self._Ns, self._Gs, self.D
+
+    def workspace(self, chunk=1024):
+        n = library().gmm_batched_workspace_bytes(self.n_models, self._Ns, self._Gs, self.D,
+                                                  int(chunk))
+        if n == 0:
+            raise GmmError("gmm_batched_workspace_bytes", GMM_EINVAL)
+        return torch.empty(int(n), dtype=torch.uint8, device=self.desc.device)
+
+    def set_params(self, m, hefts, means, covs):
+        self.hefts[m].copy_(hefts)
+        self.means[m].copy_(means)
+        self.covs[m].copy_(covs)
+
+
+def gmm_batched_workspace_bytes(batch, chunk):
+    return int(library().gmm_batched_workspace_bytes(batch.n_models, batch._Ns, batch._Gs,
+                                                     batch.D, int(chunk)))
+
+
+def gmm_em_iter_batched(batch, var_floor, prec, chunk, ws, stream=None):
+    wp, wn = _ws(ws)
+    rc = library().gmm_em_iter_batched(*batch._args(), float(var_floor), int(prec), int(chunk),
+                                       wp, wn, _stream(stream))
+    _check("gmm_em_iter_batched", rc)
+
+
+def gmm_loglik_batched(batch, prec, chunk, ws, stream=None):
+    wp, wn = _ws(ws)
+    rc = library().gmm_loglik_batched(*batch._args(), int(prec), int(chunk), wp, wn,
+                                      _stream(stream))
+    _check("gmm_loglik_batched", rc)
+
+
+def gmm_kmeans_iter_batched(batch, dist, var_floor, chunk, ws, stream=None):
+    wp, wn = _ws(ws)
+    rc = library().gmm_kmeans_iter_batched(*batch._args(), int(dist), float(var_floor),
+                                           int(chunk), wp, wn, _stream(stream))
+    _check("gmm_kmeans_iter_batched", rc)
+
+
+def gmm_global_stats_batched(batch, mean_out, var_out, stream=None):
+    shape = (batch.n_models, batch.D)
+    rc = library().gmm_global_stats_batched(
+        ctypes.c_void_p(batch.desc.data_ptr()), batch.n_models, batch.D,
+        _ptr(mean_out, torch.float64, shape, "mean_out"),
+        _ptr(var_out, torch.float64, shape, "var_out"), _stream(stream))
+    _check("gmm_global_stats_batched", rc)
+
+
+def gmm_batched_autotune(batch, prec, ws, stream=None):
+    wp, wn = _ws(ws)
+    best = _i32(0)
+    rc = library().gmm_batched_autotune(*batch._args(), int(prec), wp, wn, _stream(stream),
+                                        ctypes.byref(best))
+    _check("gmm_batched_autotune", rc)
+    return int(best.value)

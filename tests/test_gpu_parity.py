@@ -190,6 +190,35 @@ def test_em_floor_and_zero_weight(G_, oracle):
     check_em(gpu, ref, len(X))
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
+@pytest.mark.parametrize("N,D,G", [(3000, 40, 16), (2000, 100, 100), (1500, 8, 150)])
+def test_em_floored_singleton_component(G_, oracle, N, D, G, prec):
+    """A k-means hand-off can leave a one-sample cluster whose variances sit at
+    the floor: its log-density spans ~1e10 nats over the data, far beyond the
+    near window, so the screening form's rounding error must widen the window
+    for that component (and the reference of the log-sum-exp must not come
+    from its screened value)."""
+    X, _ = synth.diag_gmm(77 + D, D, 8, N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
+    w, mu, var = _params(G + D, D, G, X)
+    mu[3] = X[11]
+    var[3] = 1e-10
+    mu[5] = X[200] + 0.01
+    var[5] = 1e-8
+    w = (w / w.sum()).astype(np.float32)
+    for floor in (1e-10,):
+        gpu = gpu_em_step(G_, X, w, mu, var, floor, prec=prec)
+        assert gpu["status"] == 0
+        ref = oracle.em_iter(X, w, mu, var, floor)
+        assert ref.L[3] > 0.5  # the floored component keeps its own sample
+        check_em(gpu, ref, N)
+    ll = torch.zeros(1, dtype=torch.float64, device=DEV)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    G_.gmm_loglik(_t(X), G_.COV_DIAG, _t(w), _t(mu), _t(var), prec, ll, None, st,
+                  G_.workspace(N, D, G, G_.COV_DIAG, prec, DEV))
+    ref_ll = oracle.loglik(X, w, mu, var)
+    assert abs(ll.item() - ref_ll) <= 1e-6 * abs(ref_ll)
+
+
 def test_em_nan_sets_status(G_):
     X = np.ones((100, 3), np.float32)
     X[17, 1] = np.nan
