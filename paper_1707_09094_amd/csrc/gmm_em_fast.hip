@@ -90,7 +90,7 @@ struct Lds {
   int* ncnt;        // [T]
   int* pcount;      // [1]
   uint16_t* plist;  // [T*G]
-  float* cq;        // [2][G] c_g (hi) and Q_g = sum_d lam mu^2, for the error bounds
+  float* cq;        // [5][G] c_g (hi), Q_g = sum_d lam mu^2, c lo, cexp hi, cexp lo
   int* dmax;        // [T] max over the near set of (a - M_lo), order-mapped
 };
 
@@ -117,7 +117,7 @@ __host__ __device__ inline size_t lds_walk(int D, int G, int KS, int form, F&& a
   put(11, 1, 1);
   put(12, ((size_t)kT * G + 1) / 2, 1);
   put(13, bf ? 0 : (size_t)G * D, 1);
-  put(14, (size_t)2 * G, 1);
+  put(14, (size_t)5 * G, 1);
   put(15, kT, 1);
   return w;
 }
@@ -211,6 +211,9 @@ __device__ __forceinline__ void em_range(const FastArgs& a, int64_t i0, int64_t 
     const float Q = 2.0f * ((c + a.cc[G + g]) - (a.cexp[g] + a.cexp[G + g]));
     L.cq[g] = c;
     L.cq[G + g] = isfinite(Q) ? 1.0001f * fmaxf(Q, 0.0f) : 0.0f;
+    L.cq[2 * G + g] = a.cc[G + g];
+    L.cq[3 * G + g] = a.cexp[g];
+    L.cq[4 * G + g] = a.cexp[G + g];
   }
   const float ecoef = err_expanded_coef(KS);
   // rounding-error bound (nats) of a screening value v of component g
@@ -335,7 +338,7 @@ __device__ __forceinline__ void em_range(const FastArgs& a, int64_t i0, int64_t 
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int g = 16 * w + 4 * (lane >> 4) + j;
-            if (g < G) L.as[g * kT + n] = (acc[j] + a.cexp[g]) + a.cexp[G + g];
+            if (g < G) L.as[g * kT + n] = (acc[j] + L.cq[3 * G + g]) + L.cq[4 * G + g];
           }
         }
       }
@@ -358,8 +361,9 @@ __device__ __forceinline__ void em_range(const FastArgs& a, int64_t i0, int64_t 
             acc[q] = fmaf(u, u, acc[q]);
           }
         }
+        const float chi = L.cq[g], clo = L.cq[2 * G + g];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) L.as[g * kT + n0 + q] = (a.cc[g] - 0.5f * acc[q]) + a.cc[G + g];
+        for (int q = 0; q < 8; ++q) L.as[g * kT + n0 + q] = (chi - 0.5f * acc[q]) + clo;
       }
     }
     __syncthreads();
@@ -426,7 +430,7 @@ __device__ __forceinline__ void em_range(const FastArgs& a, int64_t i0, int64_t 
               }
             }
             q32 = group8_sum(q);
-            val = ((double)a.cc[g] + (double)a.cc[G + g]) - 0.5 * (double)q32;
+            val = ((double)L.cq[g] + (double)L.cq[2 * G + g]) - 0.5 * (double)q32;
           } else {
             // the screening value is already the direct form
             const float v = L.as[g * kT + pn];
