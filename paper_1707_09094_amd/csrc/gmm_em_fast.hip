@@ -17,14 +17,19 @@
 //                    v_mfma_f32_16x16x32_bf16 with both operands split into
 //                    BF16 hi + lo and the three products hi*hi, hi*lo, lo*hi
 //                    accumulated in FP32;
-//   3. per sample, the best FP32 value M_n and the near set {g: a_gn >= M_n - 30}.
+//   3. per sample, M_n = max_g (a_gn - e_gn), a lower bound of the exact best
+//      log-density, where e_gn bounds the rounding error of the screening value
+//      (err_direct / err_expanded: from q = 2 (c_g - a_gn) and
+//      Q_g = sum_d lam_gd mu_gd^2), and the near set {g: a_gn + e_gn >= M_n - 30}.
 //      Near (sample, component) pairs are recomputed by 8-lane groups: in FP64
 //      from the FP32 parameters when the sample has two or more near
-//      components (their relative values decide shared responsibilities), in
-//      the FP32 direct form when it has one (BF16X3 only: that value sets the
-//      sample's log-likelihood);
-//   4. log-sum-exp per sample (Eqs. 16-18) summed in FP64, responsibilities
-//      (Eq. 3); responsibilities below exp(-80) are 0;
+//      components (their relative values decide shared responsibilities), else
+//      in the FP32 direct form when its bound is below 1e-3 nats (FP64
+//      otherwise): that value sets the sample's log-likelihood.  A component
+//      with a tiny variance (a floored one-sample cluster) has a huge e_gn, so
+//      its pairs join the near set wherever its exact value could matter;
+//   4. log-sum-exp per sample (Eqs. 16-18) about M_n + max(recomputed - M_n),
+//      summed in FP64; responsibilities (Eq. 3); those below exp(-80) are 0;
 //   5. the map step of Sec. 2.1 (Eqs. 9-11) in a weighted Welford form (West's
 //      update) on the deviations y = x - mu_old from the current mean: wave w
 //      owns components g = w, w+8, ...; lane owns dimensions d = lane, lane+64
