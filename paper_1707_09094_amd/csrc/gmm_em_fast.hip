@@ -673,7 +673,7 @@ __device__ void pre_component(const float* __restrict__ hefts, const float* __re
                               float* __restrict__ prm, float* __restrict__ cc,
                               float* __restrict__ cexp, bf16x8* __restrict__ Whi,
                               bf16x8* __restrict__ Wlo, double* __restrict__ c64,
-                              double* __restrict__ lam64) {
+                              double* __restrict__ lam64, int inter) {
   __shared__ double sh[256];
   const int DP = D + 1;
   double ld = 0.0, q = 0.0;
@@ -705,17 +705,21 @@ __device__ void pre_component(const float* __restrict__ hefts, const float* __re
     cexp[g] = ehi;
     cexp[G + g] = isfinite(ce) ? (float)(ce - (double)ehi) : 0.0f;
   }
-  // fragments of A row g: A_gk = lam mu (k < D), -lam/2 (D <= k < 2D), 0 beyond
+  // MFMA fragments of component g's row: the coefficient A_gk of feature k is
+  // lam mu for the feature x_d and -lam/2 for x_d^2, 0 beyond.  Feature order:
+  // inter == 0: k = d for x_d, k = D + d for x_d^2; inter == 1: k = 2d for x_d,
+  // k = 2d + 1 for x_d^2.  The fragment of (row block, k-step ks, lane l) holds
+  // features 32 ks + 8 (l/16) + i, i = 0..7, of component 16 rb + l%16.
   const int rb = g >> 4, row = g & 15;
   for (int e = threadIdx.x; e < KS * 4 * 8; e += 256) {
     const int ks = e / 32, r = e - ks * 32, lq = r >> 3, i = r & 7;
     const int k = 32 * ks + 8 * lq + i;
+    const int d = inter ? (k >> 1) : (k < D ? k : k - D);
+    const bool sq = inter ? (k & 1) : (k >= D);
     float v = 0.0f;
-    if (k < D) {
-      const double lam = 1.0 / (double)covs[(size_t)g * D + k];
-      v = (float)(lam * (double)means[(size_t)g * D + k]);
-    } else if (k < 2 * D) {
-      v = (float)(-0.5 / (double)covs[(size_t)g * D + k - D]);
+    if (d < D && k < 2 * D) {
+      const double lam = 1.0 / (double)covs[(size_t)g * D + d];
+      v = sq ? (float)(-0.5 * lam) : (float)(lam * (double)means[(size_t)g * D + d]);
     }
     const __bf16 h = (__bf16)v;
     const __bf16 l = (__bf16)(v - (float)h);
@@ -749,13 +753,14 @@ __global__ void __launch_bounds__(256) k_pre_fast(const float* __restrict__ heft
                                                   bf16x8* __restrict__ Whi,
                                                   bf16x8* __restrict__ Wlo,
                                                   double* __restrict__ c64,
-                                                  double* __restrict__ lam64) {
-  pre_component(hefts, means, covs, D, G, KS, blockIdx.x, prm, cc, cexp, Whi, Wlo, c64, lam64);
+                                                  double* __restrict__ lam64, int inter) {
+  pre_component(hefts, means, covs, D, G, KS, blockIdx.x, prm, cc, cexp, Whi, Wlo, c64, lam64,
+                inter);
 }
 
 // grid (16 * RBmax, n_models): component g of model blockIdx.y.
 __global__ void __launch_bounds__(256) k_pre_fast_batched(const gmm_model_desc* models, int D,
-                                                          BatchConst bc) {
+                                                          BatchConst bc, int inter) {
   const int mi = blockIdx.y;
   const gmm_model_desc& m = models[mi];
   if (!batch_desc_ok(m, bc.Gmax)) return;
@@ -769,7 +774,7 @@ __global__ void __launch_bounds__(256) k_pre_fast_batched(const gmm_model_desc* 
   }
   pre_component(m.hefts, m.means, m.covs, D, G, bc.KS, g, bc.prm + (size_t)mi * 2 * bc.Gmax * (D + 1),
                 bc.cc + (size_t)mi * 2 * bc.Gmax, bc.cexp + (size_t)mi * 2 * bc.Gmax, Whi, Wlo,
-                bc.c64 + (size_t)mi * bc.Gmax, bc.lam64 + (size_t)mi * bc.Gmax * D);
+                bc.c64 + (size_t)mi * bc.Gmax, bc.lam64 + (size_t)mi * bc.Gmax * D, inter);
 }
 
 // Rows of the last row block past G get zero weights.
@@ -919,6 +924,648 @@ __global__ void __launch_bounds__(256) k_fin_welford_batched(const gmm_model_des
   if (threadIdx.x == 0 && bad) atomicOr(m.dev_status, GMM_DEV_NONFINITE);
 }
 
+// ---- sample-major BF16X3 kernel ----------------------------------------------
+//
+// Each wave owns groups of 16 consecutive samples and runs their E-step in
+// registers.  The MFMA A operand holds the samples' features, interleaved as
+// [x_d, x_d^2] and split into BF16 hi + lo; the B operand holds the
+// components' coefficients [lam mu, -lam/2] (hi + lo, staged in LDS once per
+// work range).  Output lane l, register j is (sample 4 (l/16) + j, component
+// 16 cb + l%16), so every per-sample reduction (bounded maximum, near count,
+// log-sum-exp) is a butterfly over the 16 lanes of a lane row.  Near pairs are
+// recomputed exactly (FP64, or the FP32 direct form under its bound) by
+// 4-lane groups reading the sample and parameters from global memory.  The
+// map step of component g is done by wave g % 8 (its "owner"), which keeps
+// (L, m, Q) of its components in registers; every 128 samples the waves pass
+// their non-zero responsibilities to the owners through LDS lists, in a fixed
+// order, with two barriers per 128 samples.
+
+constexpr int kGS = 16;             // samples per wave group
+constexpr int kRoundN = kNW * kGS;  // samples per block round
+constexpr int kCapM = 32;           // pairs per (source, owner) list per pass
+constexpr int kCapR = 64;           // near pairs recomputed per chunk per wave
+
+struct Lds2 {
+  bf16x8* wh;    // [RB][KS][64] B fragments (hi)
+  bf16x8* wl;    // lo
+  float* cq;     // [G][8]: c hi, Q, c lo, cexp hi, cexp lo, -, -, -
+  float* mw;     // [NW][16] per-sample bounded maximum
+  int* cw;       // [NW][16] per-sample near count
+  int* rcode;    // [NW][kCapR] near pair: sample | component << 8
+  float* rval;   // [NW][kCapR] exact value - maximum bound
+  int2* sub;     // [NW source][NW owner][kCapM] (sample | component << 8, r)
+  int* subn;     // [NW source][NW owner] pairs of the round
+  int* need;     // [2] largest list of the round
+  double* llw;   // [NW]
+  int2* osort;   // [NW][64] an owner's pairs ordered by component slot
+};
+
+template <typename F>
+__host__ __device__ inline size_t lds2_walk(int G, int KS, F&& at) {
+  size_t w = 0;
+  auto put = [&](int which, size_t words, size_t align_words) {
+    w = (w + align_words - 1) / align_words * align_words;
+    at(which, w);
+    w += words;
+  };
+  const size_t RB = ((size_t)G + 15) / 16;
+  put(0, RB * KS * 64 * 4, 4);
+  put(1, RB * KS * 64 * 4, 4);
+  put(2, 8 * 16 * RB, 4);  // padded to whole row blocks
+  put(3, kNW * 16, 1);
+  put(4, kNW * 16, 1);
+  put(5, kNW * kCapR, 1);
+  put(6, kNW * kCapR, 1);
+  put(7, (size_t)kNW * kNW * kCapM * 2, 2);
+  put(8, kNW * kNW, 1);
+  put(9, 2, 1);
+  put(10, 2 * kNW, 2);
+  put(11, kNW * 64 * 2, 2);
+  return w;
+}
+
+__host__ __device__ inline size_t em2_lds_bytes(int G, int KS) {
+  return lds2_walk(G, KS, [](int, size_t) {}) * 4 + 64;
+}
+
+// k-steps of the sample-major fragment layout (compile-time in the kernel)
+__host__ __device__ inline int em2_ks(int D) { return D <= 64 ? 4 : 8; }
+
+__device__ inline Lds2 carve_lds2(char* base, int G, int KS) {
+  Lds2 L;
+  float* f = (float*)base;
+  lds2_walk(G, KS, [&](int which, size_t off) {
+    switch (which) {
+      case 0: L.wh = (bf16x8*)(f + off); break;
+      case 1: L.wl = (bf16x8*)(f + off); break;
+      case 2: L.cq = f + off; break;
+      case 3: L.mw = f + off; break;
+      case 4: L.cw = (int*)(f + off); break;
+      case 5: L.rcode = (int*)(f + off); break;
+      case 6: L.rval = f + off; break;
+      case 7: L.sub = (int2*)(f + off); break;
+      case 8: L.subn = (int*)(f + off); break;
+      case 9: L.need = (int*)(f + off); break;
+      case 10: L.llw = (double*)(f + off); break;
+      default: L.osort = (int2*)(f + off); break;
+    }
+  });
+  return L;
+}
+
+// Butterflies over the 16 lanes of a row by DPP row rotations (no address
+// registers): after rotations by 1, 2, 4 and 8 every lane holds the reduction
+// of all 16.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float row16_max(float v) {
+  v = fmaxf(v, dpp_f<0x121>(v));
+  v = fmaxf(v, dpp_f<0x122>(v));
+  v = fmaxf(v, dpp_f<0x124>(v));
+  v = fmaxf(v, dpp_f<0x128>(v));
+  return v;
+}
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_d<0x121>(v);
+  v += dpp_d<0x122>(v);
+  v += dpp_d<0x124>(v);
+  v += dpp_d<0x128>(v);
+  return v;
+}
+// quad (4-lane) sums by DPP quad permutations
+__device__ __forceinline__ float quad_sum(float v) {
+  v += dpp_f<0xB1>(v);  // quad_perm [1,0,3,2]
+  v += dpp_f<0x4E>(v);  // quad_perm [2,3,0,1]
+  return v;
+}
+__device__ __forceinline__ double quad_sum_d(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  return v;
+}
+
+// Orders this wave's LDS accesses across lanes (the LDS executes one wave's
+// operations in issue order; this keeps the compiler from reordering them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Fragments are laid out for KST = 4 DPL k-steps (16 dimensions each, zero
+// past D), so every LDS offset below is a compile-time immediate.
+template <int CPW, int DPL, bool MSTEP>
+__device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t i1, int b,
+                                          char* lds_raw) {
+  constexpr int RBT = (CPW + 1) / 2;  // row blocks of 16 components
+  constexpr int KST = 4 * DPL;        // k-steps of 16 dimensions
+  const int D = a.D, G = a.G;
+  const int DP = D + 1;
+  const int P = 2 * D + 1;
+  const int RB = (G + 15) / 16;
+  const Lds2 L = carve_lds2(lds_raw, G, KST);
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int w = tid / kWave;
+  const int KSr = (2 * D + 31) / 32;  // k-steps holding data
+  const float ecoef = err_expanded_coef(KSr);
+
+  for (int p = tid; p < RB * KST * 64; p += kThreads) {
+    L.wh[p] = a.Whi[p];
+    L.wl[p] = a.Wlo[p];
+  }
+  for (int g = tid; g < 16 * RB; g += kThreads) {
+    float* q = L.cq + 8 * g;
+    if (g < G) {
+      const float c = a.cc[g];
+      const float Q = 2.0f * ((c + a.cc[G + g]) - (a.cexp[g] + a.cexp[G + g]));
+      q[0] = c;
+      q[1] = isfinite(Q) ? 1.0001f * fmaxf(Q, 0.0f) : 0.0f;
+      q[2] = a.cc[G + g];
+      q[3] = a.cexp[g];
+      q[4] = a.cexp[G + g];
+    } else {  // padding component: value -inf
+      q[0] = 0.0f;
+      q[1] = 0.0f;
+      q[2] = 0.0f;
+      q[3] = -INFINITY;
+      q[4] = 0.0f;
+    }
+  }
+  if (tid < 2) L.need[tid] = 0;
+
+  // owner accumulators: component g = w + 8 c, dimension d = lane + 64 j
+  float Lc[CPW], S1[CPW][DPL], S2[CPW][DPL];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    Lc[c] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+      S1[c][j] = 0.0f;
+      S2[c][j] = 0.0f;
+    }
+  }
+  double llacc = 0.0;
+  int bad = 0;
+  long long nrec = 0;
+  __syncthreads();
+
+  const int rowq = lane >> 4;  // output rows: samples 4 rowq + j
+  const int colc = lane & 15;  // output column: component 16 cb + colc
+  const int kg = lane >> 4;    // A operand: dimensions 16 ks + 4 kg + 0..3
+  const int na = lane & 15;    // A operand: sample na
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const unsigned long long cls = 0x0101010101010101ull << (lane & 7);
+  float* const mw = L.mw + w * 16;
+  int* const cw = L.cw + w * 16;
+  int* const rcode = L.rcode + w * kCapR;
+  float* const rval = L.rval + w * kCapR;
+  const bf16x8* const whl = L.wh + lane;
+  const bf16x8* const wll = L.wl + lane;
+  const float* const cql = L.cq + 8 * colc;
+
+  int round = 0;
+  for (int64_t base = i0; base < i1; base += kRoundN, ++round) {
+    const int64_t s0 = base + (int64_t)kGS * w;
+
+    // 1-2. screening on the matrix cores.  A fragments: the group's samples,
+    // features [x_d, x_d^2] interleaved, split into BF16 hi + lo; each block
+    // of 16 components accumulates in FP32 and lands in the scalar array
+    // acc[cb][j] (sample 4 rowq + j, component 16 cb + colc).
+    float acc[RBT][4];
+    {
+      bf16x8 ah[KST], al[KST];
+      const int64_t ia = s0 + na;
+      const bool va = ia < i1;
+      const float* xr = a.X + (va ? ia : i0) * a.ldx + 4 * kg;
+      int dl = D - 4 * kg;  // this lane's dimensions are 16 ks + q < dl
+      // opaque per round, so the bound tests are not hoisted out of the round
+      // loop (they would stay live in registers for the whole kernel)
+      asm volatile("" : "+v"(dl));
+#pragma unroll
+      for (int ks = 0; ks < KST; ++ks) {
+        float xv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xv[q] = (va && 16 * ks + q < dl) ? xr[16 * ks + q] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float x = xv[i >> 1];
+          const float v = (i & 1) ? x * x : x;
+          const __bf16 h = (__bf16)v;
+          ah[ks][i] = h;
+          al[ks][i] = (__bf16)(v - (float)h);
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < RBT; ++cb) {
+        f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (cb < RB) {
+#pragma unroll
+          for (int ks = 0; ks < KST; ++ks) {
+            const bf16x8 bh = whl[(cb * KST + ks) * 64];
+            const bf16x8 bl = wll[(cb * KST + ks) * 64];
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[ks], bh, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ks], bl, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ks], bh, c, 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[cb][j] = c[j];
+      }
+    }
+
+    // 3. values, their error bounds, per-sample bounded maximum M and near set
+    bool vj[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) vj[j] = s0 + 4 * rowq + j < i1;
+    float M[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+    for (int cb = 0; cb < RBT; ++cb) {
+      const float* q = cql + 8 * 16 * cb;
+      const bool vg = cb < RB;
+      const float ch = vg ? q[0] : 0.0f, Qg = vg ? q[1] : 0.0f;
+      const float eh = vg ? q[3] : -INFINITY, el = vg ? q[4] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float v = vj[j] ? (acc[cb][j] + eh) + el : -INFINITY;
+        acc[cb][j] = v;
+        M[j] = fmaxf(M[j], v - err_expanded(2.0f * (ch - v), Qg, ch, ecoef));
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) M[j] = row16_max(M[j]);
+    uint32_t nearb = 0;  // bit 4 cb + j
+#pragma unroll
+    for (int cb = 0; cb < RBT; ++cb) {
+      const float* q = cql + 8 * 16 * cb;
+      const bool vg = cb < RB;
+      const float ch = vg ? q[0] : 0.0f, Qg = vg ? q[1] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float v = acc[cb][j];
+        if (v > -INFINITY && v + err_expanded(2.0f * (ch - v), Qg, ch, ecoef) >= M[j] - kNearGap)
+          nearb |= 1u << (4 * cb + j);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    int cnt[4] = {0, 0, 0, 0};
+    int np = 0;
+#pragma unroll
+    for (int cb = 0; cb < RBT; ++cb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const unsigned long long m = __ballot((nearb >> (4 * cb + j)) & 1u);
+        cnt[j] += __popcll((m >> (16 * rowq)) & 0xFFFFull);
+        np += __popcll(m);
+      }
+    if (colc == 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        mw[4 * rowq + j] = M[j];
+        cw[4 * rowq + j] = cnt[j];
+      }
+    }
+    nrec += np;
+
+    // 4. exact values of the near pairs, kCapR at a time
+    for (int c0 = 0; c0 < np; c0 += kCapR) {
+      int pos = 0;
+#pragma unroll
+      for (int cb = 0; cb < RBT; ++cb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bool nr = (nearb >> (4 * cb + j)) & 1u;
+          const unsigned long long m = __ballot(nr);
+          if (nr) {
+            const int p = pos + __popcll(m & lt);
+            if (p >= c0 && p < c0 + kCapR) rcode[p - c0] = (4 * rowq + j) | ((16 * cb + colc) << 8);
+          }
+          pos += __popcll(m);
+        }
+      wave_lds_sync();
+      {
+        // one pair per 16-lane row; lane l16 of the row takes dimensions
+        // l16 + 16 i, and every load of the pair is issued before any use
+        constexpr int NE = 4 * DPL;  // dimensions per lane (D <= 64 NE)
+        const int rid = lane >> 4, l16 = lane & 15;
+        const int nc = min(kCapR, np - c0);
+        for (int p = rid; p < nc; p += 4) {
+          const int code = rcode[p];
+          const int n = code & 15, g = code >> 8;
+          const float* xr = a.X + (s0 + n) * a.ldx;
+          const float Mn = mw[n];
+          bool ex64 = cw[n] >= 2;
+          float xv[NE];
+#pragma unroll
+          for (int i = 0; i < NE; ++i) xv[i] = xr[min(l16 + 16 * i, D - 1)];
+          double val = 0.0;
+          if (!ex64) {
+            const float* sg = a.prm + (size_t)g * DP;
+            const float* mg = a.prm + (size_t)G * DP + (size_t)g * DP;
+            float sv[NE], mv[NE];
+#pragma unroll
+            for (int i = 0; i < NE; ++i) {
+              const int dc = min(l16 + 16 * i, D - 1);
+              sv[i] = sg[dc];
+              mv[i] = mg[dc];
+            }
+            float q = 0.0f;
+#pragma unroll
+            for (int i = 0; i < NE; ++i) {
+              const float u = fmaf(xv[i], sv[i], -mv[i]);
+              q = l16 + 16 * i < D ? fmaf(u, u, q) : q;
+            }
+            q = (float)row16_sum((double)q);
+            const float* qg = L.cq + 8 * g;
+            val = ((double)qg[0] + (double)qg[2]) - 0.5 * (double)q;
+            ex64 = !(err_direct(q, qg[1], qg[0], D) <= kExactTol);
+          }
+          if (ex64) {
+            const float* mu_g = a.means + (size_t)g * D;
+            const double* lg = a.lam64 + (size_t)g * D;
+            float mv[NE];
+            double lv[NE];
+#pragma unroll
+            for (int i = 0; i < NE; ++i) {
+              const int dc = min(l16 + 16 * i, D - 1);
+              mv[i] = mu_g[dc];
+              lv[i] = lg[dc];
+            }
+            double q = 0.0;
+#pragma unroll
+            for (int i = 0; i < NE; ++i) {
+              const double u = (double)xv[i] - (double)mv[i];
+              q = l16 + 16 * i < D ? q + u * u * lv[i] : q;
+            }
+            q = row16_sum(q);
+            val = a.c64[g] - 0.5 * q;
+          }
+          if (l16 == 0) rval[p] = (float)(val - (double)Mn);
+        }
+      }
+      wave_lds_sync();
+      pos = 0;
+#pragma unroll
+      for (int cb = 0; cb < RBT; ++cb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bool nr = (nearb >> (4 * cb + j)) & 1u;
+          const unsigned long long m = __ballot(nr);
+          if (nr) {
+            const int p = pos + __popcll(m & lt);
+            if (p >= c0 && p < c0 + kCapR) acc[cb][j] = rval[p - c0];
+          }
+          pos += __popcll(m);
+        }
+      wave_lds_sync();
+    }
+
+    // 5. log-sum-exp about M + max(near - M) (Eqs. 16-18) and responsibilities
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float dm = -INFINITY;
+#pragma unroll
+      for (int cb = 0; cb < RBT; ++cb)
+        if ((nearb >> (4 * cb + j)) & 1u) dm = fmaxf(dm, acc[cb][j]);
+      dm = row16_max(dm);
+      const float dn = dm > -INFINITY ? dm : 0.0f;
+      double sm = 0.0;
+#pragma unroll
+      for (int cb = 0; cb < RBT; ++cb) {
+        const bool nr = (nearb >> (4 * cb + j)) & 1u;
+        const float t = nr ? acc[cb][j] - dn : (acc[cb][j] - M[j]) - dn;
+        sm += (double)__expf(t);
+      }
+      sm = row16_sum(sm);
+      const float ls = __logf((float)sm);
+      const double lse = ((double)M[j] + (double)dn) + (double)ls;
+      if (vj[j] && colc == 0) {
+        llacc += lse;
+        if (!isfinite(lse)) bad = 1;
+        if (a.per_sample) a.per_sample[s0 + 4 * rowq + j] = (float)lse;
+      }
+      if (MSTEP) {
+#pragma unroll
+        for (int cb = 0; cb < RBT; ++cb) {
+          const bool nr = (nearb >> (4 * cb + j)) & 1u;
+          const float z = (nr ? acc[cb][j] - dn : (acc[cb][j] - M[j]) - dn) - ls;
+          acc[cb][j] = (vj[j] && z >= -kRespCut) ? __expf(z) : 0.0f;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+
+    if (MSTEP) {
+      // 6. hand the non-zero responsibilities to their owners (the owner of
+      // component 16 cb + colc is wave colc % 8 = lane % 8)
+      int mine = 0;
+#pragma unroll
+      for (int cb = 0; cb < RBT; ++cb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mine += __popcll(__ballot(acc[cb][j] != 0.0f) & cls);
+      if (lane < kNW) L.subn[w * kNW + lane] = mine;
+      int mx = mine;
+      mx = max(mx, __builtin_amdgcn_update_dpp(0, mx, 0xB1, 0xF, 0xF, false));
+      mx = max(mx, __builtin_amdgcn_update_dpp(0, mx, 0x4E, 0xF, 0xF, false));
+      mx = max(mx, __builtin_amdgcn_update_dpp(0, mx, 0x124, 0xF, 0xF, false));  // row_ror:4
+      if (lane == 0) atomicMax(&L.need[round & 1], mx);
+      __syncthreads();
+      const int need = L.need[round & 1];
+      if (tid == 0) L.need[(round + 1) & 1] = 0;
+      for (int pass = 0; pass * kCapM < need; ++pass) {
+        int pos = 0;
+        int2* const dst = L.sub + (size_t)(w * kNW + (lane & 7)) * kCapM;
+#pragma unroll
+        for (int cb = 0; cb < RBT; ++cb)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float r = acc[cb][j];
+            const unsigned long long m = __ballot(r != 0.0f) & cls;
+            if (r != 0.0f) {
+              const int p = pos + __popcll(m & lt) - pass * kCapM;
+              if (p >= 0 && p < kCapM)
+                dst[p] = make_int2((4 * rowq + j) | ((16 * cb + colc) << 8), __float_as_int(r));
+            }
+            pos += __popcll(m);
+          }
+        __syncthreads();
+        // owner w: the map step (Eqs. 9-11) in West's weighted Welford form on
+        // y = x - mu_old, lists taken in source-wave order
+        int pre[kNW + 1];
+        pre[0] = 0;
+#pragma unroll
+        for (int src = 0; src < kNW; ++src)
+          pre[src + 1] = pre[src] + max(0, min(kCapM, L.subn[src * kNW + w] - pass * kCapM));
+        const int tot = pre[kNW];
+        int2* const os = L.osort + w * 64;
+        for (int k0 = 0; k0 < tot; k0 += 64) {
+          // stable partition of up to 64 of this owner's pairs by component
+          // slot c = g / 8 (source order kept within a slot)
+          const int k = k0 + lane;
+          const bool ok = k < tot;
+          int src = 0;
+#pragma unroll
+          for (int t = 1; t < kNW; ++t) src = k >= pre[t] ? t : src;
+          const int2 e = ok ? L.sub[(size_t)(src * kNW + w) * kCapM + (k - pre[src])]
+                            : make_int2(0, 0);
+          const int cs = ok ? (e.x >> 11) : -1;
+          int cnt[CPW];
+          int off = 0, mypos = 0;
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) {
+            const unsigned long long m = __ballot(cs == c);
+            if (cs == c) mypos = off + __popcll(m & lt);
+            cnt[c] = __popcll(m);
+            off += cnt[c];
+          }
+          // row of the sample within the round | component << 8
+          if (ok) os[mypos] = make_int2((kGS * src + (e.x & 15)) | (e.x & ~0xFF), e.y);
+          wave_lds_sync();
+          // the map step (Eqs. 9-11) in West's weighted Welford form on
+          // y = x - mu_old, slot by slot, pairs in the order above
+          int o = 0;
+          // opaque per chunk, so the per-slot row addresses below are not
+          // hoisted out of the round loop
+          int wo = w;
+          asm volatile("" : "+v"(wo));
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) {
+            const int cc = cnt[c];
+            if (cc > 0) {
+              const int g = wo + kNW * c;
+              float mu[DPL];
+#pragma unroll
+              for (int jd = 0; jd < DPL; ++jd)
+                mu[jd] = a.means[(size_t)g * D + min(lane + kWave * jd, D - 1)];
+              for (int q0 = 0; q0 < cc; q0 += 4) {
+                float rq[4], y[4][DPL];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  const int2 e2 = os[o + min(q0 + i, cc - 1)];
+                  rq[i] = q0 + i < cc ? __int_as_float(e2.y) : 0.0f;
+                  const float* xr = a.X + (base + (e2.x & 0xFF)) * a.ldx;
+#pragma unroll
+                  for (int jd = 0; jd < DPL; ++jd)
+                    y[i][jd] = xr[min(lane + kWave * jd, D - 1)] - mu[jd];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  const float r = rq[i];
+                  if (r != 0.0f) {
+                    const float Lo = Lc[c];
+                    const float Ln = Lo + r;
+                    const float inv = r * __builtin_amdgcn_rcpf(Ln);
+                    const float w2 = inv * Lo;
+                    Lc[c] = Ln;
+#pragma unroll
+                    for (int jd = 0; jd < DPL; ++jd) {
+                      const float dl = y[i][jd] - S1[c][jd];
+                      // the first sample sets the mean exactly (Lo = 0: inv = 1)
+                      S1[c][jd] = Lo == 0.0f ? y[i][jd] : fmaf(inv, dl, S1[c][jd]);
+                      S2[c][jd] = fmaf(w2 * dl, dl, S2[c][jd]);
+                    }
+                  }
+                }
+              }
+              o += cc;
+            }
+          }
+          wave_lds_sync();
+        }
+        __syncthreads();
+      }
+      if (need == 0) __syncthreads();
+    }
+  }
+
+  if (MSTEP) {
+    double* pb = a.part + (size_t)b * G * P;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int g = w + kNW * c;
+      if (g < G) {
+        if (lane == 0) pb[(size_t)g * P] = (double)Lc[c];
+#pragma unroll
+        for (int jd = 0; jd < DPL; ++jd) {
+          const int d = lane + kWave * jd;
+          if (d < D) {
+            pb[(size_t)g * P + 1 + d] = (double)S1[c][jd];
+            pb[(size_t)g * P + 1 + D + d] = (double)S2[c][jd];
+          }
+        }
+      }
+    }
+  }
+  {
+    const double v = wave_sum_d(llacc);
+    if (lane == 0) L.llw[w] = v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kNW; ++q) s += L.llw[q];
+    a.ll_part[b] = s;
+  }
+  if (bad) atomicOr(a.dev_status, GMM_DEV_NONFINITE);
+  if (a.n_rec && lane == 0 && nrec) atomicAdd((unsigned long long*)a.n_rec, (unsigned long long)nrec);
+}
+
+template <int CPW, int DPL, bool MSTEP>
+__global__ void __launch_bounds__(kThreads) k_em2(FastArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const int b = blockIdx.x;
+  const int64_t i0 = (int64_t)b * a.chunk;
+  const int64_t i1 = min(a.N, i0 + a.chunk);
+  em2_range<CPW, DPL, MSTEP>(a, i0, i1, b, lds_raw);
+}
+
+template <int CPW, int DPL, bool MSTEP>
+__global__ void __launch_bounds__(kThreads) k_em2_batched(FastArgs base,
+                                                          const gmm_model_desc* models,
+                                                          const BatchItemDev* items,
+                                                          const int* n_items, BatchConst bc) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const int ni = *n_items;
+  const int D = base.D;
+  const int P = 2 * D + 1;
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    const BatchItemDev item = items[it];
+    const gmm_model_desc& m = models[item.model];
+    FastArgs a = base;
+    const size_t mi = (size_t)item.model;
+    a.X = m.X;
+    a.N = m.N;
+    a.ldx = D;
+    a.G = m.G;
+    a.prm = bc.prm + mi * 2 * bc.Gmax * (D + 1);
+    a.cc = bc.cc + mi * 2 * bc.Gmax;
+    a.cexp = bc.cexp + mi * 2 * bc.Gmax;
+    a.Whi = bc.Whi + mi * bc.RBmax * bc.KS * 64;
+    a.Wlo = bc.Wlo + mi * bc.RBmax * bc.KS * 64;
+    a.c64 = bc.c64 + mi * bc.Gmax;
+    a.lam64 = bc.lam64 + mi * bc.Gmax * D;
+    a.means = m.means;
+    a.part = base.part + (size_t)it * bc.Gmax * P;
+    a.ll_part = base.ll_part + it;
+    a.per_sample = nullptr;
+    a.dev_status = m.dev_status;
+    a.n_rec = nullptr;
+    em2_range<CPW, DPL, MSTEP>(a, item.i0, item.i1, 0, lds_raw);
+    __syncthreads();
+  }
+}
+
 template <int FORM, int CPW, int DPL, bool MSTEP>
 void launch_one(const FastArgs& a, int nb, size_t lds, hipStream_t st) {
   auto kern = k_em_fast<FORM, CPW, DPL, MSTEP>;
@@ -952,11 +1599,42 @@ void dispatch_cpw(const FastArgs& a, int nb, size_t lds, hipStream_t st) {
   }
 }
 
+template <int CPW, int DPL, bool MSTEP>
+void launch_em2_one(const FastArgs& a, int nb, size_t lds, hipStream_t st) {
+  auto kern = k_em2<CPW, DPL, MSTEP>;
+  static bool attr_set = false;  // benign race: setting the attribute twice is harmless
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), lds, st, a);
+}
+
+template <bool MSTEP>
+void dispatch_em2(const FastArgs& a, int nb, size_t lds, hipStream_t st) {
+  const int cpw = (a.G + kNW - 1) / kNW;
+  if (a.D <= 64) {
+    if (cpw <= 2) launch_em2_one<2, 1, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 4) launch_em2_one<4, 1, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 8) launch_em2_one<8, 1, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 13) launch_em2_one<13, 1, MSTEP>(a, nb, lds, st);
+    else launch_em2_one<16, 1, MSTEP>(a, nb, lds, st);
+  } else {
+    if (cpw <= 2) launch_em2_one<2, 2, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 4) launch_em2_one<4, 2, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 8) launch_em2_one<8, 2, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 13) launch_em2_one<13, 2, MSTEP>(a, nb, lds, st);
+    else launch_em2_one<16, 2, MSTEP>(a, nb, lds, st);
+  }
+}
+
 }  // namespace
 
 bool em_fast_supported(int D, int G, int prec) {
   if (D < 1 || D > 128 || G < 1 || G > 128) return false;
   const int KS = (2 * D + 31) / 32;
+  if (prec == GMM_PREC_BF16X3) return em2_lds_bytes(G, em2_ks(D)) <= 160 * 1024;
   return fast_lds_bytes(D, G, KS, prec) <= 160 * 1024;
 }
 
@@ -994,20 +1672,28 @@ hipError_t launch_em_fast(const float* X, int64_t N, int D, int64_t ldx, int G, 
   a.per_sample = per_sample;
   a.dev_status = dev_status;
   a.n_rec = n_recomputed;
-  hipLaunchKernelGGL(k_pre_fast, dim3(G), dim3(256), 0, st, hefts, means, covs, D, G, KS, w.prm,
-                     w.c, w.cexp, (bf16x8*)w.Bhi, (bf16x8*)w.Blo, w.c64, w.lamg64);
+  const int inter = prec == GMM_PREC_BF16X3 ? 1 : 0;
+  const int KSl = inter ? em2_ks(D) : KS;  // fragment layout depth
+  hipLaunchKernelGGL(k_pre_fast, dim3(G), dim3(256), 0, st, hefts, means, covs, D, G, KSl, w.prm,
+                     w.c, w.cexp, (bf16x8*)w.Bhi, (bf16x8*)w.Blo, w.c64, w.lamg64, inter);
   if (G % 16) hipLaunchKernelGGL(k_zero_pad_rows, dim3(1), dim3(256), 0, st, (bf16x8*)w.Bhi,
-                                 (bf16x8*)w.Blo, G, KS);
-  const size_t lds = fast_lds_bytes(D, G, KS, prec);
+                                 (bf16x8*)w.Blo, G, KSl);
   {
     ProfScope ps(mstep ? kProfEM : kProfLoglik, st);
     if (prec == GMM_PREC_BF16X3) {
-      if (mstep) dispatch_cpw<GMM_PREC_BF16X3, true>(a, nb, lds, st);
-      else dispatch_cpw<GMM_PREC_BF16X3, false>(a, nb, lds, st);
-    } else {
-      if (mstep) dispatch_cpw<GMM_PREC_FP32, true>(a, nb, lds, st);
-      else dispatch_cpw<GMM_PREC_FP32, false>(a, nb, lds, st);
+      // sample-major kernel: work ranges in whole 128-sample rounds
+      const int64_t ch = ((N + nb - 1) / nb + kRoundN - 1) / kRoundN * kRoundN;
+      a.chunk = ch;
+      const int nb2 = (int)((N + ch - 1) / ch);
+      const size_t lds = em2_lds_bytes(G, KSl);
+      if (mstep) dispatch_em2<true>(a, nb2, lds, st);
+      else dispatch_em2<false>(a, nb2, lds, st);
+      *nb_out = nb2;
+      return hipGetLastError();
     }
+    const size_t lds = fast_lds_bytes(D, G, KS, prec);
+    if (mstep) dispatch_cpw<GMM_PREC_FP32, true>(a, nb, lds, st);
+    else dispatch_cpw<GMM_PREC_FP32, false>(a, nb, lds, st);
   }
   *nb_out = nb;
   return hipGetLastError();
@@ -1035,6 +1721,39 @@ void launch_batched_one(const FastArgs& base, const gmm_model_desc* models, cons
   }
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, st, base, models, bw.items,
                      bw.n_items, bc);
+}
+
+template <bool MSTEP, int CPW, int DPL>
+void launch_em2_batched_one(const FastArgs& base, const gmm_model_desc* models,
+                            const BatchWorkspace& bw, const BatchConst& bc, int grid, size_t lds,
+                            hipStream_t st) {
+  auto kern = k_em2_batched<CPW, DPL, MSTEP>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, st, base, models, bw.items,
+                     bw.n_items, bc);
+}
+
+template <bool MSTEP>
+void dispatch_em2_batched(const FastArgs& base, const gmm_model_desc* models,
+                          const BatchWorkspace& bw, const BatchConst& bc, int grid, size_t lds,
+                          hipStream_t st) {
+  const int cpw = (bw.Gmax + kNW - 1) / kNW;
+  if (bw.D <= 64) {
+    if (cpw <= 2) launch_em2_batched_one<MSTEP, 2, 1>(base, models, bw, bc, grid, lds, st);
+    else if (cpw <= 4) launch_em2_batched_one<MSTEP, 4, 1>(base, models, bw, bc, grid, lds, st);
+    else if (cpw <= 8) launch_em2_batched_one<MSTEP, 8, 1>(base, models, bw, bc, grid, lds, st);
+    else launch_em2_batched_one<MSTEP, 16, 1>(base, models, bw, bc, grid, lds, st);
+  } else {
+    if (cpw <= 2) launch_em2_batched_one<MSTEP, 2, 2>(base, models, bw, bc, grid, lds, st);
+    else if (cpw <= 4) launch_em2_batched_one<MSTEP, 4, 2>(base, models, bw, bc, grid, lds, st);
+    else if (cpw <= 8) launch_em2_batched_one<MSTEP, 8, 2>(base, models, bw, bc, grid, lds, st);
+    else launch_em2_batched_one<MSTEP, 16, 2>(base, models, bw, bc, grid, lds, st);
+  }
 }
 
 template <int FORM, bool MSTEP>
@@ -1080,14 +1799,15 @@ hipError_t launch_em_batched(const gmm_model_desc* models, int n_models, int n_i
   base.part = bw.partials;
   base.ll_part = bw.sparts;
   hipLaunchKernelGGL(k_pre_fast_batched, dim3(16 * bw.RBmax, n_models), dim3(256), 0, st, models,
-                     D, bc);
-  const size_t lds = fast_lds_bytes(D, bw.Gmax, bw.KS, prec);
+                     D, bc, prec == GMM_PREC_BF16X3 ? 1 : 0);
+  const size_t lds = prec == GMM_PREC_BF16X3 ? em2_lds_bytes(bw.Gmax, em2_ks(D))
+                                             : fast_lds_bytes(D, bw.Gmax, bw.KS, prec);
   const int grid = n_items_host < 256 ? (n_items_host < 1 ? 1 : n_items_host) : 256;
   {
     ProfScope ps(kProfBatched, st);
     if (prec == GMM_PREC_BF16X3) {
-      if (mstep) dispatch_batched<GMM_PREC_BF16X3, true>(base, models, bw, bc, grid, lds, st);
-      else dispatch_batched<GMM_PREC_BF16X3, false>(base, models, bw, bc, grid, lds, st);
+      if (mstep) dispatch_em2_batched<true>(base, models, bw, bc, grid, lds, st);
+      else dispatch_em2_batched<false>(base, models, bw, bc, grid, lds, st);
     } else {
       if (mstep) dispatch_batched<GMM_PREC_FP32, true>(base, models, bw, bc, grid, lds, st);
       else dispatch_batched<GMM_PREC_FP32, false>(base, models, bw, bc, grid, lds, st);

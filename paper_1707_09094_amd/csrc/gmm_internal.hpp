@@ -94,7 +94,9 @@ struct Workspace {
   size_t bytes;
 };
 
-inline int kexp_K(int D) { return ((2 * D + 31) / 32) * 32; }  // expanded-form depth, padded
+// expanded-form depth (features) of the MFMA fragments: 128 or 256 for the
+// one-pass kernels (D <= 64 / D <= 128), padded to 32 beyond
+inline int kexp_K(int D) { return D <= 64 ? 128 : (D <= 128 ? 256 : ((2 * D + 31) / 32) * 32); }
 
 inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Workspace* w) {
   size_t off = 0;
@@ -200,7 +202,7 @@ inline bool carve_batched(void* base, size_t avail, int n_models, int D, int Gma
   };
   const size_t M = (size_t)n_models;
   const int RBmax = (Gmax + 15) / 16;
-  const int KS = (2 * D + 31) / 32;
+  const int KS = D <= 64 ? 4 : ((2 * D + 31) / 32 <= 8 ? 8 : (2 * D + 31) / 32);
   const size_t o_it = take(sizeof(BatchItemDev) * (size_t)cap);
   const size_t o_mi = take(sizeof(int2) * M);
   const size_t o_ni = take(sizeof(int) * 4);
