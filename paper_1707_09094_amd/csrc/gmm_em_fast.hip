@@ -1053,6 +1053,31 @@ __device__ __forceinline__ double quad_sum_d(double v) {
   return v;
 }
 
+// Exclusive prefix over lanes (and wave total) of a per-lane count v < 64,
+// by bit slices: 6 ballots instead of a scan.  With a lane mask `sel`, only
+// lanes in sel are counted (prefix and total over them).
+__device__ __forceinline__ int wave_prefix_small(int v, unsigned long long lt,
+                                                 unsigned long long sel, int* total) {
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b) {
+    const unsigned long long m = __ballot((v >> b) & 1) & sel;
+    pre += __popcll(m & lt) << b;
+    tot += __popcll(m) << b;
+  }
+  *total = tot;
+  return pre;
+}
+
+// Row (16-lane) sum of an int by DPP rotations.
+__device__ __forceinline__ int row16_sum_i(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x121, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x122, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x124, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+  return v;
+}
+
 // Orders this wave's LDS accesses across lanes (the LDS executes one wave's
 // operations in issue order; this keeps the compiler from reordering them).
 __device__ __forceinline__ void wave_lds_sync() {
@@ -1218,40 +1243,36 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
       }
       __builtin_amdgcn_sched_barrier(0);
     }
-    int cnt[4] = {0, 0, 0, 0};
+    // near pairs in lane-major order: lane l's pairs (block-major) follow
+    // those of lanes < l; per-sample counts packed one byte per row sample
     int np = 0;
+    const int mybase = wave_prefix_small(__popc(nearb), lt, ~0ull, &np);
+    {
+      int pk = 0;
 #pragma unroll
-    for (int cb = 0; cb < RBT; ++cb)
+      for (int j = 0; j < 4; ++j) pk += __popc(nearb & (0x11111111u << j)) << (8 * j);
+      pk = row16_sum_i(pk);
+      if (colc == 0) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const unsigned long long m = __ballot((nearb >> (4 * cb + j)) & 1u);
-        cnt[j] += __popcll((m >> (16 * rowq)) & 0xFFFFull);
-        np += __popcll(m);
-      }
-    if (colc == 0) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        mw[4 * rowq + j] = M[j];
-        cw[4 * rowq + j] = cnt[j];
+        for (int j = 0; j < 4; ++j) {
+          mw[4 * rowq + j] = M[j];
+          cw[4 * rowq + j] = (pk >> (8 * j)) & 0xFF;
+        }
       }
     }
     nrec += np;
 
     // 4. exact values of the near pairs, kCapR at a time
     for (int c0 = 0; c0 < np; c0 += kCapR) {
-      int pos = 0;
+      int k = mybase - c0;
 #pragma unroll
       for (int cb = 0; cb < RBT; ++cb)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const bool nr = (nearb >> (4 * cb + j)) & 1u;
-          const unsigned long long m = __ballot(nr);
-          if (nr) {
-            const int p = pos + __popcll(m & lt);
-            if (p >= c0 && p < c0 + kCapR) rcode[p - c0] = (4 * rowq + j) | ((16 * cb + colc) << 8);
+        for (int j = 0; j < 4; ++j)
+          if ((nearb >> (4 * cb + j)) & 1u) {
+            if (k >= 0 && k < kCapR) rcode[k] = (4 * rowq + j) | ((16 * cb + colc) << 8);
+            ++k;
           }
-          pos += __popcll(m);
-        }
       wave_lds_sync();
       {
         // one pair per 16-lane row; lane l16 of the row takes dimensions
@@ -1314,19 +1335,15 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
         }
       }
       wave_lds_sync();
-      pos = 0;
+      k = mybase - c0;
 #pragma unroll
       for (int cb = 0; cb < RBT; ++cb)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const bool nr = (nearb >> (4 * cb + j)) & 1u;
-          const unsigned long long m = __ballot(nr);
-          if (nr) {
-            const int p = pos + __popcll(m & lt);
-            if (p >= c0 && p < c0 + kCapR) acc[cb][j] = rval[p - c0];
+        for (int j = 0; j < 4; ++j)
+          if ((nearb >> (4 * cb + j)) & 1u) {
+            if (k >= 0 && k < kCapR) acc[cb][j] = rval[k];
+            ++k;
           }
-          pos += __popcll(m);
-        }
       wave_lds_sync();
     }
 
@@ -1368,11 +1385,16 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
     if (MSTEP) {
       // 6. hand the non-zero responsibilities to their owners (the owner of
       // component 16 cb + colc is wave colc % 8 = lane % 8)
-      int mine = 0;
+      // non-zero responsibilities, lane-major within each owner class (lanes
+      // l with l % 8 = owner)
+      uint32_t nzb = 0;
 #pragma unroll
       for (int cb = 0; cb < RBT; ++cb)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) mine += __popcll(__ballot(acc[cb][j] != 0.0f) & cls);
+        for (int j = 0; j < 4; ++j)
+          if (acc[cb][j] != 0.0f) nzb |= 1u << (4 * cb + j);
+      int mine = 0;
+      const int cbase = wave_prefix_small(__popc(nzb), lt, cls, &mine);
       if (lane < kNW) L.subn[w * kNW + lane] = mine;
       int mx = mine;
       mx = max(mx, __builtin_amdgcn_update_dpp(0, mx, 0xB1, 0xF, 0xF, false));
@@ -1383,21 +1405,18 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
       const int need = L.need[round & 1];
       if (tid == 0) L.need[(round + 1) & 1] = 0;
       for (int pass = 0; pass * kCapM < need; ++pass) {
-        int pos = 0;
         int2* const dst = L.sub + (size_t)(w * kNW + (lane & 7)) * kCapM;
+        int k = cbase - pass * kCapM;
 #pragma unroll
         for (int cb = 0; cb < RBT; ++cb)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const float r = acc[cb][j];
-            const unsigned long long m = __ballot(r != 0.0f) & cls;
-            if (r != 0.0f) {
-              const int p = pos + __popcll(m & lt) - pass * kCapM;
-              if (p >= 0 && p < kCapM)
-                dst[p] = make_int2((4 * rowq + j) | ((16 * cb + colc) << 8), __float_as_int(r));
+          for (int j = 0; j < 4; ++j)
+            if ((nzb >> (4 * cb + j)) & 1u) {
+              if (k >= 0 && k < kCapM)
+                dst[k] = make_int2((4 * rowq + j) | ((16 * cb + colc) << 8),
+                                   __float_as_int(acc[cb][j]));
+              ++k;
             }
-            pos += __popcll(m);
-          }
         __syncthreads();
         // owner w: the map step (Eqs. 9-11) in West's weighted Welford form on
         // y = x - mu_old, lists taken in source-wave order
