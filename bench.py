@@ -168,7 +168,7 @@ def main():
         hefts = torch.full((G,), 1.0 / G, device=dev)
         tr.global_stats()
         for _ in range(KM_ITERS):
-            tr.kmeans_iter(means, dcovs, hefts, gmm.DIST_MAHA, VAR_FLOOR, prec=gmm.PREC_FP32)
+            tr.kmeans_iter(means, dcovs, hefts, gmm.DIST_MAHA, VAR_FLOOR, prec=head)
         ev_km = torch.cuda.Event(enable_timing=True)
         ev_km.record()
         if keep_handoff:

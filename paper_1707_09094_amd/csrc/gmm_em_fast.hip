@@ -53,8 +53,6 @@ constexpr int kThreads = kNW * kWave;
 constexpr int kT = 32;            // samples per tile
 constexpr int kPF = 8;            // prefetch registers per thread: kT * 128 / kThreads
 
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
-typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 struct FastArgs {
   const float* X;
@@ -1011,79 +1009,6 @@ __device__ inline Lds2 carve_lds2(char* base, int G, int KS) {
     }
   });
   return L;
-}
-
-// Butterflies over the 16 lanes of a row by DPP row rotations (no address
-// registers): after rotations by 1, 2, 4 and 8 every lane holds the reduction
-// of all 16.
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ float row16_max(float v) {
-  v = fmaxf(v, dpp_f<0x121>(v));
-  v = fmaxf(v, dpp_f<0x122>(v));
-  v = fmaxf(v, dpp_f<0x124>(v));
-  v = fmaxf(v, dpp_f<0x128>(v));
-  return v;
-}
-__device__ __forceinline__ double row16_sum(double v) {
-  v += dpp_d<0x121>(v);
-  v += dpp_d<0x122>(v);
-  v += dpp_d<0x124>(v);
-  v += dpp_d<0x128>(v);
-  return v;
-}
-// quad (4-lane) sums by DPP quad permutations
-__device__ __forceinline__ float quad_sum(float v) {
-  v += dpp_f<0xB1>(v);  // quad_perm [1,0,3,2]
-  v += dpp_f<0x4E>(v);  // quad_perm [2,3,0,1]
-  return v;
-}
-__device__ __forceinline__ double quad_sum_d(double v) {
-  v += dpp_d<0xB1>(v);
-  v += dpp_d<0x4E>(v);
-  return v;
-}
-
-// Exclusive prefix over lanes (and wave total) of a per-lane count v < 64,
-// by bit slices: 6 ballots instead of a scan.  With a lane mask `sel`, only
-// lanes in sel are counted (prefix and total over them).
-__device__ __forceinline__ int wave_prefix_small(int v, unsigned long long lt,
-                                                 unsigned long long sel, int* total) {
-  int pre = 0, tot = 0;
-#pragma unroll
-  for (int b = 0; b < 6; ++b) {
-    const unsigned long long m = __ballot((v >> b) & 1) & sel;
-    pre += __popcll(m & lt) << b;
-    tot += __popcll(m) << b;
-  }
-  *total = tot;
-  return pre;
-}
-
-// Row (16-lane) sum of an int by DPP rotations.
-__device__ __forceinline__ int row16_sum_i(int v) {
-  v += __builtin_amdgcn_update_dpp(0, v, 0x121, 0xF, 0xF, false);
-  v += __builtin_amdgcn_update_dpp(0, v, 0x122, 0xF, 0xF, false);
-  v += __builtin_amdgcn_update_dpp(0, v, 0x124, 0xF, 0xF, false);
-  v += __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
-  return v;
-}
-
-// Orders this wave's LDS accesses across lanes (the LDS executes one wave's
-// operations in issue order; this keeps the compiler from reordering them).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Fragments are laid out for KST = 4 DPL k-steps (16 dimensions each, zero

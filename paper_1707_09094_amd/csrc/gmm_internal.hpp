@@ -54,6 +54,84 @@ __device__ __forceinline__ int f2ord(float f) {
 }
 __device__ __forceinline__ float ord2f(int i) { return __int_as_float(i >= 0 ? i : i ^ 0x7FFFFFFF); }
 
+// ---- wave-level helpers of the sample-major kernels --------------------------
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+// Butterflies over the 16 lanes of a row by DPP row rotations (no address
+// registers): after rotations by 1, 2, 4 and 8 every lane holds the reduction
+// of all 16.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float row16_max(float v) {
+  v = fmaxf(v, dpp_f<0x121>(v));
+  v = fmaxf(v, dpp_f<0x122>(v));
+  v = fmaxf(v, dpp_f<0x124>(v));
+  v = fmaxf(v, dpp_f<0x128>(v));
+  return v;
+}
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_d<0x121>(v);
+  v += dpp_d<0x122>(v);
+  v += dpp_d<0x124>(v);
+  v += dpp_d<0x128>(v);
+  return v;
+}
+// quad (4-lane) sums by DPP quad permutations
+__device__ __forceinline__ float quad_sum(float v) {
+  v += dpp_f<0xB1>(v);  // quad_perm [1,0,3,2]
+  v += dpp_f<0x4E>(v);  // quad_perm [2,3,0,1]
+  return v;
+}
+__device__ __forceinline__ double quad_sum_d(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  return v;
+}
+
+// Exclusive prefix over lanes (and wave total) of a per-lane count v < 64,
+// by bit slices: 6 ballots instead of a scan.  With a lane mask `sel`, only
+// lanes in sel are counted (prefix and total over them).
+__device__ __forceinline__ int wave_prefix_small(int v, unsigned long long lt,
+                                                 unsigned long long sel, int* total) {
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b) {
+    const unsigned long long m = __ballot((v >> b) & 1) & sel;
+    pre += __popcll(m & lt) << b;
+    tot += __popcll(m) << b;
+  }
+  *total = tot;
+  return pre;
+}
+
+// Row (16-lane) sum of an int by DPP rotations.
+__device__ __forceinline__ int row16_sum_i(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x121, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x122, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x124, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+  return v;
+}
+
+// Orders this wave's LDS accesses across lanes (the LDS executes one wave's
+// operations in issue order; this keeps the compiler from reordering them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 // Number of workgroups of the per-block-partial kernels (E/M, k-means
@@ -113,7 +191,9 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   size_t o_c = take(sizeof(float) * 3 * (size_t)G);
   size_t o_W = take(cov == GMM_COV_FULL ? sizeof(float) * (size_t)D * D * G : 0);
   const size_t GP = ((size_t)G + 15) / 16 * 16;
-  size_t o_prm = take(sizeof(float) * 2 * (size_t)G * (D + 1));
+  // direct-form parameters [2][G][D+1]; also the k-means table [16 RB][4]
+  const size_t n_prm = 2 * (size_t)G * (D + 1);
+  size_t o_prm = take(sizeof(float) * (n_prm > 64 * GP / 16 ? n_prm : 64 * GP / 16));
   size_t o_bh = take(sizeof(uint16_t) * (size_t)K * GP);
   size_t o_bl = take(sizeof(uint16_t) * (size_t)K * GP);
   size_t o_ce = take(sizeof(float) * 2 * (size_t)G);
@@ -367,7 +447,7 @@ hipError_t launch_kmeans_fast(const float* X, int64_t N, int D, int64_t ldx, int
                               const double* gvar, float var_floor, float* means, float* dcovs,
                               float* hefts, int64_t* counts, int32_t* assign, double* inertia,
                               int64_t* n_recomputed, int32_t* dev_status, const Workspace& w,
-                              hipStream_t st);
+                              hipStream_t st, int prec);
 
 hipError_t launch_kmeans(const float* X, int64_t N, int D, int64_t ldx, int G, int dist,
                          const double* gvar, float var_floor, float* means, float* dcovs,

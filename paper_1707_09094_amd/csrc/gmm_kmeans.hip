@@ -407,13 +407,15 @@ hipError_t launch_kmeans(const float* X, int64_t N, int D, int64_t ldx, int G, i
                          float* hefts, int64_t* counts, int32_t* assign, double* inertia,
                          int prec, int64_t* n_recomputed, int32_t* dev_status, const Workspace& w,
                          hipStream_t st) {
-  (void)prec;  // the distance screening is the FP32 direct form for both precisions
+  // prec selects the screening form of the one-pass kernel (FP32 direct, or
+  // BF16x3 on the matrix cores); the decisions are exact either way
   int32_t* asg = assign ? assign : w.assign;
   if (km_fast_supported(D, G)) {
     hipLaunchKernelGGL(k_km_init, dim3(1), dim3(64), 0, st, dev_status, n_recomputed);
     hipError_t e = launch_kmeans_fast(X, N, D, ldx, G, dist, gvar, var_floor, means, dcovs, hefts,
                                       counts, asg, inertia,
-                                      n_recomputed ? n_recomputed : w.counters, dev_status, w, st);
+                                      n_recomputed ? n_recomputed : w.counters, dev_status, w, st,
+                                      prec);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_km_resurrect, dim3(1), dim3(kRT), 0, st, X, N, D, ldx, G, counts, asg,
                        means, (int64_t*)w.partials);

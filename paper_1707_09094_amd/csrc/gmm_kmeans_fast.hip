@@ -661,32 +661,597 @@ __global__ void __launch_bounds__(256) k_km_resurrect_batched(const gmm_model_de
 }
 
 // Per-model global mean / population variance, two FP64 passes, one
-// workgroup per model (thread per dimension, samples in order).
+// workgroup per model.  Thread t < S*D (S = 256 / D sample stripes) sums
+// dimension t % D over samples i = t / D + S k with four interleaved FP64
+// accumulators; stripes are then combined in stripe order, so the result
+// is the same on every run.
 __global__ void __launch_bounds__(256) k_gstats_batched(const gmm_model_desc* models, int D,
                                                         double* mean_out, double* var_out) {
+  __shared__ double sh[256];
+  __shared__ double mean_s[256];
   const int mi = blockIdx.x;
   const gmm_model_desc& m = models[mi];
   if (m.N < 1 || m.X == nullptr) {
     if (threadIdx.x == 0 && m.dev_status) *m.dev_status = GMM_DEV_BADDESC;
     return;
   }
-  for (int d = threadIdx.x; d < D; d += 256) {
-    double s = 0.0;
-    for (int64_t i = 0; i < m.N; ++i) s += (double)m.X[i * D + d];
-    const double mean = s / (double)m.N;
-    double q = 0.0;
-    for (int64_t i = 0; i < m.N; ++i) {
-      const double t = (double)m.X[i * D + d] - mean;
-      q += t * t;
+  const int t = threadIdx.x;
+  const int S = 256 / D;
+  const bool act = t < S * D;
+  const int d = act ? t % D : 0, stripe = act ? t / D : 0;
+  const int64_t N = m.N;
+  const float* X = m.X;
+  for (int pass = 0; pass < 2; ++pass) {
+    const double mu = pass ? mean_s[d] : 0.0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (act) {
+      int64_t i = stripe;
+      const int64_t step = S;
+      for (; i + 3 * step < N; i += 4 * step) {
+        const double x0 = (double)X[i * D + d] - mu;
+        const double x1 = (double)X[(i + step) * D + d] - mu;
+        const double x2 = (double)X[(i + 2 * step) * D + d] - mu;
+        const double x3 = (double)X[(i + 3 * step) * D + d] - mu;
+        a0 += pass ? x0 * x0 : x0;
+        a1 += pass ? x1 * x1 : x1;
+        a2 += pass ? x2 * x2 : x2;
+        a3 += pass ? x3 * x3 : x3;
+      }
+      for (; i < N; i += step) {
+        const double x0 = (double)X[i * D + d] - mu;
+        a0 += pass ? x0 * x0 : x0;
+      }
     }
-    mean_out[(size_t)mi * D + d] = mean;
-    var_out[(size_t)mi * D + d] = q / (double)m.N;
+    sh[t] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (t < D) {
+      double tot = 0.0;
+      for (int q = 0; q < S; ++q) tot += sh[q * D + t];
+      if (pass == 0) {
+        mean_s[t] = tot / (double)N;
+      } else {
+        mean_out[(size_t)mi * D + t] = mean_s[t];
+        var_out[(size_t)mi * D + t] = tot / (double)N;
+      }
+    }
+    __syncthreads();
   }
 }
 
 __global__ void k_zero_status_batched(const gmm_model_desc* models, int n_models) {
   for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n_models; m += gridDim.x * blockDim.x)
     *models[m].dev_status = 0;
+}
+
+// ---- sample-major k-means kernel ---------------------------------------------
+//
+// With u = sqrt(lam) x and m_g = sqrt(lam) mu_g, the weighted distance is
+// d_g = |u|^2 - s_g with s_g = 2 m_g.u - |m_g|^2, so the nearest mean
+// maximises s_g.  The matrix cores compute m_g.u (u and m_g split into BF16
+// hi + lo, three products, FP32 accumulation) for 16 samples x 16 means per
+// tile, samples as the A operand, so a lane row holds 4 samples x 16 means.
+// Every s_g carries a rigorous error bound e_g (representation of u and m_g,
+// the split, the accumulation, the final rounding); the candidates of a
+// sample are the means with s_g + e_g >= max_h (s_h - e_h), which always
+// include the exact nearest one.  A sample with one candidate is decided;
+// otherwise the candidates' distances are recomputed in FP64 and the first
+// minimum wins.  The FP64 distance to the chosen mean (from the features still
+// in registers and the means in LDS) gives the inertia.  The map step
+// (counts, means, variances of the assigned samples) is the owner-wave
+// Welford of the EM kernel with r = 1.
+
+constexpr int kKGS = 16;              // samples per wave group
+constexpr int kKRound = kNW * kKGS;   // samples per block round
+constexpr int kKCapM = 32;            // pairs per (source, owner) list per pass
+constexpr int kCandMax = 8;           // candidate list per sample (more: all means)
+
+struct Km2Args {
+  const float* X;
+  int64_t N;
+  int64_t ldx;
+  int64_t chunk;
+  int D, G;
+  const bf16x8* Whi;    // [RB][KSK][64] fragments of m_g (hi)
+  const bf16x8* Wlo;
+  const float* cq;      // [16 RB][4]: |m_g|^2 hi, lo, bound of |m_g|, 0
+  const float* means;   // [G][D] current means
+  const double* lam64;  // [D]
+  const float* sd;      // [D] sqrt(lam) in FP32
+  int32_t* assign;      // [N] or null
+  double* part;         // [nb][G][2D+1]
+  double* in_part;      // [nb]
+  int64_t* n_rec;
+  int32_t* dev_status;
+};
+
+struct KLds {
+  bf16x8* wh;
+  bf16x8* wl;
+  float* cq;     // [16 RB][4]
+  float* mu;     // [G][D]
+  double* lam;   // [D]
+  float* sd;     // [D]
+  float* un;     // [NW][16] |u| of each sample (bound)
+  int* cand;     // [NW][16][kCandMax]
+  int* ccnt;     // [NW][16]
+  int2* sub;     // [NW][NW][kKCapM]
+  int* subn;     // [NW][NW]
+  int* need;     // [2]
+  int2* osort;   // [NW][64]
+  double* inw;   // [NW]
+};
+
+template <typename F>
+__host__ __device__ inline size_t km2_lds_walk(int D, int G, int KSK, F&& at) {
+  size_t w = 0;
+  auto put = [&](int which, size_t words, size_t align_words) {
+    w = (w + align_words - 1) / align_words * align_words;
+    at(which, w);
+    w += words;
+  };
+  const size_t RB = ((size_t)G + 15) / 16;
+  put(0, RB * KSK * 64 * 4, 4);
+  put(1, RB * KSK * 64 * 4, 4);
+  put(2, 16 * RB * 4, 4);
+  put(3, (size_t)G * D, 1);
+  put(4, 2 * (size_t)D, 2);
+  put(5, D, 1);
+  put(6, kNW * 16, 1);
+  put(7, kNW * 16 * kCandMax, 1);
+  put(8, kNW * 16, 1);
+  put(9, (size_t)kNW * kNW * kKCapM * 2, 2);
+  put(10, kNW * kNW, 1);
+  put(11, 2, 1);
+  put(12, kNW * 64 * 2, 2);
+  put(13, 2 * kNW, 2);
+  return w;
+}
+
+__host__ __device__ inline size_t km2_lds_bytes(int D, int G, int KSK) {
+  return km2_lds_walk(D, G, KSK, [](int, size_t) {}) * 4 + 64;
+}
+
+// k-steps (32 dimensions each) of the k-means fragment layout
+__host__ __device__ inline int km2_ks(int D) { return D <= 64 ? 2 : 4; }
+
+__device__ inline KLds carve_klds(char* base, int D, int G, int KSK) {
+  KLds L;
+  float* f = (float*)base;
+  km2_lds_walk(D, G, KSK, [&](int which, size_t off) {
+    switch (which) {
+      case 0: L.wh = (bf16x8*)(f + off); break;
+      case 1: L.wl = (bf16x8*)(f + off); break;
+      case 2: L.cq = f + off; break;
+      case 3: L.mu = f + off; break;
+      case 4: L.lam = (double*)(f + off); break;
+      case 5: L.sd = f + off; break;
+      case 6: L.un = f + off; break;
+      case 7: L.cand = (int*)(f + off); break;
+      case 8: L.ccnt = (int*)(f + off); break;
+      case 9: L.sub = (int2*)(f + off); break;
+      case 10: L.subn = (int*)(f + off); break;
+      case 11: L.need = (int*)(f + off); break;
+      case 12: L.osort = (int2*)(f + off); break;
+      default: L.inw = (double*)(f + off); break;
+    }
+  });
+  return L;
+}
+
+template <int CPW, int DPL>
+__device__ __forceinline__ void km2_range(const Km2Args& a, int64_t i0, int64_t i1, int b,
+                                          char* lds_raw) {
+  constexpr int RBT = (CPW + 1) / 2;  // row blocks of 16 means
+  constexpr int KSK = 2 * DPL;        // k-steps of 32 dimensions
+  const int D = a.D, G = a.G;
+  const int P = 2 * D + 1;
+  const int RB = (G + 15) / 16;
+  const KLds L = carve_klds(lds_raw, D, G, KSK);
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int w = tid / kWave;
+  // bound of |s_g error| / (|m_g| |u|): representation of u and m (2 x 2
+  // roundings each), the BF16 split (3 x 2^-16), FP32 accumulation of
+  // 3 x 32 x KSK products, times 2 for s = 2 m.u, plus 5 % margin
+  const float kcoef =
+      1.05f * 2.0f * (3.0f * 0x1p-16f + 96.0f * (float)KSK * 0x1p-24f + 4.0f * 0x1p-24f);
+
+  for (int p = tid; p < RB * KSK * 64; p += kThreads) {
+    L.wh[p] = a.Whi[p];
+    L.wl[p] = a.Wlo[p];
+  }
+  for (int p = tid; p < 16 * RB * 4; p += kThreads) L.cq[p] = a.cq[p];
+  for (int p = tid; p < G * D; p += kThreads) L.mu[p] = a.means[p];
+  for (int d = tid; d < D; d += kThreads) {
+    L.lam[d] = a.lam64[d];
+    L.sd[d] = a.sd[d];
+  }
+  if (tid < 2) L.need[tid] = 0;
+
+  float Lc[CPW], S1[CPW][DPL], S2[CPW][DPL];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    Lc[c] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+      S1[c][j] = 0.0f;
+      S2[c][j] = 0.0f;
+    }
+  }
+  double inacc = 0.0;
+  long long nrec = 0;
+  __syncthreads();
+
+  const int rowq = lane >> 4, colc = lane & 15;  // output layout
+  const int kg = lane >> 4, na = lane & 15;      // A operand layout
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  float* const un = L.un + w * 16;
+  int* const cand = L.cand + w * 16 * kCandMax;
+  int* const ccnt = L.ccnt + w * 16;
+  const bf16x8* const whl = L.wh + lane;
+  const bf16x8* const wll = L.wl + lane;
+  const float* const cql = L.cq + 4 * colc;
+
+  int round = 0;
+  for (int64_t base = i0; base < i1; base += kKRound, ++round) {
+    const int64_t s0 = base + (int64_t)kKGS * w;
+    const int64_t ia = s0 + na;
+    const bool va = ia < i1;
+
+    // 1. features (kept for the FP64 distances) and the A fragments of u
+    float xv[KSK][8];
+    float acc[RBT][4];
+    {
+      const float* xr = a.X + (va ? ia : i0) * a.ldx + 8 * kg;
+      int dl = D - 8 * kg;  // this lane's dimensions are 32 ks + i < dl
+      asm volatile("" : "+v"(dl));
+#pragma unroll
+      for (int ks = 0; ks < KSK; ++ks)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) xv[ks][i] = (va && 32 * ks + i < dl) ? xr[32 * ks + i] : 0.0f;
+      bf16x8 ah[KSK], al[KSK];
+      float usq = 0.0f;
+#pragma unroll
+      for (int ks = 0; ks < KSK; ++ks)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int d = 32 * ks + 8 * kg + i;
+          const float u = d < D ? xv[ks][i] * L.sd[min(d, D - 1)] : 0.0f;
+          usq = fmaf(u, u, usq);
+          const __bf16 h = (__bf16)u;
+          ah[ks][i] = h;
+          al[ks][i] = (__bf16)(u - (float)h);
+        }
+      usq += __shfl_xor(usq, 16, kWave);
+      usq += __shfl_xor(usq, 32, kWave);
+      if (kg == 0) un[na] = sqrtf(usq) * 1.0001f + 1e-30f;
+#pragma unroll
+      for (int cb = 0; cb < RBT; ++cb) {
+        f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (cb < RB) {
+#pragma unroll
+          for (int ks = 0; ks < KSK; ++ks) {
+            const bf16x8 bh = whl[(cb * KSK + ks) * 64];
+            const bf16x8 bl = wll[(cb * KSK + ks) * 64];
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[ks], bh, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ks], bl, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ks], bh, c, 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[cb][j] = c[j];
+      }
+    }
+    wave_lds_sync();
+
+    // 2. s_g, bounds, candidates (per sample, in increasing mean index)
+    bool vj[4];
+    float unj[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      vj[j] = s0 + 4 * rowq + j < i1;
+      unj[j] = un[4 * rowq + j];
+    }
+    float M[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+    for (int cb = 0; cb < RBT; ++cb) {
+      const float* q = cql + 4 * 16 * cb;
+      const bool vg = cb < RB;
+      const float mh = vg ? q[0] : INFINITY, ml = vg ? q[1] : 0.0f, mn = vg ? q[2] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float sv = vj[j] ? (2.0f * acc[cb][j] - mh) - ml : -INFINITY;
+        acc[cb][j] = sv;
+        const float e = kcoef * mn * unj[j] + 0x1p-22f * (2.0f * mn * unj[j] + fabsf(mh));
+        M[j] = fmaxf(M[j], sv - e);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) M[j] = row16_max(M[j]);
+    uint32_t candb = 0;
+#pragma unroll
+    for (int cb = 0; cb < RBT; ++cb) {
+      const float* q = cql + 4 * 16 * cb;
+      const bool vg = cb < RB;
+      const float mh = vg ? q[0] : INFINITY, mn = vg ? q[2] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float sv = acc[cb][j];
+        const float e = kcoef * mn * unj[j] + 0x1p-22f * (2.0f * mn * unj[j] + fabsf(mh));
+        if (sv > -INFINITY && sv + e >= M[j]) candb |= 1u << (4 * cb + j);
+      }
+    }
+    {
+      int cntj[4] = {0, 0, 0, 0};
+      const unsigned int below = (1u << colc) - 1u;
+#pragma unroll
+      for (int cb = 0; cb < RBT; ++cb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bool cd = (candb >> (4 * cb + j)) & 1u;
+          const unsigned int seg =
+              (unsigned int)((__ballot(cd) >> (16 * rowq)) & 0xFFFFull);
+          if (cd) {
+            const int pos = cntj[j] + __popc(seg & below);
+            if (pos < kCandMax) cand[(4 * rowq + j) * kCandMax + pos] = 16 * cb + colc;
+          }
+          cntj[j] += __popc(seg);
+        }
+      if (colc == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ccnt[4 * rowq + j] = cntj[j];
+      }
+    }
+    wave_lds_sync();
+
+    // 3. decision and FP64 distance of the chosen mean (A layout: the 4 lanes
+    // of sample na hold all its dimensions)
+    int best = -1;
+    double bestd = INFINITY;
+    {
+      const int cn = va ? ccnt[na] : 0;
+      const int ncand = cn > kCandMax ? G : cn;
+      int kmax = ncand;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) kmax = max(kmax, __shfl_xor(kmax, o, kWave));
+      for (int k = 0; k < kmax; ++k) {
+        if (k < ncand) {
+          const int g = cn > kCandMax ? k : cand[na * kCandMax + k];
+          const float* mug = L.mu + g * D;
+          double d64 = 0.0;
+#pragma unroll
+          for (int ks = 0; ks < KSK; ++ks)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              const int d = 32 * ks + 8 * kg + i;
+              const int dc = min(d, D - 1);
+              const double t = (double)xv[ks][i] - (double)mug[dc];
+              d64 = d < D ? fma(t * t, L.lam[dc], d64) : d64;
+            }
+          d64 += __shfl_xor(d64, 16, kWave);
+          d64 += __shfl_xor(d64, 32, kWave);
+          if (d64 < bestd) {
+            bestd = d64;
+            best = g;
+          }
+        }
+      }
+      if (kg == 0 && cn > 1) ++nrec;
+      if (va && kg == 0) {
+        if (a.assign) a.assign[ia] = best;
+        inacc += bestd;
+      }
+    }
+
+    // 4. hand (sample, chosen mean) to the mean's owner wave best % 8
+    const bool has = va && kg == 0 && best >= 0;
+    const int own = has ? (best & 7) : 0;
+    int mypos = 0, mine = 0;
+#pragma unroll
+    for (int o = 0; o < kNW; ++o) {
+      const unsigned long long m = __ballot(has && own == o);
+      if (own == o) mypos = __popcll(m & lt);
+      if (lane == o) mine = __popcll(m);
+    }
+    if (lane < kNW) L.subn[w * kNW + lane] = mine;
+    int mx = mine;
+    mx = max(mx, __builtin_amdgcn_update_dpp(0, mx, 0xB1, 0xF, 0xF, false));
+    mx = max(mx, __builtin_amdgcn_update_dpp(0, mx, 0x4E, 0xF, 0xF, false));
+    mx = max(mx, __builtin_amdgcn_update_dpp(0, mx, 0x124, 0xF, 0xF, false));
+    if (lane == 0) atomicMax(&L.need[round & 1], mx);
+    __syncthreads();
+    const int need = L.need[round & 1];
+    if (tid == 0) L.need[(round + 1) & 1] = 0;
+    for (int pass = 0; pass * kKCapM < need; ++pass) {
+      const int k = mypos - pass * kKCapM;
+      if (has && k >= 0 && k < kKCapM)
+        L.sub[(size_t)(w * kNW + own) * kKCapM + k] = make_int2(na | (best << 8), 0);
+      __syncthreads();
+      int pre[kNW + 1];
+      pre[0] = 0;
+#pragma unroll
+      for (int src = 0; src < kNW; ++src)
+        pre[src + 1] = pre[src] + max(0, min(kKCapM, L.subn[src * kNW + w] - pass * kKCapM));
+      const int tot = pre[kNW];
+      int2* const os = L.osort + w * 64;
+      for (int k0 = 0; k0 < tot; k0 += 64) {
+        const int kk = k0 + lane;
+        const bool ok = kk < tot;
+        int src = 0;
+#pragma unroll
+        for (int t = 1; t < kNW; ++t) src = kk >= pre[t] ? t : src;
+        const int2 e = ok ? L.sub[(size_t)(src * kNW + w) * kKCapM + (kk - pre[src])]
+                          : make_int2(0, 0);
+        const int cs = ok ? (e.x >> 11) : -1;
+        int cnt[CPW];
+        int off = 0, pos = 0;
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          const unsigned long long m = __ballot(cs == c);
+          if (cs == c) pos = off + __popcll(m & lt);
+          cnt[c] = __popcll(m);
+          off += cnt[c];
+        }
+        if (ok) os[pos] = make_int2((kKGS * src + (e.x & 15)) | (e.x & ~0xFF), 0);
+        wave_lds_sync();
+        // the map step with l in {0, 1}: West's Welford on y = x - mu_old,
+        // slot by slot, samples in the order above
+        int o = 0;
+        int wo = w;
+        asm volatile("" : "+v"(wo));
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          const int cc = cnt[c];
+          if (cc > 0) {
+            const int g = wo + kNW * c;
+            float mu[DPL];
+#pragma unroll
+            for (int jd = 0; jd < DPL; ++jd) mu[jd] = L.mu[g * D + min(lane + kWave * jd, D - 1)];
+            for (int q0 = 0; q0 < cc; q0 += 4) {
+              bool okq[4];
+              float y[4][DPL];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int2 e2 = os[o + min(q0 + i, cc - 1)];
+                okq[i] = q0 + i < cc;
+                const float* xr = a.X + (base + (e2.x & 0xFF)) * a.ldx;
+#pragma unroll
+                for (int jd = 0; jd < DPL; ++jd)
+                  y[i][jd] = xr[min(lane + kWave * jd, D - 1)] - mu[jd];
+              }
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                if (okq[i]) {
+                  const float Lo = Lc[c];
+                  const float Ln = Lo + 1.0f;
+                  const float inv = __builtin_amdgcn_rcpf(Ln);
+                  const float w2 = inv * Lo;
+                  Lc[c] = Ln;
+#pragma unroll
+                  for (int jd = 0; jd < DPL; ++jd) {
+                    const float dlt = y[i][jd] - S1[c][jd];
+                    S1[c][jd] = Lo == 0.0f ? y[i][jd] : fmaf(inv, dlt, S1[c][jd]);
+                    S2[c][jd] = fmaf(w2 * dlt, dlt, S2[c][jd]);
+                  }
+                }
+              }
+            }
+            o += cc;
+          }
+        }
+        wave_lds_sync();
+      }
+      __syncthreads();
+    }
+    if (need == 0) __syncthreads();
+  }
+
+  double* pb = a.part + (size_t)b * G * P;
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int g = w + kNW * c;
+    if (g < G) {
+      if (lane == 0) pb[(size_t)g * P] = (double)Lc[c];
+#pragma unroll
+      for (int jd = 0; jd < DPL; ++jd) {
+        const int d = lane + kWave * jd;
+        if (d < D) {
+          pb[(size_t)g * P + 1 + d] = (double)S1[c][jd];
+          pb[(size_t)g * P + 1 + D + d] = (double)S2[c][jd];
+        }
+      }
+    }
+  }
+  {
+    const double v = wave_sum_d(inacc);
+    if (lane == 0) L.inw[w] = v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kNW; ++q) s += L.inw[q];
+    a.in_part[b] = s;
+  }
+  if (a.n_rec) {
+    long long v = nrec;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    if (lane == 0 && v) atomicAdd((unsigned long long*)a.n_rec, (unsigned long long)v);
+  }
+}
+
+template <int CPW, int DPL>
+__global__ void __launch_bounds__(kThreads) k_km2(Km2Args a) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const int b = blockIdx.x;
+  const int64_t i0 = (int64_t)b * a.chunk;
+  const int64_t i1 = min(a.N, i0 + a.chunk);
+  km2_range<CPW, DPL>(a, i0, i1, b, lds_raw);
+}
+
+// Per-mean constants: block g < 16 RB.  lam and s = sqrt(lam) per dimension
+// (block 0 stores them), m_g = mu_g s in FP32, its MFMA fragments (hi/lo;
+// zero for padding means), |m_g|^2 in FP64 split hi/lo, and a bound of |m_g|.
+__device__ void km2_pre_mean(const double* __restrict__ gvar, int D, int G, float var_floor,
+                             int dist, const float* __restrict__ means, int KSK, int g,
+                             double* __restrict__ lam64, float* __restrict__ sd,
+                             bf16x8* __restrict__ Whi, bf16x8* __restrict__ Wlo,
+                             float* __restrict__ cq) {
+  __shared__ float sdl[128];
+  __shared__ double sh[256];
+  for (int d = threadIdx.x; d < D; d += 256) {
+    double l = 1.0;
+    if (dist == GMM_DIST_MAHA) {
+      double v = gvar[d];
+      v = v > (double)var_floor ? v : (double)var_floor;
+      l = 1.0 / v;
+    }
+    const float s = (float)sqrt(l);
+    sdl[d] = s;
+    if (g == 0) {
+      lam64[d] = l;
+      sd[d] = s;
+    }
+  }
+  __syncthreads();
+  const int rb = g >> 4, row = g & 15;
+  double q = 0.0;
+  for (int e = threadIdx.x; e < KSK * 4 * 8; e += 256) {
+    const int ks = e / 32, r = e - ks * 32, lq = r >> 3, i = r & 7;
+    const int d = 32 * ks + 8 * lq + i;
+    float v = 0.0f;
+    if (g < G && d < D) v = (float)((double)means[(size_t)g * D + d] * (double)sdl[d]);
+    q += (double)v * (double)v;
+    const __bf16 h = (__bf16)v;
+    const size_t idx = ((size_t)rb * KSK + ks) * 64 + 16 * lq + row;
+    ((__bf16*)(Whi + idx))[i] = h;
+    ((__bf16*)(Wlo + idx))[i] = (__bf16)(v - (float)h);
+  }
+  const double mm = block_sum_d<256>(q, sh);
+  if (threadIdx.x == 0) {
+    float* c = cq + 4 * g;
+    if (g < G) {
+      const float hi = (float)mm;
+      c[0] = hi;
+      c[1] = (float)(mm - (double)hi);
+      c[2] = (float)sqrt(mm) * 1.0001f;
+    } else {
+      c[0] = INFINITY;  // padding mean: s = -inf
+      c[1] = 0.0f;
+      c[2] = 0.0f;
+    }
+    c[3] = 0.0f;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_km2_pre(const double* __restrict__ gvar, int D, int G,
+                                                 float var_floor, int dist,
+                                                 const float* __restrict__ means, int KSK,
+                                                 double* __restrict__ lam64,
+                                                 float* __restrict__ sd, bf16x8* __restrict__ Whi,
+                                                 bf16x8* __restrict__ Wlo,
+                                                 float* __restrict__ cq) {
+  km2_pre_mean(gvar, D, G, var_floor, dist, means, KSK, blockIdx.x, lam64, sd, Whi, Wlo, cq);
 }
 
 template <int CPW, int DPL>
@@ -701,7 +1266,41 @@ void km_launch_one(const KmArgs& a, int nb, size_t lds, hipStream_t st) {
   hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), lds, st, a);
 }
 
+template <int CPW, int DPL>
+void km2_launch_one(const Km2Args& a, int nb, size_t lds, hipStream_t st) {
+  auto kern = k_km2<CPW, DPL>;
+  static bool attr_set = false;  // benign race: setting the attribute twice is harmless
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), lds, st, a);
+}
+
+void km2_dispatch(const Km2Args& a, int nb, size_t lds, hipStream_t st) {
+  const int cpw = (a.G + kNW - 1) / kNW;
+  if (a.D <= 64) {
+    if (cpw <= 2) km2_launch_one<2, 1>(a, nb, lds, st);
+    else if (cpw <= 4) km2_launch_one<4, 1>(a, nb, lds, st);
+    else if (cpw <= 8) km2_launch_one<8, 1>(a, nb, lds, st);
+    else if (cpw <= 13) km2_launch_one<13, 1>(a, nb, lds, st);
+    else km2_launch_one<16, 1>(a, nb, lds, st);
+  } else {
+    if (cpw <= 2) km2_launch_one<2, 2>(a, nb, lds, st);
+    else if (cpw <= 4) km2_launch_one<4, 2>(a, nb, lds, st);
+    else if (cpw <= 8) km2_launch_one<8, 2>(a, nb, lds, st);
+    else if (cpw <= 13) km2_launch_one<13, 2>(a, nb, lds, st);
+    else km2_launch_one<16, 2>(a, nb, lds, st);
+  }
+}
+
 }  // namespace
+
+bool km2_supported(int D, int G) {
+  if (D < 1 || D > 128 || G < 1 || G > 128) return false;
+  return km2_lds_bytes(D, G, km2_ks(D)) <= 160 * 1024;
+}
 
 bool km_fast_supported(int D, int G) {
   if (D < 1 || D > 128 || G < 1 || G > 128) return false;
@@ -712,7 +1311,43 @@ hipError_t launch_kmeans_fast(const float* X, int64_t N, int D, int64_t ldx, int
                               const double* gvar, float var_floor, float* means, float* dcovs,
                               float* hefts, int64_t* counts, int32_t* assign, double* inertia,
                               int64_t* n_recomputed, int32_t* dev_status, const Workspace& w,
-                              hipStream_t st) {
+                              hipStream_t st, int prec) {
+  if (prec == GMM_PREC_BF16X3 && km2_supported(D, G)) {
+    const int KSK = km2_ks(D);
+    const int RB = (G + 15) / 16;
+    hipLaunchKernelGGL(k_km2_pre, dim3(16 * RB), dim3(256), 0, st, gvar, D, G, var_floor, dist,
+                       means, KSK, w.lam64, w.lam32, (bf16x8*)w.Bhi, (bf16x8*)w.Blo, w.prm);
+    int64_t nb64 = (N + kKRound - 1) / kKRound;
+    if (nb64 < 1) nb64 = 1;
+    if (nb64 > 256) nb64 = 256;
+    const int64_t ch = ((N + nb64 - 1) / nb64 + kKRound - 1) / kKRound * kKRound;
+    const int nb = (int)((N + ch - 1) / ch);
+    Km2Args a;
+    a.X = X;
+    a.N = N;
+    a.ldx = ldx;
+    a.chunk = ch;
+    a.D = D;
+    a.G = G;
+    a.Whi = (const bf16x8*)w.Bhi;
+    a.Wlo = (const bf16x8*)w.Blo;
+    a.cq = w.prm;
+    a.means = means;
+    a.lam64 = w.lam64;
+    a.sd = w.lam32;
+    a.assign = assign;
+    a.part = w.partials;
+    a.in_part = w.scalars;
+    a.n_rec = n_recomputed;
+    a.dev_status = dev_status;
+    {
+      ProfScope ps(kProfKmAssign, st);
+      km2_dispatch(a, nb, km2_lds_bytes(D, G, KSK), st);
+    }
+    hipLaunchKernelGGL(k_km_fin_fast, dim3(G), dim3(256), 0, st, w.partials, nb, N, D, G,
+                       var_floor, means, dcovs, hefts, counts, w.scalars, inertia, dev_status);
+    return hipGetLastError();
+  }
   int64_t nb64 = (N + 2 * kT - 1) / (2 * kT);
   if (nb64 < 1) nb64 = 1;
   if (nb64 > 256) nb64 = 256;

@@ -284,14 +284,16 @@ def test_loglik_diag(G_, oracle, N, D, G, prec):
 @pytest.mark.parametrize("N,D,G,maha", [(10_000, 4, 4, True), (20_000, 100, 100, True),
                                         (999, 3, 7, False), (1, 2, 1, False), (4, 2, 9, False),
                                         (3000, 40, 128, True), (2000, 150, 6, True),
-                                        (2500, 8, 160, False), (777, 1, 5, True)])
-def test_kmeans_step(G_, oracle, N, D, G, maha):
+                                        (2500, 8, 160, False), (777, 1, 5, True),
+                                        (5000, 128, 128, True), (3001, 65, 17, False)])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
+def test_kmeans_step(G_, oracle, N, D, G, maha, prec):
     X, _ = synth.diag_gmm(300 + N, D, max(G, 2), N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
     mu = synth.static_subset(X, G) if N >= G else np.concatenate(
         [X, np.full((G - N, D), 100.0, np.float32)])
     gv = oracle.global_stats(X)[1] if maha else None
     lam = oracle.maha_lambda(gv, 1e-10) if maha else np.ones(D)
-    gk = gpu_kmeans_step(G_, X, mu, 1 if maha else 0, 1e-10, gvar=gv)
+    gk = gpu_kmeans_step(G_, X, mu, 1 if maha else 0, 1e-10, gvar=gv, prec=prec)
     rk = oracle.kmeans_iter(X, mu, lam, 1e-10)
     assert gk["status"] == 0
     ok = rk.gap >= 1e-6
@@ -307,14 +309,15 @@ def test_kmeans_step(G_, oracle, N, D, G, maha):
         np.testing.assert_array_equal(gk["means"][~live], rk.means[~live].astype(np.float32))
 
 
-def test_kmeans_resurrection_golden(G_):
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
+def test_kmeans_resurrection_golden(G_, prec):
     import json
     import os
     with open(os.path.join(os.path.dirname(__file__), "golden", "resurrection_1d.json")) as f:
         gd = json.load(f)
     X = np.array(gd["X"], np.float32)[:, None]
     mu = np.array(gd["means_in"], np.float32)[:, None]
-    gk = gpu_kmeans_step(G_, X, mu, 0, gd["var_floor"])
+    gk = gpu_kmeans_step(G_, X, mu, 0, gd["var_floor"], prec=prec)
     assert list(gk["assign"]) == gd["assign"]
     assert list(gk["counts"]) == gd["counts"]
     np.testing.assert_allclose(gk["means"][:, 0], gd["means_out"], rtol=1e-7)
@@ -323,10 +326,11 @@ def test_kmeans_resurrection_golden(G_):
     assert abs(gk["inertia"] - gd["inertia"]) <= 1e-9 * gd["inertia"]
 
 
-def test_kmeans_duplicate_means_tie(G_):
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
+def test_kmeans_duplicate_means_tie(G_, prec):
     X = np.array([[0.0, 0.0], [1.0, 1.0], [5.0, 5.0]], np.float32)
     mu = np.array([[5.0, 5.0], [0.5, 0.5], [0.5, 0.5]], np.float32)
-    gk = gpu_kmeans_step(G_, X, mu, 0, 1e-10)
+    gk = gpu_kmeans_step(G_, X, mu, 0, 1e-10, prec=prec)
     assert list(gk["assign"]) == [1, 1, 0]
     assert gk["nrec"] >= 2
 
