@@ -262,7 +262,9 @@ struct BatchWorkspace {
   double* c64;     // Gmax
   double* lam64;   // Gmax * D
   // k-means constants (stride per model)
-  float* kmprm;    // Gmax * (D+1)
+  float* kmprm;    // kpstride: [Gmax][D+1] m of the FP32 k-means form, or the
+                   // [16 RBmax][4] table of the matrix-core form
+  size_t kpstride;
   float* ksd;      // D
   double* klam64;  // D
   float* kmnorm;   // 1
@@ -293,7 +295,9 @@ inline bool carve_batched(void* base, size_t avail, int n_models, int D, int Gma
   const size_t o_wl = take(M * RBmax * KS * 64 * 16);
   const size_t o_c64 = take(sizeof(double) * M * Gmax);
   const size_t o_l64 = take(sizeof(double) * M * Gmax * D);
-  const size_t o_kp = take(sizeof(float) * M * Gmax * (D + 1));
+  const size_t kps = (size_t)Gmax * (D + 1) > (size_t)64 * RBmax ? (size_t)Gmax * (D + 1)
+                                                                   : (size_t)64 * RBmax;
+  const size_t o_kp = take(sizeof(float) * M * kps);
   const size_t o_ks = take(sizeof(float) * M * D);
   const size_t o_kl = take(sizeof(double) * M * D);
   const size_t o_kn = take(sizeof(float) * M);
@@ -306,6 +310,7 @@ inline bool carve_batched(void* base, size_t avail, int n_models, int D, int Gma
   w->RBmax = RBmax;
   w->KS = KS;
   w->cap = cap;
+  w->kpstride = kps;
   w->bytes = off;
   if (!base) return true;
   if (avail < off) return false;

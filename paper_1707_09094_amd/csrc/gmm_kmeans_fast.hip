@@ -1051,7 +1051,9 @@ __device__ __forceinline__ void km2_range(const Km2Args& a, int64_t i0, int64_t 
     for (int o = 0; o < kNW; ++o) {
       const unsigned long long m = __ballot(has && own == o);
       if (own == o) mypos = __popcll(m & lt);
-      if (lane == o) mine = __popcll(m);
+      // every lane of class o (lane % 8 == o) holds owner o's count: the
+      // row-rotation maximum below reads lanes 0-15
+      if ((lane & 7) == o) mine = __popcll(m);
     }
     if (lane < kNW) L.subn[w * kNW + lane] = mine;
     int mx = mine;
@@ -1254,6 +1256,67 @@ __global__ void __launch_bounds__(256) k_km2_pre(const double* __restrict__ gvar
   km2_pre_mean(gvar, D, G, var_floor, dist, means, KSK, blockIdx.x, lam64, sd, Whi, Wlo, cq);
 }
 
+// Per-model constants of the batched form: per-model strides of the fragment
+// (RBmax * KSl * 64), table (kps), lam and s (D) regions.
+struct Km2Batch {
+  bf16x8* Whi;
+  bf16x8* Wlo;
+  float* cq;
+  double* lam64;
+  float* sd;
+  int RBmax, KSl, Gmax;
+  size_t kps;
+};
+
+// grid (16 RBmax, n_models)
+__global__ void __launch_bounds__(256) k_km2_pre_batched(const gmm_model_desc* models, int D,
+                                                         float var_floor, int dist, int KSK,
+                                                         Km2Batch kb) {
+  const int mi = blockIdx.y;
+  const gmm_model_desc& m = models[mi];
+  if (!batch_desc_ok(m, kb.Gmax)) return;
+  if ((int)blockIdx.x >= 16 * ((m.G + 15) / 16)) return;
+  const size_t fo = (size_t)mi * kb.RBmax * kb.KSl * 64;
+  km2_pre_mean(m.gvar, D, m.G, var_floor, dist, m.means, KSK, blockIdx.x,
+               kb.lam64 + (size_t)mi * D, kb.sd + (size_t)mi * D, kb.Whi + fo, kb.Wlo + fo,
+               kb.cq + (size_t)mi * kb.kps);
+}
+
+template <int CPW, int DPL>
+__global__ void __launch_bounds__(kThreads) k_km2_batched(Km2Args base,
+                                                          const gmm_model_desc* models,
+                                                          const BatchItemDev* items,
+                                                          const int* n_items, Km2Batch kb) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const int ni = *n_items;
+  const int D = base.D;
+  const int P = 2 * D + 1;
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    const BatchItemDev item = items[it];
+    const gmm_model_desc& m = models[item.model];
+    const size_t mi = (size_t)item.model;
+    Km2Args a = base;
+    a.X = m.X;
+    a.N = m.N;
+    a.ldx = D;
+    a.G = m.G;
+    const size_t fo = mi * kb.RBmax * kb.KSl * 64;
+    a.Whi = kb.Whi + fo;
+    a.Wlo = kb.Wlo + fo;
+    a.cq = kb.cq + mi * kb.kps;
+    a.means = m.means;
+    a.lam64 = kb.lam64 + mi * D;
+    a.sd = kb.sd + mi * D;
+    a.assign = m.assign;
+    a.part = base.part + (size_t)it * kb.Gmax * P;
+    a.in_part = base.in_part + it;
+    a.n_rec = nullptr;
+    a.dev_status = m.dev_status;
+    km2_range<CPW, DPL>(a, item.i0, item.i1, 0, lds_raw);
+    __syncthreads();
+  }
+}
+
 template <int CPW, int DPL>
 void km_launch_one(const KmArgs& a, int nb, size_t lds, hipStream_t st) {
   auto kern = k_km_fast<CPW, DPL>;
@@ -1293,6 +1356,21 @@ void km2_dispatch(const Km2Args& a, int nb, size_t lds, hipStream_t st) {
     else if (cpw <= 13) km2_launch_one<13, 2>(a, nb, lds, st);
     else km2_launch_one<16, 2>(a, nb, lds, st);
   }
+}
+
+template <int CPW, int DPL>
+void km2_launch_batched_one(const Km2Args& base, const gmm_model_desc* models,
+                            const BatchWorkspace& bw, const Km2Batch& kb, int grid, size_t lds,
+                            hipStream_t st) {
+  auto kern = k_km2_batched<CPW, DPL>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, st, base, models, bw.items,
+                     bw.n_items, kb);
 }
 
 }  // namespace
@@ -1415,31 +1493,39 @@ void km_launch_batched_one(const KmArgs& base, const gmm_model_desc* models,
 hipError_t launch_kmeans_batched(const gmm_model_desc* models, int n_models, int n_items_host,
                                  int D, int dist, float var_floor, const BatchWorkspace& bw,
                                  hipStream_t st) {
-  hipLaunchKernelGGL(k_km_pre_batched, dim3(n_models), dim3(256), 0, st, models, D, bw.Gmax,
-                     var_floor, dist, bw.klam64, bw.ksd, bw.kmprm, bw.kmnorm);
-  KmArgs base{};
+  // every model through the matrix-core screening kernel (decisions exact)
+  const int KSK = km2_ks(D);
+  Km2Batch kb;
+  kb.Whi = (bf16x8*)bw.Whi;
+  kb.Wlo = (bf16x8*)bw.Wlo;
+  kb.cq = bw.kmprm;
+  kb.lam64 = bw.klam64;
+  kb.sd = bw.ksd;
+  kb.RBmax = bw.RBmax;
+  kb.KSl = bw.KS;
+  kb.Gmax = bw.Gmax;
+  kb.kps = bw.kpstride;
+  hipLaunchKernelGGL(k_km2_pre_batched, dim3(16 * bw.RBmax, n_models), dim3(256), 0, st, models,
+                     D, var_floor, dist, KSK, kb);
+  Km2Args base{};
   base.D = D;
-  base.mprm = bw.kmprm;
-  base.sd = bw.ksd;
-  base.lam64 = bw.klam64;
-  base.mnorm = bw.kmnorm;
   base.part = bw.partials;
   base.in_part = bw.sparts;
-  const size_t lds = km_lds_bytes(D, bw.Gmax);
+  const size_t lds = km2_lds_bytes(D, bw.Gmax, KSK);
   const int grid = n_items_host < 256 ? (n_items_host < 1 ? 1 : n_items_host) : 256;
   {
     ProfScope ps(kProfBatched, st);
     const int cpw = (bw.Gmax + kNW - 1) / kNW;
     if (D <= 64) {
-      if (cpw <= 2) km_launch_batched_one<2, 1>(base, models, bw, grid, lds, st);
-      else if (cpw <= 4) km_launch_batched_one<4, 1>(base, models, bw, grid, lds, st);
-      else if (cpw <= 8) km_launch_batched_one<8, 1>(base, models, bw, grid, lds, st);
-      else km_launch_batched_one<16, 1>(base, models, bw, grid, lds, st);
+      if (cpw <= 2) km2_launch_batched_one<2, 1>(base, models, bw, kb, grid, lds, st);
+      else if (cpw <= 4) km2_launch_batched_one<4, 1>(base, models, bw, kb, grid, lds, st);
+      else if (cpw <= 8) km2_launch_batched_one<8, 1>(base, models, bw, kb, grid, lds, st);
+      else km2_launch_batched_one<16, 1>(base, models, bw, kb, grid, lds, st);
     } else {
-      if (cpw <= 2) km_launch_batched_one<2, 2>(base, models, bw, grid, lds, st);
-      else if (cpw <= 4) km_launch_batched_one<4, 2>(base, models, bw, grid, lds, st);
-      else if (cpw <= 8) km_launch_batched_one<8, 2>(base, models, bw, grid, lds, st);
-      else km_launch_batched_one<16, 2>(base, models, bw, grid, lds, st);
+      if (cpw <= 2) km2_launch_batched_one<2, 2>(base, models, bw, kb, grid, lds, st);
+      else if (cpw <= 4) km2_launch_batched_one<4, 2>(base, models, bw, kb, grid, lds, st);
+      else if (cpw <= 8) km2_launch_batched_one<8, 2>(base, models, bw, kb, grid, lds, st);
+      else km2_launch_batched_one<16, 2>(base, models, bw, kb, grid, lds, st);
     }
   }
   hipLaunchKernelGGL(k_km_fin_batched, dim3(bw.Gmax, n_models), dim3(256), 0, st, models,

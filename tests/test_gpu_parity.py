@@ -285,7 +285,8 @@ def test_loglik_diag(G_, oracle, N, D, G, prec):
                                         (999, 3, 7, False), (1, 2, 1, False), (4, 2, 9, False),
                                         (3000, 40, 128, True), (2000, 150, 6, True),
                                         (2500, 8, 160, False), (777, 1, 5, True),
-                                        (5000, 128, 128, True), (3001, 65, 17, False)])
+                                        (5000, 128, 128, True), (3001, 65, 17, False),
+                                        (1025, 40, 64, False), (129, 40, 16, True)])
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
 def test_kmeans_step(G_, oracle, N, D, G, maha, prec):
     X, _ = synth.diag_gmm(300 + N, D, max(G, 2), N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
