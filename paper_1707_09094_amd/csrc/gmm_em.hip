@@ -81,6 +81,7 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
   float* xs = lds;                  // [T][D]
   float* as = xs + (size_t)T * D;   // [T][G]
   double* lse = (double*)(as + (size_t)T * G + ((T * G) & 1));  // [T]
+  uint32_t* gbits = (uint32_t*)(lse + T);  // [G/32]: component has a non-zero r in the tile
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -90,6 +91,7 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
   const int64_t i0 = (int64_t)b * chunk;
   const int64_t i1 = min(N, i0 + chunk);
   const int P = 2 * D + 1;
+  const int NGB = (G + 31) / 32;
   double* pb = part + (size_t)b * G * P;
   if (tid == 0) bad = 0;
   if (MSTEP)
@@ -103,6 +105,7 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
       const int t = p / D, d = p - t * D;
       xs[p] = X[(t0 + t) * ldx + d];
     }
+    for (int p = tid; p < NGB; p += kNT) gbits[p] = 0u;
     __syncthreads();
     // a_gi: one (sample, component) pair per thread iteration.
     for (int p = tid; p < nt * G; p += kNT) {
@@ -177,7 +180,9 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
           const int g = g0 + lane;
           if (g < G) {
             const float z = (((nearbits >> c) & 1ull) ? a[g] - dn : (a[g] - mx) - dn) - dl;
-            a[g] = z >= -kRespCut ? __expf(z) : 0.0f;
+            const float r = z >= -kRespCut ? __expf(z) : 0.0f;
+            a[g] = r;
+            if (r != 0.0f) atomicOr(&gbits[g >> 5], 1u << (g & 31));
           }
         }
       }
@@ -191,25 +196,31 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
     if (tid == 0)
       for (int t = 0; t < nt; ++t) llacc += lse[t];
     if (MSTEP) {
-      // map step (Eqs. 9-11) about the current mean: thread owns pairs (g, d).
-      for (int p = tid; p < G * D; p += kNT) {
-        const int g = p / D, d = p - g * D;
-        const float mu = means[(size_t)g * D + d];
-        double s1 = 0.0, s2 = 0.0, sl = 0.0;
-        for (int t = 0; t < nt; ++t) {
-          const float r = as[(size_t)t * G + g];
-          if (r != 0.0f) {
-            const double y = (double)(xs[(size_t)t * D + d] - mu);
-            const double ry = (double)r * y;
-            s1 += ry;
-            s2 += ry * y;
-            sl += (double)r;
-          }
-        }
+      // map step (Eqs. 9-11) about the current mean: wave per component that
+      // has a non-zero responsibility in the tile, lanes over dimensions; the
+      // tile's contributions are added to the block's FP64 partials once.
+      for (int g = wid; g < G; g += nw) {
+        if (!((gbits[g >> 5] >> (g & 31)) & 1u)) continue;
         double* q = pb + (size_t)g * P;
-        q[1 + d] += s1;
-        q[1 + D + d] += s2;
-        if (d == 0) q[0] += sl;
+        double slw = 0.0;
+        for (int d = lane; d < D; d += kWave) {
+          const float mu = means[(size_t)g * D + d];
+          double s1 = 0.0, s2 = 0.0, sl = 0.0;
+          for (int t = 0; t < nt; ++t) {
+            const float r = as[(size_t)t * G + g];
+            if (r != 0.0f) {
+              const double y = (double)(xs[(size_t)t * D + d] - mu);
+              const double ry = (double)r * y;
+              s1 += ry;
+              s2 += ry * y;
+              sl += (double)r;
+            }
+          }
+          q[1 + d] += s1;
+          q[1 + D + d] += s2;
+          slw = sl;
+        }
+        if (lane == 0) q[0] += slw;
       }
     }
     __syncthreads();
@@ -281,7 +292,8 @@ __global__ void k_ll_finish(const double* __restrict__ ll_part, int nb, int64_t 
 
 int tile_rows(int D, int G) {
   int T = 64;
-  while (T > 1 && (size_t)T * (D + G + 2) * sizeof(float) > 60 * 1024) T >>= 1;
+  while (T > 1 && (size_t)T * (D + G + 2) * sizeof(float) + (size_t)(G / 8 + 8) > 60 * 1024)
+    T >>= 1;
   return T;
 }
 
@@ -310,7 +322,8 @@ hipError_t launch_em_diag(const float* X, int64_t N, int D, int64_t ldx, int G, 
   const int T = tile_rows(D, G);
   const int nb = partial_blocks(N, 4 * T);
   int64_t chunk = (N + nb - 1) / nb;
-  const size_t lds = sizeof(float) * ((size_t)T * (D + G) + 1) + sizeof(double) * T;
+  const size_t lds = sizeof(float) * ((size_t)T * (D + G) + 1) + sizeof(double) * T +
+                     sizeof(uint32_t) * ((G + 31) / 32);
   hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, dev_status, n_recomputed, w.counters);
   hipLaunchKernelGGL(k_pre_diag, dim3(G), dim3(kNT), 0, st, hefts, means, covs, D, G, w.s, w.m,
                      w.c, w.c64, w.lamg64);
@@ -343,7 +356,8 @@ hipError_t launch_loglik_diag(const float* X, int64_t N, int D, int64_t ldx, int
   const int T = tile_rows(D, G);
   const int nb = partial_blocks(N, 4 * T);
   int64_t chunk = (N + nb - 1) / nb;
-  const size_t lds = sizeof(float) * ((size_t)T * (D + G) + 1) + sizeof(double) * T;
+  const size_t lds = sizeof(float) * ((size_t)T * (D + G) + 1) + sizeof(double) * T +
+                     sizeof(uint32_t) * ((G + 31) / 32);
   hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, dev_status, nullptr, w.counters);
   hipLaunchKernelGGL(k_pre_diag, dim3(G), dim3(kNT), 0, st, hefts, means, covs, D, G, w.s, w.m,
                      w.c, w.c64, w.lamg64);

@@ -109,9 +109,12 @@ __global__ void __launch_bounds__(kNT) k_estep_full(
     double* __restrict__ part, double* __restrict__ ll_part, float* __restrict__ per_sample,
     int32_t* __restrict__ dev_status) {
   extern __shared__ float lds[];
-  float* xs = lds;                  // [T][D]
-  float* as = xs + (size_t)T * D;   // [T][G]
+  const int DS = D + 1;             // padded row stride (conflict-free column reads)
+  float* xs = lds;                  // [T][D+1]
+  float* as = xs + (size_t)T * DS;  // [T][G]
   double* lse = (double*)(as + (size_t)T * G + ((T * G) & 1));  // [T]
+  uint32_t* gbits = (uint32_t*)(lse + T);  // [G/32]: component has a non-zero r in the tile
+  const int NGB = (G + 31) / 32;
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -132,21 +135,25 @@ __global__ void __launch_bounds__(kNT) k_estep_full(
     const int nt = (int)min((int64_t)T, i1 - t0);
     for (int p = tid; p < nt * D; p += kNT) {
       const int t = p / D, d = p - t * D;
-      xs[p] = X[(t0 + t) * ldx + d];
+      xs[(size_t)t * DS + d] = X[(t0 + t) * ldx + d];
     }
+    for (int p = tid; p < NGB; p += kNT) gbits[p] = 0u;
     __syncthreads();
-    for (int p = tid; p < nt * G; p += kNT) {
-      const int t = p / G, g = p - t * G;
-      const float* x = xs + (size_t)t * D;
+    // a_gi: wave per component (W_g and mu_g read uniformly), lane per sample
+    for (int g = __builtin_amdgcn_readfirstlane(wid); g < G; g += nw) {
       const float* mu = means + (size_t)g * D;
       const float* Wg = W + (size_t)g * D * D;
-      float acc = 0.0f;
-      for (int r = 0; r < D; ++r) {
-        float z = 0.0f;
-        for (int c = 0; c <= r; ++c) z = fmaf(Wg[(size_t)r * D + c], x[c] - mu[c], z);
-        acc = fmaf(z, z, acc);
+      const float cg = cc[g], cl = cc[G + g];
+      for (int t = lane; t < nt; t += kWave) {
+        const float* x = xs + (size_t)t * DS;
+        float acc = 0.0f;
+        for (int r = 0; r < D; ++r) {
+          float z = 0.0f;
+          for (int c = 0; c <= r; ++c) z = fmaf(Wg[(size_t)r * D + c], x[c] - mu[c], z);
+          acc = fmaf(z, z, acc);
+        }
+        as[(size_t)t * G + g] = (cg - 0.5f * acc) + cl;
       }
-      as[p] = (cc[g] - 0.5f * acc) + cc[G + g];
     }
     __syncthreads();
     // Screening in FP32, FP64 recompute of the near set (see the diagonal
@@ -154,7 +161,7 @@ __global__ void __launch_bounds__(kNT) k_estep_full(
     // lanes own rows r of the triangular product.
     for (int t = wid; t < nt; t += nw) {
       float* a = as + (size_t)t * G;
-      const float* x = xs + (size_t)t * D;
+      const float* x = xs + (size_t)t * DS;
       float mx = -INFINITY;
       for (int g = lane; g < G; g += kWave) mx = fmaxf(mx, a[g]);
       mx = wave_max(mx);
@@ -195,7 +202,9 @@ __global__ void __launch_bounds__(kNT) k_estep_full(
           const int g = g0 + lane;
           if (g < G) {
             const float z = (((nearbits >> c) & 1ull) ? a[g] : a[g] - mx) - dl;
-            a[g] = z >= -kRespCut ? __expf(z) : 0.0f;
+            const float r = z >= -kRespCut ? __expf(z) : 0.0f;
+            a[g] = r;
+            if (r != 0.0f) atomicOr(&gbits[g >> 5], 1u << (g & 31));
           }
         }
       }
@@ -210,38 +219,42 @@ __global__ void __launch_bounds__(kNT) k_estep_full(
       for (int t = 0; t < nt; ++t) llacc += lse[t];
     if (MSTEP) {
       // entry k of component g: 0 -> L, 1..D -> sum r y_d, then the packed
-      // lower triangle sum r y_d y_e (d >= e).
-      for (int p = tid; p < G * P; p += kNT) {
-        const int g = p / P, k = p - g * P;
-        int d = 0, e = 0;
-        if (k >= 1 && k <= D) {
-          d = k - 1;
-        } else if (k > D) {
-          int q = k - 1 - D;
-          e = 0;
-          while (q >= D - e) {
-            q -= D - e;
-            ++e;
+      // lower triangle sum r y_d y_e (d >= e, column e after column e-1).
+      // Wave per component with a non-zero responsibility in the tile, lanes
+      // over entries; the tile's contributions are added to the partials once.
+      for (int g = wid; g < G; g += nw) {
+        if (!((gbits[g >> 5] >> (g & 31)) & 1u)) continue;
+        double* q = pb + (size_t)g * P;
+        for (int k = lane; k < P; k += kWave) {
+          int d = 0, e = 0;
+          if (k >= 1 && k <= D) {
+            d = k - 1;
+          } else if (k > D) {
+            int qq = k - 1 - D;
+            while (qq >= D - e) {
+              qq -= D - e;
+              ++e;
+            }
+            d = e + qq;
           }
-          d = e + q;
-        }
-        const float mud = means[(size_t)g * D + d];
-        const float mue = means[(size_t)g * D + e];
-        double s = 0.0;
-        for (int t = 0; t < nt; ++t) {
-          const float r = as[(size_t)t * G + g];
-          if (r != 0.0f) {
-            if (k == 0) {
-              s += (double)r;
-            } else if (k <= D) {
-              s += (double)r * (double)(xs[(size_t)t * D + d] - mud);
-            } else {
-              s += (double)r * (double)(xs[(size_t)t * D + d] - mud) *
-                   (double)(xs[(size_t)t * D + e] - mue);
+          const float mud = means[(size_t)g * D + d];
+          const float mue = means[(size_t)g * D + e];
+          double s = 0.0;
+          for (int t = 0; t < nt; ++t) {
+            const float r = as[(size_t)t * G + g];
+            if (r != 0.0f) {
+              if (k == 0) {
+                s += (double)r;
+              } else if (k <= D) {
+                s += (double)r * (double)(xs[(size_t)t * DS + d] - mud);
+              } else {
+                s += (double)r * (double)(xs[(size_t)t * DS + d] - mud) *
+                     (double)(xs[(size_t)t * DS + e] - mue);
+              }
             }
           }
+          q[k] += s;
         }
-        pb[p] += s;
       }
     }
     __syncthreads();
@@ -321,7 +334,8 @@ __global__ void k_ll_finish_full(const double* __restrict__ ll_part, int nb, int
 
 int tile_rows_full(int D, int G) {
   int T = 64;
-  while (T > 1 && (size_t)T * (D + G + 2) * sizeof(float) > 60 * 1024) T >>= 1;
+  while (T > 1 && (size_t)T * (D + G + 3) * sizeof(float) + (size_t)(G / 8 + 8) > 60 * 1024)
+    T >>= 1;
   return T;
 }
 
@@ -335,7 +349,8 @@ hipError_t launch_em_full(const float* X, int64_t N, int D, int64_t ldx, int G, 
   const int nb = partial_blocks(N, 4 * T);
   const int64_t chunk = (N + nb - 1) / nb;
   const int P = 1 + D + D * (D + 1) / 2;
-  const size_t lds = sizeof(float) * ((size_t)T * (D + G) + 1) + sizeof(double) * T;
+  const size_t lds = sizeof(float) * ((size_t)T * (D + 1 + G) + 1) + sizeof(double) * T +
+                     sizeof(uint32_t) * ((G + 31) / 32);
   hipLaunchKernelGGL(k_init_full, dim3(1), dim3(64), 0, st, dev_status, n_recomputed);
   hipLaunchKernelGGL(k_pre_full, dim3(G), dim3(kNT), 0, st, hefts, covs, D, G, w.partials, w.W,
                      w.W64, w.c, w.c64, dev_status);
@@ -357,7 +372,8 @@ hipError_t launch_loglik_full(const float* X, int64_t N, int D, int64_t ldx, int
   const int T = tile_rows_full(D, G);
   const int nb = partial_blocks(N, 4 * T);
   const int64_t chunk = (N + nb - 1) / nb;
-  const size_t lds = sizeof(float) * ((size_t)T * (D + G) + 1) + sizeof(double) * T;
+  const size_t lds = sizeof(float) * ((size_t)T * (D + 1 + G) + 1) + sizeof(double) * T +
+                     sizeof(uint32_t) * ((G + 31) / 32);
   hipLaunchKernelGGL(k_init_full, dim3(1), dim3(64), 0, st, dev_status, nullptr);
   hipLaunchKernelGGL(k_pre_full, dim3(G), dim3(kNT), 0, st, hefts, covs, D, G, w.partials, w.W,
                      w.W64, w.c, w.c64, dev_status);
