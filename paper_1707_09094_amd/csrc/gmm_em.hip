@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(kNT) k_pre_diag(const float* __restrict__ heft
 // E-step (+ optional M-step map) over the block's contiguous sample range.
 // LDS: xs[T][D] samples, as[T][G] log-densities then responsibilities,
 // lse[T].  T is chosen on the host so the tile fits in LDS.
-template <bool MSTEP>
+template <bool MSTEP, bool WIDE>
 __global__ void __launch_bounds__(kNT) k_estep_diag(
     const float* __restrict__ X, int64_t N, int D, int64_t ldx, int G, int T, int64_t chunk,
     const float* __restrict__ sT, const float* __restrict__ mT, const float* __restrict__ cc,
@@ -78,10 +78,14 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
     const float* __restrict__ means, double* __restrict__ part, double* __restrict__ ll_part,
     float* __restrict__ per_sample, int32_t* __restrict__ dev_status) {
   extern __shared__ float lds[];
-  float* xs = lds;                  // [T][D]
-  float* as = xs + (size_t)T * D;   // [T][G]
+  const int XS = WIDE ? ((D + 3) & ~3) : D;  // row stride of xs
+  float* xs = lds;                   // [T][XS]
+  float* as = xs + (size_t)T * XS;   // [T][G]
   double* lse = (double*)(as + (size_t)T * G + ((T * G) & 1));  // [T]
   uint32_t* gbits = (uint32_t*)(lse + T);  // [G/32]: component has a non-zero r in the tile
+  const int GC = WIDE ? wide_gc(D) : 0;
+  float* pcs = (float*)(gbits + ((G + 31) / 32 + 3) / 4 * 4);  // WIDE: [XS][GC] s
+  float* pcm = pcs + (size_t)XS * GC;                            // WIDE: [XS][GC] m
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -101,22 +105,26 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
 
   for (int64_t t0 = i0; t0 < i1; t0 += T) {
     const int nt = (int)min((int64_t)T, i1 - t0);
-    for (int p = tid; p < nt * D; p += kNT) {
-      const int t = p / D, d = p - t * D;
-      xs[p] = X[(t0 + t) * ldx + d];
+    for (int p = tid; p < nt * XS; p += kNT) {
+      const int t = p / XS, d = p - t * XS;
+      xs[p] = d < D ? X[(t0 + t) * ldx + d] : 0.0f;
     }
     for (int p = tid; p < NGB; p += kNT) gbits[p] = 0u;
     __syncthreads();
-    // a_gi: one (sample, component) pair per thread iteration.
-    for (int p = tid; p < nt * G; p += kNT) {
-      const int t = p / G, g = p - t * G;
-      const float* x = xs + (size_t)t * D;
-      float acc = 0.0f;
-      for (int d = 0; d < D; ++d) {
-        const float u = fmaf(x[d], sT[(size_t)d * G + g], -mT[(size_t)d * G + g]);
-        acc = fmaf(u, u, acc);
+    if (!WIDE) {
+      // a_gi: one (sample, component) pair per thread iteration.
+      for (int p = tid; p < nt * G; p += kNT) {
+        const int t = p / G, g = p - t * G;
+        const float* x = xs + (size_t)t * XS;
+        float acc = 0.0f;
+        for (int d = 0; d < D; ++d) {
+          const float u = fmaf(x[d], sT[(size_t)d * G + g], -mT[(size_t)d * G + g]);
+          acc = fmaf(u, u, acc);
+        }
+        as[p] = (cc[g] - 0.5f * acc) + cc[G + g];
       }
-      as[p] = (cc[g] - 0.5f * acc) + cc[G + g];
+    } else {
+      screen_blocked<false>(xs, XS, nt, D, G, GC, sT, mT, cc, as, pcs, pcm);
     }
     __syncthreads();
     // One wave per sample: the FP32 values screen the components; every one
@@ -127,7 +135,7 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
     // is max_g (a_g - err_g), a lower bound of the exact maximum.
     for (int t = wid; t < nt; t += nw) {
       float* a = as + (size_t)t * G;
-      const float* x = xs + (size_t)t * D;
+      const float* x = xs + (size_t)t * XS;
       float mx = -INFINITY;
       for (int g = lane; g < G; g += kWave)
         mx = fmaxf(mx, a[g] - err_direct(2.0f * (cc[g] - a[g]), cc[2 * G + g], cc[g], D));
@@ -209,7 +217,7 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
           for (int t = 0; t < nt; ++t) {
             const float r = as[(size_t)t * G + g];
             if (r != 0.0f) {
-              const double y = (double)(xs[(size_t)t * D + d] - mu);
+              const double y = (double)(xs[(size_t)t * XS + d] - mu);
               const double ry = (double)r * y;
               s1 += ry;
               s2 += ry * y;
@@ -290,6 +298,32 @@ __global__ void k_ll_finish(const double* __restrict__ ll_part, int nb, int64_t 
   }
 }
 
+// LDS bytes of k_estep_diag for tile rows T (WIDE adds the parameter chunk).
+size_t estep_lds(int D, int G, int T, bool wide) {
+  const size_t XS = wide ? (size_t)((D + 3) & ~3) : (size_t)D;
+  size_t b = sizeof(float) * ((size_t)T * (XS + G) + 1) + sizeof(double) * T;
+  b += sizeof(uint32_t) * (((size_t)(G + 31) / 32 + 3) / 4 * 4);
+  if (wide) b += sizeof(float) * 2 * XS * (size_t)wide_gc(D);
+  return b;
+}
+
+// The WIDE form (register-blocked screening) is used for D <= 128 and more
+// components than the one-pass kernels take, when its tile fits in LDS.
+bool use_wide(int D, int G) {
+  return D <= 128 && G > 128 && estep_lds(D, G, kWT, true) <= 159 * 1024;  // + static LDS
+}
+
+template <bool MSTEP, bool WIDE, typename... Args>
+void launch_estep_diag(int nb, size_t lds, hipStream_t st, Args... args) {
+  auto kern = k_estep_diag<MSTEP, WIDE>;
+  // dynamic LDS above the 64 KB default: raise the kernel's limit to exactly
+  // this launch's size (limit plus static LDS must fit the CU's 160 KB)
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(kNT), lds, st, args...);
+}
+
 int tile_rows(int D, int G) {
   int T = 64;
   while (T > 1 && (size_t)T * (D + G + 2) * sizeof(float) + (size_t)(G / 8 + 8) > 60 * 1024)
@@ -319,19 +353,26 @@ hipError_t launch_em_diag(const float* X, int64_t N, int D, int64_t ldx, int G, 
     return launch_fin_welford(nb, N, D, G, var_floor, hefts, means, covs, mean_loglik,
                               dev_status, w, st);
   }
-  const int T = tile_rows(D, G);
+  const bool wide = use_wide(D, G);
+  const int T = wide ? kWT : tile_rows(D, G);
   const int nb = partial_blocks(N, 4 * T);
   int64_t chunk = (N + nb - 1) / nb;
-  const size_t lds = sizeof(float) * ((size_t)T * (D + G) + 1) + sizeof(double) * T +
-                     sizeof(uint32_t) * ((G + 31) / 32);
+  const size_t lds = estep_lds(D, G, T, wide);
   hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, dev_status, n_recomputed, w.counters);
   hipLaunchKernelGGL(k_pre_diag, dim3(G), dim3(kNT), 0, st, hefts, means, covs, D, G, w.s, w.m,
                      w.c, w.c64, w.lamg64);
   {
     ProfScope ps(kProfEM, st);
-    hipLaunchKernelGGL(k_estep_diag<true>, dim3(nb), dim3(kNT), lds, st, X, N, D, ldx, G, T,
-                       chunk, w.s, w.m, w.c, w.c64, w.lamg64, means, w.partials, w.scalars, nullptr,
-                       dev_status);
+    if (wide)
+      launch_estep_diag<true, true>(nb, lds, st, X, N, D, ldx, G, T, chunk, (const float*)w.s,
+                                    (const float*)w.m, (const float*)w.c, (const double*)w.c64,
+                                    (const double*)w.lamg64, (const float*)means, w.partials,
+                                    w.scalars, (float*)nullptr, dev_status);
+    else
+      launch_estep_diag<true, false>(nb, lds, st, X, N, D, ldx, G, T, chunk, (const float*)w.s,
+                                     (const float*)w.m, (const float*)w.c, (const double*)w.c64,
+                                     (const double*)w.lamg64, (const float*)means, w.partials,
+                                     w.scalars, (float*)nullptr, dev_status);
   }
   hipLaunchKernelGGL(k_fin_diag, dim3(G), dim3(kNT), sizeof(double) * (2 * D + 1), st, w.partials,
                      nb, N, D, G, var_floor, hefts, means, covs, w.scalars, mean_loglik,
@@ -353,19 +394,26 @@ hipError_t launch_loglik_diag(const float* X, int64_t N, int D, int64_t ldx, int
                        dev_status);
     return hipGetLastError();
   }
-  const int T = tile_rows(D, G);
+  const bool wide = use_wide(D, G);
+  const int T = wide ? kWT : tile_rows(D, G);
   const int nb = partial_blocks(N, 4 * T);
   int64_t chunk = (N + nb - 1) / nb;
-  const size_t lds = sizeof(float) * ((size_t)T * (D + G) + 1) + sizeof(double) * T +
-                     sizeof(uint32_t) * ((G + 31) / 32);
+  const size_t lds = estep_lds(D, G, T, wide);
   hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, dev_status, nullptr, w.counters);
   hipLaunchKernelGGL(k_pre_diag, dim3(G), dim3(kNT), 0, st, hefts, means, covs, D, G, w.s, w.m,
                      w.c, w.c64, w.lamg64);
   {
     ProfScope ps(kProfLoglik, st);
-    hipLaunchKernelGGL(k_estep_diag<false>, dim3(nb), dim3(kNT), lds, st, X, N, D, ldx, G, T,
-                       chunk, w.s, w.m, w.c, w.c64, w.lamg64, means, w.partials, w.scalars,
-                       per_sample, dev_status);
+    if (wide)
+      launch_estep_diag<false, true>(nb, lds, st, X, N, D, ldx, G, T, chunk, (const float*)w.s,
+                                     (const float*)w.m, (const float*)w.c, (const double*)w.c64,
+                                     (const double*)w.lamg64, (const float*)means, w.partials,
+                                     w.scalars, per_sample, dev_status);
+    else
+      launch_estep_diag<false, false>(nb, lds, st, X, N, D, ldx, G, T, chunk, (const float*)w.s,
+                                      (const float*)w.m, (const float*)w.c, (const double*)w.c64,
+                                      (const double*)w.lamg64, (const float*)means, w.partials,
+                                      w.scalars, per_sample, dev_status);
   }
   hipLaunchKernelGGL(k_ll_finish, dim3(1), dim3(64), 0, st, w.scalars, nb, N, mean_loglik,
                      dev_status);

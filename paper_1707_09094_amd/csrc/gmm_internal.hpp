@@ -132,6 +132,81 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 
+// ---- register-blocked screening of the WIDE generic kernels ------------------
+// (D <= 128 and many components): tile rows padded to a multiple of 4 (zeros);
+// the direct-form parameters of wide_gc(D) components at a time are staged in
+// LDS and each thread of a 256-thread block computes a 4 x 4 (sample x
+// component) block from float4 reads.
+constexpr int kWNT = 256;  // threads of the WIDE kernels
+constexpr int kWT = 32;    // tile rows of the WIDE kernels
+__host__ __device__ inline int wide_gc(int D) { return D <= 64 ? 128 : 64; }
+
+// Register-blocked FP32 direct-form screening of a tile (WIDE forms): for
+// every sample t < nt and component g, v = sum_d (x_td s_dg - m_dg)^2 with the
+// parameters of GC components at a time staged in LDS ([XS][GC] each; rows of
+// xs padded with zeros to XS).  KM: as[t][g] = v (weighted distance); else
+// as[t][g] = c_g - v/2 (hi + lo).  Starts and ends with the block in sync.
+template <bool KM>
+__device__ void screen_blocked(const float* __restrict__ xs, int XS, int nt, int D, int G, int GC,
+                               const float* __restrict__ sT, const float* __restrict__ mT,
+                               const float* __restrict__ cc, float* __restrict__ as,
+                               float* __restrict__ pcs, float* __restrict__ pcm) {
+  const int tid = threadIdx.x;
+  const int NBG = GC / 4;
+  for (int gc0 = 0; gc0 < G; gc0 += GC) {
+    const int gn = min(GC, G - gc0);
+    if (gc0 > 0) __syncthreads();  // the previous chunk's readers are done
+    for (int p = tid; p < XS * GC; p += kWNT) {
+      const int d = p / GC, j = p - d * GC;
+      const bool ok = d < D && j < gn;
+      pcs[p] = ok ? sT[(size_t)d * G + gc0 + j] : 0.0f;
+      pcm[p] = ok ? mT[(size_t)d * G + gc0 + j] : 0.0f;
+    }
+    __syncthreads();
+    for (int q = tid; q < (kWT / 4) * NBG; q += kWNT) {
+      const int tb = q / NBG, gb = q - tb * NBG;
+      float acc[4][4];
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+        for (int gi = 0; gi < 4; ++gi) acc[ti][gi] = 0.0f;
+      for (int d0 = 0; d0 < XS; d0 += 4) {
+        float4 xv[4];
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti)
+          xv[ti] = *(const float4*)(xs + (size_t)(4 * tb + ti) * XS + d0);
+#pragma unroll
+        for (int dd = 0; dd < 4; ++dd) {
+          const float4 sv = *(const float4*)(pcs + (size_t)(d0 + dd) * GC + 4 * gb);
+          const float4 mv = *(const float4*)(pcm + (size_t)(d0 + dd) * GC + 4 * gb);
+#pragma unroll
+          for (int ti = 0; ti < 4; ++ti) {
+            const float x = dd == 0 ? xv[ti].x : dd == 1 ? xv[ti].y : dd == 2 ? xv[ti].z
+                                                                              : xv[ti].w;
+            float u;
+            u = fmaf(x, sv.x, -mv.x);
+            acc[ti][0] = fmaf(u, u, acc[ti][0]);
+            u = fmaf(x, sv.y, -mv.y);
+            acc[ti][1] = fmaf(u, u, acc[ti][1]);
+            u = fmaf(x, sv.z, -mv.z);
+            acc[ti][2] = fmaf(u, u, acc[ti][2]);
+            u = fmaf(x, sv.w, -mv.w);
+            acc[ti][3] = fmaf(u, u, acc[ti][3]);
+          }
+        }
+      }
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+        for (int gi = 0; gi < 4; ++gi) {
+          const int t = 4 * tb + ti, g = gc0 + 4 * gb + gi;
+          if (t < nt && g < G)
+            as[(size_t)t * G + g] = KM ? acc[ti][gi] : (cc[g] - 0.5f * acc[ti][gi]) + cc[G + g];
+        }
+    }
+  }
+}
+
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 // Number of workgroups of the per-block-partial kernels (E/M, k-means

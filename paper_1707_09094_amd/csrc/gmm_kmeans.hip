@@ -17,6 +17,8 @@
 //                   weights (Sec. 3, Eqs. 5-7 with hard l), counts, inertia
 //   k_km_resurrect  dead-mean resurrection (Sec. 3.1), a single workgroup that
 //                   does nothing unless some cluster is empty
+#include <algorithm>
+
 #include "gmm_internal.hpp"
 
 namespace gmm {
@@ -395,9 +397,342 @@ __global__ void __launch_bounds__(kNT) k_assign(const float* __restrict__ X, int
   if (hist) atomicAdd(hist + arg, 1ull);
 }
 
+// ---- WIDE forms (D <= 128, more components than the one-pass kernel takes) --
+// Direct-form constants of the screening: s_d = sqrt(lam_d) and m_gd = mu_gd
+// sqrt(lam_d), each rounded once to FP32 from FP64, stored [D][G]; Q_g =
+// sum_d lam_d mu_gd^2 (rounded up) for the rounding-error bound.
+__global__ void __launch_bounds__(kNT) k_km_pre_wide(const double* __restrict__ lam64,
+                                                     const float* __restrict__ means, int D,
+                                                     int G, float* __restrict__ sT,
+                                                     float* __restrict__ mT,
+                                                     float* __restrict__ Qout) {
+  __shared__ double sh[kNT];
+  const int g = blockIdx.x;
+  double q = 0.0;
+  for (int d = threadIdx.x; d < D; d += kNT) {
+    const double l = lam64[d];
+    const double sd = sqrt(l);
+    const double mu = (double)means[(size_t)g * D + d];
+    sT[(size_t)d * G + g] = (float)sd;
+    mT[(size_t)d * G + g] = (float)(mu * sd);
+    q += l * mu * mu;
+  }
+  q = block_sum_d<kNT>(q, sh);
+  if (threadIdx.x == 0) Qout[g] = isfinite(q) ? (float)(1.0001 * q) : INFINITY;
+}
+
+// Bound on |v - q| for the screened distance v of a sample whose exact
+// distance is q: with u_d = fma(x_d, s_d, -m_d), |du_d| <= 2^-24 (|u_d| +
+// sqrt(lam_d)(|x_d| + |mu_d|)); summing the squares with D FMAs gives
+// 2^-24 ((2 + D) q + 2 sqrt(q (2q + 8Q))), evaluated at the screened value
+// with a 1% margin plus 2^-42 Q for the difference between screened and
+// exact q near zero.
+__device__ __forceinline__ float km_err(float v, float Q, int D) {
+  v = fmaxf(v, 0.0f);
+  return 1.01f * 0x1p-24f * ((2.0f + (float)D) * v + 2.0f * sqrtf(v * (2.0f * v + 8.0f * Q))) +
+         0x1p-42f * Q;
+}
+
+// Hard assignment (Eq. 19) over tiles of kWT samples: register-blocked FP32
+// screening of all components, then one wave per sample takes the two
+// smallest screened distances; when every other component's distance, lowered
+// by its bound, stays above the best one raised by its bound, the FP32 argmin
+// is the exact one.  Otherwise the candidates (and the best) are re-decided in
+// FP64, first minimum wins.  The inertia term is the FP64 distance to the
+// chosen mean.  LDS: xs[kWT][XS], as[kWT][G], screening parameter chunks.
+__global__ void __launch_bounds__(kWNT) k_km_assign_wide(
+    const float* __restrict__ X, int64_t N, int D, int64_t ldx, int G, int64_t chunk,
+    const float* __restrict__ sT, const float* __restrict__ mT, const float* __restrict__ Qg,
+    const float* __restrict__ means, const double* __restrict__ lam64,
+    int32_t* __restrict__ assign, double* __restrict__ inertia_part,
+    int64_t* __restrict__ n_recomputed, int32_t* __restrict__ dev_status) {
+  extern __shared__ float lds[];
+  const int XS = (D + 3) & ~3;
+  const int GC = wide_gc(D);
+  float* xs = lds;                       // [kWT][XS]
+  float* as = xs + (size_t)kWT * XS;     // [kWT][G]
+  float* pcs = as + (size_t)kWT * G;     // [XS][GC]
+  float* pcm = pcs + (size_t)XS * GC;    // [XS][GC]
+  __shared__ double wacc[kWNT / kWave];
+  __shared__ int wrec[kWNT / kWave];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wid = tid / kWave;
+  const int b = blockIdx.x;
+  const int64_t i0 = (int64_t)b * chunk;
+  const int64_t i1 = min(N, i0 + chunk);
+  if (tid == 0) bad = 0;
+  double acc = 0.0;  // lane 0 of each wave
+  int nrec = 0;
+  for (int64_t t0 = i0; t0 < i1; t0 += kWT) {
+    const int nt = (int)min((int64_t)kWT, i1 - t0);
+    for (int p = tid; p < nt * XS; p += kWNT) {
+      const int t = p / XS, d = p - t * XS;
+      xs[p] = d < D ? X[(t0 + t) * ldx + d] : 0.0f;
+    }
+    __syncthreads();
+    screen_blocked<true>(xs, XS, nt, D, G, GC, sT, mT, nullptr, as, pcs, pcm);
+    __syncthreads();
+    for (int t = wid; t < nt; t += kWNT / kWave) {
+      const float* row = as + (size_t)t * G;
+      const float* x = xs + (size_t)t * XS;
+      float v1 = INFINITY, v2 = INFINITY;
+      int g1 = G;
+      for (int g = lane; g < G; g += kWave) {
+        const float v = row[g];
+        if (v < v1) {
+          v2 = v1;
+          v1 = v;
+          g1 = g;
+        } else if (v < v2) {
+          v2 = v;
+        }
+      }
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const float o1 = __shfl_xor(v1, off);
+        const float o2 = __shfl_xor(v2, off);
+        const int og = __shfl_xor(g1, off);
+        if (o1 < v1 || (o1 == v1 && og < g1)) {
+          v2 = fminf(v1, o2);
+          v1 = o1;
+          g1 = og;
+        } else {
+          v2 = fminf(v2, o1);
+        }
+      }
+      int arg = g1;
+      const bool full = !(v1 < INFINITY) || g1 >= G;  // no finite screened value
+      bool any = full;
+      const float U1 = full ? 0.0f : v1 + km_err(v1, Qg[g1], D);
+      if (!full) {
+        // every other component's distance, lowered by its bound, must stay
+        // above U1
+        bool c = false;
+        for (int g = lane; g < G; g += kWave) {
+          const float v = row[g];
+          if (g != g1 && !(v - km_err(v, Qg[g], D) > U1)) c = true;
+        }
+        any = __ballot(c) != 0;
+      }
+      if (any) {
+        // FP64 re-decision over the candidates (all components when full)
+        double bs = INFINITY;
+        int bg = G;
+        for (int g = lane; g < G; g += kWave) {
+          const float v = row[g];
+          if (!(full || g == g1 || !(v - km_err(v, Qg[g], D) > U1))) continue;
+          const float* mu = means + (size_t)g * D;
+          double s = 0.0;
+          for (int d = 0; d < D; ++d) {
+            const double u = (double)x[d] - (double)mu[d];
+            s += lam64[d] * u * u;
+          }
+          if (s < bs) {  // lanes visit their components in increasing order
+            bs = s;
+            bg = g;
+          }
+        }
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+          const double os = __shfl_xor(bs, off);
+          const int og = __shfl_xor(bg, off);
+          if (os < bs || (os == bs && og < bg)) {
+            bs = os;
+            bg = og;
+          }
+        }
+        arg = bg < G ? bg : 0;
+        ++nrec;
+      }
+      // inertia term: FP64 distance to the chosen mean, lanes over d
+      const float* mu = means + (size_t)arg * D;
+      double s = 0.0;
+      for (int d = lane; d < D; d += kWave) {
+        const double u = (double)x[d] - (double)mu[d];
+        s += lam64[d] * u * u;
+      }
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) s += __shfl_xor(s, off);
+      if (lane == 0) {
+        assign[t0 + t] = arg;
+        acc += s;
+        if (!isfinite(s)) bad = 1;
+      }
+    }
+    __syncthreads();  // xs/as are rewritten by the next tile
+  }
+  if (lane == 0) {
+    wacc[wid] = acc;
+    wrec[wid] = nrec;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0.0;
+    long long nr = 0;
+    for (int w = 0; w < kWNT / kWave; ++w) {
+      tot += wacc[w];
+      nr += wrec[w];
+    }
+    inertia_part[b] = tot;
+    if (nr) atomicAdd((unsigned long long*)n_recomputed, (unsigned long long)nr);
+    if (bad) atomicOr(dev_status, GMM_DEV_NONFINITE);
+  }
+}
+
+size_t km_wide_lds(int D, int G) {
+  const size_t XS = (size_t)((D + 3) & ~3);
+  return sizeof(float) * ((size_t)kWT * (XS + G) + 2 * XS * (size_t)wide_gc(D));
+}
+
+// Map step of the hard assignment (Eqs. 9-11) with the components split in
+// groups that fit in LDS: block (r, k) visits the samples of range r and
+// accumulates, for the components of group k, the FP64 count, sum (x - mu_old)
+// and sum (x - mu_old)^2 in LDS.  Component g is owned by wave (g - g0) % 16,
+// which collects its members of each 1024-sample slice in sample order (lane p
+// holds the p-th) and adds their rows lane-parallel over d with LDS FP64
+// atomics; one wave per address, in program order, so the sums are
+// deterministic.  Output: partials [range][G][2D+1] as the generic kernel.
+constexpr int kAT = 1024;   // threads of the grouped accumulation
+constexpr int kASL = 1024;  // assignments staged per slice
+template <int DPL>
+__global__ void __launch_bounds__(kAT) k_km_accum_grp(const float* __restrict__ X, int64_t N,
+                                                      int D, int64_t ldx, int G, int GG,
+                                                      int64_t chunk,
+                                                      const float* __restrict__ means,
+                                                      const int32_t* __restrict__ assign,
+                                                      double* __restrict__ part) {
+  extern __shared__ double lacc[];
+  const int r = blockIdx.x;
+  const int g0 = blockIdx.y * GG;
+  const int gn = min(GG, G - g0);
+  const int P = 2 * D + 1;
+  float* mu = (float*)(lacc + (size_t)GG * P);  // [GG][D]
+  int* sa = (int*)(mu + (size_t)GG * D);         // [kASL] group-relative component or -1
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wid = tid / kWave;
+  constexpr int NWV = kAT / kWave;
+  for (int p = tid; p < gn * P; p += kAT) lacc[p] = 0.0;
+  for (int p = tid; p < gn * D; p += kAT) mu[p] = means[(size_t)g0 * D + p];
+  const int64_t i0 = (int64_t)r * chunk;
+  const int64_t i1 = min(N, i0 + chunk);
+  for (int64_t s0 = i0; s0 < i1; s0 += kASL) {
+    const int ns = (int)min((int64_t)kASL, i1 - s0);
+    __syncthreads();  // previous slice consumed (and, first time, LDS set up)
+    for (int p = tid; p < kASL; p += kAT) {
+      int rel = -1;
+      if (p < ns) {
+        rel = assign[s0 + p] - g0;
+        if (rel < 0 || rel >= gn) rel = -1;
+      }
+      sa[p] = rel;
+    }
+    __syncthreads();
+    int cnt = 0;    // members collected (wave-uniform)
+    int midx = 0;   // lane p: slice offset of the p-th member
+    int mrel = 0;   // lane p: its group-relative component
+    auto flush = [&]() {
+      for (int k0 = 0; k0 < cnt; k0 += 8) {
+        float xv[8][DPL];
+        int rr[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int k = min(k0 + u, cnt - 1);
+          const int off = __builtin_amdgcn_readlane(midx, k);
+          rr[u] = __builtin_amdgcn_readlane(mrel, k);
+          const float* xr = X + (s0 + off) * ldx;
+#pragma unroll
+          for (int j = 0; j < DPL; ++j) {
+            const int d = lane + kWave * j;
+            xv[u][j] = d < D ? xr[d] : 0.0f;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (k0 + u >= cnt) break;
+          double* q = lacc + (size_t)rr[u] * P;
+          const float* m = mu + (size_t)rr[u] * D;
+#pragma unroll
+          for (int j = 0; j < DPL; ++j) {
+            const int d = lane + kWave * j;
+            if (d < D) {
+              const double y = (double)xv[u][j] - (double)m[d];
+              atomicAdd(q + 1 + d, y);
+              atomicAdd(q + 1 + D + d, y * y);
+            }
+          }
+          if (lane == 0) atomicAdd(q, 1.0);
+        }
+      }
+      cnt = 0;
+    };
+    for (int sub = 0; sub < kASL / kWave; ++sub) {
+      const int rel = sa[sub * kWave + lane];
+      const bool mine = rel >= 0 && (rel % NWV) == wid;
+      const uint64_t bal = __ballot(mine);
+      if (!bal) continue;
+      const int pc = __popcll(bal);
+      if (cnt + pc > kWave) flush();
+      // lane p in [cnt, cnt + pc) takes the (p - cnt)-th set bit of bal
+      const int k = lane - cnt;
+      if (k >= 0 && k < pc) {
+        int kk = k, pos = 0;
+        uint64_t m = bal;
+        int c = __popc((uint32_t)m);
+        if (kk >= c) { kk -= c; pos += 32; m >>= 32; }
+        c = __popc((uint32_t)m & 0xFFFFu);
+        if (kk >= c) { kk -= c; pos += 16; m >>= 16; }
+        c = __popc((uint32_t)m & 0xFFu);
+        if (kk >= c) { kk -= c; pos += 8; m >>= 8; }
+        c = __popc((uint32_t)m & 0xFu);
+        if (kk >= c) { kk -= c; pos += 4; m >>= 4; }
+        c = __popc((uint32_t)m & 0x3u);
+        if (kk >= c) { kk -= c; pos += 2; m >>= 2; }
+        c = (int)(m & 1u);
+        if (kk >= c) pos += 1;
+        midx = sub * kWave + pos;
+        mrel = sa[midx];
+      }
+      cnt += pc;
+    }
+    flush();
+  }
+  __syncthreads();
+  double* pb = part + ((size_t)r * G + g0) * P;
+  for (int p = tid; p < gn * P; p += kAT) pb[p] = lacc[p];
+}
+
+size_t km_accum_grp_lds(int D, int GG) {
+  return sizeof(double) * (size_t)GG * (2 * D + 1) + sizeof(float) * (size_t)GG * D +
+         sizeof(int) * kASL;
+}
+
 __global__ void k_zero_i64(int64_t* p, int n, int32_t* dev_status) {
   for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) p[i] = 0;
   if (dev_status && blockIdx.x == 0 && threadIdx.x == 0) *dev_status = 0;
+}
+
+// The WIDE assignment kernel is used for D <= 128 and more components than the
+// one-pass kernel takes, when its tile fits in LDS.
+bool km_use_wide(int D, int G) {
+  return D <= 128 && G > 128 && km_wide_lds(D, G) <= 159 * 1024;  // + static LDS
+}
+
+// Largest component group of the grouped map step that fits in LDS (0: none).
+int km_accum_group_max(int D) {
+  const size_t per = sizeof(double) * (2 * (size_t)D + 1) + sizeof(float) * (size_t)D;
+  const size_t avail = 160 * 1024 - sizeof(int) * kASL;
+  return (int)(avail / per);
+}
+
+// Dynamic LDS above the 64 KB default needs the kernel's limit raised; the
+// limit plus the kernel's static LDS must stay within the 160 KB of a CU, so
+// it is raised to exactly what the launch asks for.
+void set_max_lds(const void* kern, size_t bytes) {
+  if (bytes > 64 * 1024)
+    (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 }  // namespace
@@ -423,22 +758,55 @@ hipError_t launch_kmeans(const float* X, int64_t N, int D, int64_t ldx, int G, i
   }
   const int nb = partial_blocks(N, 256);
   const int64_t chunk = (N + nb - 1) / nb;
+  int64_t* nrec = n_recomputed ? n_recomputed : w.counters;
   hipLaunchKernelGGL(k_km_init, dim3(1), dim3(64), 0, st, dev_status, n_recomputed);
   hipLaunchKernelGGL(k_km_pre, dim3((D + 255) / 256), dim3(256), 0, st, gvar, D, var_floor, dist,
                      w.lam64, w.lam32);
-  {
+  if (km_use_wide(D, G)) {
+    hipLaunchKernelGGL(k_km_pre_wide, dim3(G), dim3(kNT), 0, st, w.lam64, means, D, G, w.s, w.m,
+                       w.c);
+    ProfScope ps(kProfKmAssign, st);
+    set_max_lds((const void*)k_km_assign_wide, km_wide_lds(D, G));
+    hipLaunchKernelGGL(k_km_assign_wide, dim3(nb), dim3(kWNT), km_wide_lds(D, G), st, X, N, D,
+                       ldx, G, chunk, w.s, w.m, w.c, means, w.lam64, asg, w.scalars, nrec,
+                       dev_status);
+  } else {
     ProfScope ps(kProfKmAssign, st);
     hipLaunchKernelGGL(k_km_assign, dim3(nb), dim3(kNT), 0, st, X, N, D, ldx, G, chunk, means,
-                       w.lam32, w.lam64, asg, w.scalars,
-                       n_recomputed ? n_recomputed : w.counters, dev_status);
+                       w.lam32, w.lam64, asg, w.scalars, nrec, dev_status);
   }
+  int nba = nb;  // partial sets of the map step
   {
     ProfScope ps(kProfKmAccum, st);
-    hipLaunchKernelGGL(k_km_accum, dim3(nb), dim3(kNT), 0, st, X, N, D, ldx, G, chunk, means,
-                       asg, w.partials);
+    const int GGmax = D <= 4 * kWave ? km_accum_group_max(D) : 0;
+    if (GGmax >= 1) {
+      const int ngrp = (G + GGmax - 1) / GGmax;
+      const int GG = (G + ngrp - 1) / ngrp;
+      // about 2048 blocks in all, at least 64 sample ranges (fewer when N is small)
+      const int want = std::max(64, (2048 + ngrp - 1) / ngrp);
+      nba = std::min(partial_blocks(N, 2048), want);
+      const int64_t ach = (N + nba - 1) / nba;
+      const size_t lds = km_accum_grp_lds(D, GG);
+      if (D <= kWave) {
+        set_max_lds((const void*)k_km_accum_grp<1>, lds);
+        hipLaunchKernelGGL(k_km_accum_grp<1>, dim3(nba, ngrp), dim3(kAT), lds, st, X, N, D, ldx,
+                           G, GG, ach, means, asg, w.partials);
+      } else if (D <= 2 * kWave) {
+        set_max_lds((const void*)k_km_accum_grp<2>, lds);
+        hipLaunchKernelGGL(k_km_accum_grp<2>, dim3(nba, ngrp), dim3(kAT), lds, st, X, N, D, ldx,
+                           G, GG, ach, means, asg, w.partials);
+      } else {
+        set_max_lds((const void*)k_km_accum_grp<4>, lds);
+        hipLaunchKernelGGL(k_km_accum_grp<4>, dim3(nba, ngrp), dim3(kAT), lds, st, X, N, D, ldx,
+                           G, GG, ach, means, asg, w.partials);
+      }
+    } else {
+      hipLaunchKernelGGL(k_km_accum, dim3(nb), dim3(kNT), 0, st, X, N, D, ldx, G, chunk, means,
+                         asg, w.partials);
+    }
   }
   hipLaunchKernelGGL(k_km_fin, dim3(G), dim3(kNT), sizeof(double) * (2 * D + 1), st, w.partials,
-                     nb, N, D, G, var_floor, means, dcovs, hefts, counts, w.scalars, nb, inertia,
+                     nba, N, D, G, var_floor, means, dcovs, hefts, counts, w.scalars, nb, inertia,
                      dev_status);
   hipLaunchKernelGGL(k_km_resurrect, dim3(1), dim3(kRT), 0, st, X, N, D, ldx, G, counts, asg,
                      means, (int64_t*)w.partials);

@@ -99,6 +99,8 @@ EM_CASES = [
     (2000, 40, 128),
     (1500, 200, 5),
     (2500, 8, 150),
+    (5000, 64, 512),
+    (3001, 100, 300),
 ]
 
 
@@ -286,7 +288,9 @@ def test_loglik_diag(G_, oracle, N, D, G, prec):
                                         (3000, 40, 128, True), (2000, 150, 6, True),
                                         (2500, 8, 160, False), (777, 1, 5, True),
                                         (5000, 128, 128, True), (3001, 65, 17, False),
-                                        (1025, 40, 64, False), (129, 40, 16, True)])
+                                        (1025, 40, 64, False), (129, 40, 16, True),
+                                        (6000, 64, 512, True), (3001, 100, 300, False),
+                                        (2000, 64, 1100, True), (1000, 300, 3, True)])
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
 def test_kmeans_step(G_, oracle, N, D, G, maha, prec):
     X, _ = synth.diag_gmm(300 + N, D, max(G, 2), N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
@@ -334,6 +338,22 @@ def test_kmeans_duplicate_means_tie(G_, prec):
     gk = gpu_kmeans_step(G_, X, mu, 0, 1e-10, prec=prec)
     assert list(gk["assign"]) == [1, 1, 0]
     assert gk["nrec"] >= 2
+
+
+@pytest.mark.parametrize("D,G", [(16, 200), (100, 260)])
+def test_kmeans_duplicate_means_tie_wide(G_, oracle, D, G):
+    """Many components (the register-blocked screening): means duplicated
+    exactly tie in every precision, so the lowest index must win for every
+    sample, as in the oracle's first-minimum rule."""
+    X, _ = synth.diag_gmm(17 + D, D, 8, 3000, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
+    base = synth.static_subset(X, G - 60)
+    mu = np.concatenate([base, base[:60]])  # components G-60.. repeat 0..59
+    gk = gpu_kmeans_step(G_, X, mu, 0, 1e-10)
+    rk = oracle.kmeans_iter(X, mu, np.ones(D), 1e-10)
+    assert gk["status"] == 0
+    assert np.array_equal(gk["assign"], rk.assign)
+    assert (gk["assign"] < G - 60).all()
+    np.testing.assert_array_equal(gk["counts"], rk.counts)
 
 
 # ---------------------------------------------------------------- assign()
