@@ -79,13 +79,15 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
     float* __restrict__ per_sample, int32_t* __restrict__ dev_status) {
   extern __shared__ float lds[];
   const int XS = WIDE ? ((D + 3) & ~3) : D;  // row stride of xs
+  const int AS = WIDE ? G + 8 : G;            // row stride of as
   float* xs = lds;                   // [T][XS]
-  float* as = xs + (size_t)T * XS;   // [T][G]
-  double* lse = (double*)(as + (size_t)T * G + ((T * G) & 1));  // [T]
+  float* as = xs + (size_t)T * XS;   // [T][AS]
+  double* lse = (double*)(as + (size_t)T * AS + ((T * AS) & 1));  // [T]
   uint32_t* gbits = (uint32_t*)(lse + T);  // [G/32]: component has a non-zero r in the tile
   const int GC = WIDE ? wide_gc(D) : 0;
   float* pcs = (float*)(gbits + ((G + 31) / 32 + 3) / 4 * 4);  // WIDE: [XS][GC] s
   float* pcm = pcs + (size_t)XS * GC;                            // WIDE: [XS][GC] m
+  float* ccs = pcm + (size_t)XS * GC;                            // WIDE: [3][G] copy of cc
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -100,6 +102,8 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
   if (tid == 0) bad = 0;
   if (MSTEP)
     for (int p = tid; p < G * P; p += kNT) pb[p] = 0.0;
+  if (WIDE)
+    for (int p = tid; p < 3 * G; p += kNT) ccs[p] = cc[p];
   double llacc = 0.0;  // thread 0 only
   __syncthreads();
 
@@ -124,9 +128,114 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
         as[p] = (cc[g] - 0.5f * acc) + cc[G + g];
       }
     } else {
-      screen_blocked<false>(xs, XS, nt, D, G, GC, sT, mT, cc, as, pcs, pcm);
+      screen_blocked<false>(xs, XS, nt, D, G, GC, sT, mT, ccs, as, AS, pcs, pcm);
     }
     __syncthreads();
+    if (WIDE) {
+      // kKL threads per sample.  mx = a_h - err_h for the screened argmax h is
+      // a lower bound of the exact maximum.  Every value is moved to the frame
+      // of M = mx; a component whose screened value, widened by its bound,
+      // comes within kNearGap nats of mx is recomputed in FP64 (Eq. 15); the
+      // log-sum-exp (Eqs. 16-18) is taken about the largest value in that
+      // frame.
+      const int ts = tid / kKL, j = tid % kKL;
+      if (ts < nt) {  // uniform over the kKL threads of a sample
+        float* a = as + (size_t)ts * AS;
+        const float* x = xs + (size_t)ts * XS;
+        float am = -INFINITY;
+        int ga = G;
+        for (int g = j; g < G; g += kKL) {
+          const float v = a[g];
+          if (v > am) {
+            am = v;
+            ga = g;
+          }
+        }
+#pragma unroll
+        for (int off = 1; off < kKL; off <<= 1) {
+          const float o = __shfl_xor(am, off);
+          const int og = __shfl_xor(ga, off);
+          if (o > am || (o == am && og < ga)) {
+            am = o;
+            ga = og;
+          }
+        }
+        const float mx =
+            ga < G ? am - err_direct(2.0f * (ccs[ga] - am), ccs[2 * G + ga], ccs[ga], D)
+                   : -INFINITY;
+        const double M = (double)mx;
+        // components in chunks of kKL, one per thread; the near ones of a
+        // chunk are recomputed by all kKL threads, each over every kKL-th
+        // dimension, and the partial sums are reduce-scattered so that thread
+        // j ends with component g0 + j's
+        static_assert(kKL == 8, "the reduce-scatter below is written for groups of 8");
+        float dn = -INFINITY;
+        const int sh = lane & ~(kKL - 1);
+        for (int g0 = 0; g0 < G; g0 += kKL) {
+          const int g = g0 + j;
+          const float v = g < G ? a[g] : -INFINITY;
+          const bool nr = g < G && v + err_direct(2.0f * (ccs[g] - v), ccs[2 * G + g], ccs[g],
+                                                  D) >= mx - kNearGap;
+          const unsigned m = (unsigned)(__ballot(nr) >> sh) & 0xFFu;  // uniform in the group
+          float w = v - mx;
+          if (m) {
+            double q[kKL];
+#pragma unroll
+            for (int k = 0; k < kKL; ++k) {
+              q[k] = 0.0;
+              if ((m >> k) & 1u) {
+                const float* mu = means + (size_t)(g0 + k) * D;
+                const double* lg = lam64 + (size_t)(g0 + k) * D;
+                for (int d = j; d < D; d += kKL) {
+                  const double u = (double)x[d] - (double)mu[d];
+                  q[k] += u * u * lg[d];
+                }
+              }
+            }
+            double r4[4], r2[2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const double o = __shfl_xor((j & 4) ? q[i] : q[i + 4], 4);
+              r4[i] = ((j & 4) ? q[i + 4] : q[i]) + o;
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+              const double o = __shfl_xor((j & 2) ? r4[i] : r4[i + 2], 2);
+              r2[i] = ((j & 2) ? r4[i + 2] : r4[i]) + o;
+            }
+            const double o = __shfl_xor((j & 1) ? r2[0] : r2[1], 1);
+            const double qj = ((j & 1) ? r2[1] : r2[0]) + o;
+            if (nr) w = (float)(c64[g] - 0.5 * qj - M);
+          }
+          if (g < G) {
+            a[g] = w;
+            dn = fmaxf(dn, w);
+          }
+        }
+#pragma unroll
+        for (int off = 1; off < kKL; off <<= 1) dn = fmaxf(dn, __shfl_xor(dn, off));
+        dn = dn > -INFINITY ? dn : 0.0f;
+        double sm = 0.0;
+        for (int g = j; g < G; g += kKL) sm += (double)__expf(a[g] - dn);
+#pragma unroll
+        for (int off = 1; off < kKL; off <<= 1) sm += __shfl_xor(sm, off);
+        const double l = (M + (double)dn) + log(sm);
+        if (MSTEP) {
+          const float dl = (float)log(sm);
+          for (int g = j; g < G; g += kKL) {
+            const float z = (a[g] - dn) - dl;
+            const float r = z >= -kRespCut ? __expf(z) : 0.0f;
+            a[g] = r;
+            if (r != 0.0f) atomicOr(&gbits[g >> 5], 1u << (g & 31));
+          }
+        }
+        if (j == 0) {
+          lse[ts] = l;
+          if (!isfinite(l)) bad = 1;
+          if (per_sample) per_sample[t0 + ts] = (float)l;
+        }
+      }
+    } else
     // One wave per sample: the FP32 values screen the components; every one
     // that, widened by its rounding-error bound, could come within kNearGap
     // nats of the best is recomputed in FP64 (a_g = c_g - 1/2 sum_d (x_d -
@@ -207,28 +316,59 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
       // map step (Eqs. 9-11) about the current mean: wave per component that
       // has a non-zero responsibility in the tile, lanes over dimensions; the
       // tile's contributions are added to the block's FP64 partials once.
-      for (int g = wid; g < G; g += nw) {
-        if (!((gbits[g >> 5] >> (g & 31)) & 1u)) continue;
-        double* q = pb + (size_t)g * P;
-        double slw = 0.0;
+      // Two components at a time, their partials loaded before the tile loop
+      // so that the loads' latency overlaps it.
+      auto active = [&](int g) { return ((gbits[g >> 5] >> (g & 31)) & 1u) != 0u; };
+      for (int g = wid;;) {
+        while (g < G && !active(g)) g += nw;
+        if (g >= G) break;
+        int h = g + nw;
+        while (h < G && !active(h)) h += nw;
+        const bool two = h < G;  // wave-uniform
+        double* qg = pb + (size_t)g * P;
+        double* qh = pb + (size_t)(two ? h : g) * P;
+        const double cg0 = lane == 0 ? qg[0] : 0.0;
+        const double ch0 = lane == 0 && two ? qh[0] : 0.0;
+        double slg = 0.0, slh = 0.0;
         for (int d = lane; d < D; d += kWave) {
-          const float mu = means[(size_t)g * D + d];
-          double s1 = 0.0, s2 = 0.0, sl = 0.0;
+          const double og1 = qg[1 + d], og2 = qg[1 + D + d];
+          const double oh1 = two ? qh[1 + d] : 0.0, oh2 = two ? qh[1 + D + d] : 0.0;
+          const float mug = means[(size_t)g * D + d];
+          const float muh = two ? means[(size_t)h * D + d] : 0.0f;
+          double g1 = 0.0, g2 = 0.0, gl = 0.0, h1 = 0.0, h2 = 0.0, hl = 0.0;
           for (int t = 0; t < nt; ++t) {
-            const float r = as[(size_t)t * G + g];
-            if (r != 0.0f) {
-              const double y = (double)(xs[(size_t)t * XS + d] - mu);
-              const double ry = (double)r * y;
-              s1 += ry;
-              s2 += ry * y;
-              sl += (double)r;
+            const float xv = xs[(size_t)t * XS + d];
+            const float rg = as[(size_t)t * AS + g];
+            const float rh = two ? as[(size_t)t * AS + h] : 0.0f;
+            if (rg != 0.0f) {
+              const double y = (double)(xv - mug);
+              const double ry = (double)rg * y;
+              g1 += ry;
+              g2 += ry * y;
+              gl += (double)rg;
+            }
+            if (rh != 0.0f) {
+              const double y = (double)(xv - muh);
+              const double ry = (double)rh * y;
+              h1 += ry;
+              h2 += ry * y;
+              hl += (double)rh;
             }
           }
-          q[1 + d] += s1;
-          q[1 + D + d] += s2;
-          slw = sl;
+          qg[1 + d] = og1 + g1;
+          qg[1 + D + d] = og2 + g2;
+          if (two) {
+            qh[1 + d] = oh1 + h1;
+            qh[1 + D + d] = oh2 + h2;
+          }
+          slg = gl;
+          slh = hl;
         }
-        if (lane == 0) q[0] += slw;
+        if (lane == 0) {
+          qg[0] = cg0 + slg;
+          if (two) qh[0] = ch0 + slh;
+        }
+        g = h + nw;
       }
     }
     __syncthreads();
@@ -303,7 +443,7 @@ size_t estep_lds(int D, int G, int T, bool wide) {
   const size_t XS = wide ? (size_t)((D + 3) & ~3) : (size_t)D;
   size_t b = sizeof(float) * ((size_t)T * (XS + G) + 1) + sizeof(double) * T;
   b += sizeof(uint32_t) * (((size_t)(G + 31) / 32 + 3) / 4 * 4);
-  if (wide) b += sizeof(float) * 2 * XS * (size_t)wide_gc(D);
+  if (wide) b += sizeof(float) * (2 * XS * (size_t)wide_gc(D) + 3 * (size_t)G + 8 * (size_t)T);
   return b;
 }
 

@@ -139,17 +139,19 @@ __device__ __forceinline__ void wave_lds_sync() {
 // component) block from float4 reads.
 constexpr int kWNT = 256;  // threads of the WIDE kernels
 constexpr int kWT = 32;    // tile rows of the WIDE kernels
+constexpr int kKL = 8;     // threads per sample in their per-sample passes
 __host__ __device__ inline int wide_gc(int D) { return D <= 64 ? 128 : 64; }
 
 // Register-blocked FP32 direct-form screening of a tile (WIDE forms): for
 // every sample t < nt and component g, v = sum_d (x_td s_dg - m_dg)^2 with the
 // parameters of GC components at a time staged in LDS ([XS][GC] each; rows of
 // xs padded with zeros to XS).  KM: as[t][g] = v (weighted distance); else
-// as[t][g] = c_g - v/2 (hi + lo).  Starts and ends with the block in sync.
+// as[t][g] = c_g - v/2 (hi + lo); rows of as are AS apart.  Starts with the
+// block in sync; the caller syncs before reading as.
 template <bool KM>
 __device__ void screen_blocked(const float* __restrict__ xs, int XS, int nt, int D, int G, int GC,
                                const float* __restrict__ sT, const float* __restrict__ mT,
-                               const float* __restrict__ cc, float* __restrict__ as,
+                               const float* __restrict__ cc, float* __restrict__ as, int AS,
                                float* __restrict__ pcs, float* __restrict__ pcm) {
   const int tid = threadIdx.x;
   const int NBG = GC / 4;
@@ -170,19 +172,35 @@ __device__ void screen_blocked(const float* __restrict__ xs, int XS, int nt, int
       for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
         for (int gi = 0; gi < 4; ++gi) acc[ti][gi] = 0.0f;
-      for (int d0 = 0; d0 < XS; d0 += 4) {
-        float4 xv[4];
+      // operands of four dimensions at a time, the next group's loads in
+      // flight while the current one is used
+      const float* xb = xs + (size_t)(4 * tb) * XS;
+      const float* sb = pcs + 4 * gb;
+      const float* mb = pcm + 4 * gb;
+      float4 xc[4], sc[4], mc[4];
 #pragma unroll
-        for (int ti = 0; ti < 4; ++ti)
-          xv[ti] = *(const float4*)(xs + (size_t)(4 * tb + ti) * XS + d0);
+      for (int i = 0; i < 4; ++i) {
+        xc[i] = *(const float4*)(xb + (size_t)i * XS);
+        sc[i] = *(const float4*)(sb + (size_t)i * GC);
+        mc[i] = *(const float4*)(mb + (size_t)i * GC);
+      }
+      for (int d0 = 0; d0 < XS; d0 += 4) {
+        float4 xn[4], sn[4], mn[4];
+        const int dn = d0 + 4 < XS ? d0 + 4 : d0;  // last group: harmless reload
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          xn[i] = *(const float4*)(xb + (size_t)i * XS + dn);
+          sn[i] = *(const float4*)(sb + (size_t)(dn + i) * GC);
+          mn[i] = *(const float4*)(mb + (size_t)(dn + i) * GC);
+        }
 #pragma unroll
         for (int dd = 0; dd < 4; ++dd) {
-          const float4 sv = *(const float4*)(pcs + (size_t)(d0 + dd) * GC + 4 * gb);
-          const float4 mv = *(const float4*)(pcm + (size_t)(d0 + dd) * GC + 4 * gb);
+          const float4 sv = sc[dd];
+          const float4 mv = mc[dd];
 #pragma unroll
           for (int ti = 0; ti < 4; ++ti) {
-            const float x = dd == 0 ? xv[ti].x : dd == 1 ? xv[ti].y : dd == 2 ? xv[ti].z
-                                                                              : xv[ti].w;
+            const float x = dd == 0 ? xc[ti].x : dd == 1 ? xc[ti].y : dd == 2 ? xc[ti].z
+                                                                              : xc[ti].w;
             float u;
             u = fmaf(x, sv.x, -mv.x);
             acc[ti][0] = fmaf(u, u, acc[ti][0]);
@@ -194,6 +212,12 @@ __device__ void screen_blocked(const float* __restrict__ xs, int XS, int nt, int
             acc[ti][3] = fmaf(u, u, acc[ti][3]);
           }
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          xc[i] = xn[i];
+          sc[i] = sn[i];
+          mc[i] = mn[i];
+        }
       }
 #pragma unroll
       for (int ti = 0; ti < 4; ++ti)
@@ -201,7 +225,7 @@ __device__ void screen_blocked(const float* __restrict__ xs, int XS, int nt, int
         for (int gi = 0; gi < 4; ++gi) {
           const int t = 4 * tb + ti, g = gc0 + 4 * gb + gi;
           if (t < nt && g < G)
-            as[(size_t)t * G + g] = KM ? acc[ti][gi] : (cc[g] - 0.5f * acc[ti][gi]) + cc[G + g];
+            as[(size_t)t * AS + g] = KM ? acc[ti][gi] : (cc[g] - 0.5f * acc[ti][gi]) + cc[G + g];
         }
     }
   }

@@ -9,12 +9,15 @@
 //                   distances, lowest index on ties; when the two best FP32
 //                   distances are within twice their rounding-error bound the
 //                   sample is re-decided in FP64, so the result is the FP64
-//                   argmin.  The distance to the chosen mean is re-evaluated in
-//                   FP64 for the inertia.
+//                   argmin.  (k_km_assign_wide: the same decision with a
+//                   register-blocked screening, for many components.)
 //   k_km_accum      map step of Sec. 2.1 with hard l (Eqs. 9-11): per-block
 //                   FP64 count, sum (x - mu_old), sum (x - mu_old)^2
+//                   (k_km_accum_grp: components in LDS-sized groups)
 //   k_km_fin        reduce step (Eqs. 12-14): new means, hand-off variances and
-//                   weights (Sec. 3, Eqs. 5-7 with hard l), counts, inertia
+//                   weights (Sec. 3, Eqs. 5-7 with hard l), counts, and each
+//                   component's inertia term sum_d lam_d sum (x - mu_old)^2
+//   k_km_inertia    inertia = sum of those terms in component order
 //   k_km_resurrect  dead-mean resurrection (Sec. 3.1), a single workgroup that
 //                   does nothing unless some cluster is empty
 #include <algorithm>
@@ -70,17 +73,11 @@ __global__ void __launch_bounds__(kNT) k_km_assign(
     const float* __restrict__ X, int64_t N, int D, int64_t ldx, int G, int64_t chunk,
     const float* __restrict__ means, const float* __restrict__ lam32,
     const double* __restrict__ lam64, int32_t* __restrict__ assign,
-    double* __restrict__ inertia_part, int64_t* __restrict__ n_recomputed,
-    int32_t* __restrict__ dev_status) {
-  __shared__ double sh[kNT];
-  __shared__ int bad;
+    int64_t* __restrict__ n_recomputed) {
   const int b = blockIdx.x;
   const int64_t i0 = (int64_t)b * chunk;
   const int64_t i1 = min(N, i0 + chunk);
   const float gamma = 2.0f * (float)(D + 4) * kU32;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  double acc = 0.0;
   long long nrec = 0;
   for (int64_t i = i0 + threadIdx.x; i < i1; i += kNT) {
     const float* x = X + i * ldx;
@@ -101,11 +98,10 @@ __global__ void __launch_bounds__(kNT) k_km_assign(
         d2 = s;
       }
     }
-    double best;
     if (G > 1 && !(d2 - d1 > gamma * (d1 + d2))) {
       // near tie (or non-finite): decide in FP64, first minimum wins
       ++nrec;
-      best = INFINITY;
+      double best = INFINITY;
       arg = 0;
       for (int g = 0; g < G; ++g) {
         const double s = dist64(x, means + (size_t)g * D, lam64, D);
@@ -114,19 +110,10 @@ __global__ void __launch_bounds__(kNT) k_km_assign(
           arg = g;
         }
       }
-    } else {
-      best = dist64(x, means + (size_t)arg * D, lam64, D);
     }
-    if (!isfinite(best)) bad = 1;
     assign[i] = arg;
-    acc += best;
   }
-  const double tot = block_sum_d<kNT>(acc, sh);
   if (nrec) atomicAdd((unsigned long long*)n_recomputed, (unsigned long long)nrec);
-  if (threadIdx.x == 0) {
-    inertia_part[b] = tot;
-    if (bad) atomicOr(dev_status, GMM_DEV_NONFINITE);
-  }
 }
 
 // Per-block FP64 partials [G][2D+1]: count, sum y, sum y^2 with y = x - mu_old.
@@ -155,16 +142,19 @@ __global__ void __launch_bounds__(kNT) k_km_accum(const float* __restrict__ X, i
   }
 }
 
+// Reduce step, one workgroup per component.  The inertia term of the
+// component, sum_d lam_d sum_i (x_id - mu_gd)^2 about the input mean, comes
+// from the same partials and is left in ig[g] for k_km_inertia.
 __global__ void __launch_bounds__(kNT) k_km_fin(const double* __restrict__ part, int nb, int64_t N,
                                                 int D, int G, float var_floor,
+                                                const double* __restrict__ lam64,
                                                 float* __restrict__ means,
                                                 float* __restrict__ dcovs,
                                                 float* __restrict__ hefts,
                                                 int64_t* __restrict__ counts,
-                                                const double* __restrict__ inertia_part,
-                                                int nbi, double* __restrict__ inertia,
-                                                int32_t* __restrict__ dev_status) {
+                                                double* __restrict__ ig) {
   extern __shared__ double tot[];
+  __shared__ double sh[kNT];
   const int g = blockIdx.x;
   const int P = 2 * D + 1;
   for (int j = threadIdx.x; j < P; j += kNT) {
@@ -178,7 +168,9 @@ __global__ void __launch_bounds__(kNT) k_km_fin(const double* __restrict__ part,
     counts[g] = (int64_t)c;
     hefts[g] = (float)(c / (double)N);
   }
+  double in = 0.0;
   for (int d = threadIdx.x; d < D; d += kNT) {
+    in += lam64[d] * tot[1 + D + d];
     if (c > 0.0) {
       const double dm = tot[1 + d] / c;
       double v = tot[1 + D + d] / c - dm * dm;
@@ -190,9 +182,16 @@ __global__ void __launch_bounds__(kNT) k_km_fin(const double* __restrict__ part,
       dcovs[(size_t)g * D + d] = 1.0f;
     }
   }
-  if (g == 0 && threadIdx.x == 0) {
+  in = block_sum_d<kNT>(in, sh);
+  if (threadIdx.x == 0) ig[g] = in;
+}
+
+// Inertia = sum over components in index order.
+__global__ void k_km_inertia(const double* __restrict__ ig, int G, double* __restrict__ inertia,
+                             int32_t* __restrict__ dev_status) {
+  if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int b = 0; b < nbi; ++b) s += inertia_part[b];
+    for (int g = 0; g < G; ++g) s += ig[g];
     *inertia = s;
     if (!isfinite(s)) atomicOr(dev_status, GMM_DEV_NONFINITE);
   }
@@ -425,45 +424,63 @@ __global__ void __launch_bounds__(kNT) k_km_pre_wide(const double* __restrict__ 
 // distance is q: with u_d = fma(x_d, s_d, -m_d), |du_d| <= 2^-24 (|u_d| +
 // sqrt(lam_d)(|x_d| + |mu_d|)); summing the squares with D FMAs gives
 // 2^-24 ((2 + D) q + 2 sqrt(q (2q + 8Q))), evaluated at the screened value
-// with a 1% margin plus 2^-42 Q for the difference between screened and
-// exact q near zero.
+// with a 1% margin, plus 2^-42 Q for the difference between screened and
+// exact q near zero and 2^-22 v for the FP32 evaluation of the comparisons
+// that use it.
 __device__ __forceinline__ float km_err(float v, float Q, int D) {
   v = fmaxf(v, 0.0f);
   return 1.01f * 0x1p-24f * ((2.0f + (float)D) * v + 2.0f * sqrtf(v * (2.0f * v + 8.0f * Q))) +
-         0x1p-42f * Q;
+         0x1p-22f * v + 0x1p-42f * Q;
 }
 
 // Hard assignment (Eq. 19) over tiles of kWT samples: register-blocked FP32
-// screening of all components, then one wave per sample takes the two
-// smallest screened distances; when every other component's distance, lowered
-// by its bound, stays above the best one raised by its bound, the FP32 argmin
-// is the exact one.  Otherwise the candidates (and the best) are re-decided in
-// FP64, first minimum wins.  The inertia term is the FP64 distance to the
-// chosen mean.  LDS: xs[kWT][XS], as[kWT][G], screening parameter chunks.
+// screening of all components, then kKL threads per sample take the two
+// smallest screened distances v1 <= v2.  With U1 = v1 + err(v1), a component
+// is a candidate when v_g - err(v_g) <= U1; none besides the best means the
+// FP32 argmin is the exact one.  Bounding 2 sqrt(8 Q v) <= sqrt(8 Q / vr) v +
+// sqrt(8 Q vr) (AM-GM about vr = v1) makes err(v) <= A v + B for every
+// component (Q <= Qmax), so v2 (1 - A) - B > U1 rules out all of them at
+// once; otherwise each component is tested with its own bound, and the
+// candidates (and the best) are re-decided in FP64, first minimum wins.
+// LDS: xs[kWT][XS], as[kWT][G + 8], screening parameter chunks, Q_g, lam_d.
 __global__ void __launch_bounds__(kWNT) k_km_assign_wide(
     const float* __restrict__ X, int64_t N, int D, int64_t ldx, int G, int64_t chunk,
     const float* __restrict__ sT, const float* __restrict__ mT, const float* __restrict__ Qg,
     const float* __restrict__ means, const double* __restrict__ lam64,
-    int32_t* __restrict__ assign, double* __restrict__ inertia_part,
-    int64_t* __restrict__ n_recomputed, int32_t* __restrict__ dev_status) {
+    int32_t* __restrict__ assign, int64_t* __restrict__ n_recomputed) {
   extern __shared__ float lds[];
   const int XS = (D + 3) & ~3;
   const int GC = wide_gc(D);
+  const int AS = G + 8;  // the kKL threads of a sample read distinct banks
   float* xs = lds;                       // [kWT][XS]
-  float* as = xs + (size_t)kWT * XS;     // [kWT][G]
-  float* pcs = as + (size_t)kWT * G;     // [XS][GC]
+  float* as = xs + (size_t)kWT * XS;     // [kWT][AS]
+  float* pcs = as + (size_t)kWT * AS;    // [XS][GC]
   float* pcm = pcs + (size_t)XS * GC;    // [XS][GC]
-  __shared__ double wacc[kWNT / kWave];
+  float* qs = pcm + (size_t)XS * GC;     // [G]
+  double* l64 = (double*)(qs + ((G + 1) & ~1));  // [D]
+  __shared__ float wq[kWNT / kWave];
   __shared__ int wrec[kWNT / kWave];
-  __shared__ int bad;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wid = tid / kWave;
+  const int ts = tid / kKL, j = tid % kKL;  // sample slot of the decision pass, sub-lane
   const int b = blockIdx.x;
   const int64_t i0 = (int64_t)b * chunk;
   const int64_t i1 = min(N, i0 + chunk);
-  if (tid == 0) bad = 0;
-  double acc = 0.0;  // lane 0 of each wave
+  float qm = 0.0f;
+  for (int g = tid; g < G; g += kWNT) {
+    const float q = Qg[g];
+    qs[g] = q;
+    qm = fmaxf(qm, q);
+  }
+  for (int d = tid; d < D; d += kWNT) l64[d] = lam64[d];
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) qm = fmaxf(qm, __shfl_xor(qm, off));
+  if (lane == 0) wq[wid] = qm;
+  __syncthreads();
+  float Qmax = wq[0];
+  for (int w = 1; w < kWNT / kWave; ++w) Qmax = fmaxf(Qmax, wq[w]);
+  const float a0 = 1.01f * 0x1p-24f * (2.0f + (float)D + 2.8284272f) + 0x1p-21f;
   int nrec = 0;
   for (int64_t t0 = i0; t0 < i1; t0 += kWT) {
     const int nt = (int)min((int64_t)kWT, i1 - t0);
@@ -472,14 +489,14 @@ __global__ void __launch_bounds__(kWNT) k_km_assign_wide(
       xs[p] = d < D ? X[(t0 + t) * ldx + d] : 0.0f;
     }
     __syncthreads();
-    screen_blocked<true>(xs, XS, nt, D, G, GC, sT, mT, nullptr, as, pcs, pcm);
+    screen_blocked<true>(xs, XS, nt, D, G, GC, sT, mT, nullptr, as, AS, pcs, pcm);
     __syncthreads();
-    for (int t = wid; t < nt; t += kWNT / kWave) {
-      const float* row = as + (size_t)t * G;
-      const float* x = xs + (size_t)t * XS;
+    if (ts < nt) {  // uniform over the kKL threads of a sample
+      const float* row = as + (size_t)ts * AS;
+      const float* x = xs + (size_t)ts * XS;
       float v1 = INFINITY, v2 = INFINITY;
       int g1 = G;
-      for (int g = lane; g < G; g += kWave) {
+      for (int g = j; g < G; g += kKL) {  // increasing g: the first minimum stays
         const float v = row[g];
         if (v < v1) {
           v2 = v1;
@@ -490,7 +507,7 @@ __global__ void __launch_bounds__(kWNT) k_km_assign_wide(
         }
       }
 #pragma unroll
-      for (int off = 1; off < kWave; off <<= 1) {
+      for (int off = 1; off < kKL; off <<= 1) {
         const float o1 = __shfl_xor(v1, off);
         const float o2 = __shfl_xor(v2, off);
         const int og = __shfl_xor(g1, off);
@@ -502,40 +519,49 @@ __global__ void __launch_bounds__(kWNT) k_km_assign_wide(
           v2 = fminf(v2, o1);
         }
       }
-      int arg = g1;
       const bool full = !(v1 < INFINITY) || g1 >= G;  // no finite screened value
-      bool any = full;
-      const float U1 = full ? 0.0f : v1 + km_err(v1, Qg[g1], D);
+      bool need = full;
+      float U1 = 0.0f;
       if (!full) {
-        // every other component's distance, lowered by its bound, must stay
-        // above U1
-        bool c = false;
-        for (int g = lane; g < G; g += kWave) {
-          const float v = row[g];
-          if (g != g1 && !(v - km_err(v, Qg[g], D) > U1)) c = true;
+        U1 = v1 + km_err(v1, qs[g1], D);
+        const float vr = fmaxf(v1, 1e-30f);
+        const float A = a0 + 1.01f * 0x1p-24f * sqrtf(8.0f * Qmax / vr);
+        const float B = 1.01f * 0x1p-24f * sqrtf(8.0f * Qmax * vr) + 0x1p-42f * Qmax;
+        if (!(A < 0.5f && v2 * (1.0f - A) - B > U1)) {
+          bool c = false;
+          for (int g = j; g < G; g += kKL) {
+            const float v = row[g];
+            if (g != g1 && !(v - km_err(v, qs[g], D) > U1)) c = true;
+          }
+#pragma unroll
+          for (int off = 1; off < kKL; off <<= 1) {
+            const int o = __shfl_xor((int)c, off);  // every lane takes part
+            c = c || o != 0;
+          }
+          need = c;
         }
-        any = __ballot(c) != 0;
       }
-      if (any) {
+      int arg = g1;
+      if (need) {
         // FP64 re-decision over the candidates (all components when full)
         double bs = INFINITY;
         int bg = G;
-        for (int g = lane; g < G; g += kWave) {
+        for (int g = j; g < G; g += kKL) {
           const float v = row[g];
-          if (!(full || g == g1 || !(v - km_err(v, Qg[g], D) > U1))) continue;
+          if (!(full || g == g1 || !(v - km_err(v, qs[g], D) > U1))) continue;
           const float* mu = means + (size_t)g * D;
           double s = 0.0;
           for (int d = 0; d < D; ++d) {
             const double u = (double)x[d] - (double)mu[d];
-            s += lam64[d] * u * u;
+            s += l64[d] * u * u;
           }
-          if (s < bs) {  // lanes visit their components in increasing order
+          if (s < bs) {
             bs = s;
             bg = g;
           }
         }
 #pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
+        for (int off = 1; off < kKL; off <<= 1) {
           const double os = __shfl_xor(bs, off);
           const int og = __shfl_xor(bg, off);
           if (os < bs || (os == bs && og < bg)) {
@@ -544,46 +570,28 @@ __global__ void __launch_bounds__(kWNT) k_km_assign_wide(
           }
         }
         arg = bg < G ? bg : 0;
-        ++nrec;
+        nrec += j == 0;
       }
-      // inertia term: FP64 distance to the chosen mean, lanes over d
-      const float* mu = means + (size_t)arg * D;
-      double s = 0.0;
-      for (int d = lane; d < D; d += kWave) {
-        const double u = (double)x[d] - (double)mu[d];
-        s += lam64[d] * u * u;
-      }
-#pragma unroll
-      for (int off = 1; off < kWave; off <<= 1) s += __shfl_xor(s, off);
-      if (lane == 0) {
-        assign[t0 + t] = arg;
-        acc += s;
-        if (!isfinite(s)) bad = 1;
-      }
+      if (j == 0) assign[t0 + ts] = arg;
     }
     __syncthreads();  // xs/as are rewritten by the next tile
   }
-  if (lane == 0) {
-    wacc[wid] = acc;
-    wrec[wid] = nrec;
-  }
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) nrec += __shfl_xor(nrec, off);
+  if (lane == 0) wrec[wid] = nrec;
   __syncthreads();
   if (tid == 0) {
-    double tot = 0.0;
     long long nr = 0;
-    for (int w = 0; w < kWNT / kWave; ++w) {
-      tot += wacc[w];
-      nr += wrec[w];
-    }
-    inertia_part[b] = tot;
+    for (int w = 0; w < kWNT / kWave; ++w) nr += wrec[w];
     if (nr) atomicAdd((unsigned long long*)n_recomputed, (unsigned long long)nr);
-    if (bad) atomicOr(dev_status, GMM_DEV_NONFINITE);
   }
 }
 
 size_t km_wide_lds(int D, int G) {
   const size_t XS = (size_t)((D + 3) & ~3);
-  return sizeof(float) * ((size_t)kWT * (XS + G) + 2 * XS * (size_t)wide_gc(D));
+  return sizeof(float) * ((size_t)kWT * (XS + G + 8) + 2 * XS * (size_t)wide_gc(D) +
+                          (size_t)((G + 1) & ~1)) +
+         sizeof(double) * (size_t)D;
 }
 
 // Map step of the hard assignment (Eqs. 9-11) with the components split in
@@ -768,12 +776,11 @@ hipError_t launch_kmeans(const float* X, int64_t N, int D, int64_t ldx, int G, i
     ProfScope ps(kProfKmAssign, st);
     set_max_lds((const void*)k_km_assign_wide, km_wide_lds(D, G));
     hipLaunchKernelGGL(k_km_assign_wide, dim3(nb), dim3(kWNT), km_wide_lds(D, G), st, X, N, D,
-                       ldx, G, chunk, w.s, w.m, w.c, means, w.lam64, asg, w.scalars, nrec,
-                       dev_status);
+                       ldx, G, chunk, w.s, w.m, w.c, means, w.lam64, asg, nrec);
   } else {
     ProfScope ps(kProfKmAssign, st);
     hipLaunchKernelGGL(k_km_assign, dim3(nb), dim3(kNT), 0, st, X, N, D, ldx, G, chunk, means,
-                       w.lam32, w.lam64, asg, w.scalars, nrec, dev_status);
+                       w.lam32, w.lam64, asg, nrec);
   }
   int nba = nb;  // partial sets of the map step
   {
@@ -805,9 +812,10 @@ hipError_t launch_kmeans(const float* X, int64_t N, int D, int64_t ldx, int G, i
                          asg, w.partials);
     }
   }
+  // per-component inertia terms in c64 (unused by k-means)
   hipLaunchKernelGGL(k_km_fin, dim3(G), dim3(kNT), sizeof(double) * (2 * D + 1), st, w.partials,
-                     nba, N, D, G, var_floor, means, dcovs, hefts, counts, w.scalars, nb, inertia,
-                     dev_status);
+                     nba, N, D, G, var_floor, w.lam64, means, dcovs, hefts, counts, w.c64);
+  hipLaunchKernelGGL(k_km_inertia, dim3(1), dim3(64), 0, st, w.c64, G, inertia, dev_status);
   hipLaunchKernelGGL(k_km_resurrect, dim3(1), dim3(kRT), 0, st, X, N, D, ldx, G, counts, asg,
                      means, (int64_t*)w.partials);
   return hipGetLastError();
