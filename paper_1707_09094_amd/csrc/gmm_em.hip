@@ -329,6 +329,10 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
         double* qh = pb + (size_t)(two ? h : g) * P;
         const double cg0 = lane == 0 ? qg[0] : 0.0;
         const double ch0 = lane == 0 && two ? qh[0] : 0.0;
+        // the tile's samples with a non-zero responsibility for g or h (T <= 64)
+        const unsigned long long mem =
+            __ballot(lane < nt && (as[(size_t)lane * AS + g] != 0.0f ||
+                                   (two && as[(size_t)lane * AS + h] != 0.0f)));
         double slg = 0.0, slh = 0.0;
         for (int d = lane; d < D; d += kWave) {
           const double og1 = qg[1 + d], og2 = qg[1 + D + d];
@@ -336,7 +340,8 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
           const float mug = means[(size_t)g * D + d];
           const float muh = two ? means[(size_t)h * D + d] : 0.0f;
           double g1 = 0.0, g2 = 0.0, gl = 0.0, h1 = 0.0, h2 = 0.0, hl = 0.0;
-          for (int t = 0; t < nt; ++t) {
+          for (unsigned long long m = mem; m; m &= m - 1) {
+            const int t = __ffsll((long long)m) - 1;
             const float xv = xs[(size_t)t * XS + d];
             const float rg = as[(size_t)t * AS + g];
             const float rh = two ? as[(size_t)t * AS + h] : 0.0f;

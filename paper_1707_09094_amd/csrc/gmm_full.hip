@@ -101,6 +101,11 @@ __global__ void __launch_bounds__(kNT) k_pre_full(const float* __restrict__ heft
 // e*D - e*(e-1)/2.
 __device__ __forceinline__ int tri_index(int d, int e, int D) { return e * D - (e * (e - 1)) / 2 + (d - e); }
 
+// LDS of the near-set recompute: per wave, up to kWB FP64 entries of W_g's
+// packed rows and up to kWR row offsets b_r = (W_g mu_g)_r.
+constexpr int kWB = 1024;
+constexpr int kWR = 64;
+
 template <bool MSTEP>
 __global__ void __launch_bounds__(kNT) k_estep_full(
     const float* __restrict__ X, int64_t N, int D, int64_t ldx, int G, int T, int64_t chunk,
@@ -108,24 +113,31 @@ __global__ void __launch_bounds__(kNT) k_estep_full(
     const double* __restrict__ c64, const float* __restrict__ means,
     double* __restrict__ part, double* __restrict__ ll_part, float* __restrict__ per_sample,
     int32_t* __restrict__ dev_status) {
-  extern __shared__ float lds[];
-  const int DS = D + 1;             // padded row stride (conflict-free column reads)
-  float* xs = lds;                  // [T][D+1]
-  float* as = xs + (size_t)T * DS;  // [T][G]
-  double* lse = (double*)(as + (size_t)T * G + ((T * G) & 1));  // [T]
-  uint32_t* gbits = (uint32_t*)(lse + T);  // [G/32]: component has a non-zero r in the tile
+  extern __shared__ double ldsd[];
+  const int nw = kNT / kWave;
+  double* wst = ldsd;                          // [nw][kWB] packed rows of W_g (FP64)
+  double* bst = wst + (size_t)nw * kWB;        // [nw][kWR] b_r
+  double* lse = bst + (size_t)nw * kWR;        // [T]
+  double* mst = lse + T;                       // [nw][D] mu_g of the near recompute
+  float* xs = (float*)(mst + (size_t)nw * D);  // [T][D+1]
+  const int DS = D + 1;                        // padded row stride (conflict-free column reads)
+  float* as = xs + (size_t)T * DS;             // [T][G]
+  float* mxs = as + (size_t)T * G;             // [T] screened maximum
+  uint32_t* gbits = (uint32_t*)(mxs + T);      // [G/32]: component has a non-zero r in the tile
   const int NGB = (G + 31) / 32;
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wid = tid / kWave;
-  const int nw = kNT / kWave;
   const int b = blockIdx.x;
   const int64_t i0 = (int64_t)b * chunk;
   const int64_t i1 = min(N, i0 + chunk);
   const int NT2 = D * (D + 1) / 2;
   const int P = 1 + D + NT2;
   double* pb = part + (size_t)b * G * P;
+  double* wl = wst + (size_t)wid * kWB;
+  double* bl = bst + (size_t)wid * kWR;
+  double* ml = mst + (size_t)wid * D;
   if (tid == 0) bad = 0;
   if (MSTEP)
     for (int p = tid; p < G * P; p += kNT) pb[p] = 0.0;
@@ -133,9 +145,9 @@ __global__ void __launch_bounds__(kNT) k_estep_full(
   __syncthreads();
   for (int64_t t0 = i0; t0 < i1; t0 += T) {
     const int nt = (int)min((int64_t)T, i1 - t0);
-    for (int p = tid; p < nt * D; p += kNT) {
-      const int t = p / D, d = p - t * D;
-      xs[(size_t)t * DS + d] = X[(t0 + t) * ldx + d];
+    for (int p = tid; p < nt * DS; p += kNT) {  // column D holds 1 (see the map step)
+      const int t = p / DS, d = p - t * DS;
+      xs[p] = d < D ? X[(t0 + t) * ldx + d] : 1.0f;
     }
     for (int p = tid; p < NGB; p += kNT) gbits[p] = 0u;
     __syncthreads();
@@ -148,64 +160,120 @@ __global__ void __launch_bounds__(kNT) k_estep_full(
         const float* x = xs + (size_t)t * DS;
         float acc = 0.0f;
         for (int r = 0; r < D; ++r) {
+          const float* wr = Wg + (size_t)r * D;
           float z = 0.0f;
-          for (int c = 0; c <= r; ++c) z = fmaf(Wg[(size_t)r * D + c], x[c] - mu[c], z);
+          int c = 0;
+          for (; c + 8 <= r + 1; c += 8) {  // operands of 8 terms loaded together
+            float wv[8], mv[8], xv[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              wv[i] = wr[c + i];
+              mv[i] = mu[c + i];
+              xv[i] = x[c + i];
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) z = fmaf(wv[i], xv[i] - mv[i], z);
+          }
+          for (; c <= r; ++c) z = fmaf(wr[c], x[c] - mu[c], z);
           acc = fmaf(z, z, acc);
         }
         as[(size_t)t * G + g] = (cg - 0.5f * acc) + cl;
       }
     }
     __syncthreads();
-    // Screening in FP32, FP64 recompute of the near set (see the diagonal
-    // kernel): a64 = c_g - 1/2 ||W_g (x - mu_g)||^2 with W_g = L_g^-1 in FP64;
-    // lanes own rows r of the triangular product.
+    // screened maximum per sample
     for (int t = wid; t < nt; t += nw) {
-      float* a = as + (size_t)t * G;
-      const float* x = xs + (size_t)t * DS;
+      const float* a = as + (size_t)t * G;
       float mx = -INFINITY;
       for (int g = lane; g < G; g += kWave) mx = fmaxf(mx, a[g]);
       mx = wave_max(mx);
-      const double M = (double)mx;
-      unsigned long long nearbits = 0;
-      for (int c = 0, g0 = 0; g0 < G; ++c, g0 += kWave) {
-        const int g = g0 + lane;
-        const bool near = g < G && a[g] >= mx - kNearGap;
-        if (near) nearbits |= 1ull << c;
-        unsigned long long msk = __ballot(near);
-        while (msk) {
-          const int j = __ffsll((long long)msk) - 1;
-          msk &= msk - 1;
-          const int gg = g0 + j;
-          const double* Wg = W64 + (size_t)gg * D * D;
-          const float* mu = means + (size_t)gg * D;
-          double q = 0.0;
-          for (int r = lane; r < D; r += kWave) {
-            double z = 0.0;
-            for (int cc2 = 0; cc2 <= r; ++cc2)
-              z += Wg[(size_t)r * D + cc2] * ((double)x[cc2] - (double)mu[cc2]);
-            q += z * z;
+      if (lane == 0) mxs[t] = mx;
+    }
+    __syncthreads();
+    // Near set {g : a_g >= mx - kNearGap} recomputed in FP64 from the FP32
+    // parameters: a64 = c_g - 1/2 ||z||^2, z = W_g x - W_g mu_g with W_g =
+    // L_g^-1 in FP64.  Wave per component, lane per sample; the packed rows of
+    // W_g are staged in LDS a chunk at a time and read by all near lanes.
+    // Every value is moved to the frame of its sample's M = mx.
+    for (int g = __builtin_amdgcn_readfirstlane(wid); g < G; g += nw) {
+      float* ag = as + g;
+      const int t = lane;
+      const float mx = t < nt ? mxs[t] : 0.0f;
+      const float v = t < nt ? ag[(size_t)t * G] : -INFINITY;
+      const bool near = t < nt && v >= mx - kNearGap;
+      const unsigned long long msk = __ballot(near);
+      double q = 0.0;
+      if (msk) {
+        const double* Wg = W64 + (size_t)g * D * D;
+        const float* x = xs + (size_t)(t < nt ? t : 0) * DS;
+        for (int c = lane; c < D; c += kWave) ml[c] = (double)means[(size_t)g * D + c];
+        for (int r0 = 0; r0 < D;) {
+          // rows r0 .. r1-1: packed entries off(r) = r(r+1)/2 - off(r0)
+          int r1 = r0, ne = 0;
+          while (r1 < D && r1 - r0 < kWR && ne + r1 + 1 <= kWB) {
+            ne += r1 + 1;
+            ++r1;
           }
-          q = wave_sum_d(q);
-          if (lane == j) a[gg] = (float)(c64[gg] - 0.5 * q - M);
+          const int base = r0 * (r0 + 1) / 2;
+          for (int r = r0; r < r1; ++r)
+            for (int c = lane; c <= r; c += kWave) wl[r * (r + 1) / 2 - base + c] = Wg[(size_t)r * D + c];
+          wave_lds_sync();
+          for (int r = r0 + lane; r < r1; r += kWave) {
+            const double* wr = wl + r * (r + 1) / 2 - base;
+            double s = 0.0;
+            for (int c = 0; c <= r; ++c) s = fma(wr[c], ml[c], s);
+            bl[r - r0] = s;
+          }
+          wave_lds_sync();
+          if (near) {
+            for (int r = r0; r < r1; ++r) {
+              const double* wr = wl + r * (r + 1) / 2 - base;
+              double z = -bl[r - r0];
+              int c = 0;
+              for (; c + 8 <= r + 1; c += 8) {
+                double wv[8];
+                float xv[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                  wv[i] = wr[c + i];
+                  xv[i] = x[c + i];
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) z = fma(wv[i], (double)xv[i], z);
+              }
+              for (; c <= r; ++c) z = fma(wr[c], (double)x[c], z);
+              q = fma(z, z, q);
+            }
+          }
+          wave_lds_sync();  // the next chunk overwrites the staging buffers
+          r0 = r1;
         }
       }
-      double sm = 0.0;
-      for (int c = 0, g0 = 0; g0 < G; ++c, g0 += kWave) {
-        const int g = g0 + lane;
-        if (g < G) sm += (double)__expf(((nearbits >> c) & 1ull) ? a[g] : a[g] - mx);
+      if (t < nt) {
+        const double M = (double)mx;
+        ag[(size_t)t * G] = near ? (float)(c64[g] - 0.5 * q - M) : v - mx;
       }
+    }
+    __syncthreads();
+    // log-sum-exp about M + max (Eqs. 16-18) and responsibilities
+    for (int t = wid; t < nt; t += nw) {
+      float* a = as + (size_t)t * G;
+      const double M = (double)mxs[t];
+      float dn = -INFINITY;
+      for (int g = lane; g < G; g += kWave) dn = fmaxf(dn, a[g]);
+      dn = wave_max(dn);
+      dn = dn > -INFINITY ? dn : 0.0f;
+      double sm = 0.0;
+      for (int g = lane; g < G; g += kWave) sm += (double)__expf(a[g] - dn);
       sm = wave_sum_d(sm);
-      const double l = M + log(sm);
+      const double l = (M + (double)dn) + log(sm);
       if (MSTEP) {
-        const float dl = (float)(l - M);
-        for (int c = 0, g0 = 0; g0 < G; ++c, g0 += kWave) {
-          const int g = g0 + lane;
-          if (g < G) {
-            const float z = (((nearbits >> c) & 1ull) ? a[g] : a[g] - mx) - dl;
-            const float r = z >= -kRespCut ? __expf(z) : 0.0f;
-            a[g] = r;
-            if (r != 0.0f) atomicOr(&gbits[g >> 5], 1u << (g & 31));
-          }
+        const float dl = (float)log(sm);
+        for (int g = lane; g < G; g += kWave) {
+          const float z = (a[g] - dn) - dl;
+          const float r = z >= -kRespCut ? __expf(z) : 0.0f;
+          a[g] = r;
+          if (r != 0.0f) atomicOr(&gbits[g >> 5], 1u << (g & 31));
         }
       }
       if (lane == 0) {
@@ -221,39 +289,61 @@ __global__ void __launch_bounds__(kNT) k_estep_full(
       // entry k of component g: 0 -> L, 1..D -> sum r y_d, then the packed
       // lower triangle sum r y_d y_e (d >= e, column e after column e-1).
       // Wave per component with a non-zero responsibility in the tile, lanes
-      // over entries; the tile's contributions are added to the partials once.
+      // over entries (kSL per lane at a time, their (d, e) decoded once),
+      // visiting only the tile's samples with r != 0 (a ballot mask, T <= 64).
+      // Every entry is (r y_d) y_e: column D of the tile holds 1 and mu is taken
+      // as 0 there, so y = 1 stands in for the missing factors of L and sum r y.
+      // The tile's contributions are added to the partials once.
+      constexpr int kSL = 9;
       for (int g = wid; g < G; g += nw) {
         if (!((gbits[g >> 5] >> (g & 31)) & 1u)) continue;
+        const unsigned long long mem = __ballot(lane < nt && as[(size_t)lane * G + g] != 0.0f);
         double* q = pb + (size_t)g * P;
-        for (int k = lane; k < P; k += kWave) {
-          int d = 0, e = 0;
-          if (k >= 1 && k <= D) {
-            d = k - 1;
-          } else if (k > D) {
-            int qq = k - 1 - D;
-            while (qq >= D - e) {
-              qq -= D - e;
-              ++e;
-            }
-            d = e + qq;
-          }
-          const float mud = means[(size_t)g * D + d];
-          const float mue = means[(size_t)g * D + e];
-          double s = 0.0;
-          for (int t = 0; t < nt; ++t) {
-            const float r = as[(size_t)t * G + g];
-            if (r != 0.0f) {
-              if (k == 0) {
-                s += (double)r;
-              } else if (k <= D) {
-                s += (double)r * (double)(xs[(size_t)t * DS + d] - mud);
-              } else {
-                s += (double)r * (double)(xs[(size_t)t * DS + d] - mud) *
-                     (double)(xs[(size_t)t * DS + e] - mue);
+        const float* mug = means + (size_t)g * D;
+        for (int k0 = 0; k0 < P; k0 += kWave * kSL) {
+          int od[kSL], oe[kSL];
+          float md[kSL], me[kSL];
+          double acc[kSL];
+#pragma unroll
+          for (int i = 0; i < kSL; ++i) {
+            const int k = k0 + lane + kWave * i;
+            int d = D, e = D;  // k = 0 (and k >= P): both factors 1
+            if (k >= 1 && k <= D) {
+              d = k - 1;
+            } else if (k > D && k < P) {
+              int qq = k - 1 - D;
+              e = 0;
+              while (qq >= D - e) {
+                qq -= D - e;
+                ++e;
               }
+              d = e + qq;
+            }
+            od[i] = d;
+            oe[i] = e;
+            md[i] = d < D ? mug[d] : 0.0f;
+            me[i] = e < D ? mug[e] : 0.0f;
+            acc[i] = k < P ? q[k] : 0.0;
+          }
+          double sum[kSL];
+#pragma unroll
+          for (int i = 0; i < kSL; ++i) sum[i] = 0.0;
+          for (unsigned long long m = mem; m; m &= m - 1) {
+            const int t = __ffsll((long long)m) - 1;
+            const double r = (double)as[(size_t)t * G + g];
+            const float* xt = xs + (size_t)t * DS;
+#pragma unroll
+            for (int i = 0; i < kSL; ++i) {
+              const double yd = (double)(xt[od[i]] - md[i]);
+              const double ye = (double)(xt[oe[i]] - me[i]);
+              sum[i] = fma(r * yd, ye, sum[i]);
             }
           }
-          q[k] += s;
+#pragma unroll
+          for (int i = 0; i < kSL; ++i) {
+            const int k = k0 + lane + kWave * i;
+            if (k < P) q[k] = acc[i] + sum[i];
+          }
         }
       }
     }
@@ -332,10 +422,15 @@ __global__ void k_ll_finish_full(const double* __restrict__ ll_part, int nb, int
   }
 }
 
+// LDS of k_estep_full for tile rows T.
+size_t estep_full_lds(int D, int G, int T) {
+  return sizeof(double) * ((size_t)(kNT / kWave) * (kWB + kWR + D) + T) +
+         sizeof(float) * ((size_t)T * (D + 1 + G) + T) + sizeof(uint32_t) * ((G + 31) / 32);
+}
+
 int tile_rows_full(int D, int G) {
-  int T = 64;
-  while (T > 1 && (size_t)T * (D + G + 3) * sizeof(float) + (size_t)(G / 8 + 8) > 60 * 1024)
-    T >>= 1;
+  int T = 64;  // at most one wave of samples (ballot masks over the tile)
+  while (T > 1 && estep_full_lds(D, G, T) > 62 * 1024) T >>= 1;  // default LDS limit
   return T;
 }
 
@@ -349,8 +444,7 @@ hipError_t launch_em_full(const float* X, int64_t N, int D, int64_t ldx, int G, 
   const int nb = partial_blocks(N, 4 * T);
   const int64_t chunk = (N + nb - 1) / nb;
   const int P = 1 + D + D * (D + 1) / 2;
-  const size_t lds = sizeof(float) * ((size_t)T * (D + 1 + G) + 1) + sizeof(double) * T +
-                     sizeof(uint32_t) * ((G + 31) / 32);
+  const size_t lds = estep_full_lds(D, G, T);
   hipLaunchKernelGGL(k_init_full, dim3(1), dim3(64), 0, st, dev_status, n_recomputed);
   hipLaunchKernelGGL(k_pre_full, dim3(G), dim3(kNT), 0, st, hefts, covs, D, G, w.partials, w.W,
                      w.W64, w.c, w.c64, dev_status);
@@ -372,8 +466,7 @@ hipError_t launch_loglik_full(const float* X, int64_t N, int D, int64_t ldx, int
   const int T = tile_rows_full(D, G);
   const int nb = partial_blocks(N, 4 * T);
   const int64_t chunk = (N + nb - 1) / nb;
-  const size_t lds = sizeof(float) * ((size_t)T * (D + 1 + G) + 1) + sizeof(double) * T +
-                     sizeof(uint32_t) * ((G + 31) / 32);
+  const size_t lds = estep_full_lds(D, G, T);
   hipLaunchKernelGGL(k_init_full, dim3(1), dim3(64), 0, st, dev_status, nullptr);
   hipLaunchKernelGGL(k_pre_full, dim3(G), dim3(kNT), 0, st, hefts, covs, D, G, w.partials, w.W,
                      w.W64, w.c, w.c64, dev_status);
