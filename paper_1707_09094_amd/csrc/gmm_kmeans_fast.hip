@@ -1,6 +1,9 @@
 // gmm_kmeans_fast.hip -- one-pass k-means iteration for D <= 128 dimensions
 // and G <= 128 means (larger shapes use the generic kernels of
-// gmm_kmeans.hip).
+// gmm_kmeans.hip).  Two screening forms: k_km2 (matrix cores, BF16x3; every
+// batched call and the single-model call in that precision; described at its
+// definition) and k_km_fast (FP32 direct form, the single-model FP32 call),
+// described here.
 //
 // Workgroup of 8 waves, persistent over a contiguous sample range, tiles of 32
 // samples (next tile prefetched into registers).  Per tile:
@@ -353,41 +356,6 @@ __global__ void __launch_bounds__(kThreads) k_km_fast(KmArgs a) {
   km_range<CPW, DPL>(a, i0, i1, b, lds_raw);
 }
 
-// Batched: persistent grid over the work items; per-model constants at
-// model * stride in the batched workspace.
-template <int CPW, int DPL>
-__global__ void __launch_bounds__(kThreads) k_km_fast_batched(KmArgs base,
-                                                              const gmm_model_desc* models,
-                                                              const BatchItemDev* items,
-                                                              const int* n_items, int Gmax) {
-  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
-  const int ni = *n_items;
-  const int D = base.D;
-  const int P = 2 * D + 1;
-  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
-    const BatchItemDev item = items[it];
-    const gmm_model_desc& m = models[item.model];
-    const size_t mi = (size_t)item.model;
-    KmArgs a = base;
-    a.X = m.X;
-    a.N = m.N;
-    a.ldx = D;
-    a.G = m.G;
-    a.means = m.means;
-    a.mprm = base.mprm + mi * Gmax * (D + 1);
-    a.sd = base.sd + mi * D;
-    a.lam64 = base.lam64 + mi * D;
-    a.mnorm = base.mnorm + mi;
-    a.assign = m.assign;
-    a.part = base.part + (size_t)it * Gmax * P;
-    a.in_part = base.in_part + it;
-    a.n_rec = nullptr;
-    a.dev_status = m.dev_status;
-    km_range<CPW, DPL>(a, item.i0, item.i1, 0, lds_raw);
-    __syncthreads();
-  }
-}
-
 // lam_d, s_d = sqrt(lam_d), m_gd = mu_gd s_d and max_g |m_g| (one workgroup).
 __device__ void km_pre(const double* __restrict__ gvar, int D, int G, float var_floor, int dist,
                        const float* __restrict__ means, double* __restrict__ lam64,
@@ -433,19 +401,6 @@ __global__ void __launch_bounds__(256) k_km_pre_fast(const double* __restrict__ 
                                                      float* __restrict__ mprm,
                                                      float* __restrict__ mnorm) {
   km_pre(gvar, D, G, var_floor, dist, means, lam64, sd, mprm, mnorm);
-}
-
-// one workgroup per model
-__global__ void __launch_bounds__(256) k_km_pre_batched(const gmm_model_desc* models, int D,
-                                                        int Gmax, float var_floor, int dist,
-                                                        double* lam64, float* sd, float* mprm,
-                                                        float* mnorm) {
-  const int mi = blockIdx.x;
-  const gmm_model_desc& m = models[mi];
-  if (!batch_desc_ok(m, Gmax)) return;
-  if (threadIdx.x == 0 && m.inertia) *m.inertia = 0.0;
-  km_pre(m.gvar, D, m.G, var_floor, dist, m.means, lam64 + (size_t)mi * D, sd + (size_t)mi * D,
-         mprm + (size_t)mi * Gmax * (D + 1), mnorm + mi);
 }
 
 // Reduce step of the k-means map: pairwise (count, mean, M2) combination in
@@ -1471,24 +1426,6 @@ hipError_t launch_kmeans_fast(const float* X, int64_t N, int D, int64_t ldx, int
                      means, dcovs, hefts, counts, w.scalars, inertia, dev_status);
   return hipGetLastError();
 }
-
-namespace {
-
-template <int CPW, int DPL>
-void km_launch_batched_one(const KmArgs& base, const gmm_model_desc* models,
-                           const BatchWorkspace& bw, int grid, size_t lds, hipStream_t st) {
-  auto kern = k_km_fast_batched<CPW, DPL>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
-    attr_set = true;
-  }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, st, base, models, bw.items,
-                     bw.n_items, bw.Gmax);
-}
-
-}  // namespace
 
 hipError_t launch_kmeans_batched(const gmm_model_desc* models, int n_models, int n_items_host,
                                  int D, int dist, float var_floor, const BatchWorkspace& bw,
