@@ -932,7 +932,7 @@ __global__ void __launch_bounds__(256) k_fin_welford_batched(const gmm_model_des
 // 16 cb + l%16), so every per-sample reduction (bounded maximum, near count,
 // log-sum-exp) is a butterfly over the 16 lanes of a lane row.  Near pairs are
 // recomputed exactly (FP64, or the FP32 direct form under its bound) by
-// 4-lane groups reading the sample and parameters from global memory.  The
+// 16-lane rows reading the sample and parameters from global memory.  The
 // map step of component g is done by wave g % 8 (its "owner"), which keeps
 // (L, m, Q) of its components in registers; every 128 samples the waves pass
 // their non-zero responsibilities to the owners through LDS lists, in a fixed
