@@ -1,26 +1,25 @@
-// gmm_em_fast.hip -- one-pass EM kernel for diagonal covariances with up to
+// gmm_em_fast.hip -- one-pass EM kernels for diagonal covariances with up to
 // 128 Gaussians and 128 dimensions (the shapes of the D=100/G=100 and batched
 // D=40 workloads).  Shapes outside that envelope use the generic kernels of
-// gmm_em.hip.
+// gmm_em.hip.  Two arithmetic forms:
+//   k_em2      the expanded form c'_g + sum_k A_gk B_kn (Sec. 2.2 Eq. 15
+//              expanded, A_g = [Lambda_g mu_g ; -1/2 Lambda_g], B_n = [x_n ;
+//              x_n^2]) on the matrix cores, v_mfma_f32_16x16x32_bf16 with both
+//              operands split into BF16 hi + lo and the three products hi*hi,
+//              hi*lo, lo*hi accumulated in FP32; described at its definition;
+//   k_em_fast  the FP32 direct form on the vector ALUs, described here.
 //
-// Workgroup of 8 waves, persistent over a contiguous range of samples, tiles of
-// T = 32 samples; the next tile is loaded into registers (all loads issued at
-// once) while the current one is processed.  Per tile:
+// k_em_fast: workgroup of 8 waves, persistent over a contiguous range of
+// samples, tiles of T = 32 samples; the next tile is loaded into registers (all
+// loads issued at once) while the current one is processed.  Per tile:
 //   1. the tile's samples are staged in LDS (xf[n][d]);
-//   2. screening: FP32 log-densities a_gn of every (component, sample) pair,
-//      either
-//        FORM_FP32   direct form c_g - 1/2 sum_d (x_d s_gd - m_gd)^2 on the
-//                    vector ALUs (s = 1/sigma, m = mu/sigma, staged in LDS), or
-//        FORM_BF16X3 expanded form c'_g + sum_k A_gk B_kn with
-//                    A_g = [Lambda_g mu_g ; -1/2 Lambda_g] and B_n = [x_n ; x_n^2]
-//                    (Sec. 2.2 Eq. 15 expanded) on the matrix cores,
-//                    v_mfma_f32_16x16x32_bf16 with both operands split into
-//                    BF16 hi + lo and the three products hi*hi, hi*lo, lo*hi
-//                    accumulated in FP32;
+//   2. screening: FP32 log-densities a_gn = c_g - 1/2 sum_d (x_d s_gd - m_gd)^2
+//      of every (component, sample) pair (s = 1/sigma, m = mu/sigma, staged in
+//      LDS);
 //   3. per sample, M_n = max_g (a_gn - e_gn), a lower bound of the exact best
 //      log-density, where e_gn bounds the rounding error of the screening value
-//      (err_direct / err_expanded: from q = 2 (c_g - a_gn) and
-//      Q_g = sum_d lam_gd mu_gd^2), and the near set {g: a_gn + e_gn >= M_n - 30}.
+//      (err_direct: from q = 2 (c_g - a_gn) and Q_g = sum_d lam_gd mu_gd^2),
+//      and the near set {g: a_gn + e_gn >= M_n - 30}.
 //      Near (sample, component) pairs are recomputed by 8-lane groups: in FP64
 //      from the FP32 parameters when the sample has two or more near
 //      components (their relative values decide shared responsibilities), else
@@ -33,7 +32,7 @@
 //   5. the map step of Sec. 2.1 (Eqs. 9-11) in a weighted Welford form (West's
 //      update) on the deviations y = x - mu_old from the current mean: wave w
 //      owns components g = w, w+8, ...; lane owns dimensions d = lane, lane+64
-//      (the old means sit in LDS for the FP32 form, in registers for BF16X3);
+//      (the old means sit in LDS);
 //      for every sample with a non-zero responsibility r, in sample order,
 //        L' = L + r, delta = y - m, m += delta r / L', Q += delta^2 r L / L'
 //      (the first sample sets m = y exactly).  m is the block's weighted mean of
@@ -75,72 +74,61 @@ struct FastArgs {
   int64_t* n_rec;           // or null
 };
 
-// LDS layout.  FP32 form: the direct-form parameters are staged (ps, pm) and
-// the moment accumulators live in registers.  BF16X3 form: the B fragments
-// (bhi, blo) and the FP32 moment accumulators acc[G][2D+1] live in LDS.
+// LDS layout of k_em_fast: the direct-form parameters are staged (ps, pm); the
+// moment accumulators live in registers.
 struct Lds {
-  float* ps;        // [G][D+1]   (FP32 form)
-  float* pm;        // [G][D+1]   (FP32 form)
+  float* ps;        // [G][D+1]
+  float* pm;        // [G][D+1]
   float* xf;        // [T][D]
   float* as;        // [G][T]
-  bf16x8* bhi;      // [KS][2][64] (BF16X3 form)
-  bf16x8* blo;
-  float* acc;       // [G][2D+1]  (BF16X3 form)
-  float* mu;        // [G][D]     (FP32 form) current means
+  float* mu;        // [G][D] current means
   float* pmax;      // [NW][T]
   double* psum;     // [NW][T]
   uint32_t* nbits;  // [T][4]
   int* ncnt;        // [T]
   int* pcount;      // [1]
   uint16_t* plist;  // [T*G]
-  float* cq;        // [5][G] c_g (hi), Q_g = sum_d lam mu^2, c lo, cexp hi, cexp lo
+  float* cq;        // [3][G] c_g (hi), Q_g = sum_d lam mu^2, c lo
   int* dmax;        // [T] max over the near set of (a - M_lo), order-mapped
 };
 
 template <typename F>
-__host__ __device__ inline size_t lds_walk(int D, int G, int KS, int form, F&& at) {
+__host__ __device__ inline size_t lds_walk(int D, int G, F&& at) {
   size_t w = 0;
   auto put = [&](int which, size_t words, size_t align_words) {
     w = (w + align_words - 1) / align_words * align_words;
     at(which, w);
     w += words;
   };
-  const bool bf = form == GMM_PREC_BF16X3;
-  put(0, bf ? 0 : (size_t)G * (D + 1), 1);
-  put(1, bf ? 0 : (size_t)G * (D + 1), 1);
+  put(0, (size_t)G * (D + 1), 1);
+  put(1, (size_t)G * (D + 1), 1);
   put(2, (size_t)kT * D, 4);
   put(3, (size_t)G * kT, 1);
-  put(4, bf ? (size_t)KS * 2 * 64 * 4 : 0, 4);
-  put(5, bf ? (size_t)KS * 2 * 64 * 4 : 0, 4);
-  put(6, bf ? (size_t)G * (2 * D + 1) : 0, 1);
   put(7, kNW * kT, 1);
   put(8, 2 * kNW * kT, 2);
   put(9, kT * 4, 1);
   put(10, kT, 1);
   put(11, 1, 1);
   put(12, ((size_t)kT * G + 1) / 2, 1);
-  put(13, bf ? 0 : (size_t)G * D, 1);
-  put(14, (size_t)5 * G, 1);
+  put(13, (size_t)G * D, 1);
+  put(14, (size_t)3 * G, 1);
   put(15, kT, 1);
   return w;
 }
 
-__host__ __device__ inline size_t fast_lds_bytes(int D, int G, int KS, int form) {
-  return lds_walk(D, G, KS, form, [](int, size_t) {}) * 4 + 64;
+__host__ __device__ inline size_t fast_lds_bytes(int D, int G) {
+  return lds_walk(D, G, [](int, size_t) {}) * 4 + 64;
 }
 
-__device__ inline Lds carve_lds(char* base, int D, int G, int KS, int form) {
+__device__ inline Lds carve_lds(char* base, int D, int G) {
   Lds L;
   float* f = (float*)base;
-  lds_walk(D, G, KS, form, [&](int which, size_t off) {
+  lds_walk(D, G, [&](int which, size_t off) {
     switch (which) {
       case 0: L.ps = f + off; break;
       case 1: L.pm = f + off; break;
       case 2: L.xf = f + off; break;
       case 3: L.as = f + off; break;
-      case 4: L.bhi = (bf16x8*)(f + off); break;
-      case 5: L.blo = (bf16x8*)(f + off); break;
-      case 6: L.acc = f + off; break;
       case 7: L.pmax = f + off; break;
       case 8: L.psum = (double*)(f + off); break;
       case 9: L.nbits = (uint32_t*)(f + off); break;
@@ -153,13 +141,6 @@ __device__ inline Lds carve_lds(char* base, int D, int G, int KS, int form) {
     }
   });
   return L;
-}
-
-__device__ __forceinline__ float group8_sum(float v) {
-  v += __shfl_xor(v, 1, kWave);
-  v += __shfl_xor(v, 2, kWave);
-  v += __shfl_xor(v, 4, kWave);
-  return v;
 }
 
 __device__ __forceinline__ double group8_sum_d(double v) {
@@ -197,80 +178,47 @@ __device__ __forceinline__ void tile_prefetch(const FastArgs& a, int64_t t0, int
 }
 
 // The tile loop over samples [i0, i1) of one model; partials go to slot b.
-template <int FORM, int CPW, int DPL, bool MSTEP>
+template <int CPW, int DPL, bool MSTEP>
 __device__ __forceinline__ void em_range(const FastArgs& a, int64_t i0, int64_t i1, int b,
                                          char* lds_raw) {
-  const int D = a.D, G = a.G, KS = a.KS;
+  const int D = a.D, G = a.G;
   const int DP = D + 1;
-  const Lds L = carve_lds(lds_raw, D, G, KS, FORM);
+  const Lds L = carve_lds(lds_raw, D, G);
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int w = tid / kWave;
 
-  constexpr bool ACCLDS = FORM == GMM_PREC_BF16X3;
   const int P = 2 * D + 1;
   for (int g = tid; g < G; g += kThreads) {
     const float c = a.cc[g];
+    // Q_g from the two forms' constants: c - cexp = Q_g / 2
     const float Q = 2.0f * ((c + a.cc[G + g]) - (a.cexp[g] + a.cexp[G + g]));
     L.cq[g] = c;
     L.cq[G + g] = isfinite(Q) ? 1.0001f * fmaxf(Q, 0.0f) : 0.0f;
     L.cq[2 * G + g] = a.cc[G + g];
-    L.cq[3 * G + g] = a.cexp[g];
-    L.cq[4 * G + g] = a.cexp[G + g];
   }
-  const float ecoef = err_expanded_coef(KS);
   // rounding-error bound (nats) of a screening value v of component g
   auto scr_err = [&](float v, int g) -> float {
     const float c = L.cq[g], Q = L.cq[G + g];
-    const float q = 2.0f * (c - v);
-    return FORM == GMM_PREC_BF16X3 ? err_expanded(q, Q, c, ecoef) : err_direct(q, Q, c, D);
+    return err_direct(2.0f * (c - v), Q, c, D);
   };
-  if (!ACCLDS) {  // stage the direct-form parameters and the current means
-    for (int p = tid; p < G * DP; p += kThreads) {
-      L.ps[p] = a.prm[p];
-      L.pm[p] = a.prm[(size_t)G * DP + p];
-    }
-    if (MSTEP)
-      for (int p = tid; p < G * D; p += kThreads) L.mu[p] = a.means[p];
-  } else if (MSTEP) {
-    for (int p = tid; p < G * P; p += kThreads) L.acc[p] = 0.0f;
+  // stage the direct-form parameters and the current means
+  for (int p = tid; p < G * DP; p += kThreads) {
+    L.ps[p] = a.prm[p];
+    L.pm[p] = a.prm[(size_t)G * DP + p];
   }
+  if (MSTEP)
+    for (int p = tid; p < G * D; p += kThreads) L.mu[p] = a.means[p];
 
-  // expanded-form weights of this wave's row block, kept in registers
-  constexpr int KSMAX = 8;
-  bf16x8 whi[KSMAX], wlo[KSMAX];
-  const int RB = (G + 15) / 16;
-  if (FORM == GMM_PREC_BF16X3 && w < RB) {
+  // Welford accumulators of component g = w + 8c, dimension d = lane + 64j
+  float S1[CPW][DPL], S2[CPW][DPL], Lc[CPW];
 #pragma unroll
-    for (int ks = 0; ks < KSMAX; ++ks)
-      if (ks < KS) {
-        whi[ks] = a.Whi[((size_t)w * KS + ks) * 64 + lane];
-        wlo[ks] = a.Wlo[((size_t)w * KS + ks) * 64 + lane];
-      }
-  }
-
-  // Welford accumulators (FP32 form) of component g = w + 8c, dimension
-  // d = lane + 64j; the BF16X3 form keeps them in LDS and only the current
-  // means of its components in registers
-  constexpr int CA = ACCLDS ? 1 : CPW;
-  constexpr int CM = ACCLDS ? CPW : 1;
-  float S1[CA][DPL], S2[CA][DPL], Lc[CA], mur[CM][DPL];
-#pragma unroll
-  for (int c = 0; c < CA; ++c) {
+  for (int c = 0; c < CPW; ++c) {
     Lc[c] = 0.0f;
 #pragma unroll
     for (int j = 0; j < DPL; ++j) {
       S1[c][j] = 0.0f;
       S2[c][j] = 0.0f;
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < CM; ++c) {
-    const int g = w + kNW * c;
-#pragma unroll
-    for (int j = 0; j < DPL; ++j) {
-      const int d = lane + kWave * j;
-      mur[c][j] = (ACCLDS && MSTEP && g < G && d < D) ? a.means[(size_t)g * D + d] : 0.0f;
     }
   }
   double llacc = 0.0;  // lanes < kT of wave 0: samples n = lane of every tile
@@ -299,53 +247,7 @@ __device__ __forceinline__ void em_range(const FastArgs& a, int64_t i0, int64_t 
     __syncthreads();
 
     // 2. screening
-    if (FORM == GMM_PREC_BF16X3) {
-      // B fragments: element i of lane l in k-step ks, column block cb is
-      // feature k = 32 ks + 8 (l/16) + i of sample n = 16 cb + l%16.
-      for (int p = tid; p < KS * 2 * 64; p += kThreads) {
-        const int l = p & 63, cb = (p >> 6) & 1, ks = p >> 7;
-        const int n = 16 * cb + (l & 15);
-        bf16x8 hi, lo;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int k = 32 * ks + 8 * (l >> 4) + i;
-          float v = 0.0f;
-          if (k < D) {
-            v = L.xf[n * D + k];
-          } else if (k < 2 * D) {
-            const float x = L.xf[n * D + k - D];
-            v = x * x;
-          }
-          const __bf16 h = (__bf16)v;
-          hi[i] = h;
-          lo[i] = (__bf16)(v - (float)h);
-        }
-        L.bhi[p] = hi;
-        L.blo[p] = lo;
-      }
-      __syncthreads();
-      if (w < RB) {
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-          f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-          for (int ks = 0; ks < KSMAX; ++ks)
-            if (ks < KS) {
-              const bf16x8 bh = L.bhi[(ks * 2 + cb) * 64 + lane];
-              const bf16x8 bl = L.blo[(ks * 2 + cb) * 64 + lane];
-              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wlo[ks], bh, acc, 0, 0, 0);
-              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(whi[ks], bl, acc, 0, 0, 0);
-              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(whi[ks], bh, acc, 0, 0, 0);
-            }
-          const int n = 16 * cb + (lane & 15);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int g = 16 * w + 4 * (lane >> 4) + j;
-            if (g < G) L.as[g * kT + n] = (acc[j] + L.cq[3 * G + g]) + L.cq[4 * G + g];
-          }
-        }
-      }
-    } else {
+    {
       // direct form: thread owns component g = lane + 64 (w & 1) and samples
       // n = 8 (w >> 1) .. + 7
       const int g = lane + kWave * (w & 1);
@@ -419,28 +321,10 @@ __device__ __forceinline__ void em_range(const FastArgs& a, int64_t i0, int64_t 
         bool exact64 = L.ncnt[pn] >= 2;
         double val = 0.0;
         if (!exact64) {
-          float q32;
-          if (FORM == GMM_PREC_BF16X3) {
-            const float* sg = a.prm + (size_t)g * DP;
-            const float* mg = a.prm + (size_t)G * DP + (size_t)g * DP;
-            float q = 0.0f;
-#pragma unroll 8
-            for (int i = 0; i < 16; ++i) {
-              const int d = gl + 8 * i;
-              if (d < D) {
-                const float u = fmaf(x[d], sg[d], -mg[d]);
-                q = fmaf(u, u, q);
-              }
-            }
-            q32 = group8_sum(q);
-            val = ((double)L.cq[g] + (double)L.cq[2 * G + g]) - 0.5 * (double)q32;
-          } else {
-            // the screening value is already the direct form
-            const float v = L.as[g * kT + pn];
-            q32 = 2.0f * (L.cq[g] - v);
-            val = (double)v;
-          }
-          exact64 = !(err_direct(q32, L.cq[G + g], L.cq[g], D) <= kExactTol);
+          // the screening value is already the direct form
+          const float v = L.as[g * kT + pn];
+          val = (double)v;
+          exact64 = !(err_direct(2.0f * (L.cq[g] - v), L.cq[G + g], L.cq[g], D) <= kExactTol);
         }
         if (exact64) {
           const float* mu_g = a.means + (size_t)g * D;
@@ -457,7 +341,7 @@ __device__ __forceinline__ void em_range(const FastArgs& a, int64_t i0, int64_t 
           const float rel = (float)(val - (double)Mp);
           L.as[g * kT + pn] = rel;
           atomicMax(&L.dmax[pn], f2ord(rel));
-          if (exact64 || FORM == GMM_PREC_BF16X3) ++nrec;
+          if (exact64) ++nrec;
         }
       }
     }
@@ -495,46 +379,8 @@ __device__ __forceinline__ void em_range(const FastArgs& a, int64_t i0, int64_t 
         L.as[g * kT + n] = (n < nt && z >= -kRespCut) ? __expf(z) : 0.0f;
       }
       // 5. moments of this wave's components (written above by this wave only)
-      if (ACCLDS) {
 #pragma unroll
-        for (int c = 0; c < CM; ++c) {
-          const int g = w + kNW * c;
-          if (g >= G) continue;
-          const float r_l = lane < kT ? L.as[g * kT + lane] : 0.0f;
-          unsigned long long msk = __ballot(r_l != 0.0f);
-          if (!msk) continue;
-          float* ag = L.acc + (size_t)g * P;
-          float Lg = ag[0];
-          while (msk) {
-            const int nn = __ffsll((long long)msk) - 1;
-            msk &= msk - 1;
-            const float r = L.as[g * kT + nn];
-            const float Lo = Lg;
-            const float Ln = Lo + r;
-            const float inv = r / Ln;
-            const float w2 = inv * Lo;
-            Lg = Ln;
-#pragma unroll
-            for (int j = 0; j < DPL; ++j) {
-              const int d = lane + kWave * j;
-              if (d < D) {
-                const float y = L.xf[nn * D + d] - mur[c][j];
-                if (Lo == 0.0f) {
-                  ag[1 + d] = y;
-                } else {
-                  const float m0 = ag[1 + d];
-                  const float dl = y - m0;
-                  ag[1 + d] = fmaf(inv, dl, m0);
-                  ag[1 + D + d] = fmaf(w2 * dl, dl, ag[1 + D + d]);
-                }
-              }
-            }
-          }
-          if (lane == 0) ag[0] = Lg;
-        }
-      } else
-#pragma unroll
-      for (int c = 0; c < CA; ++c) {
+      for (int c = 0; c < CPW; ++c) {
         const int g = w + kNW * c;
         if (g < G) {
           const float r_l = lane < kT ? L.as[g * kT + lane] : 0.0f;
@@ -570,14 +416,10 @@ __device__ __forceinline__ void em_range(const FastArgs& a, int64_t i0, int64_t 
   }
 
   // block partials in FP64
-  if (MSTEP && ACCLDS) {
-    __syncthreads();
-    double* pb = a.part + (size_t)b * G * P;
-    for (int p = tid; p < G * P; p += kThreads) pb[p] = (double)L.acc[p];
-  } else if (MSTEP) {
+  if (MSTEP) {
     double* pb = a.part + (size_t)b * G * P;
 #pragma unroll
-    for (int c = 0; c < CA; ++c) {
+    for (int c = 0; c < CPW; ++c) {
       const int g = w + kNW * c;
       if (g < G) {
         if (lane == 0) pb[(size_t)g * P] = (double)Lc[c];
@@ -606,13 +448,13 @@ __device__ __forceinline__ void em_range(const FastArgs& a, int64_t i0, int64_t 
   }
 }
 
-template <int FORM, int CPW, int DPL, bool MSTEP>
+template <int CPW, int DPL, bool MSTEP>
 __global__ void __launch_bounds__(kThreads) k_em_fast(FastArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds_raw[];
   const int b = blockIdx.x;
   const int64_t i0 = (int64_t)b * a.chunk;
   const int64_t i1 = min(a.N, i0 + a.chunk);
-  em_range<FORM, CPW, DPL, MSTEP>(a, i0, i1, b, lds_raw);
+  em_range<CPW, DPL, MSTEP>(a, i0, i1, b, lds_raw);
 }
 
 // ---- many models ----------------------------------------------------------
@@ -629,7 +471,7 @@ struct BatchConst {
   int Gmax, RBmax, KS;
 };
 
-template <int FORM, int CPW, int DPL, bool MSTEP>
+template <int CPW, int DPL, bool MSTEP>
 __global__ void __launch_bounds__(kThreads) k_em_fast_batched(FastArgs base,
                                                               const gmm_model_desc* models,
                                                               const BatchItemDev* items,
@@ -660,7 +502,7 @@ __global__ void __launch_bounds__(kThreads) k_em_fast_batched(FastArgs base,
     a.per_sample = nullptr;
     a.dev_status = m.dev_status;
     a.n_rec = nullptr;
-    em_range<FORM, CPW, DPL, MSTEP>(a, item.i0, item.i1, 0, lds_raw);
+    em_range<CPW, DPL, MSTEP>(a, item.i0, item.i1, 0, lds_raw);
     __syncthreads();
   }
 }
@@ -671,7 +513,7 @@ __device__ void pre_component(const float* __restrict__ hefts, const float* __re
                               float* __restrict__ prm, float* __restrict__ cc,
                               float* __restrict__ cexp, bf16x8* __restrict__ Whi,
                               bf16x8* __restrict__ Wlo, double* __restrict__ c64,
-                              double* __restrict__ lam64, int inter) {
+                              double* __restrict__ lam64) {
   __shared__ double sh[256];
   const int DP = D + 1;
   double ld = 0.0, q = 0.0;
@@ -704,16 +546,16 @@ __device__ void pre_component(const float* __restrict__ hefts, const float* __re
     cexp[G + g] = isfinite(ce) ? (float)(ce - (double)ehi) : 0.0f;
   }
   // MFMA fragments of component g's row: the coefficient A_gk of feature k is
-  // lam mu for the feature x_d and -lam/2 for x_d^2, 0 beyond.  Feature order:
-  // inter == 0: k = d for x_d, k = D + d for x_d^2; inter == 1: k = 2d for x_d,
-  // k = 2d + 1 for x_d^2.  The fragment of (row block, k-step ks, lane l) holds
-  // features 32 ks + 8 (l/16) + i, i = 0..7, of component 16 rb + l%16.
+  // lam mu for the feature x_d and -lam/2 for x_d^2, 0 beyond, interleaved:
+  // k = 2d for x_d, k = 2d + 1 for x_d^2.  The fragment of (row block, k-step
+  // ks, lane l) holds features 32 ks + 8 (l/16) + i, i = 0..7, of component
+  // 16 rb + l%16.
   const int rb = g >> 4, row = g & 15;
   for (int e = threadIdx.x; e < KS * 4 * 8; e += 256) {
     const int ks = e / 32, r = e - ks * 32, lq = r >> 3, i = r & 7;
     const int k = 32 * ks + 8 * lq + i;
-    const int d = inter ? (k >> 1) : (k < D ? k : k - D);
-    const bool sq = inter ? (k & 1) : (k >= D);
+    const int d = k >> 1;
+    const bool sq = k & 1;
     float v = 0.0f;
     if (d < D && k < 2 * D) {
       const double lam = 1.0 / (double)covs[(size_t)g * D + d];
@@ -751,14 +593,13 @@ __global__ void __launch_bounds__(256) k_pre_fast(const float* __restrict__ heft
                                                   bf16x8* __restrict__ Whi,
                                                   bf16x8* __restrict__ Wlo,
                                                   double* __restrict__ c64,
-                                                  double* __restrict__ lam64, int inter) {
-  pre_component(hefts, means, covs, D, G, KS, blockIdx.x, prm, cc, cexp, Whi, Wlo, c64, lam64,
-                inter);
+                                                  double* __restrict__ lam64) {
+  pre_component(hefts, means, covs, D, G, KS, blockIdx.x, prm, cc, cexp, Whi, Wlo, c64, lam64);
 }
 
 // grid (16 * RBmax, n_models): component g of model blockIdx.y.
 __global__ void __launch_bounds__(256) k_pre_fast_batched(const gmm_model_desc* models, int D,
-                                                          BatchConst bc, int inter) {
+                                                          BatchConst bc) {
   const int mi = blockIdx.y;
   const gmm_model_desc& m = models[mi];
   if (!batch_desc_ok(m, bc.Gmax)) return;
@@ -772,7 +613,7 @@ __global__ void __launch_bounds__(256) k_pre_fast_batched(const gmm_model_desc* 
   }
   pre_component(m.hefts, m.means, m.covs, D, G, bc.KS, g, bc.prm + (size_t)mi * 2 * bc.Gmax * (D + 1),
                 bc.cc + (size_t)mi * 2 * bc.Gmax, bc.cexp + (size_t)mi * 2 * bc.Gmax, Whi, Wlo,
-                bc.c64 + (size_t)mi * bc.Gmax, bc.lam64 + (size_t)mi * bc.Gmax * D, inter);
+                bc.c64 + (size_t)mi * bc.Gmax, bc.lam64 + (size_t)mi * bc.Gmax * D);
 }
 
 // Rows of the last row block past G get zero weights.
@@ -1510,9 +1351,9 @@ __global__ void __launch_bounds__(kThreads) k_em2_batched(FastArgs base,
   }
 }
 
-template <int FORM, int CPW, int DPL, bool MSTEP>
+template <int CPW, int DPL, bool MSTEP>
 void launch_one(const FastArgs& a, int nb, size_t lds, hipStream_t st) {
-  auto kern = k_em_fast<FORM, CPW, DPL, MSTEP>;
+  auto kern = k_em_fast<CPW, DPL, MSTEP>;
   static bool attr_set = false;  // benign race: setting the attribute twice is harmless
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1522,23 +1363,23 @@ void launch_one(const FastArgs& a, int nb, size_t lds, hipStream_t st) {
   hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), lds, st, a);
 }
 
-template <int FORM, bool MSTEP>
+template <bool MSTEP>
 void dispatch_cpw(const FastArgs& a, int nb, size_t lds, hipStream_t st) {
   {
   const int cpw = (a.G + kNW - 1) / kNW;
   const int dpl = (a.D + kWave - 1) / kWave;
   if (dpl == 1) {
-    if (cpw <= 2) launch_one<FORM, 2, 1, MSTEP>(a, nb, lds, st);
-    else if (cpw <= 4) launch_one<FORM, 4, 1, MSTEP>(a, nb, lds, st);
-    else if (cpw <= 8) launch_one<FORM, 8, 1, MSTEP>(a, nb, lds, st);
-    else if (cpw <= 13) launch_one<FORM, 13, 1, MSTEP>(a, nb, lds, st);
-    else launch_one<FORM, 16, 1, MSTEP>(a, nb, lds, st);
+    if (cpw <= 2) launch_one<2, 1, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 4) launch_one<4, 1, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 8) launch_one<8, 1, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 13) launch_one<13, 1, MSTEP>(a, nb, lds, st);
+    else launch_one<16, 1, MSTEP>(a, nb, lds, st);
   } else {
-    if (cpw <= 2) launch_one<FORM, 2, 2, MSTEP>(a, nb, lds, st);
-    else if (cpw <= 4) launch_one<FORM, 4, 2, MSTEP>(a, nb, lds, st);
-    else if (cpw <= 8) launch_one<FORM, 8, 2, MSTEP>(a, nb, lds, st);
-    else if (cpw <= 13) launch_one<FORM, 13, 2, MSTEP>(a, nb, lds, st);
-    else launch_one<FORM, 16, 2, MSTEP>(a, nb, lds, st);
+    if (cpw <= 2) launch_one<2, 2, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 4) launch_one<4, 2, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 8) launch_one<8, 2, MSTEP>(a, nb, lds, st);
+    else if (cpw <= 13) launch_one<13, 2, MSTEP>(a, nb, lds, st);
+    else launch_one<16, 2, MSTEP>(a, nb, lds, st);
   }
   }
 }
@@ -1577,9 +1418,8 @@ void dispatch_em2(const FastArgs& a, int nb, size_t lds, hipStream_t st) {
 
 bool em_fast_supported(int D, int G, int prec) {
   if (D < 1 || D > 128 || G < 1 || G > 128) return false;
-  const int KS = (2 * D + 31) / 32;
   if (prec == GMM_PREC_BF16X3) return em2_lds_bytes(G, em2_ks(D)) <= 160 * 1024;
-  return fast_lds_bytes(D, G, KS, prec) <= 160 * 1024;
+  return fast_lds_bytes(D, G) <= 160 * 1024;
 }
 
 int em_fast_blocks(int64_t N) {
@@ -1593,7 +1433,7 @@ hipError_t launch_em_fast(const float* X, int64_t N, int D, int64_t ldx, int G, 
                           const float* means, const float* covs, int prec, bool mstep,
                           int64_t* n_recomputed, float* per_sample, int32_t* dev_status,
                           const Workspace& w, hipStream_t st, int* nb_out) {
-  const int KS = (2 * D + 31) / 32;
+  const int KS = em2_ks(D);  // k-steps of the expanded form's fragments
   const int nb = em_fast_blocks(N);
   FastArgs a;
   a.X = X;
@@ -1616,12 +1456,10 @@ hipError_t launch_em_fast(const float* X, int64_t N, int D, int64_t ldx, int G, 
   a.per_sample = per_sample;
   a.dev_status = dev_status;
   a.n_rec = n_recomputed;
-  const int inter = prec == GMM_PREC_BF16X3 ? 1 : 0;
-  const int KSl = inter ? em2_ks(D) : KS;  // fragment layout depth
-  hipLaunchKernelGGL(k_pre_fast, dim3(G), dim3(256), 0, st, hefts, means, covs, D, G, KSl, w.prm,
-                     w.c, w.cexp, (bf16x8*)w.Bhi, (bf16x8*)w.Blo, w.c64, w.lamg64, inter);
+  hipLaunchKernelGGL(k_pre_fast, dim3(G), dim3(256), 0, st, hefts, means, covs, D, G, KS, w.prm,
+                     w.c, w.cexp, (bf16x8*)w.Bhi, (bf16x8*)w.Blo, w.c64, w.lamg64);
   if (G % 16) hipLaunchKernelGGL(k_zero_pad_rows, dim3(1), dim3(256), 0, st, (bf16x8*)w.Bhi,
-                                 (bf16x8*)w.Blo, G, KSl);
+                                 (bf16x8*)w.Blo, G, KS);
   {
     ProfScope ps(mstep ? kProfEM : kProfLoglik, st);
     if (prec == GMM_PREC_BF16X3) {
@@ -1629,15 +1467,15 @@ hipError_t launch_em_fast(const float* X, int64_t N, int D, int64_t ldx, int G, 
       const int64_t ch = ((N + nb - 1) / nb + kRoundN - 1) / kRoundN * kRoundN;
       a.chunk = ch;
       const int nb2 = (int)((N + ch - 1) / ch);
-      const size_t lds = em2_lds_bytes(G, KSl);
+      const size_t lds = em2_lds_bytes(G, KS);
       if (mstep) dispatch_em2<true>(a, nb2, lds, st);
       else dispatch_em2<false>(a, nb2, lds, st);
       *nb_out = nb2;
       return hipGetLastError();
     }
-    const size_t lds = fast_lds_bytes(D, G, KS, prec);
-    if (mstep) dispatch_cpw<GMM_PREC_FP32, true>(a, nb, lds, st);
-    else dispatch_cpw<GMM_PREC_FP32, false>(a, nb, lds, st);
+    const size_t lds = fast_lds_bytes(D, G);
+    if (mstep) dispatch_cpw<true>(a, nb, lds, st);
+    else dispatch_cpw<false>(a, nb, lds, st);
   }
   *nb_out = nb;
   return hipGetLastError();
@@ -1653,10 +1491,10 @@ hipError_t launch_fin_welford(int nb, int64_t N, int D, int G, float var_floor, 
 
 namespace {
 
-template <int FORM, bool MSTEP, int CPW, int DPL>
+template <bool MSTEP, int CPW, int DPL>
 void launch_batched_one(const FastArgs& base, const gmm_model_desc* models, const BatchWorkspace& bw,
                         const BatchConst& bc, int grid, size_t lds, hipStream_t st) {
-  auto kern = k_em_fast_batched<FORM, CPW, DPL, MSTEP>;
+  auto kern = k_em_fast_batched<CPW, DPL, MSTEP>;
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1700,20 +1538,20 @@ void dispatch_em2_batched(const FastArgs& base, const gmm_model_desc* models,
   }
 }
 
-template <int FORM, bool MSTEP>
+template <bool MSTEP>
 void dispatch_batched(const FastArgs& base, const gmm_model_desc* models, const BatchWorkspace& bw,
                       const BatchConst& bc, int grid, size_t lds, hipStream_t st) {
   const int cpw = (bw.Gmax + kNW - 1) / kNW;
   if (bw.D <= 64) {
-    if (cpw <= 2) launch_batched_one<FORM, MSTEP, 2, 1>(base, models, bw, bc, grid, lds, st);
-    else if (cpw <= 4) launch_batched_one<FORM, MSTEP, 4, 1>(base, models, bw, bc, grid, lds, st);
-    else if (cpw <= 8) launch_batched_one<FORM, MSTEP, 8, 1>(base, models, bw, bc, grid, lds, st);
-    else launch_batched_one<FORM, MSTEP, 16, 1>(base, models, bw, bc, grid, lds, st);
+    if (cpw <= 2) launch_batched_one<MSTEP, 2, 1>(base, models, bw, bc, grid, lds, st);
+    else if (cpw <= 4) launch_batched_one<MSTEP, 4, 1>(base, models, bw, bc, grid, lds, st);
+    else if (cpw <= 8) launch_batched_one<MSTEP, 8, 1>(base, models, bw, bc, grid, lds, st);
+    else launch_batched_one<MSTEP, 16, 1>(base, models, bw, bc, grid, lds, st);
   } else {
-    if (cpw <= 2) launch_batched_one<FORM, MSTEP, 2, 2>(base, models, bw, bc, grid, lds, st);
-    else if (cpw <= 4) launch_batched_one<FORM, MSTEP, 4, 2>(base, models, bw, bc, grid, lds, st);
-    else if (cpw <= 8) launch_batched_one<FORM, MSTEP, 8, 2>(base, models, bw, bc, grid, lds, st);
-    else launch_batched_one<FORM, MSTEP, 16, 2>(base, models, bw, bc, grid, lds, st);
+    if (cpw <= 2) launch_batched_one<MSTEP, 2, 2>(base, models, bw, bc, grid, lds, st);
+    else if (cpw <= 4) launch_batched_one<MSTEP, 4, 2>(base, models, bw, bc, grid, lds, st);
+    else if (cpw <= 8) launch_batched_one<MSTEP, 8, 2>(base, models, bw, bc, grid, lds, st);
+    else launch_batched_one<MSTEP, 16, 2>(base, models, bw, bc, grid, lds, st);
   }
 }
 
@@ -1743,9 +1581,9 @@ hipError_t launch_em_batched(const gmm_model_desc* models, int n_models, int n_i
   base.part = bw.partials;
   base.ll_part = bw.sparts;
   hipLaunchKernelGGL(k_pre_fast_batched, dim3(16 * bw.RBmax, n_models), dim3(256), 0, st, models,
-                     D, bc, prec == GMM_PREC_BF16X3 ? 1 : 0);
+                     D, bc);
   const size_t lds = prec == GMM_PREC_BF16X3 ? em2_lds_bytes(bw.Gmax, em2_ks(D))
-                                             : fast_lds_bytes(D, bw.Gmax, bw.KS, prec);
+                                             : fast_lds_bytes(D, bw.Gmax);
   const int grid = n_items_host < 256 ? (n_items_host < 1 ? 1 : n_items_host) : 256;
   {
     ProfScope ps(kProfBatched, st);
@@ -1753,8 +1591,8 @@ hipError_t launch_em_batched(const gmm_model_desc* models, int n_models, int n_i
       if (mstep) dispatch_em2_batched<true>(base, models, bw, bc, grid, lds, st);
       else dispatch_em2_batched<false>(base, models, bw, bc, grid, lds, st);
     } else {
-      if (mstep) dispatch_batched<GMM_PREC_FP32, true>(base, models, bw, bc, grid, lds, st);
-      else dispatch_batched<GMM_PREC_FP32, false>(base, models, bw, bc, grid, lds, st);
+      if (mstep) dispatch_batched<true>(base, models, bw, bc, grid, lds, st);
+      else dispatch_batched<false>(base, models, bw, bc, grid, lds, st);
     }
   }
   hipLaunchKernelGGL(k_fin_welford_batched, dim3(bw.Gmax, n_models), dim3(256), 0, st, models,
