@@ -30,10 +30,13 @@ __global__ void k_init_full(int32_t* dev_status, int64_t* n_recomputed) {
 // scratch: FP64 [G][D][D] factor L (column-major, L[e*D + d] = L_{d,e})
 // followed by FP64 [G][D][D] inverse (row-major, Wi[r*D + c] = W_{r,c}).
 __global__ void __launch_bounds__(kNT) k_pre_full(const float* __restrict__ hefts,
-                                                  const float* __restrict__ covs, int D, int G,
+                                                  const float* __restrict__ covs,
+                                                  const float* __restrict__ means, int D, int G,
                                                   double* __restrict__ scratch,
                                                   float* __restrict__ W_out,
                                                   double* __restrict__ W64_out,
+                                                  bf16x8* __restrict__ Wfh, bf16x8* __restrict__ Wfl,
+                                                  float* __restrict__ bW,
                                                   float* __restrict__ c_out,
                                                   double* __restrict__ c64_out,
                                                   int32_t* __restrict__ dev_status) {
@@ -85,6 +88,30 @@ __global__ void __launch_bounds__(kNT) k_pre_full(const float* __restrict__ heft
     Wg[p] = (float)Wi[p];
     Wg64[p] = Wi[p];
   }
+  if (D <= 64) {
+    // B-operand fragments of W_g^T for v_mfma_f32_16x16x32_bf16: fragment
+    // (row block cb, k-step ks, lane l) holds W_g[16 cb + l%16][32 ks + 8 (l/16)
+    // + i], i = 0..7 (zero past D), split into BF16 hi + lo; and b_g = W_g mu_g
+    // (FP64, rounded once), zero-padded to whole row blocks.
+    const int RBr = (D + 15) / 16, KS = (D + 31) / 32;
+    __bf16* fh = (__bf16*)(Wfh + (size_t)g * RBr * KS * 64);
+    __bf16* fl = (__bf16*)(Wfl + (size_t)g * RBr * KS * 64);
+    for (int e = tid; e < RBr * KS * 64 * 8; e += kNT) {
+      const int i = e & 7, l = (e >> 3) & 63, rest = e >> 9;
+      const int ks = rest % KS, cb = rest / KS;
+      const int r = 16 * cb + (l & 15), k = 32 * ks + 8 * (l >> 4) + i;
+      const float v = (r < D && k < D) ? (float)Wi[(size_t)r * D + k] : 0.0f;
+      const __bf16 h = (__bf16)v;
+      fh[e] = h;
+      fl[e] = (__bf16)(v - (float)h);
+    }
+    for (int r = tid; r < 16 * RBr; r += kNT) {
+      double t = 0.0;
+      if (r < D)
+        for (int c = 0; c <= r; ++c) t += Wi[(size_t)r * D + c] * (double)means[(size_t)g * D + c];
+      bW[(size_t)g * 16 * RBr + r] = (float)t;
+    }
+  }
   if (tid == 0) {
     double ld = 0.0;
     for (int d = 0; d < D; ++d) ld += log(L[(size_t)d * D + d]);
@@ -106,10 +133,100 @@ __device__ __forceinline__ int tri_index(int d, int e, int D) { return e * D - (
 constexpr int kWB = 1024;
 constexpr int kWR = 64;
 
-template <bool MSTEP>
-__global__ void __launch_bounds__(kNT) k_estep_full(
+// Screening of a tile on the matrix cores (D <= 32 KS): Z = X W_g^T - 1 b_g^T with
+// the samples as the A operand (16 per row block, features split into BF16 hi +
+// lo) and W_g^T as B (three products hi*hi, hi*lo, lo*hi accumulated in FP32),
+// then a_g = c_g - 1/2 sum_r Z_r^2.  Wave per component; output lane l, register
+// j is (sample 4 (l/16) + j of the row block, row 16 cb + l%16 of W_g), so the
+// sum over rows is a 16-lane butterfly.
+template <int KS>
+__device__ void screen_full_mfma(const float* __restrict__ xs, int DS, int nt, int D, int G,
+                                 const bf16x8* __restrict__ Wfh,
+                                 const bf16x8* __restrict__ Wfl,
+                                 const float* __restrict__ bW, const float* __restrict__ cc,
+                                 float* __restrict__ as, int wid, int nw, int lane) {
+  constexpr int RBM = 2 * KS;  // most row blocks of W_g
+  const int RBr = (D + 15) / 16;
+  const int NRB = (nt + 15) / 16;  // row blocks of samples (nt <= 64)
+  const int m = lane & 15, kb = lane >> 4;
+  bf16x8 ah[4][KS], al[4][KS];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    const int t = min(16 * rb + m, nt - 1);  // rows past nt: a valid row, output dropped
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = 32 * ks + 8 * kb + i;
+        const float v = k < D ? xs[(size_t)t * DS + k] : 0.0f;
+        const __bf16 h = (__bf16)v;
+        ah[rb][ks][i] = h;
+        al[rb][ks][i] = (__bf16)(v - (float)h);
+      }
+    }
+  }
+  const int g0 = __builtin_amdgcn_readfirstlane(wid);
+  const size_t fstride = (size_t)RBr * KS * 64;
+  for (int g = g0; g < G; g += nw) {
+    // component g's fragments (rows past the last row block repeat it, unused)
+    bf16x8 ch[RBM][KS], cl[RBM][KS];
+    float cv[RBM];
+#pragma unroll
+    for (int cb = 0; cb < RBM; ++cb) {
+      const int c = min(cb, RBr - 1);
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        ch[cb][ks] = Wfh[(size_t)g * fstride + ((size_t)c * KS + ks) * 64 + lane];
+        cl[cb][ks] = Wfl[(size_t)g * fstride + ((size_t)c * KS + ks) * 64 + lane];
+      }
+      cv[cb] = bW[(size_t)g * 16 * RBr + 16 * c + m];
+    }
+    float qp[4][4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) qp[rb][j] = 0.0f;
+#pragma unroll
+    for (int cb = 0; cb < RBM; ++cb) {
+      if (cb >= RBr) break;
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        if (rb >= NRB) break;
+        f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[rb][ks], ch[cb][ks], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb][ks], cl[cb][ks], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb][ks], ch[cb][ks], c, 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float z = c[j] - cv[cb];  // rows past D: 0 - 0
+          qp[rb][j] = fmaf(z, z, qp[rb][j]);
+        }
+      }
+    }
+    const float cg = cc[g], cl2 = cc[G + g];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      if (rb >= NRB) break;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float q = row16_sum_f(qp[rb][j]);
+        const int t = 16 * rb + 4 * kb + j;
+        if (m == 0 && t < nt) as[(size_t)t * G + g] = (cg - 0.5f * q) + cl2;
+      }
+    }
+  }
+}
+
+// FKS: k-steps of the matrix-core screening (1: D <= 32, 2: D <= 64), 0 for
+// the vector-ALU screening.
+template <bool MSTEP, int FKS>
+__global__ void __launch_bounds__(kNT, 2) k_estep_full(
     const float* __restrict__ X, int64_t N, int D, int64_t ldx, int G, int T, int64_t chunk,
-    const float* __restrict__ W, const float* __restrict__ cc, const double* __restrict__ W64,
+    const float* __restrict__ W, const bf16x8* __restrict__ Wfh, const bf16x8* __restrict__ Wfl,
+    const float* __restrict__ bW, const float* __restrict__ cc, const double* __restrict__ W64,
     const double* __restrict__ c64, const float* __restrict__ means,
     double* __restrict__ part, double* __restrict__ ll_part, float* __restrict__ per_sample,
     int32_t* __restrict__ dev_status) {
@@ -151,7 +268,12 @@ __global__ void __launch_bounds__(kNT) k_estep_full(
     }
     for (int p = tid; p < NGB; p += kNT) gbits[p] = 0u;
     __syncthreads();
-    // a_gi: wave per component (W_g and mu_g read uniformly), lane per sample
+    // a_gi: on the matrix cores for D <= 64; otherwise wave per component (W_g
+    // and mu_g read uniformly), lane per sample
+    if (FKS > 0)
+      screen_full_mfma<(FKS > 0 ? FKS : 1)>(xs, DS, nt, D, G, Wfh, Wfl, bW, cc, as, wid, nw,
+                                             lane);
+    else
     for (int g = __builtin_amdgcn_readfirstlane(wid); g < G; g += nw) {
       const float* mu = means + (size_t)g * D;
       const float* Wg = W + (size_t)g * D * D;
@@ -446,13 +568,15 @@ hipError_t launch_em_full(const float* X, int64_t N, int D, int64_t ldx, int G, 
   const int P = 1 + D + D * (D + 1) / 2;
   const size_t lds = estep_full_lds(D, G, T);
   hipLaunchKernelGGL(k_init_full, dim3(1), dim3(64), 0, st, dev_status, n_recomputed);
-  hipLaunchKernelGGL(k_pre_full, dim3(G), dim3(kNT), 0, st, hefts, covs, D, G, w.partials, w.W,
-                     w.W64, w.c, w.c64, dev_status);
+  hipLaunchKernelGGL(k_pre_full, dim3(G), dim3(kNT), 0, st, hefts, covs, means, D, G, w.partials,
+                     w.W, w.W64, (bf16x8*)w.Wfh, (bf16x8*)w.Wfl, w.bW, w.c, w.c64, dev_status);
   {
     ProfScope ps(kProfEM, st);
-    hipLaunchKernelGGL(k_estep_full<true>, dim3(nb), dim3(kNT), lds, st, X, N, D, ldx, G, T,
-                       chunk, w.W, w.c, w.W64, w.c64, means, w.partials, w.scalars, nullptr,
-                       dev_status);
+    auto kern = D <= 32 ? k_estep_full<true, 1> : D <= 64 ? k_estep_full<true, 2>
+                                                           : k_estep_full<true, 0>;
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(kNT), lds, st, X, N, D, ldx, G, T, chunk, w.W,
+                       (const bf16x8*)w.Wfh, (const bf16x8*)w.Wfl, w.bW, w.c, w.W64, w.c64, means,
+                       w.partials, w.scalars, nullptr, dev_status);
   }
   hipLaunchKernelGGL(k_fin_full, dim3(G), dim3(kNT), sizeof(double) * P, st, w.partials, nb, N, D,
                      G, var_floor, hefts, means, covs, w.scalars, mean_loglik, dev_status);
@@ -468,13 +592,15 @@ hipError_t launch_loglik_full(const float* X, int64_t N, int D, int64_t ldx, int
   const int64_t chunk = (N + nb - 1) / nb;
   const size_t lds = estep_full_lds(D, G, T);
   hipLaunchKernelGGL(k_init_full, dim3(1), dim3(64), 0, st, dev_status, nullptr);
-  hipLaunchKernelGGL(k_pre_full, dim3(G), dim3(kNT), 0, st, hefts, covs, D, G, w.partials, w.W,
-                     w.W64, w.c, w.c64, dev_status);
+  hipLaunchKernelGGL(k_pre_full, dim3(G), dim3(kNT), 0, st, hefts, covs, means, D, G, w.partials,
+                     w.W, w.W64, (bf16x8*)w.Wfh, (bf16x8*)w.Wfl, w.bW, w.c, w.c64, dev_status);
   {
     ProfScope ps(kProfLoglik, st);
-    hipLaunchKernelGGL(k_estep_full<false>, dim3(nb), dim3(kNT), lds, st, X, N, D, ldx, G, T,
-                       chunk, w.W, w.c, w.W64, w.c64, means, w.partials, w.scalars, per_sample,
-                       dev_status);
+    auto kern = D <= 32 ? k_estep_full<false, 1> : D <= 64 ? k_estep_full<false, 2>
+                                                            : k_estep_full<false, 0>;
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(kNT), lds, st, X, N, D, ldx, G, T, chunk, w.W,
+                       (const bf16x8*)w.Wfh, (const bf16x8*)w.Wfl, w.bW, w.c, w.W64, w.c64, means,
+                       w.partials, w.scalars, per_sample, dev_status);
   }
   hipLaunchKernelGGL(k_ll_finish_full, dim3(1), dim3(64), 0, st, w.scalars, nb, N, mean_loglik,
                      dev_status);

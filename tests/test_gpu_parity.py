@@ -387,7 +387,10 @@ def test_binding_raises_on_invalid(G_):
 
 
 # ---------------------------------------------------------------- full covariance
-@pytest.mark.parametrize("N,D,G", [(5000, 4, 3), (3000, 32, 8), (257, 7, 2)])
+# D <= 32 and D <= 64 screen on the matrix cores (one and two k-steps), D > 64
+# on the vector ALUs; N = 70 leaves a tile of 6 samples
+@pytest.mark.parametrize("N,D,G", [(5000, 4, 3), (3000, 32, 8), (257, 7, 2), (70, 33, 5),
+                                   (4000, 48, 6), (3001, 64, 17), (1500, 80, 3)])
 def test_em_step_full(G_, oracle, N, D, G):
     X, truth = synth.full_gmm(500 + D, D, G, N)
     rng = np.random.Generator(np.random.PCG64(D))
