@@ -3,10 +3,14 @@
 //
 //   k_pre_full     one workgroup per component: Cholesky Sigma_g = L L^T in
 //                  FP64, log|Sigma_g| = 2 sum_d log L_dd, the inverse factor
-//                  W_g = L^-1 by forward substitution in FP64 (stored rounded to
-//                  FP32) and c_g = log w_g - 1/2 (D log 2pi + log|Sigma_g|)
-//                  (hi/lo FP32).  A non-positive pivot sets GMM_DEV_NOTPD.
-//   k_estep_full   a_gi = c_g - 1/2 ||W_g (x_i - mu_g)||^2, log-sum-exp,
+//                  W_g = L^-1 by forward substitution in FP64 (also rounded to
+//                  FP32), c_g = log w_g - 1/2 (D log 2pi + log|Sigma_g|) (FP64
+//                  and hi/lo FP32) and, for D <= 64, W_g in the FP64 MFMA
+//                  operand layout with b_g = W_g mu_g.  A non-positive pivot
+//                  sets GMM_DEV_NOTPD.
+//   k_estep_full   a_gi = c_g - 1/2 ||W_g (x_i - mu_g)||^2 (D <= 64: exact FP64
+//                  on the matrix cores; larger D: FP32 screening with an FP64
+//                  recompute of the 30-nat window), log-sum-exp,
 //                  responsibilities, and per-block FP64 partials of
 //                  L, sum l*y, sum l*y y^T (lower triangle, packed) with
 //                  y = x - mu_old.
@@ -35,8 +39,8 @@ __global__ void __launch_bounds__(kNT) k_pre_full(const float* __restrict__ heft
                                                   double* __restrict__ scratch,
                                                   float* __restrict__ W_out,
                                                   double* __restrict__ W64_out,
-                                                  bf16x8* __restrict__ Wfh, bf16x8* __restrict__ Wfl,
-                                                  float* __restrict__ bW,
+                                                  double* __restrict__ Wf64,
+                                                  double* __restrict__ b64,
                                                   float* __restrict__ c_out,
                                                   double* __restrict__ c64_out,
                                                   int32_t* __restrict__ dev_status) {
@@ -89,27 +93,22 @@ __global__ void __launch_bounds__(kNT) k_pre_full(const float* __restrict__ heft
     Wg64[p] = Wi[p];
   }
   if (D <= 64) {
-    // B-operand fragments of W_g^T for v_mfma_f32_16x16x32_bf16: fragment
-    // (row block cb, k-step ks, lane l) holds W_g[16 cb + l%16][32 ks + 8 (l/16)
-    // + i], i = 0..7 (zero past D), split into BF16 hi + lo; and b_g = W_g mu_g
-    // (FP64, rounded once), zero-padded to whole row blocks.
-    const int RBr = (D + 15) / 16, KS = (D + 31) / 32;
-    __bf16* fh = (__bf16*)(Wfh + (size_t)g * RBr * KS * 64);
-    __bf16* fl = (__bf16*)(Wfl + (size_t)g * RBr * KS * 64);
-    for (int e = tid; e < RBr * KS * 64 * 8; e += kNT) {
-      const int i = e & 7, l = (e >> 3) & 63, rest = e >> 9;
-      const int ks = rest % KS, cb = rest / KS;
-      const int r = 16 * cb + (l & 15), k = 32 * ks + 8 * (l >> 4) + i;
-      const float v = (r < D && k < D) ? (float)Wi[(size_t)r * D + k] : 0.0f;
-      const __bf16 h = (__bf16)v;
-      fh[e] = h;
-      fl[e] = (__bf16)(v - (float)h);
+    // B-operand fragments of W_g^T for v_mfma_f64_16x16x4f64: fragment (row
+    // block cb, k-step ks, lane l) is W_g[16 cb + l%16][4 ks + l/16] (zero past
+    // D); and b_g = W_g mu_g in FP64, zero-padded to whole row blocks.
+    const int RBr = (D + 15) / 16, KQ = D <= 32 ? 8 : 16;
+    double* f = Wf64 + (size_t)g * RBr * KQ * 64;
+    for (int e = tid; e < RBr * KQ * 64; e += kNT) {
+      const int l = e & 63, rest = e >> 6;
+      const int ks = rest % KQ, cb = rest / KQ;
+      const int r = 16 * cb + (l & 15), k = 4 * ks + (l >> 4);
+      f[e] = (r < D && k < D) ? Wi[(size_t)r * D + k] : 0.0;
     }
     for (int r = tid; r < 16 * RBr; r += kNT) {
       double t = 0.0;
       if (r < D)
         for (int c = 0; c <= r; ++c) t += Wi[(size_t)r * D + c] * (double)means[(size_t)g * D + c];
-      bW[(size_t)g * 16 * RBr + r] = (float)t;
+      b64[(size_t)g * 16 * RBr + r] = t;
     }
   }
   if (tid == 0) {
@@ -133,110 +132,95 @@ __device__ __forceinline__ int tri_index(int d, int e, int D) { return e * D - (
 constexpr int kWB = 1024;
 constexpr int kWR = 64;
 
-// Screening of a tile on the matrix cores (D <= 32 KS): Z = X W_g^T - 1 b_g^T with
-// the samples as the A operand (16 per row block, features split into BF16 hi +
-// lo) and W_g^T as B (three products hi*hi, hi*lo, lo*hi accumulated in FP32),
-// then a_g = c_g - 1/2 sum_r Z_r^2.  Wave per component; output lane l, register
-// j is (sample 4 (l/16) + j of the row block, row 16 cb + l%16 of W_g), so the
-// sum over rows is a 16-lane butterfly.
-template <int KS>
-__device__ void screen_full_mfma(const float* __restrict__ xs, int DS, int nt, int D, int G,
-                                 const bf16x8* __restrict__ Wfh,
-                                 const bf16x8* __restrict__ Wfl,
-                                 const float* __restrict__ bW, const float* __restrict__ cc,
-                                 float* __restrict__ as, int wid, int nw, int lane) {
-  constexpr int RBM = 2 * KS;  // most row blocks of W_g
+// Exact log-densities of a tile on the matrix cores (D <= 4 KQ): Z = X W_g^T -
+// 1 b_g^T in FP64 (v_mfma_f64_16x16x4f64; the samples are the A operand, 16 per
+// row block, W_g^T the B operand), then a_g = c_g - 1/2 sum_r Z_r^2 in FP64.
+// Wave per component; output lane l, register j is (sample 4 j + l/16 of the row
+// block, row 16 cb + l%16 of W_g), so the sum over rows is a 16-lane butterfly.
+template <int KQ>
+__device__ void logdens_full_f64(const float* __restrict__ xs, int DS, int nt, int D, int G,
+                                 const double* __restrict__ Wf64,
+                                 const double* __restrict__ b64,
+                                 const double* __restrict__ c64, double* __restrict__ as64,
+                                 int wid, int nw, int lane) {
+  constexpr int RBM = KQ / 2;  // most row blocks of W_g (D <= 4 KQ)
   const int RBr = (D + 15) / 16;
   const int NRB = (nt + 15) / 16;  // row blocks of samples (nt <= 64)
   const int m = lane & 15, kb = lane >> 4;
-  bf16x8 ah[4][KS], al[4][KS];
+  double xa[4][KQ];  // A operands: sample 16 rb + m, dimension 4 ks + kb
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) {
     const int t = min(16 * rb + m, nt - 1);  // rows past nt: a valid row, output dropped
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = 32 * ks + 8 * kb + i;
-        const float v = k < D ? xs[(size_t)t * DS + k] : 0.0f;
-        const __bf16 h = (__bf16)v;
-        ah[rb][ks][i] = h;
-        al[rb][ks][i] = (__bf16)(v - (float)h);
-      }
+    for (int ks = 0; ks < KQ; ++ks) {
+      const int k = 4 * ks + kb;
+      xa[rb][ks] = k < D ? (double)xs[(size_t)t * DS + k] : 0.0;
     }
   }
-  const int g0 = __builtin_amdgcn_readfirstlane(wid);
-  const size_t fstride = (size_t)RBr * KS * 64;
-  for (int g = g0; g < G; g += nw) {
-    // component g's fragments (rows past the last row block repeat it, unused)
-    bf16x8 ch[RBM][KS], cl[RBM][KS];
-    float cv[RBM];
-#pragma unroll
-    for (int cb = 0; cb < RBM; ++cb) {
-      const int c = min(cb, RBr - 1);
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        ch[cb][ks] = Wfh[(size_t)g * fstride + ((size_t)c * KS + ks) * 64 + lane];
-        cl[cb][ks] = Wfl[(size_t)g * fstride + ((size_t)c * KS + ks) * 64 + lane];
-      }
-      cv[cb] = bW[(size_t)g * 16 * RBr + 16 * c + m];
-    }
-    float qp[4][4];
+  const size_t fstride = (size_t)RBr * KQ * 64;
+  for (int g = __builtin_amdgcn_readfirstlane(wid); g < G; g += nw) {
+    double qp[4][4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) qp[rb][j] = 0.0f;
+      for (int j = 0; j < 4; ++j) qp[rb][j] = 0.0;
 #pragma unroll
     for (int cb = 0; cb < RBM; ++cb) {
       if (cb >= RBr) break;
+      double wb[KQ];
+#pragma unroll
+      for (int ks = 0; ks < KQ; ++ks)
+        wb[ks] = Wf64[(size_t)g * fstride + ((size_t)cb * KQ + ks) * 64 + lane];
+      const double bv = b64[(size_t)g * 16 * RBr + 16 * cb + m];
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb) {
         if (rb >= NRB) break;
-        f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+        f64x4 c = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[rb][ks], ch[cb][ks], c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb][ks], cl[cb][ks], c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb][ks], ch[cb][ks], c, 0, 0, 0);
+        for (int ks = 0; ks < KQ; ++ks) {
+          if (4 * ks >= D) break;
+          c = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[rb][ks], wb[ks], c, 0, 0, 0);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const float z = c[j] - cv[cb];  // rows past D: 0 - 0
-          qp[rb][j] = fmaf(z, z, qp[rb][j]);
+          const double z = c[j] - bv;  // rows past D: 0 - 0
+          qp[rb][j] = fma(z, z, qp[rb][j]);
         }
       }
     }
-    const float cg = cc[g], cl2 = cc[G + g];
+    const double cg = c64[g];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
       if (rb >= NRB) break;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const float q = row16_sum_f(qp[rb][j]);
-        const int t = 16 * rb + 4 * kb + j;
-        if (m == 0 && t < nt) as[(size_t)t * G + g] = (cg - 0.5f * q) + cl2;
+        const double q = row16_sum(qp[rb][j]);
+        const int t = 16 * rb + 4 * j + kb;
+        if (m == 0 && t < nt) as64[(size_t)t * G + g] = cg - 0.5 * q;
       }
     }
   }
 }
 
-// FKS: k-steps of the matrix-core screening (1: D <= 32, 2: D <= 64), 0 for
-// the vector-ALU screening.
+// FKS: k-steps of 4 of the FP64 matrix-core log-densities (8: D <= 32, 16:
+// D <= 64), 0 for the vector-ALU screening with the FP64 near-set recompute.
 template <bool MSTEP, int FKS>
 __global__ void __launch_bounds__(kNT, 2) k_estep_full(
     const float* __restrict__ X, int64_t N, int D, int64_t ldx, int G, int T, int64_t chunk,
-    const float* __restrict__ W, const bf16x8* __restrict__ Wfh, const bf16x8* __restrict__ Wfl,
-    const float* __restrict__ bW, const float* __restrict__ cc, const double* __restrict__ W64,
+    const float* __restrict__ W, const double* __restrict__ Wf64, const double* __restrict__ b64,
+    const float* __restrict__ cc, const double* __restrict__ W64,
     const double* __restrict__ c64, const float* __restrict__ means,
     double* __restrict__ part, double* __restrict__ ll_part, float* __restrict__ per_sample,
     int32_t* __restrict__ dev_status) {
   extern __shared__ double ldsd[];
   const int nw = kNT / kWave;
-  double* wst = ldsd;                          // [nw][kWB] packed rows of W_g (FP64)
-  double* bst = wst + (size_t)nw * kWB;        // [nw][kWR] b_r
-  double* lse = bst + (size_t)nw * kWR;        // [T]
-  double* mst = lse + T;                       // [nw][D] mu_g of the near recompute
-  float* xs = (float*)(mst + (size_t)nw * D);  // [T][D+1]
+  constexpr bool F64 = FKS > 0;
+  double* as64 = ldsd;                                      // F64: [T][G] log-densities
+  double* wst = as64 + (F64 ? (size_t)T * G : 0);           // [nw][kWB] packed rows of W_g
+  double* bst = wst + (F64 ? 0 : (size_t)nw * kWB);         // [nw][kWR] b_r
+  double* lse = bst + (F64 ? 0 : (size_t)nw * kWR);         // [T]
+  double* mst = lse + T;                                    // [nw][D] mu_g (near recompute)
+  float* xs = (float*)(mst + (F64 ? 0 : (size_t)nw * D));   // [T][D+1]
   const int DS = D + 1;                        // padded row stride (conflict-free column reads)
   float* as = xs + (size_t)T * DS;             // [T][G]
   float* mxs = as + (size_t)T * G;             // [T] screened maximum
@@ -268,11 +252,11 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_full(
     }
     for (int p = tid; p < NGB; p += kNT) gbits[p] = 0u;
     __syncthreads();
-    // a_gi: on the matrix cores for D <= 64; otherwise wave per component (W_g
-    // and mu_g read uniformly), lane per sample
-    if (FKS > 0)
-      screen_full_mfma<(FKS > 0 ? FKS : 1)>(xs, DS, nt, D, G, Wfh, Wfl, bW, cc, as, wid, nw,
-                                             lane);
+    // a_gi: exact FP64 values on the matrix cores for D <= 64; otherwise FP32
+    // screening (wave per component, W_g and mu_g read uniformly, lane per
+    // sample) and the FP64 near-set recompute below
+    if (F64)
+      logdens_full_f64<(F64 ? FKS : 8)>(xs, DS, nt, D, G, Wf64, b64, c64, as64, wid, nw, lane);
     else
     for (int g = __builtin_amdgcn_readfirstlane(wid); g < G; g += nw) {
       const float* mu = means + (size_t)g * D;
@@ -304,7 +288,7 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_full(
     }
     __syncthreads();
     // screened maximum per sample
-    for (int t = wid; t < nt; t += nw) {
+    for (int t = wid; t < nt && !F64; t += nw) {
       const float* a = as + (size_t)t * G;
       float mx = -INFINITY;
       for (int g = lane; g < G; g += kWave) mx = fmaxf(mx, a[g]);
@@ -317,7 +301,7 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_full(
     // L_g^-1 in FP64.  Wave per component, lane per sample; the packed rows of
     // W_g are staged in LDS a chunk at a time and read by all near lanes.
     // Every value is moved to the frame of its sample's M = mx.
-    for (int g = __builtin_amdgcn_readfirstlane(wid); g < G; g += nw) {
+    for (int g = __builtin_amdgcn_readfirstlane(wid); g < G && !F64; g += nw) {
       float* ag = as + g;
       const int t = lane;
       const float mx = t < nt ? mxs[t] : 0.0f;
@@ -378,7 +362,32 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_full(
     }
     __syncthreads();
     // log-sum-exp about M + max (Eqs. 16-18) and responsibilities
-    for (int t = wid; t < nt; t += nw) {
+    for (int t = wid; t < nt && F64; t += nw) {
+      const double* a64 = as64 + (size_t)t * G;
+      float* a = as + (size_t)t * G;
+      double M = -INFINITY;
+      for (int g = lane; g < G; g += kWave) M = fmax(M, a64[g]);
+      for (int off = 1; off < kWave; off <<= 1) M = fmax(M, __shfl_xor(M, off));
+      const double Mr = M > -INFINITY ? M : 0.0;
+      double sm = 0.0;
+      for (int g = lane; g < G; g += kWave) sm += (double)__expf((float)(a64[g] - Mr));
+      sm = wave_sum_d(sm);
+      const double l = Mr + log(sm);
+      if (MSTEP) {
+        for (int g = lane; g < G; g += kWave) {
+          const float z = (float)(a64[g] - l);
+          const float r = z >= -kRespCut ? __expf(z) : 0.0f;
+          a[g] = r;
+          if (r != 0.0f) atomicOr(&gbits[g >> 5], 1u << (g & 31));
+        }
+      }
+      if (lane == 0) {
+        lse[t] = l;
+        if (!isfinite(l)) bad = 1;
+        if (per_sample) per_sample[t0 + t] = (float)l;
+      }
+    }
+    for (int t = wid; t < nt && !F64; t += nw) {
       float* a = as + (size_t)t * G;
       const double M = (double)mxs[t];
       float dn = -INFINITY;
@@ -545,14 +554,16 @@ __global__ void k_ll_finish_full(const double* __restrict__ ll_part, int nb, int
 }
 
 // LDS of k_estep_full for tile rows T.
-size_t estep_full_lds(int D, int G, int T) {
-  return sizeof(double) * ((size_t)(kNT / kWave) * (kWB + kWR + D) + T) +
-         sizeof(float) * ((size_t)T * (D + 1 + G) + T) + sizeof(uint32_t) * ((G + 31) / 32);
+// LDS of k_estep_full for tile rows T (f64: the FP64 matrix-core form).
+size_t estep_full_lds(int D, int G, int T, bool f64) {
+  const size_t dbl = f64 ? (size_t)T * G + T : (size_t)(kNT / kWave) * (kWB + kWR + D) + T;
+  return sizeof(double) * dbl + sizeof(float) * ((size_t)T * (D + 1 + G) + T) +
+         sizeof(uint32_t) * ((G + 31) / 32);
 }
 
 int tile_rows_full(int D, int G) {
   int T = 64;  // at most one wave of samples (ballot masks over the tile)
-  while (T > 1 && estep_full_lds(D, G, T) > 62 * 1024) T >>= 1;  // default LDS limit
+  while (T > 1 && estep_full_lds(D, G, T, D <= 64) > 62 * 1024) T >>= 1;  // default LDS limit
   return T;
 }
 
@@ -566,17 +577,17 @@ hipError_t launch_em_full(const float* X, int64_t N, int D, int64_t ldx, int G, 
   const int nb = partial_blocks(N, 4 * T);
   const int64_t chunk = (N + nb - 1) / nb;
   const int P = 1 + D + D * (D + 1) / 2;
-  const size_t lds = estep_full_lds(D, G, T);
+  const size_t lds = estep_full_lds(D, G, T, D <= 64);
   hipLaunchKernelGGL(k_init_full, dim3(1), dim3(64), 0, st, dev_status, n_recomputed);
   hipLaunchKernelGGL(k_pre_full, dim3(G), dim3(kNT), 0, st, hefts, covs, means, D, G, w.partials,
-                     w.W, w.W64, (bf16x8*)w.Wfh, (bf16x8*)w.Wfl, w.bW, w.c, w.c64, dev_status);
+                     w.W, w.W64, w.Wf64, w.b64, w.c, w.c64, dev_status);
   {
     ProfScope ps(kProfEM, st);
-    auto kern = D <= 32 ? k_estep_full<true, 1> : D <= 64 ? k_estep_full<true, 2>
+    auto kern = D <= 32 ? k_estep_full<true, 8> : D <= 64 ? k_estep_full<true, 16>
                                                            : k_estep_full<true, 0>;
     hipLaunchKernelGGL(kern, dim3(nb), dim3(kNT), lds, st, X, N, D, ldx, G, T, chunk, w.W,
-                       (const bf16x8*)w.Wfh, (const bf16x8*)w.Wfl, w.bW, w.c, w.W64, w.c64, means,
-                       w.partials, w.scalars, nullptr, dev_status);
+                       w.Wf64, w.b64, w.c, w.W64, w.c64, means, w.partials, w.scalars, nullptr,
+                       dev_status);
   }
   hipLaunchKernelGGL(k_fin_full, dim3(G), dim3(kNT), sizeof(double) * P, st, w.partials, nb, N, D,
                      G, var_floor, hefts, means, covs, w.scalars, mean_loglik, dev_status);
@@ -590,17 +601,17 @@ hipError_t launch_loglik_full(const float* X, int64_t N, int D, int64_t ldx, int
   const int T = tile_rows_full(D, G);
   const int nb = partial_blocks(N, 4 * T);
   const int64_t chunk = (N + nb - 1) / nb;
-  const size_t lds = estep_full_lds(D, G, T);
+  const size_t lds = estep_full_lds(D, G, T, D <= 64);
   hipLaunchKernelGGL(k_init_full, dim3(1), dim3(64), 0, st, dev_status, nullptr);
   hipLaunchKernelGGL(k_pre_full, dim3(G), dim3(kNT), 0, st, hefts, covs, means, D, G, w.partials,
-                     w.W, w.W64, (bf16x8*)w.Wfh, (bf16x8*)w.Wfl, w.bW, w.c, w.c64, dev_status);
+                     w.W, w.W64, w.Wf64, w.b64, w.c, w.c64, dev_status);
   {
     ProfScope ps(kProfLoglik, st);
-    auto kern = D <= 32 ? k_estep_full<false, 1> : D <= 64 ? k_estep_full<false, 2>
+    auto kern = D <= 32 ? k_estep_full<false, 8> : D <= 64 ? k_estep_full<false, 16>
                                                             : k_estep_full<false, 0>;
     hipLaunchKernelGGL(kern, dim3(nb), dim3(kNT), lds, st, X, N, D, ldx, G, T, chunk, w.W,
-                       (const bf16x8*)w.Wfh, (const bf16x8*)w.Wfl, w.bW, w.c, w.W64, w.c64, means,
-                       w.partials, w.scalars, per_sample, dev_status);
+                       w.Wf64, w.b64, w.c, w.W64, w.c64, means, w.partials, w.scalars,
+                       per_sample, dev_status);
   }
   hipLaunchKernelGGL(k_ll_finish_full, dim3(1), dim3(64), 0, st, w.scalars, nb, N, mean_loglik,
                      dev_status);

@@ -57,6 +57,7 @@ __device__ __forceinline__ float ord2f(int i) { return __int_as_float(i >= 0 ? i
 // ---- wave-level helpers of the sample-major kernels --------------------------
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4;
 
 // Butterflies over the 16 lanes of a row by DPP row rotations (no address
 // registers): after rotations by 1, 2, 4 and 8 every lane holds the reduction
@@ -269,9 +270,8 @@ struct Workspace {
   double* c64;     // [G] log w - 1/2 (D log 2pi + log|Sigma|) in FP64
   double* lamg64;  // diag: [G][D] 1/sigma2 in FP64
   double* W64;     // full: [G][D][D] inverse Cholesky factor in FP64 (row-major lower)
-  void* Wfh;       // full, D <= 64: MFMA fragments of W (BF16 hi), see full_frag_count
-  void* Wfl;       // the same, lo parts
-  float* bW;       // full, D <= 64: [G][16 * ceil(D/16)] b_g = W_g mu_g
+  double* Wf64;    // full, D <= 64: FP64 MFMA fragments of W, see full_frag_count
+  double* b64;     // full, D <= 64: [G][16 * ceil(D/16)] b_g = W_g mu_g
   double* partials;   // [B][G][P]
   double* scalars;    // [4][B] per-block FP64 sums (log-likelihood / inertia)
   int32_t* assign;    // [N] k-means assignment scratch
@@ -285,11 +285,12 @@ struct Workspace {
 // one-pass kernels (D <= 64 / D <= 128), padded to 32 beyond
 inline int kexp_K(int D) { return D <= 64 ? 128 : (D <= 128 ? 256 : ((2 * D + 31) / 32) * 32); }
 
-// Full covariances with D <= 64: the whitening W_g (x - mu_g) runs on the matrix
-// cores; per component ceil(D/16) row blocks x ceil(D/32) k-steps x 64 lanes of
-// 8 BF16 (hi and lo).
+// Full covariances with D <= 64: the whitening W_g (x - mu_g) runs in FP64 on
+// the matrix cores; per component ceil(D/16) row blocks x kq(D) k-steps of 4 x
+// 64 lanes, one double each.
+inline int full_kq(int D) { return D <= 32 ? 8 : 16; }
 inline size_t full_frag_count(int D, int G) {
-  return D <= 64 ? (size_t)G * ((D + 15) / 16) * ((D + 31) / 32) * 64 : 0;
+  return D <= 64 ? (size_t)G * ((D + 15) / 16) * full_kq(D) * 64 : 0;
 }
 
 inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Workspace* w) {
@@ -317,9 +318,8 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   size_t o_lg = take(sizeof(double) * (size_t)G * D);
   size_t o_w64 = take(cov == GMM_COV_FULL ? sizeof(double) * (size_t)D * D * G : 0);
   const size_t nfr = cov == GMM_COV_FULL ? full_frag_count(D, G) : 0;
-  size_t o_wfh = take(16 * nfr);
-  size_t o_wfl = take(16 * nfr);
-  size_t o_bw = take(nfr ? sizeof(float) * (size_t)G * 16 * ((D + 15) / 16) : 0);
+  size_t o_wf = take(sizeof(double) * nfr);
+  size_t o_bw = take(nfr ? sizeof(double) * (size_t)G * 16 * ((D + 15) / 16) : 0);
   size_t o_p = take(sizeof(double) * (size_t)B * G * P);
   size_t o_sc = take(sizeof(double) * 4 * (size_t)B);
   size_t o_a = take(sizeof(int32_t) * (size_t)N);
@@ -341,9 +341,8 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   w->c64 = (double*)(b + o_c64);
   w->lamg64 = (double*)(b + o_lg);
   w->W64 = (double*)(b + o_w64);
-  w->Wfh = (void*)(b + o_wfh);
-  w->Wfl = (void*)(b + o_wfl);
-  w->bW = (float*)(b + o_bw);
+  w->Wf64 = (double*)(b + o_wf);
+  w->b64 = (double*)(b + o_bw);
   w->partials = (double*)(b + o_p);
   w->scalars = (double*)(b + o_sc);
   w->assign = (int32_t*)(b + o_a);
