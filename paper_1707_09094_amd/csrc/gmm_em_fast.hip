@@ -28,7 +28,7 @@
 //      with a tiny variance (a floored one-sample cluster) has a huge e_gn, so
 //      its pairs join the near set wherever its exact value could matter;
 //   4. log-sum-exp per sample (Eqs. 16-18) about M_n + max(recomputed - M_n),
-//      summed in FP64; responsibilities (Eq. 3); those below exp(-80) are 0;
+//      summed in FP64; responsibilities (Eq. 3); those below exp(-40) are 0;
 //   5. the map step of Sec. 2.1 (Eqs. 9-11) in a weighted Welford form (West's
 //      update) on the deviations y = x - mu_old from the current mean: wave w
 //      owns components g = w, w+8, ...; lane owns dimensions d = lane, lane+64

@@ -12,7 +12,9 @@ namespace gmm {
 
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kMaxBlocks = 512;      // E/M grid: 2 workgroups per CU on 256 CUs
-constexpr float kRespCut = 80.0f;    // responsibilities below exp(-80) of the best are 0
+// Responsibilities (normalised per sample) below exp(-40) are set to 0: a
+// component then loses at most N e^-40 ~ 4e-18 N of its mass L_g.
+constexpr float kRespCut = 40.0f;
 // Near set of a sample: every component whose screened log-density, widened by
 // its rounding-error bound, comes within this many nats of the largest
 // guaranteed lower bound.  Those are recomputed exactly (FP64 from the FP32
