@@ -202,6 +202,80 @@ __device__ void logdens_full_f64(const float* __restrict__ xs, int DS, int nt, i
   }
 }
 
+// Map step of one component over one tile on the matrix cores (FP64): with
+// y' = [x - mu_g, 1] (D + 1 entries), C = sum_t r_t y'_t y'_t^T is the rank
+// update v_mfma_f64_16x16x4f64 builds from A = (r y')^T and B = y' (4 samples
+// per k-step); its lower triangle holds sum r y_d y_e, its last row sum r y_e
+// and its corner sum r.  Lane l, register j of block (rb, cb) is entry
+// (16 rb + 4 j + l/16, 16 cb + l%16).  The tile's sums are added to the
+// component's FP64 partials q (count, first moments, packed lower triangle).
+template <int RBYM, int KC>
+__device__ void map_full_f64(const float* __restrict__ xs, int DS, int nt, int D, int G,
+                             const float* __restrict__ as, const float* __restrict__ mu_g,
+                             double* __restrict__ q, int g, int lane) {
+  constexpr int NB = RBYM * (RBYM + 1) / 2;  // lower-triangle blocks
+  const int RBY = (D + 16) / 16;             // row blocks of y'
+  const int m = lane & 15, kb = lane >> 4;
+  float mue[RBYM];
+#pragma unroll
+  for (int cb = 0; cb < RBYM; ++cb) {
+    const int e = 16 * cb + m;
+    mue[cb] = e < D ? mu_g[e] : 0.0f;  // column D of the tile holds 1
+  }
+  f64x4 c[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) c[i] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int nks = (nt + 3) / 4;
+  // k-steps (4 samples each) KC at a time: their fragments of y' are built,
+  // then every block takes them
+  for (int k0 = 0; k0 < nks; k0 += KC) {
+    double yb[RBYM][KC], rr[KC];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const int t = 4 * (k0 + kk) + kb;
+      const bool ok = t < nt;
+      const int tt = ok ? t : 0;
+      rr[kk] = ok ? (double)as[(size_t)tt * G + g] : 0.0;
+#pragma unroll
+      for (int cb = 0; cb < RBYM; ++cb) {
+        const int e = 16 * cb + m;
+        yb[cb][kk] = (ok && e <= D) ? (double)(xs[(size_t)tt * DS + e] - mue[cb]) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int rb = 0, i = 0; rb < RBYM; ++rb)
+#pragma unroll
+      for (int cb = 0; cb <= rb; ++cb, ++i) {
+        if (rb >= RBY) continue;
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk)
+          c[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(rr[kk] * yb[rb][kk], yb[cb][kk], c[i], 0,
+                                                      0, 0);
+      }
+  }
+#pragma unroll
+  for (int rb = 0, i = 0; rb < RBYM; ++rb)
+#pragma unroll
+    for (int cb = 0; cb <= rb; ++cb, ++i) {
+      if (rb >= RBY) continue;
+      int kk[4];
+      double old[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int d = 16 * rb + 4 * j + kb, e = 16 * cb + m;
+        int k = -1;
+        if (d == D && e == D) k = 0;
+        else if (d == D && e < D) k = 1 + e;
+        else if (d < D && e <= d) k = 1 + D + tri_index(d, e, D);
+        kk[j] = k;
+        old[j] = k >= 0 ? q[k] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (kk[j] >= 0) q[kk[j]] = old[j] + c[i][j];
+    }
+}
+
 // FKS: k-steps of 4 of the FP64 matrix-core log-densities (8: D <= 32, 16:
 // D <= 64), 0 for the vector-ALU screening with the FP64 near-set recompute.
 template <bool MSTEP, int FKS>
@@ -416,7 +490,17 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_full(
     __syncthreads();
     if (tid == 0)
       for (int t = 0; t < nt; ++t) llacc += lse[t];
-    if (MSTEP) {
+    constexpr bool MAP64 = FKS == 8;  // D <= 32: the map step on the matrix cores too
+    if (MSTEP && MAP64) {
+      // map step (Eqs. 9-11) on the matrix cores, wave per component with a
+      // non-zero responsibility in the tile
+      for (int g = wid; g < G; g += nw) {
+        if (!((gbits[g >> 5] >> (g & 31)) & 1u)) continue;
+        map_full_f64<3, 4>(xs, DS, nt, D, G, as, means + (size_t)g * D, pb + (size_t)g * P, g,
+                           lane);
+      }
+    }
+    if (MSTEP && !MAP64) {
       // entry k of component g: 0 -> L, 1..D -> sum r y_d, then the packed
       // lower triangle sum r y_d y_e (d >= e, column e after column e-1).
       // Wave per component with a non-zero responsibility in the tile, lanes
