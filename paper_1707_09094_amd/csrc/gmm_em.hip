@@ -1,18 +1,23 @@
 // gmm_em.hip -- EM iteration and log-likelihood for diagonal covariances,
 // generic kernels valid for every shape the API accepts.
 //
-// One EM iteration (Sec. 2, Eqs. 3-7) is three launches on one stream:
+// One EM iteration (Sec. 2, Eqs. 3-7) is three or four launches on one stream:
 //   k_pre_diag      per-component constants in FP64 (Sec. 2.2, Eq. 15):
 //                   s_gd = 1/sigma_gd, m_gd = mu_gd/sigma_gd (rounded to FP32)
 //                   and c_g = log w_g - 1/2 (D log 2pi + sum_d log sigma2_gd)
 //                   (kept as an FP32 hi/lo pair)
-//   k_estep_diag    sample tiles: log-densities a_gi = c_g - 1/2 sum_d
-//                   (x_di s_gd - m_gd)^2, max-shifted log-sum-exp per sample
-//                   (Eqs. 16-18), responsibilities (Eq. 3), and the map step of
-//                   Sec. 2.1 (Eqs. 9-11) into per-block FP64 partials.  The
-//                   moments are accumulated about the component's current mean
-//                   (y = x - mu_old): L, sum l*y, sum l*y^2, which makes the
-//                   one-pass covariance of Eq. 8 free of cancellation.
+//   k_frag_diag64   (G > 128, D <= 128) the expanded form's coefficients
+//                   [-lam/2, lam mu] in the FP64 MFMA operand layout
+//   k_estep_diag    sample tiles: log-densities a_gi (G > 128, D <= 128: exact
+//                   FP64 on the matrix cores, logdens_diag_f64; otherwise the
+//                   FP32 direct form c_g - 1/2 sum_d (x_di s_gd - m_gd)^2 with
+//                   an FP64 recompute of the near set), max-shifted
+//                   log-sum-exp per sample (Eqs. 16-18), responsibilities
+//                   (Eq. 3), and the map step of Sec. 2.1 (Eqs. 9-11) into
+//                   per-block FP64 partials.  The moments are accumulated about
+//                   the component's current mean (y = x - mu_old): L, sum l*y,
+//                   sum l*y^2, which makes the one-pass covariance of Eq. 8
+//                   free of cancellation.
 //   k_fin_diag      reduce step (Eqs. 12-14) over the block partials in a fixed
 //                   order, Eq. 5 weights, Eq. 6 means, Eq. 7 variances about the
 //                   new mean, the variance floor, and the mean log-likelihood.
@@ -67,14 +72,169 @@ __global__ void __launch_bounds__(kNT) k_pre_diag(const float* __restrict__ heft
   }
 }
 
+// Expanded-form operands of the FP64 matrix-core E-step (D <= 128): block
+// 16 cb + n (n < 16) writes component g's B fragments, feature k = 4 ks + kr
+// (kr = lane / 16) holding -lam_gk / 2 for k < dpad4(D) (x_k^2) and
+// lam mu for k - dpad4(D) (x); zero for padding components and dimensions.
+// Also c0_g = c_g - Q_g / 2 and Q_g = sum_d lam mu^2 in FP64.
+__global__ void __launch_bounds__(kNT) k_frag_diag64(const float* __restrict__ means,
+                                                     const double* __restrict__ lam64,
+                                                     const double* __restrict__ c64, int D, int G,
+                                                     double* __restrict__ Bx64,
+                                                     double* __restrict__ cq64) {
+  __shared__ double sh[kNT];
+  const int g = blockIdx.x;
+  const int DP4 = dpad4(D), KQ = DP4 / 2;
+  const int cb = g >> 4, n = g & 15;
+  double* f = Bx64 + (size_t)cb * KQ * 64;
+  double q = 0.0;
+  for (int k = threadIdx.x; k < 2 * DP4; k += kNT) {
+    const int ks = k >> 2, kr = k & 3;
+    double v = 0.0;
+    if (g < G) {
+      const int d = k < DP4 ? k : k - DP4;
+      if (d < D) {
+        const double lam = lam64[(size_t)g * D + d];
+        const double mu = (double)means[(size_t)g * D + d];
+        v = k < DP4 ? -0.5 * lam : lam * mu;
+        if (k >= DP4) q += lam * mu * mu;
+      }
+    }
+    f[(size_t)ks * 64 + n + 16 * kr] = v;
+  }
+  q = block_sum_d<kNT>(q, sh);
+  if (g < G && threadIdx.x == 0) {
+    cq64[g] = c64[g] - 0.5 * q;
+    cq64[G + g] = q;
+  }
+}
+
+// One pass of the FP64 matrix-core E-step over a tile of up to 32 samples
+// (D <= 128): a_g(x) = c0_g + sum_k A_k B_gk with A = [x_d^2, x_d] (the samples,
+// 16 per row block, as the A operand of v_mfma_f64_16x16x4f64) and B the
+// expanded coefficients [-lam/2, lam mu] (k_frag_diag64), the x^2 and x halves
+// accumulated apart.  Output lane l, register j of row block rb is (sample
+// 16 rb + 4 j + l/16, component 16 cb + l%16).  The rounding error of the sum is
+// at most (2 dpad4(D) + 8) 2^-52 (T1 + sqrt(2 T1 Q) + Q + |c0|) with T1 =
+// sum lam x^2 / 2 (the x^2 half) and Q = sum lam mu^2, since sum |lam mu x| <=
+// sqrt(Q 2 T1); a pair whose bound exceeds 1e-9 nats is recomputed in the FP64
+// direct form.  Pass 1 (store = false) raises rref[t] to the sample's maximum;
+// pass 2 stores a - R (R = rref[t]) into as[t][g].  Wave per block of 16
+// components.
+__device__ void logdens_diag_f64(const float* __restrict__ xs, int XS, int nt, int D, int G,
+                                 const double* __restrict__ Bx64,
+                                 const double* __restrict__ cq64,
+                                 const double* __restrict__ c64,
+                                 const double* __restrict__ lam64,
+                                 const float* __restrict__ means, float* __restrict__ as,
+                                 int AS, int* __restrict__ rref, int wid, int nw, int lane,
+                                 bool store) {
+  const int DP4 = XS;           // dimensions padded to 4 (zeros in xs)
+  const int KQ = DP4 / 2;       // k-steps of 4 features
+  const int KQ1 = DP4 / 4;      // of which the x^2 half
+  const int NCB = (G + 15) / 16;
+  const int m = lane & 15, kb = lane >> 4;
+  const int ta0 = min(m, nt - 1), ta1 = min(16 + m, nt - 1);  // A rows (past nt: dropped)
+  float Rv[2][4];
+  double mx[2][4];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int t = 16 * rb + 4 * j + kb;
+      Rv[rb][j] = (store && t < nt) ? ord2f(rref[t]) : 0.0f;
+      mx[rb][j] = -INFINITY;
+    }
+  for (int cb = __builtin_amdgcn_readfirstlane(wid); cb < NCB; cb += nw) {
+    f64x4 c1[2], c2[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      c1[rb] = f64x4{0.0, 0.0, 0.0, 0.0};
+      c2[rb] = f64x4{0.0, 0.0, 0.0, 0.0};
+    }
+    const double* fb = Bx64 + (size_t)cb * KQ * 64 + lane;
+    for (int k0 = 0; k0 < KQ; k0 += 8) {
+      double bb[8], a0[8], a1[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int ks = min(k0 + i, KQ - 1);
+        const int k = 4 * ks + kb;
+        const bool sq = ks < KQ1;
+        const int d = sq ? k : k - DP4;
+        bb[i] = fb[(size_t)ks * 64];
+        const double x0 = (double)xs[(size_t)ta0 * XS + d];
+        const double x1 = (double)xs[(size_t)ta1 * XS + d];
+        a0[i] = sq ? x0 * x0 : x0;
+        a1[i] = sq ? x1 * x1 : x1;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int ks = k0 + i;
+        if (ks >= KQ) break;
+        if (ks < KQ1) {
+          c1[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[i], bb[i], c1[0], 0, 0, 0);
+          c1[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[i], bb[i], c1[1], 0, 0, 0);
+        } else {
+          c2[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[i], bb[i], c2[0], 0, 0, 0);
+          c2[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[i], bb[i], c2[1], 0, 0, 0);
+        }
+      }
+    }
+    const int g = 16 * cb + m;
+    const bool gv = g < G;
+    const double c0 = gv ? cq64[g] : 0.0, Q = gv ? cq64[G + g] : 0.0;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int t = 16 * rb + 4 * j + kb;
+        if (!gv || t >= nt) continue;
+        double a = c0 + (c1[rb][j] + c2[rb][j]);
+        const double T1 = fmax(-c1[rb][j], 0.0);
+        const double e =
+            (2.0 * DP4 + 8.0) * 0x1p-52 * (T1 + sqrt(2.0 * T1 * Q) + Q + fabs(c0));
+        if (!store) {
+          mx[rb][j] = fmax(mx[rb][j], a);
+          continue;
+        }
+        if (!(e <= 1e-9)) {  // extreme data (or non-finite): FP64 direct form
+          const float* x = xs + (size_t)t * XS;
+          double q = 0.0;
+          for (int d = 0; d < D; ++d) {
+            const double u = (double)x[d] - (double)means[(size_t)g * D + d];
+            q += u * u * lam64[(size_t)g * D + d];
+          }
+          a = c64[g] - 0.5 * q;
+        }
+        as[(size_t)t * AS + g] = (float)(a - (double)Rv[rb][j]);
+      }
+  }
+  if (!store) {
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double v = mx[rb][j];
+        v = fmax(v, dpp_d<0x121>(v));
+        v = fmax(v, dpp_d<0x122>(v));
+        v = fmax(v, dpp_d<0x124>(v));
+        v = fmax(v, dpp_d<0x128>(v));
+        const int t = 16 * rb + 4 * j + kb;
+        if (m == 0 && t < nt && v > -INFINITY) atomicMax(&rref[t], f2ord((float)v));
+      }
+  }
+}
+
 // E-step (+ optional M-step map) over the block's contiguous sample range.
-// LDS: xs[T][D] samples, as[T][G] log-densities then responsibilities,
-// lse[T].  T is chosen on the host so the tile fits in LDS.
+// LDS: xs[T][D] samples (WIDE: rows padded to dpad4(D) with zeros),
+// as[T][G] log-densities (WIDE: relative to the sample's reference rref) then
+// responsibilities, lse[T].  T is chosen on the host so the tile fits in LDS.
 template <bool MSTEP, bool WIDE>
-__global__ void __launch_bounds__(kNT) k_estep_diag(
+__global__ void __launch_bounds__(kNT, 2) k_estep_diag(
     const float* __restrict__ X, int64_t N, int D, int64_t ldx, int G, int T, int64_t chunk,
     const float* __restrict__ sT, const float* __restrict__ mT, const float* __restrict__ cc,
     const double* __restrict__ c64, const double* __restrict__ lam64,
+    const double* __restrict__ Bx64, const double* __restrict__ cq64,
     const float* __restrict__ means, double* __restrict__ part, double* __restrict__ ll_part,
     float* __restrict__ per_sample, int32_t* __restrict__ dev_status) {
   extern __shared__ float lds[];
@@ -84,10 +244,7 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
   float* as = xs + (size_t)T * XS;   // [T][AS]
   double* lse = (double*)(as + (size_t)T * AS + ((T * AS) & 1));  // [T]
   uint32_t* gbits = (uint32_t*)(lse + T);  // [G/32]: component has a non-zero r in the tile
-  const int GC = WIDE ? wide_gc(D) : 0;
-  float* pcs = (float*)(gbits + ((G + 31) / 32 + 3) / 4 * 4);  // WIDE: [XS][GC] s
-  float* pcm = pcs + (size_t)XS * GC;                            // WIDE: [XS][GC] m
-  float* ccs = pcm + (size_t)XS * GC;                            // WIDE: [3][G] copy of cc
+  int* rref = (int*)(gbits + ((G + 31) / 32 + 3) / 4 * 4);  // WIDE: [T] reference, order-mapped
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -102,8 +259,6 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
   if (tid == 0) bad = 0;
   if (MSTEP)
     for (int p = tid; p < G * P; p += kNT) pb[p] = 0.0;
-  if (WIDE)
-    for (int p = tid; p < 3 * G; p += kNT) ccs[p] = cc[p];
   double llacc = 0.0;  // thread 0 only
   __syncthreads();
 
@@ -114,6 +269,8 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
       xs[p] = d < D ? X[(t0 + t) * ldx + d] : 0.0f;
     }
     for (int p = tid; p < NGB; p += kNT) gbits[p] = 0u;
+    if (WIDE)
+      for (int p = tid; p < T; p += kNT) rref[p] = f2ord(-INFINITY);
     __syncthreads();
     if (!WIDE) {
       // a_gi: one (sample, component) pair per thread iteration.
@@ -128,90 +285,23 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
         as[p] = (cc[g] - 0.5f * acc) + cc[G + g];
       }
     } else {
-      screen_blocked<false>(xs, XS, nt, D, G, GC, sT, mT, ccs, as, AS, pcs, pcm);
+      // exact log-densities on the matrix cores: pass 1 takes each sample's
+      // maximum R (its reference), pass 2 stores a - R
+      logdens_diag_f64(xs, XS, nt, D, G, Bx64, cq64, c64, lam64, means, as, AS, rref, wid, nw,
+                       lane, false);
+      __syncthreads();
+      logdens_diag_f64(xs, XS, nt, D, G, Bx64, cq64, c64, lam64, means, as, AS, rref, wid, nw,
+                       lane, true);
     }
     __syncthreads();
     if (WIDE) {
-      // kKL threads per sample.  mx = a_h - err_h for the screened argmax h is
-      // a lower bound of the exact maximum.  Every value is moved to the frame
-      // of M = mx; a component whose screened value, widened by its bound,
-      // comes within kNearGap nats of mx is recomputed in FP64 (Eq. 15); the
-      // log-sum-exp (Eqs. 16-18) is taken about the largest value in that
-      // frame.
+      // log-sum-exp about R + max (Eqs. 16-18) and responsibilities, kKL threads
+      // per sample
       const int ts = tid / kKL, j = tid % kKL;
       if (ts < nt) {  // uniform over the kKL threads of a sample
         float* a = as + (size_t)ts * AS;
-        const float* x = xs + (size_t)ts * XS;
-        float am = -INFINITY;
-        int ga = G;
-        for (int g = j; g < G; g += kKL) {
-          const float v = a[g];
-          if (v > am) {
-            am = v;
-            ga = g;
-          }
-        }
-#pragma unroll
-        for (int off = 1; off < kKL; off <<= 1) {
-          const float o = __shfl_xor(am, off);
-          const int og = __shfl_xor(ga, off);
-          if (o > am || (o == am && og < ga)) {
-            am = o;
-            ga = og;
-          }
-        }
-        const float mx =
-            ga < G ? am - err_direct(2.0f * (ccs[ga] - am), ccs[2 * G + ga], ccs[ga], D)
-                   : -INFINITY;
-        const double M = (double)mx;
-        // components in chunks of kKL, one per thread; the near ones of a
-        // chunk are recomputed by all kKL threads, each over every kKL-th
-        // dimension, and the partial sums are reduce-scattered so that thread
-        // j ends with component g0 + j's
-        static_assert(kKL == 8, "the reduce-scatter below is written for groups of 8");
         float dn = -INFINITY;
-        const int sh = lane & ~(kKL - 1);
-        for (int g0 = 0; g0 < G; g0 += kKL) {
-          const int g = g0 + j;
-          const float v = g < G ? a[g] : -INFINITY;
-          const bool nr = g < G && v + err_direct(2.0f * (ccs[g] - v), ccs[2 * G + g], ccs[g],
-                                                  D) >= mx - kNearGap;
-          const unsigned m = (unsigned)(__ballot(nr) >> sh) & 0xFFu;  // uniform in the group
-          float w = v - mx;
-          if (m) {
-            double q[kKL];
-#pragma unroll
-            for (int k = 0; k < kKL; ++k) {
-              q[k] = 0.0;
-              if ((m >> k) & 1u) {
-                const float* mu = means + (size_t)(g0 + k) * D;
-                const double* lg = lam64 + (size_t)(g0 + k) * D;
-                for (int d = j; d < D; d += kKL) {
-                  const double u = (double)x[d] - (double)mu[d];
-                  q[k] += u * u * lg[d];
-                }
-              }
-            }
-            double r4[4], r2[2];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const double o = __shfl_xor((j & 4) ? q[i] : q[i + 4], 4);
-              r4[i] = ((j & 4) ? q[i + 4] : q[i]) + o;
-            }
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-              const double o = __shfl_xor((j & 2) ? r4[i] : r4[i + 2], 2);
-              r2[i] = ((j & 2) ? r4[i + 2] : r4[i]) + o;
-            }
-            const double o = __shfl_xor((j & 1) ? r2[0] : r2[1], 1);
-            const double qj = ((j & 1) ? r2[1] : r2[0]) + o;
-            if (nr) w = (float)(c64[g] - 0.5 * qj - M);
-          }
-          if (g < G) {
-            a[g] = w;
-            dn = fmaxf(dn, w);
-          }
-        }
+        for (int g = j; g < G; g += kKL) dn = fmaxf(dn, a[g]);
 #pragma unroll
         for (int off = 1; off < kKL; off <<= 1) dn = fmaxf(dn, __shfl_xor(dn, off));
         dn = dn > -INFINITY ? dn : 0.0f;
@@ -219,7 +309,8 @@ __global__ void __launch_bounds__(kNT) k_estep_diag(
         for (int g = j; g < G; g += kKL) sm += (double)__expf(a[g] - dn);
 #pragma unroll
         for (int off = 1; off < kKL; off <<= 1) sm += __shfl_xor(sm, off);
-        const double l = (M + (double)dn) + log(sm);
+        const float R = ord2f(rref[ts]);
+        const double l = ((double)(R > -INFINITY ? R : 0.0f) + (double)dn) + log(sm);
         if (MSTEP) {
           const float dl = (float)log(sm);
           for (int g = j; g < G; g += kKL) {
@@ -448,7 +539,7 @@ size_t estep_lds(int D, int G, int T, bool wide) {
   const size_t XS = wide ? (size_t)((D + 3) & ~3) : (size_t)D;
   size_t b = sizeof(float) * ((size_t)T * (XS + G) + 1) + sizeof(double) * T;
   b += sizeof(uint32_t) * (((size_t)(G + 31) / 32 + 3) / 4 * 4);
-  if (wide) b += sizeof(float) * (2 * XS * (size_t)wide_gc(D) + 3 * (size_t)G + 8 * (size_t)T);
+  if (wide) b += sizeof(float) * 8 * (size_t)T + sizeof(int) * (size_t)T;
   return b;
 }
 
@@ -506,17 +597,22 @@ hipError_t launch_em_diag(const float* X, int64_t N, int D, int64_t ldx, int G, 
   hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, dev_status, n_recomputed, w.counters);
   hipLaunchKernelGGL(k_pre_diag, dim3(G), dim3(kNT), 0, st, hefts, means, covs, D, G, w.s, w.m,
                      w.c, w.c64, w.lamg64);
+  if (wide)
+    hipLaunchKernelGGL(k_frag_diag64, dim3(16 * ((G + 15) / 16)), dim3(kNT), 0, st, means,
+                       w.lamg64, w.c64, D, G, w.Bx64, w.cq64);
   {
     ProfScope ps(kProfEM, st);
     if (wide)
       launch_estep_diag<true, true>(nb, lds, st, X, N, D, ldx, G, T, chunk, (const float*)w.s,
                                     (const float*)w.m, (const float*)w.c, (const double*)w.c64,
-                                    (const double*)w.lamg64, (const float*)means, w.partials,
+                                    (const double*)w.lamg64, (const double*)w.Bx64, (const double*)w.cq64,
+                                    (const float*)means, w.partials,
                                     w.scalars, (float*)nullptr, dev_status);
     else
       launch_estep_diag<true, false>(nb, lds, st, X, N, D, ldx, G, T, chunk, (const float*)w.s,
                                      (const float*)w.m, (const float*)w.c, (const double*)w.c64,
-                                     (const double*)w.lamg64, (const float*)means, w.partials,
+                                     (const double*)w.lamg64, (const double*)w.Bx64, (const double*)w.cq64,
+                                    (const float*)means, w.partials,
                                      w.scalars, (float*)nullptr, dev_status);
   }
   hipLaunchKernelGGL(k_fin_diag, dim3(G), dim3(kNT), sizeof(double) * (2 * D + 1), st, w.partials,
@@ -547,17 +643,22 @@ hipError_t launch_loglik_diag(const float* X, int64_t N, int D, int64_t ldx, int
   hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, dev_status, nullptr, w.counters);
   hipLaunchKernelGGL(k_pre_diag, dim3(G), dim3(kNT), 0, st, hefts, means, covs, D, G, w.s, w.m,
                      w.c, w.c64, w.lamg64);
+  if (wide)
+    hipLaunchKernelGGL(k_frag_diag64, dim3(16 * ((G + 15) / 16)), dim3(kNT), 0, st, means,
+                       w.lamg64, w.c64, D, G, w.Bx64, w.cq64);
   {
     ProfScope ps(kProfLoglik, st);
     if (wide)
       launch_estep_diag<false, true>(nb, lds, st, X, N, D, ldx, G, T, chunk, (const float*)w.s,
                                      (const float*)w.m, (const float*)w.c, (const double*)w.c64,
-                                     (const double*)w.lamg64, (const float*)means, w.partials,
+                                     (const double*)w.lamg64, (const double*)w.Bx64, (const double*)w.cq64,
+                                    (const float*)means, w.partials,
                                      w.scalars, per_sample, dev_status);
     else
       launch_estep_diag<false, false>(nb, lds, st, X, N, D, ldx, G, T, chunk, (const float*)w.s,
                                       (const float*)w.m, (const float*)w.c, (const double*)w.c64,
-                                      (const double*)w.lamg64, (const float*)means, w.partials,
+                                      (const double*)w.lamg64, (const double*)w.Bx64, (const double*)w.cq64,
+                                    (const float*)means, w.partials,
                                       w.scalars, per_sample, dev_status);
   }
   hipLaunchKernelGGL(k_ll_finish, dim3(1), dim3(64), 0, st, w.scalars, nb, N, mean_loglik,

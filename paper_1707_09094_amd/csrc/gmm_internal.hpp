@@ -272,6 +272,9 @@ struct Workspace {
   double* c64;     // [G] log w - 1/2 (D log 2pi + log|Sigma|) in FP64
   double* lamg64;  // diag: [G][D] 1/sigma2 in FP64
   double* W64;     // full: [G][D][D] inverse Cholesky factor in FP64 (row-major lower)
+  double* Bx64;    // diag, D <= 128: FP64 MFMA fragments of the expanded form, see
+                   // diag_frag_count
+  double* cq64;    // diag, D <= 128: [2][G] c_g - Q_g / 2 and Q_g = sum_d lam mu^2 (FP64)
   double* Wf64;    // full, D <= 64: FP64 MFMA fragments of W, see full_frag_count
   double* b64;     // full, D <= 64: [G][16 * ceil(D/16)] b_g = W_g mu_g
   double* partials;   // [B][G][P]
@@ -293,6 +296,14 @@ inline int kexp_K(int D) { return D <= 64 ? 128 : (D <= 128 ? 256 : ((2 * D + 31
 inline int full_kq(int D) { return D <= 32 ? 8 : 16; }
 inline size_t full_frag_count(int D, int G) {
   return D <= 64 ? (size_t)G * ((D + 15) / 16) * full_kq(D) * 64 : 0;
+}
+
+// Diagonal covariances with D <= 128: the expanded form c_g - Q_g/2 +
+// sum_d (-lam/2 x_d^2 + lam mu x_d) in FP64 on the matrix cores; per block of 16
+// components dpad4(D)/2 k-steps of 4 features x 64 lanes, one double each.
+__host__ __device__ inline int dpad4(int D) { return (D + 3) & ~3; }
+inline size_t diag_frag_count(int D, int G) {
+  return D <= 128 ? (size_t)((G + 15) / 16) * (dpad4(D) / 2) * 64 : 0;
 }
 
 inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Workspace* w) {
@@ -320,6 +331,9 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   size_t o_lg = take(sizeof(double) * (size_t)G * D);
   size_t o_w64 = take(cov == GMM_COV_FULL ? sizeof(double) * (size_t)D * D * G : 0);
   const size_t nfr = cov == GMM_COV_FULL ? full_frag_count(D, G) : 0;
+  const size_t ndf = cov == GMM_COV_DIAG ? diag_frag_count(D, G) : 0;
+  size_t o_bx = take(sizeof(double) * ndf);
+  size_t o_cq = take(ndf ? sizeof(double) * 2 * (size_t)G : 0);
   size_t o_wf = take(sizeof(double) * nfr);
   size_t o_bw = take(nfr ? sizeof(double) * (size_t)G * 16 * ((D + 15) / 16) : 0);
   size_t o_p = take(sizeof(double) * (size_t)B * G * P);
@@ -343,6 +357,8 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   w->c64 = (double*)(b + o_c64);
   w->lamg64 = (double*)(b + o_lg);
   w->W64 = (double*)(b + o_w64);
+  w->Bx64 = (double*)(b + o_bx);
+  w->cq64 = (double*)(b + o_cq);
   w->Wf64 = (double*)(b + o_wf);
   w->b64 = (double*)(b + o_bw);
   w->partials = (double*)(b + o_p);
