@@ -152,17 +152,16 @@ constexpr int kWT = 32;    // tile rows of the WIDE kernels
 constexpr int kKL = 8;     // threads per sample in their per-sample passes
 __host__ __device__ inline int wide_gc(int D) { return D <= 64 ? 128 : 64; }
 
-// Register-blocked FP32 direct-form screening of a tile (WIDE forms): for
-// every sample t < nt and component g, v = sum_d (x_td s_dg - m_dg)^2 with the
-// parameters of GC components at a time staged in LDS ([XS][GC] each; rows of
-// xs padded with zeros to XS).  KM: as[t][g] = v (weighted distance); else
-// as[t][g] = c_g - v/2 (hi + lo); rows of as are AS apart.  Starts with the
-// block in sync; the caller syncs before reading as.
-template <bool KM>
-__device__ void screen_blocked(const float* __restrict__ xs, int XS, int nt, int D, int G, int GC,
-                               const float* __restrict__ sT, const float* __restrict__ mT,
-                               const float* __restrict__ cc, float* __restrict__ as, int AS,
-                               float* __restrict__ pcs, float* __restrict__ pcm) {
+// Register-blocked FP32 direct-form screening of a tile (k-means, WIDE form):
+// for every sample t < nt and component g, as[t][g] = v = sum_d (x_td s_dg -
+// m_dg)^2 (the weighted distance) with the parameters of GC components at a
+// time staged in LDS ([XS][GC] each; rows of xs padded with zeros to XS); rows
+// of as are AS apart.  Starts with the block in sync; the caller syncs before
+// reading as.
+__device__ inline void screen_blocked(const float* __restrict__ xs, int XS, int nt, int D, int G,
+                                      int GC, const float* __restrict__ sT,
+                                      const float* __restrict__ mT, float* __restrict__ as,
+                                      int AS, float* __restrict__ pcs, float* __restrict__ pcm) {
   const int tid = threadIdx.x;
   const int NBG = GC / 4;
   for (int gc0 = 0; gc0 < G; gc0 += GC) {
@@ -235,7 +234,7 @@ __device__ void screen_blocked(const float* __restrict__ xs, int XS, int nt, int
         for (int gi = 0; gi < 4; ++gi) {
           const int t = 4 * tb + ti, g = gc0 + 4 * gb + gi;
           if (t < nt && g < G)
-            as[(size_t)t * AS + g] = KM ? acc[ti][gi] : (cc[g] - 0.5f * acc[ti][gi]) + cc[G + g];
+            as[(size_t)t * AS + g] = acc[ti][gi];
         }
     }
   }

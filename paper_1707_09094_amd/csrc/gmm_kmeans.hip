@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(kWNT) k_km_assign_wide(
       xs[p] = d < D ? X[(t0 + t) * ldx + d] : 0.0f;
     }
     __syncthreads();
-    screen_blocked<true>(xs, XS, nt, D, G, GC, sT, mT, nullptr, as, AS, pcs, pcm);
+    screen_blocked(xs, XS, nt, D, G, GC, sT, mT, as, AS, pcs, pcm);
     __syncthreads();
     if (ts < nt) {  // uniform over the kKL threads of a sample
       const float* row = as + (size_t)ts * AS;
