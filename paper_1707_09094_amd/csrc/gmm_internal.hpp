@@ -142,103 +142,10 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 
-// ---- register-blocked screening of the WIDE generic kernels ------------------
-// (D <= 128 and many components): tile rows padded to a multiple of 4 (zeros);
-// the direct-form parameters of wide_gc(D) components at a time are staged in
-// LDS and each thread of a 256-thread block computes a 4 x 4 (sample x
-// component) block from float4 reads.
-constexpr int kWNT = 256;  // threads of the WIDE kernels
-constexpr int kWT = 32;    // tile rows of the WIDE kernels
+// ---- tiles of the kernels for D <= 128 and many components -----------------
+constexpr int kWNT = 256;  // threads per workgroup
+constexpr int kWT = 32;    // tile rows (two 16-row blocks of the matrix cores)
 constexpr int kKL = 8;     // threads per sample in their per-sample passes
-__host__ __device__ inline int wide_gc(int D) { return D <= 64 ? 128 : 64; }
-
-// Register-blocked FP32 direct-form screening of a tile (k-means, WIDE form):
-// for every sample t < nt and component g, as[t][g] = v = sum_d (x_td s_dg -
-// m_dg)^2 (the weighted distance) with the parameters of GC components at a
-// time staged in LDS ([XS][GC] each; rows of xs padded with zeros to XS); rows
-// of as are AS apart.  Starts with the block in sync; the caller syncs before
-// reading as.
-__device__ inline void screen_blocked(const float* __restrict__ xs, int XS, int nt, int D, int G,
-                                      int GC, const float* __restrict__ sT,
-                                      const float* __restrict__ mT, float* __restrict__ as,
-                                      int AS, float* __restrict__ pcs, float* __restrict__ pcm) {
-  const int tid = threadIdx.x;
-  const int NBG = GC / 4;
-  for (int gc0 = 0; gc0 < G; gc0 += GC) {
-    const int gn = min(GC, G - gc0);
-    if (gc0 > 0) __syncthreads();  // the previous chunk's readers are done
-    for (int p = tid; p < XS * GC; p += kWNT) {
-      const int d = p / GC, j = p - d * GC;
-      const bool ok = d < D && j < gn;
-      pcs[p] = ok ? sT[(size_t)d * G + gc0 + j] : 0.0f;
-      pcm[p] = ok ? mT[(size_t)d * G + gc0 + j] : 0.0f;
-    }
-    __syncthreads();
-    for (int q = tid; q < (kWT / 4) * NBG; q += kWNT) {
-      const int tb = q / NBG, gb = q - tb * NBG;
-      float acc[4][4];
-#pragma unroll
-      for (int ti = 0; ti < 4; ++ti)
-#pragma unroll
-        for (int gi = 0; gi < 4; ++gi) acc[ti][gi] = 0.0f;
-      // operands of four dimensions at a time, the next group's loads in
-      // flight while the current one is used
-      const float* xb = xs + (size_t)(4 * tb) * XS;
-      const float* sb = pcs + 4 * gb;
-      const float* mb = pcm + 4 * gb;
-      float4 xc[4], sc[4], mc[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        xc[i] = *(const float4*)(xb + (size_t)i * XS);
-        sc[i] = *(const float4*)(sb + (size_t)i * GC);
-        mc[i] = *(const float4*)(mb + (size_t)i * GC);
-      }
-      for (int d0 = 0; d0 < XS; d0 += 4) {
-        float4 xn[4], sn[4], mn[4];
-        const int dn = d0 + 4 < XS ? d0 + 4 : d0;  // last group: harmless reload
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          xn[i] = *(const float4*)(xb + (size_t)i * XS + dn);
-          sn[i] = *(const float4*)(sb + (size_t)(dn + i) * GC);
-          mn[i] = *(const float4*)(mb + (size_t)(dn + i) * GC);
-        }
-#pragma unroll
-        for (int dd = 0; dd < 4; ++dd) {
-          const float4 sv = sc[dd];
-          const float4 mv = mc[dd];
-#pragma unroll
-          for (int ti = 0; ti < 4; ++ti) {
-            const float x = dd == 0 ? xc[ti].x : dd == 1 ? xc[ti].y : dd == 2 ? xc[ti].z
-                                                                              : xc[ti].w;
-            float u;
-            u = fmaf(x, sv.x, -mv.x);
-            acc[ti][0] = fmaf(u, u, acc[ti][0]);
-            u = fmaf(x, sv.y, -mv.y);
-            acc[ti][1] = fmaf(u, u, acc[ti][1]);
-            u = fmaf(x, sv.z, -mv.z);
-            acc[ti][2] = fmaf(u, u, acc[ti][2]);
-            u = fmaf(x, sv.w, -mv.w);
-            acc[ti][3] = fmaf(u, u, acc[ti][3]);
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          xc[i] = xn[i];
-          sc[i] = sn[i];
-          mc[i] = mn[i];
-        }
-      }
-#pragma unroll
-      for (int ti = 0; ti < 4; ++ti)
-#pragma unroll
-        for (int gi = 0; gi < 4; ++gi) {
-          const int t = 4 * tb + ti, g = gc0 + 4 * gb + gi;
-          if (t < nt && g < G)
-            as[(size_t)t * AS + g] = acc[ti][gi];
-        }
-    }
-  }
-}
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
@@ -273,7 +180,8 @@ struct Workspace {
   double* W64;     // full: [G][D][D] inverse Cholesky factor in FP64 (row-major lower)
   double* Bx64;    // diag, D <= 128: FP64 MFMA fragments of the expanded form, see
                    // diag_frag_count
-  double* cq64;    // diag, D <= 128: [2][G] c_g - Q_g / 2 and Q_g = sum_d lam mu^2 (FP64)
+  double* cq64;    // D <= 128: [2][G] c_g - Q_g / 2 and Q_g = sum_d lam mu^2 (FP64); the
+                   // k-means kernel keeps its Q_g in the first half
   double* Wf64;    // full, D <= 64: FP64 MFMA fragments of W, see full_frag_count
   double* b64;     // full, D <= 64: [G][16 * ceil(D/16)] b_g = W_g mu_g
   double* partials;   // [B][G][P]
@@ -330,7 +238,7 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   size_t o_lg = take(sizeof(double) * (size_t)G * D);
   size_t o_w64 = take(cov == GMM_COV_FULL ? sizeof(double) * (size_t)D * D * G : 0);
   const size_t nfr = cov == GMM_COV_FULL ? full_frag_count(D, G) : 0;
-  const size_t ndf = cov == GMM_COV_DIAG ? diag_frag_count(D, G) : 0;
+  const size_t ndf = diag_frag_count(D, G);  // also the k-means fragments (any cov)
   size_t o_bx = take(sizeof(double) * ndf);
   size_t o_cq = take(ndf ? sizeof(double) * 2 * (size_t)G : 0);
   size_t o_wf = take(sizeof(double) * nfr);

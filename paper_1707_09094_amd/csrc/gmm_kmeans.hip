@@ -396,91 +396,94 @@ __global__ void __launch_bounds__(kNT) k_assign(const float* __restrict__ X, int
   if (hist) atomicAdd(hist + arg, 1ull);
 }
 
-// ---- WIDE forms (D <= 128, more components than the one-pass kernel takes) --
-// Direct-form constants of the screening: s_d = sqrt(lam_d) and m_gd = mu_gd
-// sqrt(lam_d), each rounded once to FP32 from FP64, stored [D][G]; Q_g =
-// sum_d lam_d mu_gd^2 (rounded up) for the rounding-error bound.
-__global__ void __launch_bounds__(kNT) k_km_pre_wide(const double* __restrict__ lam64,
-                                                     const float* __restrict__ means, int D,
-                                                     int G, float* __restrict__ sT,
-                                                     float* __restrict__ mT,
-                                                     float* __restrict__ Qout) {
+// ---- many components (G > 128, D <= 128): assignment on the matrix cores ----
+// The nearest mean minimises s_g(x) = Q_g - 2 sum_d lam_d mu_gd x_d with Q_g =
+// sum_d lam_d mu_gd^2 (the distance is sum_d lam_d x_d^2 + s_g).  s is computed
+// in FP64 by v_mfma_f64_16x16x4f64 (the samples as the A operand, 16 per row
+// block; B = -2 lam mu in its operand layout, [block of 16 means][k-step][64
+// lanes]); its rounding error is at most (D + 8) 2^-52 (Q + 2 sqrt(Q X2)) with
+// X2 = sum_d lam_d x_d^2, since sum_d |lam mu x| <= sqrt(Q X2).
+
+// Fragments and Q_g; block 16 cb + n writes mean g = 16 cb + n (zero past G).
+__global__ void __launch_bounds__(kNT) k_km_pre_f64(const double* __restrict__ lam64,
+                                                    const float* __restrict__ means, int D, int G,
+                                                    double* __restrict__ Bk,
+                                                    double* __restrict__ Qg) {
   __shared__ double sh[kNT];
   const int g = blockIdx.x;
+  const int KQ = dpad4(D) / 4;
+  const int cb = g >> 4, n = g & 15;
   double q = 0.0;
-  for (int d = threadIdx.x; d < D; d += kNT) {
-    const double l = lam64[d];
-    const double sd = sqrt(l);
-    const double mu = (double)means[(size_t)g * D + d];
-    sT[(size_t)d * G + g] = (float)sd;
-    mT[(size_t)d * G + g] = (float)(mu * sd);
-    q += l * mu * mu;
+  for (int k = threadIdx.x; k < 4 * KQ; k += kNT) {
+    double v = 0.0;
+    if (g < G && k < D) {
+      const double l = lam64[k];
+      const double mu = (double)means[(size_t)g * D + k];
+      v = -2.0 * l * mu;
+      q += l * mu * mu;
+    }
+    Bk[((size_t)cb * KQ + (k >> 2)) * 64 + n + 16 * (k & 3)] = v;
   }
   q = block_sum_d<kNT>(q, sh);
-  if (threadIdx.x == 0) Qout[g] = isfinite(q) ? (float)(1.0001 * q) : INFINITY;
+  if (g < G && threadIdx.x == 0) Qg[g] = q;
 }
 
-// Bound on |v - q| for the screened distance v of a sample whose exact
-// distance is q: with u_d = fma(x_d, s_d, -m_d), |du_d| <= 2^-24 (|u_d| +
-// sqrt(lam_d)(|x_d| + |mu_d|)); summing the squares with D FMAs gives
-// 2^-24 ((2 + D) q + 2 sqrt(q (2q + 8Q))), evaluated at the screened value
-// with a 1% margin, plus 2^-42 Q for the difference between screened and
-// exact q near zero and 2^-22 v for the FP32 evaluation of the comparisons
-// that use it.
-__device__ __forceinline__ float km_err(float v, float Q, int D) {
-  v = fmaxf(v, 0.0f);
-  return 1.01f * 0x1p-24f * ((2.0f + (float)D) * v + 2.0f * sqrtf(v * (2.0f * v + 8.0f * Q))) +
-         0x1p-22f * v + 0x1p-42f * Q;
+// merge of (smallest value, its index, second smallest) pairs; ties go to the
+// lower index, so the result is the first minimum whatever the order
+__device__ __forceinline__ void km_merge(double& v1, int& g1, double& v2, double o1, int og,
+                                         double o2) {
+  if (o1 < v1 || (o1 == v1 && og < g1)) {
+    v2 = fmin(v1, o2);
+    v1 = o1;
+    g1 = og;
+  } else {
+    v2 = fmin(v2, o1);
+  }
+}
+template <int CTRL>
+__device__ __forceinline__ void km_merge_dpp(double& v1, int& g1, double& v2) {
+  const double o1 = dpp_d<CTRL>(v1), o2 = dpp_d<CTRL>(v2);
+  const int og = __builtin_amdgcn_update_dpp(0, g1, CTRL, 0xF, 0xF, false);
+  km_merge(v1, g1, v2, o1, og, o2);
 }
 
-// Hard assignment (Eq. 19) over tiles of kWT samples: register-blocked FP32
-// screening of all components, then kKL threads per sample take the two
-// smallest screened distances v1 <= v2.  With U1 = v1 + err(v1), a component
-// is a candidate when v_g - err(v_g) <= U1; none besides the best means the
-// FP32 argmin is the exact one.  Bounding 2 sqrt(8 Q v) <= sqrt(8 Q / vr) v +
-// sqrt(8 Q vr) (AM-GM about vr = v1) makes err(v) <= A v + B for every
-// component (Q <= Qmax), so v2 (1 - A) - B > U1 rules out all of them at
-// once; otherwise each component is tested with its own bound, and the
-// candidates (and the best) are re-decided in FP64, first minimum wins.
-// LDS: xs[kWT][XS], as[kWT][G + 8], screening parameter chunks, Q_g, lam_d.
-__global__ void __launch_bounds__(kWNT) k_km_assign_wide(
+// Hard assignment (Eq. 19) over tiles of 32 samples: wave per block of 16
+// means, every sample's two smallest s and the first minimum's index (lanes,
+// then the 16 lanes of a row, then the waves through LDS); a sample whose gap
+// v2 - v1 exceeds twice the bound is decided, the others are re-decided over
+// all means in the FP64 direct form, first minimum wins.
+template <int KQM>
+__global__ void __launch_bounds__(kWNT) k_km_assign_f64(
     const float* __restrict__ X, int64_t N, int D, int64_t ldx, int G, int64_t chunk,
-    const float* __restrict__ sT, const float* __restrict__ mT, const float* __restrict__ Qg,
+    const double* __restrict__ Bk, const double* __restrict__ Qg,
     const float* __restrict__ means, const double* __restrict__ lam64,
     int32_t* __restrict__ assign, int64_t* __restrict__ n_recomputed) {
-  extern __shared__ float lds[];
-  const int XS = (D + 3) & ~3;
-  const int GC = wide_gc(D);
-  const int AS = G + 8;  // the kKL threads of a sample read distinct banks
-  float* xs = lds;                       // [kWT][XS]
-  float* as = xs + (size_t)kWT * XS;     // [kWT][AS]
-  float* pcs = as + (size_t)kWT * AS;    // [XS][GC]
-  float* pcm = pcs + (size_t)XS * GC;    // [XS][GC]
-  float* qs = pcm + (size_t)XS * GC;     // [G]
-  double* l64 = (double*)(qs + ((G + 1) & ~1));  // [D]
-  __shared__ float wq[kWNT / kWave];
-  __shared__ int wrec[kWNT / kWave];
+  constexpr int NW = kWNT / kWave;
+  __shared__ float xs[kWT * 129];
+  __shared__ double l64[128];
+  __shared__ double wv1[NW][kWT], wv2[NW][kWT];
+  __shared__ int wg1[NW][kWT];
+  __shared__ double wq[NW];
+  __shared__ int wrec[NW];
+  const int XS = dpad4(D);
+  const int KQ = XS / 4;
+  const int NCB = (G + 15) / 16;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wid = tid / kWave;
-  const int ts = tid / kKL, j = tid % kKL;  // sample slot of the decision pass, sub-lane
+  const int m = lane & 15, kb = lane >> 4;
   const int b = blockIdx.x;
   const int64_t i0 = (int64_t)b * chunk;
   const int64_t i1 = min(N, i0 + chunk);
-  float qm = 0.0f;
-  for (int g = tid; g < G; g += kWNT) {
-    const float q = Qg[g];
-    qs[g] = q;
-    qm = fmaxf(qm, q);
-  }
+  double qm = 0.0;
+  for (int g = tid; g < G; g += kWNT) qm = fmax(qm, Qg[g]);
   for (int d = tid; d < D; d += kWNT) l64[d] = lam64[d];
 #pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) qm = fmaxf(qm, __shfl_xor(qm, off));
+  for (int off = 1; off < kWave; off <<= 1) qm = fmax(qm, __shfl_xor(qm, off));
   if (lane == 0) wq[wid] = qm;
   __syncthreads();
-  float Qmax = wq[0];
-  for (int w = 1; w < kWNT / kWave; ++w) Qmax = fmaxf(Qmax, wq[w]);
-  const float a0 = 1.01f * 0x1p-24f * (2.0f + (float)D + 2.8284272f) + 0x1p-21f;
+  double Qmax = wq[0];
+  for (int w = 1; w < NW; ++w) Qmax = fmax(Qmax, wq[w]);
   int nrec = 0;
   for (int64_t t0 = i0; t0 < i1; t0 += kWT) {
     const int nt = (int)min((int64_t)kWT, i1 - t0);
@@ -489,92 +492,97 @@ __global__ void __launch_bounds__(kWNT) k_km_assign_wide(
       xs[p] = d < D ? X[(t0 + t) * ldx + d] : 0.0f;
     }
     __syncthreads();
-    screen_blocked(xs, XS, nt, D, G, GC, sT, mT, as, AS, pcs, pcm);
+    double xa[2][KQM];
+    const int ta0 = min(m, nt - 1), ta1 = min(16 + m, nt - 1);
+#pragma unroll
+    for (int ks = 0; ks < KQM; ++ks) {
+      const int d = min(4 * ks + kb, XS - 1);
+      xa[0][ks] = ks < KQ ? (double)xs[ta0 * XS + d] : 0.0;
+      xa[1][ks] = ks < KQ ? (double)xs[ta1 * XS + d] : 0.0;
+    }
+    double v1[2][4], v2[2][4];
+    int g1[2][4];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v1[rb][j] = INFINITY;
+        v2[rb][j] = INFINITY;
+        g1[rb][j] = G;
+      }
+    for (int cb = __builtin_amdgcn_readfirstlane(wid); cb < NCB; cb += NW) {
+      f64x4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+      const double* fb = Bk + (size_t)cb * KQ * 64 + lane;
+#pragma unroll
+      for (int k0 = 0; k0 < KQM; k0 += 8) {
+        double bb[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) bb[i] = k0 + i < KQ ? fb[(size_t)(k0 + i) * 64] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          if (k0 + i >= KQ) break;
+          c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[0][k0 + i], bb[i], c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[1][k0 + i], bb[i], c1, 0, 0, 0);
+        }
+      }
+      const int g = 16 * cb + m;
+      const double Q = g < G ? Qg[g] : INFINITY;  // padding means never win
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double s0 = Q + c0[j], s1 = Q + c1[j];
+        km_merge(v1[0][j], g1[0][j], v2[0][j], s0, g, INFINITY);
+        km_merge(v1[1][j], g1[1][j], v2[1][j], s1, g, INFINITY);
+      }
+    }
+    // lane (m, kb) holds samples 16 rb + 4 j + kb over means m + 16 cb: reduce
+    // over the 16 lanes of the row, then across the waves
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        km_merge_dpp<0x121>(v1[rb][j], g1[rb][j], v2[rb][j]);
+        km_merge_dpp<0x122>(v1[rb][j], g1[rb][j], v2[rb][j]);
+        km_merge_dpp<0x124>(v1[rb][j], g1[rb][j], v2[rb][j]);
+        km_merge_dpp<0x128>(v1[rb][j], g1[rb][j], v2[rb][j]);
+        const int t = 16 * rb + 4 * j + kb;
+        if (m == 0) {
+          wv1[wid][t] = v1[rb][j];
+          wv2[wid][t] = v2[rb][j];
+          wg1[wid][t] = g1[rb][j];
+        }
+      }
     __syncthreads();
-    if (ts < nt) {  // uniform over the kKL threads of a sample
-      const float* row = as + (size_t)ts * AS;
-      const float* x = xs + (size_t)ts * XS;
-      float v1 = INFINITY, v2 = INFINITY;
-      int g1 = G;
-      for (int g = j; g < G; g += kKL) {  // increasing g: the first minimum stays
-        const float v = row[g];
-        if (v < v1) {
-          v2 = v1;
-          v1 = v;
-          g1 = g;
-        } else if (v < v2) {
-          v2 = v;
-        }
-      }
-#pragma unroll
-      for (int off = 1; off < kKL; off <<= 1) {
-        const float o1 = __shfl_xor(v1, off);
-        const float o2 = __shfl_xor(v2, off);
-        const int og = __shfl_xor(g1, off);
-        if (o1 < v1 || (o1 == v1 && og < g1)) {
-          v2 = fminf(v1, o2);
-          v1 = o1;
-          g1 = og;
-        } else {
-          v2 = fminf(v2, o1);
-        }
-      }
-      const bool full = !(v1 < INFINITY) || g1 >= G;  // no finite screened value
-      bool need = full;
-      float U1 = 0.0f;
-      if (!full) {
-        U1 = v1 + km_err(v1, qs[g1], D);
-        const float vr = fmaxf(v1, 1e-30f);
-        const float A = a0 + 1.01f * 0x1p-24f * sqrtf(8.0f * Qmax / vr);
-        const float B = 1.01f * 0x1p-24f * sqrtf(8.0f * Qmax * vr) + 0x1p-42f * Qmax;
-        if (!(A < 0.5f && v2 * (1.0f - A) - B > U1)) {
-          bool c = false;
-          for (int g = j; g < G; g += kKL) {
-            const float v = row[g];
-            if (g != g1 && !(v - km_err(v, qs[g], D) > U1)) c = true;
-          }
-#pragma unroll
-          for (int off = 1; off < kKL; off <<= 1) {
-            const int o = __shfl_xor((int)c, off);  // every lane takes part
-            c = c || o != 0;
-          }
-          need = c;
-        }
-      }
-      int arg = g1;
-      if (need) {
-        // FP64 re-decision over the candidates (all components when full)
-        double bs = INFINITY;
-        int bg = G;
-        for (int g = j; g < G; g += kKL) {
-          const float v = row[g];
-          if (!(full || g == g1 || !(v - km_err(v, qs[g], D) > U1))) continue;
+    if (tid < nt) {
+      const int t = tid;
+      double V1 = wv1[0][t], V2 = wv2[0][t];
+      int G1 = wg1[0][t];
+      for (int w = 1; w < NW; ++w) km_merge(V1, G1, V2, wv1[w][t], wg1[w][t], wv2[w][t]);
+      const float* x = xs + t * XS;
+      double X2 = 0.0;
+      for (int d = 0; d < D; ++d) X2 += l64[d] * (double)x[d] * (double)x[d];
+      const double e = 1.01 * (D + 8.0) * 0x1p-52 * (Qmax + 2.0 * sqrt(Qmax * X2));
+      int arg = G1;
+      if (!(V2 - V1 > 2.0 * e) || G1 >= G) {
+        // FP64 direct form over all means, first minimum wins
+        double best = INFINITY;
+        arg = 0;
+        for (int g = 0; g < G; ++g) {
           const float* mu = means + (size_t)g * D;
-          double s = 0.0;
+          double q = 0.0;
           for (int d = 0; d < D; ++d) {
             const double u = (double)x[d] - (double)mu[d];
-            s += l64[d] * u * u;
+            q += l64[d] * u * u;
           }
-          if (s < bs) {
-            bs = s;
-            bg = g;
-          }
-        }
-#pragma unroll
-        for (int off = 1; off < kKL; off <<= 1) {
-          const double os = __shfl_xor(bs, off);
-          const int og = __shfl_xor(bg, off);
-          if (os < bs || (os == bs && og < bg)) {
-            bs = os;
-            bg = og;
+          if (q < best) {
+            best = q;
+            arg = g;
           }
         }
-        arg = bg < G ? bg : 0;
-        nrec += j == 0;
+        ++nrec;
       }
-      if (j == 0) assign[t0 + ts] = arg;
+      assign[t0 + t] = arg;
     }
-    __syncthreads();  // xs/as are rewritten by the next tile
+    __syncthreads();  // xs and the merge slots are rewritten by the next tile
   }
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) nrec += __shfl_xor(nrec, off);
@@ -582,16 +590,9 @@ __global__ void __launch_bounds__(kWNT) k_km_assign_wide(
   __syncthreads();
   if (tid == 0) {
     long long nr = 0;
-    for (int w = 0; w < kWNT / kWave; ++w) nr += wrec[w];
+    for (int w = 0; w < NW; ++w) nr += wrec[w];
     if (nr) atomicAdd((unsigned long long*)n_recomputed, (unsigned long long)nr);
   }
-}
-
-size_t km_wide_lds(int D, int G) {
-  const size_t XS = (size_t)((D + 3) & ~3);
-  return sizeof(float) * ((size_t)kWT * (XS + G + 8) + 2 * XS * (size_t)wide_gc(D) +
-                          (size_t)((G + 1) & ~1)) +
-         sizeof(double) * (size_t)D;
 }
 
 // Map step of the hard assignment (Eqs. 9-11) with the components split in
@@ -722,11 +723,9 @@ __global__ void k_zero_i64(int64_t* p, int n, int32_t* dev_status) {
   if (dev_status && blockIdx.x == 0 && threadIdx.x == 0) *dev_status = 0;
 }
 
-// The WIDE assignment kernel is used for D <= 128 and more components than the
-// one-pass kernel takes, when its tile fits in LDS.
-bool km_use_wide(int D, int G) {
-  return D <= 128 && G > 128 && km_wide_lds(D, G) <= 159 * 1024;  // + static LDS
-}
+// The matrix-core assignment kernel takes D <= 128 and more components than the
+// one-pass kernel takes.
+bool km_use_wide(int D, int G) { return D <= 128 && G > 128; }
 
 // Largest component group of the grouped map step that fits in LDS (0: none).
 int km_accum_group_max(int D) {
@@ -771,12 +770,15 @@ hipError_t launch_kmeans(const float* X, int64_t N, int D, int64_t ldx, int G, i
   hipLaunchKernelGGL(k_km_pre, dim3((D + 255) / 256), dim3(256), 0, st, gvar, D, var_floor, dist,
                      w.lam64, w.lam32);
   if (km_use_wide(D, G)) {
-    hipLaunchKernelGGL(k_km_pre_wide, dim3(G), dim3(kNT), 0, st, w.lam64, means, D, G, w.s, w.m,
-                       w.c);
+    hipLaunchKernelGGL(k_km_pre_f64, dim3(16 * ((G + 15) / 16)), dim3(kNT), 0, st, w.lam64, means,
+                       D, G, w.Bx64, w.cq64);
     ProfScope ps(kProfKmAssign, st);
-    set_max_lds((const void*)k_km_assign_wide, km_wide_lds(D, G));
-    hipLaunchKernelGGL(k_km_assign_wide, dim3(nb), dim3(kWNT), km_wide_lds(D, G), st, X, N, D,
-                       ldx, G, chunk, w.s, w.m, w.c, means, w.lam64, asg, nrec);
+    if (D <= 64)
+      hipLaunchKernelGGL(k_km_assign_f64<16>, dim3(nb), dim3(kWNT), 0, st, X, N, D, ldx, G, chunk,
+                         w.Bx64, w.cq64, means, w.lam64, asg, nrec);
+    else
+      hipLaunchKernelGGL(k_km_assign_f64<32>, dim3(nb), dim3(kWNT), 0, st, X, N, D, ldx, G, chunk,
+                         w.Bx64, w.cq64, means, w.lam64, asg, nrec);
   } else {
     ProfScope ps(kProfKmAssign, st);
     hipLaunchKernelGGL(k_km_assign, dim3(nb), dim3(kNT), 0, st, X, N, D, ldx, G, chunk, means,
