@@ -9,8 +9,8 @@
 //                   distances, lowest index on ties; when the two best FP32
 //                   distances are within twice their rounding-error bound the
 //                   sample is re-decided in FP64, so the result is the FP64
-//                   argmin.  (k_km_assign_wide: the same decision with a
-//                   register-blocked screening, for many components.)
+//                   argmin.  (k_km_assign_f64, more than 128 components:
+//                   FP64 matrix-core distances with the same gap test.)
 //   k_km_accum      map step of Sec. 2.1 with hard l (Eqs. 9-11): per-block
 //                   FP64 count, sum (x - mu_old), sum (x - mu_old)^2
 //                   (k_km_accum_grp: components in LDS-sized groups)
