@@ -109,42 +109,35 @@ __global__ void __launch_bounds__(kNT) k_frag_diag64(const float* __restrict__ m
   }
 }
 
-// One pass of the FP64 matrix-core E-step over a tile of up to 32 samples
-// (D <= 128): a_g(x) = c0_g + sum_k A_k B_gk with A = [x_d^2, x_d] (the samples,
-// 16 per row block, as the A operand of v_mfma_f64_16x16x4f64) and B the
-// expanded coefficients [-lam/2, lam mu] (k_frag_diag64), the x^2 and x halves
+// The FP64 matrix-core E-step over a tile of up to 32 samples (D <= 128):
+// a_g(x) = c0_g + sum_k A_k B_gk with A = [x_d^2, x_d] (the samples, 16 per row
+// block, as the A operand of v_mfma_f64_16x16x4f64) and B the expanded
+// coefficients [-lam/2, lam mu] (k_frag_diag64), the x^2 and x halves
 // accumulated apart.  Output lane l, register j of row block rb is (sample
 // 16 rb + 4 j + l/16, component 16 cb + l%16).  The rounding error of the sum is
 // at most (2 dpad4(D) + 8) 2^-52 (T1 + sqrt(2 T1 Q) + Q + |c0|) with T1 =
 // sum lam x^2 / 2 (the x^2 half) and Q = sum lam mu^2, since sum |lam mu x| <=
 // sqrt(Q 2 T1); a pair whose bound exceeds 1e-9 nats is recomputed in the FP64
-// direct form.  Pass 1 (store = false) raises rref[t] to the sample's maximum;
-// pass 2 stores a - R (R = rref[t]) into as[t][g].  Wave per block of 16
-// components.
+// direct form.  Each (sample, block of 16 components) gets its own reference,
+// R = the block's largest value rounded to FP32, stored in rcb[t][cb]; as[t][g]
+// receives a - R in FP32.  For every pair that can carry a responsibility above
+// e^-40, a lies within 40 nats of the sample's maximum, which bounds R from
+// above, so |a - R| <= 40 and the FP32 entry is accurate to 40 2^-24 nats.
+// Wave per block of 16 components.
 __device__ void logdens_diag_f64(const float* __restrict__ xs, int XS, int nt, int D, int G,
                                  const double* __restrict__ Bx64,
                                  const double* __restrict__ cq64,
                                  const double* __restrict__ c64,
                                  const double* __restrict__ lam64,
                                  const float* __restrict__ means, float* __restrict__ as,
-                                 int AS, int* __restrict__ rref, int wid, int nw, int lane,
-                                 bool store) {
+                                 int AS, float* __restrict__ rcb, int RS, int wid, int nw,
+                                 int lane) {
   const int DP4 = XS;           // dimensions padded to 4 (zeros in xs)
   const int KQ = DP4 / 2;       // k-steps of 4 features
   const int KQ1 = DP4 / 4;      // of which the x^2 half
   const int NCB = (G + 15) / 16;
   const int m = lane & 15, kb = lane >> 4;
   const int ta0 = min(m, nt - 1), ta1 = min(16 + m, nt - 1);  // A rows (past nt: dropped)
-  float Rv[2][4];
-  double mx[2][4];
-#pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int t = 16 * rb + 4 * j + kb;
-      Rv[rb][j] = (store && t < nt) ? ord2f(rref[t]) : 0.0f;
-      mx[rb][j] = -INFINITY;
-    }
   for (int cb = __builtin_amdgcn_readfirstlane(wid); cb < NCB; cb += nw) {
     f64x4 c1[2], c2[2];
 #pragma unroll
@@ -188,47 +181,43 @@ __device__ void logdens_diag_f64(const float* __restrict__ xs, int XS, int nt, i
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int t = 16 * rb + 4 * j + kb;
-        if (!gv || t >= nt) continue;
-        double a = c0 + (c1[rb][j] + c2[rb][j]);
-        const double T1 = fmax(-c1[rb][j], 0.0);
-        const double e =
-            (2.0 * DP4 + 8.0) * 0x1p-52 * (T1 + sqrt(2.0 * T1 * Q) + Q + fabs(c0));
-        if (!store) {
-          mx[rb][j] = fmax(mx[rb][j], a);
-          continue;
-        }
-        if (!(e <= 1e-9)) {  // extreme data (or non-finite): FP64 direct form
-          const float* x = xs + (size_t)t * XS;
-          double q = 0.0;
-          for (int d = 0; d < D; ++d) {
-            const double u = (double)x[d] - (double)means[(size_t)g * D + d];
-            q += u * u * lam64[(size_t)g * D + d];
+        double a = -INFINITY;
+        if (gv && t < nt) {
+          a = c0 + (c1[rb][j] + c2[rb][j]);
+          const double T1 = fmax(-c1[rb][j], 0.0);
+          const double e =
+              (2.0 * DP4 + 8.0) * 0x1p-52 * (T1 + sqrt(2.0 * T1 * Q) + Q + fabs(c0));
+          if (!(e <= 1e-9)) {  // extreme data (or non-finite): FP64 direct form
+            const float* x = xs + (size_t)t * XS;
+            double q = 0.0;
+            for (int d = 0; d < D; ++d) {
+              const double u = (double)x[d] - (double)means[(size_t)g * D + d];
+              q += u * u * lam64[(size_t)g * D + d];
+            }
+            a = c64[g] - 0.5 * q;
           }
-          a = c64[g] - 0.5 * q;
         }
-        as[(size_t)t * AS + g] = (float)(a - (double)Rv[rb][j]);
-      }
-  }
-  if (!store) {
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        double v = mx[rb][j];
+        // the block's largest value over the 16 lanes of the row (all lanes)
+        double v = a;
         v = fmax(v, dpp_d<0x121>(v));
         v = fmax(v, dpp_d<0x122>(v));
         v = fmax(v, dpp_d<0x124>(v));
         v = fmax(v, dpp_d<0x128>(v));
-        const int t = 16 * rb + 4 * j + kb;
-        if (m == 0 && t < nt && v > -INFINITY) atomicMax(&rref[t], f2ord((float)v));
+        const float R = (float)v;
+        if (t < nt) {
+          if (gv) as[(size_t)t * AS + g] = R > -INFINITY ? (float)(a - (double)R) : -INFINITY;
+          if (m == 0) rcb[(size_t)t * RS + cb] = R;
+        }
       }
   }
 }
 
 // E-step (+ optional M-step map) over the block's contiguous sample range.
 // LDS: xs[T][D] samples (WIDE: rows padded to dpad4(D) with zeros),
-// as[T][G] log-densities (WIDE: relative to the sample's reference rref) then
-// responsibilities, lse[T].  T is chosen on the host so the tile fits in LDS.
+// as[T][G] log-densities (WIDE: relative to the references rcb) then
+// responsibilities, lse[T], the tile's component mask (WIDE: then rcb[T][NCB],
+// a reference per sample and block of 16 components).  T is chosen on the host
+// so the tile fits in LDS.
 template <bool MSTEP, bool WIDE>
 __global__ void __launch_bounds__(kNT, 2) k_estep_diag(
     const float* __restrict__ X, int64_t N, int D, int64_t ldx, int G, int T, int64_t chunk,
@@ -244,7 +233,8 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_diag(
   float* as = xs + (size_t)T * XS;   // [T][AS]
   double* lse = (double*)(as + (size_t)T * AS + ((T * AS) & 1));  // [T]
   uint32_t* gbits = (uint32_t*)(lse + T);  // [G/32]: component has a non-zero r in the tile
-  int* rref = (int*)(gbits + ((G + 31) / 32 + 3) / 4 * 4);  // WIDE: [T] reference, order-mapped
+  const int RS = (G + 15) / 16;  // WIDE: row stride of rcb
+  float* rcb = (float*)(gbits + ((G + 31) / 32 + 3) / 4 * 4);  // WIDE: [T][RS] references
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -269,8 +259,6 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_diag(
       xs[p] = d < D ? X[(t0 + t) * ldx + d] : 0.0f;
     }
     for (int p = tid; p < NGB; p += kNT) gbits[p] = 0u;
-    if (WIDE)
-      for (int p = tid; p < T; p += kNT) rref[p] = f2ord(-INFINITY);
     __syncthreads();
     if (!WIDE) {
       // a_gi: one (sample, component) pair per thread iteration.
@@ -285,36 +273,39 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_diag(
         as[p] = (cc[g] - 0.5f * acc) + cc[G + g];
       }
     } else {
-      // exact log-densities on the matrix cores: pass 1 takes each sample's
-      // maximum R (its reference), pass 2 stores a - R
-      logdens_diag_f64(xs, XS, nt, D, G, Bx64, cq64, c64, lam64, means, as, AS, rref, wid, nw,
-                       lane, false);
-      __syncthreads();
-      logdens_diag_f64(xs, XS, nt, D, G, Bx64, cq64, c64, lam64, means, as, AS, rref, wid, nw,
-                       lane, true);
+      // exact log-densities on the matrix cores, relative to per-block references
+      logdens_diag_f64(xs, XS, nt, D, G, Bx64, cq64, c64, lam64, means, as, AS, rcb, RS, wid,
+                       nw, lane);
     }
     __syncthreads();
     if (WIDE) {
-      // log-sum-exp about R + max (Eqs. 16-18) and responsibilities, kKL threads
-      // per sample
+      // log-sum-exp (Eqs. 16-18) about M = max_cb R_cb, each value taken as
+      // (R_cb - M) + (a - R_cb) in FP64, and responsibilities; kKL threads per
+      // sample
       const int ts = tid / kKL, j = tid % kKL;
       if (ts < nt) {  // uniform over the kKL threads of a sample
         float* a = as + (size_t)ts * AS;
+        const float* rr = rcb + (size_t)ts * RS;
+        float M = -INFINITY;
+        for (int c = j; c < RS; c += kKL) M = fmaxf(M, rr[c]);
+#pragma unroll
+        for (int off = 1; off < kKL; off <<= 1) M = fmaxf(M, __shfl_xor(M, off));
+        M = M > -INFINITY ? M : 0.0f;
+        auto val = [&](int g) { return (float)(((double)rr[g >> 4] - (double)M) + (double)a[g]); };
         float dn = -INFINITY;
-        for (int g = j; g < G; g += kKL) dn = fmaxf(dn, a[g]);
+        for (int g = j; g < G; g += kKL) dn = fmaxf(dn, val(g));
 #pragma unroll
         for (int off = 1; off < kKL; off <<= 1) dn = fmaxf(dn, __shfl_xor(dn, off));
         dn = dn > -INFINITY ? dn : 0.0f;
         double sm = 0.0;
-        for (int g = j; g < G; g += kKL) sm += (double)__expf(a[g] - dn);
+        for (int g = j; g < G; g += kKL) sm += (double)__expf(val(g) - dn);
 #pragma unroll
         for (int off = 1; off < kKL; off <<= 1) sm += __shfl_xor(sm, off);
-        const float R = ord2f(rref[ts]);
-        const double l = ((double)(R > -INFINITY ? R : 0.0f) + (double)dn) + log(sm);
+        const double l = ((double)M + (double)dn) + log(sm);
         if (MSTEP) {
           const float dl = (float)log(sm);
           for (int g = j; g < G; g += kKL) {
-            const float z = (a[g] - dn) - dl;
+            const float z = (val(g) - dn) - dl;
             const float r = z >= -kRespCut ? __expf(z) : 0.0f;
             a[g] = r;
             if (r != 0.0f) atomicOr(&gbits[g >> 5], 1u << (g & 31));
@@ -539,7 +530,7 @@ size_t estep_lds(int D, int G, int T, bool wide) {
   const size_t XS = wide ? (size_t)((D + 3) & ~3) : (size_t)D;
   size_t b = sizeof(float) * ((size_t)T * (XS + G) + 1) + sizeof(double) * T;
   b += sizeof(uint32_t) * (((size_t)(G + 31) / 32 + 3) / 4 * 4);
-  if (wide) b += sizeof(float) * 8 * (size_t)T + sizeof(int) * (size_t)T;
+  if (wide) b += sizeof(float) * 8 * (size_t)T + sizeof(float) * (size_t)T * ((G + 15) / 16);
   return b;
 }
 
