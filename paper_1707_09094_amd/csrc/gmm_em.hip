@@ -247,8 +247,10 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_diag(
   const int NGB = (G + 31) / 32;
   double* pb = part + (size_t)b * G * P;
   if (tid == 0) bad = 0;
-  if (MSTEP)
+  if (MSTEP) {
     for (int p = tid; p < G * P; p += kNT) pb[p] = 0.0;
+    __threadfence();  // the zeros land before any atomic update of the partials
+  }
   double llacc = 0.0;  // thread 0 only
   __syncthreads();
 
@@ -397,9 +399,11 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_diag(
     if (MSTEP) {
       // map step (Eqs. 9-11) about the current mean: wave per component that
       // has a non-zero responsibility in the tile, lanes over dimensions; the
-      // tile's contributions are added to the block's FP64 partials once.
-      // Two components at a time, their partials loaded before the tile loop
-      // so that the loads' latency overlaps it.
+      // tile's contributions are added to the block's FP64 partials once, by
+      // atomic adds whose result is not waited for.  Component g always goes
+      // to wave g % nw and dimension d to lane d % 64, so every partial is
+      // updated by one lane only, in tile order: the sums are those of plain
+      // read-modify-write updates.  Two components at a time.
       auto active = [&](int g) { return ((gbits[g >> 5] >> (g & 31)) & 1u) != 0u; };
       for (int g = wid;;) {
         while (g < G && !active(g)) g += nw;
@@ -409,16 +413,12 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_diag(
         const bool two = h < G;  // wave-uniform
         double* qg = pb + (size_t)g * P;
         double* qh = pb + (size_t)(two ? h : g) * P;
-        const double cg0 = lane == 0 ? qg[0] : 0.0;
-        const double ch0 = lane == 0 && two ? qh[0] : 0.0;
         // the tile's samples with a non-zero responsibility for g or h (T <= 64)
         const unsigned long long mem =
             __ballot(lane < nt && (as[(size_t)lane * AS + g] != 0.0f ||
                                    (two && as[(size_t)lane * AS + h] != 0.0f)));
         double slg = 0.0, slh = 0.0;
         for (int d = lane; d < D; d += kWave) {
-          const double og1 = qg[1 + d], og2 = qg[1 + D + d];
-          const double oh1 = two ? qh[1 + d] : 0.0, oh2 = two ? qh[1 + D + d] : 0.0;
           const float mug = means[(size_t)g * D + d];
           const float muh = two ? means[(size_t)h * D + d] : 0.0f;
           double g1 = 0.0, g2 = 0.0, gl = 0.0, h1 = 0.0, h2 = 0.0, hl = 0.0;
@@ -442,18 +442,18 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_diag(
               hl += (double)rh;
             }
           }
-          qg[1 + d] = og1 + g1;
-          qg[1 + D + d] = og2 + g2;
+          unsafeAtomicAdd(qg + 1 + d, g1);
+          unsafeAtomicAdd(qg + 1 + D + d, g2);
           if (two) {
-            qh[1 + d] = oh1 + h1;
-            qh[1 + D + d] = oh2 + h2;
+            unsafeAtomicAdd(qh + 1 + d, h1);
+            unsafeAtomicAdd(qh + 1 + D + d, h2);
           }
           slg = gl;
           slh = hl;
         }
         if (lane == 0) {
-          qg[0] = cg0 + slg;
-          if (two) qh[0] = ch0 + slh;
+          unsafeAtomicAdd(qg, slg);
+          if (two) unsafeAtomicAdd(qh, slh);
         }
         g = h + nw;
       }
