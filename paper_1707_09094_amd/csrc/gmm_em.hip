@@ -124,7 +124,13 @@ __global__ void __launch_bounds__(kNT) k_frag_diag64(const float* __restrict__ m
 // e^-40, a lies within 40 nats of the sample's maximum, which bounds R from
 // above, so |a - R| <= 40 and the FP32 entry is accurate to 40 2^-24 nats.
 // Wave per block of 16 components.
-__device__ void logdens_diag_f64(const float* __restrict__ xs, int XS, int nt, int D, int G,
+// XH > 0 (dpad4(D) <= 4 XH): the A operand's x values of the tile's two row
+// blocks are held in registers for all component blocks, and both halves of
+// the expanded form run side by side (x^2 times -lam/2, x times lam mu: four
+// independent accumulator chains).  XH = 0: any D <= 128, the operand is
+// rebuilt from LDS per component block.
+template <int XH>
+__device__ __forceinline__ void logdens_diag_f64(const float* __restrict__ xs, int XS, int nt, int D, int G,
                                  const double* __restrict__ Bx64,
                                  const double* __restrict__ cq64,
                                  const double* __restrict__ c64,
@@ -138,6 +144,16 @@ __device__ void logdens_diag_f64(const float* __restrict__ xs, int XS, int nt, i
   const int NCB = (G + 15) / 16;
   const int m = lane & 15, kb = lane >> 4;
   const int ta0 = min(m, nt - 1), ta1 = min(16 + m, nt - 1);  // A rows (past nt: dropped)
+  const double ek = (2.0 * DP4 + 8.0) * 0x1p-52;
+  double xh[2][XH > 0 ? XH : 1];
+  if (XH > 0) {
+#pragma unroll
+    for (int i = 0; i < XH; ++i) {
+      const int d = min(4 * i + kb, DP4 - 1);
+      xh[0][i] = i < KQ1 ? (double)xs[(size_t)ta0 * XS + d] : 0.0;
+      xh[1][i] = i < KQ1 ? (double)xs[(size_t)ta1 * XS + d] : 0.0;
+    }
+  }
   for (int cb = __builtin_amdgcn_readfirstlane(wid); cb < NCB; cb += nw) {
     f64x4 c1[2], c2[2];
 #pragma unroll
@@ -146,30 +162,52 @@ __device__ void logdens_diag_f64(const float* __restrict__ xs, int XS, int nt, i
       c2[rb] = f64x4{0.0, 0.0, 0.0, 0.0};
     }
     const double* fb = Bx64 + (size_t)cb * KQ * 64 + lane;
-    for (int k0 = 0; k0 < KQ; k0 += 8) {
-      double bb[8], a0[8], a1[8];
+    if (XH > 0) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int ks = min(k0 + i, KQ - 1);
-        const int k = 4 * ks + kb;
-        const bool sq = ks < KQ1;
-        const int d = sq ? k : k - DP4;
-        bb[i] = fb[(size_t)ks * 64];
-        const double x0 = (double)xs[(size_t)ta0 * XS + d];
-        const double x1 = (double)xs[(size_t)ta1 * XS + d];
-        a0[i] = sq ? x0 * x0 : x0;
-        a1[i] = sq ? x1 * x1 : x1;
+      for (int i0 = 0; i0 < XH; i0 += 8) {
+        double bs[8], bx[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int ks = min(i0 + i, KQ1 - 1);
+          bs[i] = fb[(size_t)ks * 64];
+          bx[i] = fb[(size_t)(KQ1 + ks) * 64];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          if (i0 + i >= KQ1) break;
+          const double x0 = xh[0][i0 + i], x1 = xh[1][i0 + i];
+          c1[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0 * x0, bs[i], c1[0], 0, 0, 0);
+          c1[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1 * x1, bs[i], c1[1], 0, 0, 0);
+          c2[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, bx[i], c2[0], 0, 0, 0);
+          c2[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, bx[i], c2[1], 0, 0, 0);
+        }
       }
+    } else {
+      for (int k0 = 0; k0 < KQ; k0 += 8) {
+        double bb[8], a0[8], a1[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int ks = k0 + i;
-        if (ks >= KQ) break;
-        if (ks < KQ1) {
-          c1[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[i], bb[i], c1[0], 0, 0, 0);
-          c1[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[i], bb[i], c1[1], 0, 0, 0);
-        } else {
-          c2[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[i], bb[i], c2[0], 0, 0, 0);
-          c2[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[i], bb[i], c2[1], 0, 0, 0);
+        for (int i = 0; i < 8; ++i) {
+          const int ks = min(k0 + i, KQ - 1);
+          const int k = 4 * ks + kb;
+          const bool sq = ks < KQ1;
+          const int d = sq ? k : k - DP4;
+          bb[i] = fb[(size_t)ks * 64];
+          const double x0 = (double)xs[(size_t)ta0 * XS + d];
+          const double x1 = (double)xs[(size_t)ta1 * XS + d];
+          a0[i] = sq ? x0 * x0 : x0;
+          a1[i] = sq ? x1 * x1 : x1;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int ks = k0 + i;
+          if (ks >= KQ) break;
+          if (ks < KQ1) {
+            c1[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[i], bb[i], c1[0], 0, 0, 0);
+            c1[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[i], bb[i], c1[1], 0, 0, 0);
+          } else {
+            c2[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[i], bb[i], c2[0], 0, 0, 0);
+            c2[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[i], bb[i], c2[1], 0, 0, 0);
+          }
         }
       }
     }
@@ -184,10 +222,12 @@ __device__ void logdens_diag_f64(const float* __restrict__ xs, int XS, int nt, i
         double a = -INFINITY;
         if (gv && t < nt) {
           a = c0 + (c1[rb][j] + c2[rb][j]);
+          // the bound, first with sqrt(2 T1 Q) <= T1 + Q/2 (no square root)
           const double T1 = fmax(-c1[rb][j], 0.0);
-          const double e =
-              (2.0 * DP4 + 8.0) * 0x1p-52 * (T1 + sqrt(2.0 * T1 * Q) + Q + fabs(c0));
-          if (!(e <= 1e-9)) {  // extreme data (or non-finite): FP64 direct form
+          const double base = T1 + Q + fabs(c0);
+          if (!(ek * (base + (T1 + 0.5 * Q)) <= 1e-9) &&
+              !(ek * (base + sqrt(2.0 * T1 * Q)) <= 1e-9)) {
+            // extreme data (or non-finite): FP64 direct form
             const float* x = xs + (size_t)t * XS;
             double q = 0.0;
             for (int d = 0; d < D; ++d) {
@@ -197,16 +237,16 @@ __device__ void logdens_diag_f64(const float* __restrict__ xs, int XS, int nt, i
             a = c64[g] - 0.5 * q;
           }
         }
-        // the block's largest value over the 16 lanes of the row (all lanes)
-        double v = a;
-        v = fmax(v, dpp_d<0x121>(v));
-        v = fmax(v, dpp_d<0x122>(v));
-        v = fmax(v, dpp_d<0x124>(v));
-        v = fmax(v, dpp_d<0x128>(v));
-        const float R = (float)v;
+        // the block's largest value over the 16 lanes of the row (all lanes),
+        // in FP32: the largest of the rounded values is the rounded largest
+        float v = (float)a;
+        v = fmaxf(v, dpp_f<0x121>(v));
+        v = fmaxf(v, dpp_f<0x122>(v));
+        v = fmaxf(v, dpp_f<0x124>(v));
+        v = fmaxf(v, dpp_f<0x128>(v));
         if (t < nt) {
-          if (gv) as[(size_t)t * AS + g] = R > -INFINITY ? (float)(a - (double)R) : -INFINITY;
-          if (m == 0) rcb[(size_t)t * RS + cb] = R;
+          if (gv) as[(size_t)t * AS + g] = v > -INFINITY ? (float)(a - (double)v) : -INFINITY;
+          if (m == 0) rcb[(size_t)t * RS + cb] = v;
         }
       }
   }
@@ -276,8 +316,12 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_diag(
       }
     } else {
       // exact log-densities on the matrix cores, relative to per-block references
-      logdens_diag_f64(xs, XS, nt, D, G, Bx64, cq64, c64, lam64, means, as, AS, rcb, RS, wid,
-                       nw, lane);
+      if (XS <= 64)
+        logdens_diag_f64<16>(xs, XS, nt, D, G, Bx64, cq64, c64, lam64, means, as, AS, rcb, RS,
+                             wid, nw, lane);
+      else
+        logdens_diag_f64<0>(xs, XS, nt, D, G, Bx64, cq64, c64, lam64, means, as, AS, rcb, RS,
+                            wid, nw, lane);
     }
     __syncthreads();
     if (WIDE) {
