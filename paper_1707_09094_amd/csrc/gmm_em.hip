@@ -441,65 +441,66 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_diag(
     if (tid == 0)
       for (int t = 0; t < nt; ++t) llacc += lse[t];
     if (MSTEP) {
-      // map step (Eqs. 9-11) about the current mean: wave per component that
-      // has a non-zero responsibility in the tile, lanes over dimensions; the
-      // tile's contributions are added to the block's FP64 partials once, by
-      // atomic adds whose result is not waited for.  Component g always goes
-      // to wave g % nw and dimension d to lane d % 64, so every partial is
-      // updated by one lane only, in tile order: the sums are those of plain
-      // read-modify-write updates.  Two components at a time.
-      auto active = [&](int g) { return ((gbits[g >> 5] >> (g & 31)) & 1u) != 0u; };
-      for (int g = wid;;) {
-        while (g < G && !active(g)) g += nw;
-        if (g >= G) break;
-        int h = g + nw;
-        while (h < G && !active(h)) h += nw;
-        const bool two = h < G;  // wave-uniform
-        double* qg = pb + (size_t)g * P;
-        double* qh = pb + (size_t)(two ? h : g) * P;
-        // the tile's samples with a non-zero responsibility for g or h (T <= 64)
-        const unsigned long long mem =
-            __ballot(lane < nt && (as[(size_t)lane * AS + g] != 0.0f ||
-                                   (two && as[(size_t)lane * AS + h] != 0.0f)));
-        double slg = 0.0, slh = 0.0;
+      // map step (Eqs. 9-11) about the current mean: the tile's components
+      // with a non-zero responsibility, four at a time per wave, lanes over
+      // dimensions; the tile's contributions are added to the block's FP64
+      // partials once, by atomic adds whose result is not waited for.
+      // Component g always goes to wave g % 4 and dimension d to lane d % 64,
+      // so every partial is updated by one lane only, in tile order: the sums
+      // are those of plain read-modify-write updates.
+      static_assert(kNT / kWave == 4, "component ownership assumes four waves");
+      const uint32_t own = 0x11111111u << wid;  // bits g % 4 == wid of a word
+      int wi = 0;
+      uint32_t bits = __builtin_amdgcn_readfirstlane(gbits[0] & own);
+      for (;;) {
+        int gq[4] = {0, 0, 0, 0};
+        int nq = 0;
+        while (nq < 4) {
+          while (bits == 0u && ++wi < NGB)
+            bits = __builtin_amdgcn_readfirstlane(gbits[wi] & own);
+          if (bits == 0u) break;
+          const int g = 32 * wi + __builtin_ctz(bits);
+          bits &= bits - 1u;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) gq[k] = nq == k ? g : gq[k];
+          ++nq;
+        }
+        if (nq == 0) break;
+        // the tile's samples with a non-zero responsibility for each (T <= 64)
+        unsigned long long mk[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          mk[k] = k < nq ? __ballot(lane < nt && as[(size_t)lane * AS + gq[k]] != 0.0f) : 0ull;
+        double cnt[4] = {0.0, 0.0, 0.0, 0.0};
         for (int d = lane; d < D; d += kWave) {
-          const float mug = means[(size_t)g * D + d];
-          const float muh = two ? means[(size_t)h * D + d] : 0.0f;
-          double g1 = 0.0, g2 = 0.0, gl = 0.0, h1 = 0.0, h2 = 0.0, hl = 0.0;
-          for (unsigned long long m = mem; m; m &= m - 1) {
-            const int t = __ffsll((long long)m) - 1;
-            const float xv = xs[(size_t)t * XS + d];
-            const float rg = as[(size_t)t * AS + g];
-            const float rh = two ? as[(size_t)t * AS + h] : 0.0f;
-            if (rg != 0.0f) {
-              const double y = (double)(xv - mug);
-              const double ry = (double)rg * y;
-              g1 += ry;
-              g2 += ry * y;
-              gl += (double)rg;
+          float mu[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) mu[k] = k < nq ? means[(size_t)gq[k] * D + d] : 0.0f;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            if (k >= nq) break;
+            double s1 = 0.0, s2 = 0.0, l = 0.0;
+            for (unsigned long long mm = mk[k]; mm; mm &= mm - 1) {
+              const int t = __ffsll((long long)mm) - 1;
+              const float r = as[(size_t)t * AS + gq[k]];
+              const double y = (double)(xs[(size_t)t * XS + d] - mu[k]);
+              const double ry = (double)r * y;
+              s1 += ry;
+              s2 += ry * y;
+              l += (double)r;
             }
-            if (rh != 0.0f) {
-              const double y = (double)(xv - muh);
-              const double ry = (double)rh * y;
-              h1 += ry;
-              h2 += ry * y;
-              hl += (double)rh;
-            }
+            double* q = pb + (size_t)gq[k] * P;
+            unsafeAtomicAdd(q + 1 + d, s1);
+            unsafeAtomicAdd(q + 1 + D + d, s2);
+            cnt[k] = l;
           }
-          unsafeAtomicAdd(qg + 1 + d, g1);
-          unsafeAtomicAdd(qg + 1 + D + d, g2);
-          if (two) {
-            unsafeAtomicAdd(qh + 1 + d, h1);
-            unsafeAtomicAdd(qh + 1 + D + d, h2);
-          }
-          slg = gl;
-          slh = hl;
         }
         if (lane == 0) {
-          unsafeAtomicAdd(qg, slg);
-          if (two) unsafeAtomicAdd(qh, slh);
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (k < nq) unsafeAtomicAdd(pb + (size_t)gq[k] * P, cnt[k]);
         }
-        g = h + nw;
+        if (nq < 4) break;
       }
     }
     __syncthreads();
