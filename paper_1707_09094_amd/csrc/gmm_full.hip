@@ -258,8 +258,6 @@ __device__ void map_full_f64(const float* __restrict__ xs, int DS, int nt, int D
 #pragma unroll
     for (int cb = 0; cb <= rb; ++cb, ++i) {
       if (rb >= RBY) continue;
-      int kk[4];
-      double old[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int d = 16 * rb + 4 * j + kb, e = 16 * cb + m;
@@ -267,12 +265,10 @@ __device__ void map_full_f64(const float* __restrict__ xs, int DS, int nt, int D
         if (d == D && e == D) k = 0;
         else if (d == D && e < D) k = 1 + e;
         else if (d < D && e <= d) k = 1 + D + tri_index(d, e, D);
-        kk[j] = k;
-        old[j] = k >= 0 ? q[k] : 0.0;
+        // every entry has one (block, lane, register) of the one wave that
+        // owns the component: the no-return atomic add is an ordered update
+        if (k >= 0) unsafeAtomicAdd(q + k, c[i][j]);
       }
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (kk[j] >= 0) q[kk[j]] = old[j] + c[i][j];
     }
 }
 
@@ -314,8 +310,10 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_full(
   double* bl = bst + (size_t)wid * kWR;
   double* ml = mst + (size_t)wid * D;
   if (tid == 0) bad = 0;
-  if (MSTEP)
+  if (MSTEP) {
     for (int p = tid; p < G * P; p += kNT) pb[p] = 0.0;
+    __threadfence();  // the zeros land before any atomic update of the partials
+  }
   double llacc = 0.0;
   __syncthreads();
   for (int64_t t0 = i0; t0 < i1; t0 += T) {
@@ -518,7 +516,6 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_full(
         for (int k0 = 0; k0 < P; k0 += kWave * kSL) {
           int od[kSL], oe[kSL];
           float md[kSL], me[kSL];
-          double acc[kSL];
 #pragma unroll
           for (int i = 0; i < kSL; ++i) {
             const int k = k0 + lane + kWave * i;
@@ -538,7 +535,6 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_full(
             oe[i] = e;
             md[i] = d < D ? mug[d] : 0.0f;
             me[i] = e < D ? mug[e] : 0.0f;
-            acc[i] = k < P ? q[k] : 0.0;
           }
           double sum[kSL];
 #pragma unroll
@@ -557,7 +553,7 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_full(
 #pragma unroll
           for (int i = 0; i < kSL; ++i) {
             const int k = k0 + lane + kWave * i;
-            if (k < P) q[k] = acc[i] + sum[i];
+            if (k < P) unsafeAtomicAdd(q + k, sum[i]);  // entry k: this lane only
           }
         }
       }
