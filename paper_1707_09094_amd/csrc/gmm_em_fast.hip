@@ -635,9 +635,10 @@ __global__ void k_zero_pad_rows(bf16x8* Whi, bf16x8* Wlo, int G, int KS) {
 }
 
 // Reduce step for the Welford partials [nb][G][1 + 2D] = (L, m, Q), m being
-// the weighted mean of x - mu_old: one
-// workgroup per component, thread per dimension, blocks combined in order by
-// L = La + Lb, m = ma + (mb - ma) Lb / L, Q = Qa + Qb + (mb - ma)^2 La Lb / L.
+// the weighted mean of x - mu_old: one workgroup per component (D <= 128),
+// thread per dimension, blocks combined in order by L = La + Lb,
+// m = ma + (mb - ma) Lb / L, Q = Qa + Qb + (mb - ma)^2 La Lb / L
+// (welford_combine).
 // Then Eq. 5 (w = L/N), Eq. 6 (mu = mu_old + m), Eq. 7 (sigma2 = Q/L) and the
 // floor.
 __global__ void __launch_bounds__(256) k_fin_welford(const double* __restrict__ part, int nb,
@@ -649,39 +650,21 @@ __global__ void __launch_bounds__(256) k_fin_welford(const double* __restrict__ 
                                                      double* __restrict__ mean_loglik,
                                                      int32_t* __restrict__ dev_status) {
   __shared__ int bad;
+  __shared__ WelfordLds S;
   const int g = blockIdx.x;
   const int P = 2 * D + 1;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
-  double Ltot = 0.0;
-  for (int b = 0; b < nb; ++b) Ltot += part[((size_t)b * G + g) * P];
-  for (int d = threadIdx.x; d < D; d += 256) {
-    double L = 0.0, m = 0.0, Q = 0.0;
-    for (int b = 0; b < nb; ++b) {
-      const double* q = part + ((size_t)b * G + g) * P;
-      const double Lb = q[0];
-      if (Lb == 0.0) continue;
-      const double mb = q[1 + d], Qb = q[1 + D + d];
-      if (L == 0.0) {
-        L = Lb;
-        m = mb;
-        Q = Qb;
-      } else {
-        const double Ln = L + Lb;
-        const double dl = mb - m;
-        m += dl * (Lb / Ln);
-        Q += Qb + dl * dl * (L * Lb / Ln);
-        L = Ln;
-      }
-    }
-    if (L > 0.0) {
-      double v = Q / L;
-      v = v > 0.0 ? v : 0.0;
-      v = v > (double)var_floor ? v : (double)var_floor;
-      means[(size_t)g * D + d] = (float)((double)means[(size_t)g * D + d] + m);
-      covs[(size_t)g * D + d] = (float)v;
-      if (!isfinite(m) || !isfinite(v)) bad = 1;
-    }
+  double m, Q;
+  const double Ltot = welford_combine<256>(part + (size_t)g * P, (size_t)G * P, nb, D, S, m, Q);
+  const int d = threadIdx.x;
+  if (d < D && Ltot > 0.0) {
+    double v = Q / Ltot;
+    v = v > 0.0 ? v : 0.0;
+    v = v > (double)var_floor ? v : (double)var_floor;
+    means[(size_t)g * D + d] = (float)((double)means[(size_t)g * D + d] + m);
+    covs[(size_t)g * D + d] = (float)v;
+    if (!isfinite(m) || !isfinite(v)) bad = 1;
   }
   if (threadIdx.x == 0) {
     const float w = (float)(Ltot / (double)N);
@@ -707,6 +690,7 @@ __global__ void __launch_bounds__(256) k_fin_welford_batched(const gmm_model_des
                                                              const double* __restrict__ ll_part,
                                                              int mstep) {
   __shared__ int bad;
+  __shared__ WelfordLds S;
   const int mi = blockIdx.y;
   const gmm_model_desc& m = models[mi];
   const int g = blockIdx.x;
@@ -716,36 +700,18 @@ __global__ void __launch_bounds__(256) k_fin_welford_batched(const gmm_model_des
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   if (mstep) {
-    double Ltot = 0.0;
-    for (int k = 0; k < cnt; ++k) Ltot += part[((size_t)(first + k) * Gmax + g) * P];
-    for (int d = threadIdx.x; d < D; d += 256) {
-      double L = 0.0, mu = 0.0, Q = 0.0;
-      for (int k = 0; k < cnt; ++k) {
-        const double* q = part + ((size_t)(first + k) * Gmax + g) * P;
-        const double Lb = q[0];
-        if (Lb == 0.0) continue;
-        const double mb = q[1 + d], Qb = q[1 + D + d];
-        if (L == 0.0) {
-          L = Lb;
-          mu = mb;
-          Q = Qb;
-        } else {
-          const double Ln = L + Lb;
-          const double dl = mb - mu;
-          mu += dl * (Lb / Ln);
-          Q += Qb + dl * dl * (L * Lb / Ln);
-          L = Ln;
-        }
-      }
-      if (L > 0.0) {
-        double v = Q / L;
-        v = v > 0.0 ? v : 0.0;
-        v = v > (double)var_floor ? v : (double)var_floor;
-        const double mn = (double)m.means[(size_t)g * D + d] + mu;
-        m.means[(size_t)g * D + d] = (float)mn;
-        m.covs[(size_t)g * D + d] = (float)v;
-        if (!isfinite(mn) || !isfinite(v)) bad = 1;
-      }
+    double mu, Q;
+    const double Ltot = welford_combine<256>(part + ((size_t)first * Gmax + g) * P,
+                                             (size_t)Gmax * P, cnt, D, S, mu, Q);
+    const int d = threadIdx.x;
+    if (d < D && Ltot > 0.0) {
+      double v = Q / Ltot;
+      v = v > 0.0 ? v : 0.0;
+      v = v > (double)var_floor ? v : (double)var_floor;
+      const double mn = (double)m.means[(size_t)g * D + d] + mu;
+      m.means[(size_t)g * D + d] = (float)mn;
+      m.covs[(size_t)g * D + d] = (float)v;
+      if (!isfinite(mn) || !isfinite(v)) bad = 1;
     }
     if (threadIdx.x == 0) {
       const float w = (float)(Ltot / (double)m.N);

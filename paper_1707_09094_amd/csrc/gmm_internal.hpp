@@ -432,6 +432,85 @@ __device__ __forceinline__ double block_sum_d(double v, double* sh) {
   return r;
 }
 
+// Fixed-order combination of one component's per-block Welford partials
+// (Eqs. 12-14 in the pairwise form): block b's partials [L_b, m_b[D], Q_b[D]]
+// start at base + b * stride; blocks are taken in order b = 0..nb-1, empty ones
+// skipped, the first non-empty one as is, every later one by L' = L + L_b,
+// m += (m_b - m) L_b / L', Q += Q_b + (m_b - m)^2 L L_b / L'.  The running
+// totals L depend on the counts alone, so they are taken first (one thread, in
+// block order) and each block's two weights computed from them in parallel;
+// then thread d runs the chain of dimension d with the loads of eight blocks in
+// flight.  The arithmetic is that of the plain block-by-block loop.  Needs
+// D <= NT; every thread must call it.  Returns the total L; thread d < D gets
+// its (m, Q).
+constexpr int kWcChunk = 256;  // blocks per pass
+struct WelfordLds {
+  double lb[kWcChunk], la[kWcChunk], w1[kWcChunk], w2[kWcChunk];
+  int kind[kWcChunk];
+  double run;
+};
+template <int NT>
+__device__ double welford_combine(const double* __restrict__ base, size_t stride, int nb, int D,
+                                  WelfordLds& S, double& m, double& Q) {
+  const int tid = threadIdx.x;
+  const int d = tid;
+  if (tid == 0) S.run = 0.0;
+  m = 0.0;
+  Q = 0.0;
+  __syncthreads();
+  for (int c0 = 0; c0 < nb; c0 += kWcChunk) {
+    const int nc = min(kWcChunk, nb - c0);
+    for (int i = tid; i < nc; i += NT) S.lb[i] = base[(size_t)(c0 + i) * stride];
+    __syncthreads();
+    if (tid == 0) {
+      double L = S.run;
+      for (int i = 0; i < nc; ++i) {
+        const double Lb = S.lb[i];
+        S.la[i] = L;
+        if (Lb != 0.0) L = L == 0.0 ? Lb : L + Lb;
+      }
+      S.run = L;
+    }
+    __syncthreads();
+    for (int i = tid; i < nc; i += NT) {
+      const double Lb = S.lb[i], La = S.la[i];
+      const double Ln = La + Lb;
+      S.kind[i] = Lb == 0.0 ? 0 : (La == 0.0 ? 1 : 2);
+      S.w1[i] = Lb / Ln;
+      S.w2[i] = La * Lb / Ln;
+    }
+    __syncthreads();
+    if (d < D) {
+      const double* q = base + (size_t)c0 * stride + 1 + d;
+      for (int i0 = 0; i0 < nc; i0 += 8) {
+        double mb[8], Qb[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int i = min(i0 + j, nc - 1);
+          mb[j] = q[(size_t)i * stride];
+          Qb[j] = q[(size_t)i * stride + D];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int i = i0 + j;
+          if (i >= nc) break;
+          const int k = S.kind[i];
+          if (k == 1) {
+            m = mb[j];
+            Q = Qb[j];
+          } else if (k == 2) {
+            const double dl = mb[j] - m;
+            m += dl * S.w1[i];
+            Q += Qb[j] + dl * dl * S.w2[i];
+          }
+        }
+      }
+    }
+    __syncthreads();  // the chunk's arrays are rewritten by the next pass
+  }
+  return S.run;
+}
+
 // ---- optional event timing of the data-pass kernels (gmm_profile.hip) ------
 
 constexpr int kProfKinds = 8;

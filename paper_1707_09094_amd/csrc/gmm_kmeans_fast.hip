@@ -414,31 +414,15 @@ __global__ void __launch_bounds__(256) k_km_fin_fast(const double* __restrict__ 
                                                      const double* __restrict__ in_part,
                                                      double* __restrict__ inertia,
                                                      int32_t* __restrict__ dev_status) {
+  __shared__ WelfordLds S;
   const int g = blockIdx.x;
   const int P = 2 * D + 1;
-  double Ltot = 0.0;
-  for (int b = 0; b < nb; ++b) Ltot += part[((size_t)b * G + g) * P];
-  for (int d = threadIdx.x; d < D; d += 256) {
-    double L = 0.0, m = 0.0, Q = 0.0;
-    for (int b = 0; b < nb; ++b) {
-      const double* q = part + ((size_t)b * G + g) * P;
-      const double Lb = q[0];
-      if (Lb == 0.0) continue;
-      const double mb = q[1 + d], Qb = q[1 + D + d];
-      if (L == 0.0) {
-        L = Lb;
-        m = mb;
-        Q = Qb;
-      } else {
-        const double Ln = L + Lb;
-        const double dl = mb - m;
-        m += dl * (Lb / Ln);
-        Q += Qb + dl * dl * (L * Lb / Ln);
-        L = Ln;
-      }
-    }
-    if (L > 0.0) {
-      double v = Q / L;
+  double m, Q;
+  const double Ltot = welford_combine<256>(part + (size_t)g * P, (size_t)G * P, nb, D, S, m, Q);
+  const int d = threadIdx.x;
+  if (d < D) {
+    if (Ltot > 0.0) {
+      double v = Q / Ltot;
       v = v > 0.0 ? v : 0.0;
       v = v > (double)var_floor ? v : (double)var_floor;
       means[(size_t)g * D + d] = (float)((double)means[(size_t)g * D + d] + m);
@@ -464,35 +448,20 @@ __global__ void __launch_bounds__(256) k_km_fin_batched(const gmm_model_desc* mo
                                                         float var_floor,
                                                         const double* __restrict__ part,
                                                         const double* __restrict__ in_part) {
+  __shared__ WelfordLds S;
   const int mi = blockIdx.y;
   const gmm_model_desc& m = models[mi];
   const int g = blockIdx.x;
   const int first = mitems[mi].x, cnt = mitems[mi].y;
   if (cnt == 0 || g >= m.G) return;
   const int P = 2 * D + 1;
-  double Ltot = 0.0;
-  for (int k = 0; k < cnt; ++k) Ltot += part[((size_t)(first + k) * Gmax + g) * P];
-  for (int d = threadIdx.x; d < D; d += 256) {
-    double L = 0.0, mu = 0.0, Q = 0.0;
-    for (int k = 0; k < cnt; ++k) {
-      const double* q = part + ((size_t)(first + k) * Gmax + g) * P;
-      const double Lb = q[0];
-      if (Lb == 0.0) continue;
-      const double mb = q[1 + d], Qb = q[1 + D + d];
-      if (L == 0.0) {
-        L = Lb;
-        mu = mb;
-        Q = Qb;
-      } else {
-        const double Ln = L + Lb;
-        const double dl = mb - mu;
-        mu += dl * (Lb / Ln);
-        Q += Qb + dl * dl * (L * Lb / Ln);
-        L = Ln;
-      }
-    }
-    if (L > 0.0) {
-      double v = Q / L;
+  double mu, Q;
+  const double Ltot = welford_combine<256>(part + ((size_t)first * Gmax + g) * P,
+                                           (size_t)Gmax * P, cnt, D, S, mu, Q);
+  const int d = threadIdx.x;
+  if (d < D) {
+    if (Ltot > 0.0) {
+      double v = Q / Ltot;
       v = v > 0.0 ? v : 0.0;
       v = v > (double)var_floor ? v : (double)var_floor;
       m.means[(size_t)g * D + d] = (float)((double)m.means[(size_t)g * D + d] + mu);
