@@ -149,9 +149,12 @@ def _km_check(oracle, X, mu, gv, got, k):
 
 
 @pytest.mark.parametrize("maha", [True, False], ids=["maha", "eucl"])
-def test_kmeans_batched_vs_oracle(G_, oracle, maha):
-    shapes = SHAPES_D40
-    Xs, _ = _data(211, 40, shapes)
+@pytest.mark.parametrize("D,shapes,chunk", [(40, SHAPES_D40, 1024), (5, SHAPES_D5, 32)],
+                         ids=["d40", "d5-313items"])
+def test_kmeans_batched_vs_oracle(G_, oracle, maha, D, shapes, chunk):
+    # d5-313items: 10000 samples in items of 32, so the reduce step combines
+    # more than 256 partials of one model (two passes of its weight table)
+    Xs, _ = _data(211, D, shapes)
     means = []
     for X, (N, G) in zip(Xs, shapes):
         # more means than samples: the surplus are dead and get resurrected
@@ -162,8 +165,8 @@ def test_kmeans_batched_vs_oracle(G_, oracle, maha):
         b.means[m].copy_(_t(mu))
     if maha:
         G_.gmm_global_stats_batched(b, b.gmean, b.gvar)
-    ws = b.workspace(1024)
-    G_.gmm_kmeans_iter_batched(b, 1 if maha else 0, 1e-10, 1024, ws)
+    ws = b.workspace(chunk)
+    G_.gmm_kmeans_iter_batched(b, 1 if maha else 0, 1e-10, chunk, ws)
     torch.cuda.synchronize()
     assert not _np(b.dev_status).any()
     for m, (X, mu) in enumerate(zip(Xs, means)):
