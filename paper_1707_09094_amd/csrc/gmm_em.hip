@@ -618,7 +618,7 @@ hipError_t launch_em_diag(const float* X, int64_t N, int D, int64_t ldx, int G, 
                           const Workspace& w, hipStream_t st) {
   if (em_fast_supported(D, G, prec)) {
     int nb = 0;
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, dev_status, n_recomputed, w.counters);
+    // k_pre_fast clears the status word and the counters
     hipError_t e = launch_em_fast(X, N, D, ldx, G, hefts, means, covs, prec, true, n_recomputed,
                                   nullptr, dev_status, w, st, &nb);
     if (e != hipSuccess) return e;
@@ -663,7 +663,7 @@ hipError_t launch_loglik_diag(const float* X, int64_t N, int D, int64_t ldx, int
                               const Workspace& w, hipStream_t st) {
   if (em_fast_supported(D, G, prec)) {
     int nb = 0;
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, dev_status, nullptr, w.counters);
+    // k_pre_fast clears the status word and the counters
     hipError_t e = launch_em_fast(X, N, D, ldx, G, hefts, means, covs, prec, false, nullptr,
                                   per_sample, dev_status, w, st, &nb);
     if (e != hipSuccess) return e;

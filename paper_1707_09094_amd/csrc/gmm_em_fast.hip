@@ -584,6 +584,9 @@ __device__ void zero_component_rows(bf16x8* Whi, bf16x8* Wlo, int KS, int g) {
   }
 }
 
+// grid 16 * ceil(G / 16): block g < G computes component g, the others zero
+// the padding rows of the last row block; block 0 also clears the status word,
+// the recompute counter and the workspace counters of the call.
 __global__ void __launch_bounds__(256) k_pre_fast(const float* __restrict__ hefts,
                                                   const float* __restrict__ means,
                                                   const float* __restrict__ covs, int D, int G,
@@ -593,8 +596,23 @@ __global__ void __launch_bounds__(256) k_pre_fast(const float* __restrict__ heft
                                                   bf16x8* __restrict__ Whi,
                                                   bf16x8* __restrict__ Wlo,
                                                   double* __restrict__ c64,
-                                                  double* __restrict__ lam64) {
-  pre_component(hefts, means, covs, D, G, KS, blockIdx.x, prm, cc, cexp, Whi, Wlo, c64, lam64);
+                                                  double* __restrict__ lam64,
+                                                  int32_t* __restrict__ dev_status,
+                                                  int64_t* __restrict__ n_recomputed,
+                                                  int64_t* __restrict__ counters) {
+  const int g = blockIdx.x;
+  if (g == 0) {
+    if (threadIdx.x == 0) {
+      *dev_status = 0;
+      if (n_recomputed) *n_recomputed = 0;
+    }
+    if (threadIdx.x < 8) counters[threadIdx.x] = 0;
+  }
+  if (g >= G) {
+    zero_component_rows(Whi, Wlo, KS, g);
+    return;
+  }
+  pre_component(hefts, means, covs, D, G, KS, g, prm, cc, cexp, Whi, Wlo, c64, lam64);
 }
 
 // grid (16 * RBmax, n_models): component g of model blockIdx.y.
@@ -614,24 +632,6 @@ __global__ void __launch_bounds__(256) k_pre_fast_batched(const gmm_model_desc* 
   pre_component(m.hefts, m.means, m.covs, D, G, bc.KS, g, bc.prm + (size_t)mi * 2 * bc.Gmax * (D + 1),
                 bc.cc + (size_t)mi * 2 * bc.Gmax, bc.cexp + (size_t)mi * 2 * bc.Gmax, Whi, Wlo,
                 bc.c64 + (size_t)mi * bc.Gmax, bc.lam64 + (size_t)mi * bc.Gmax * D);
-}
-
-// Rows of the last row block past G get zero weights.
-__global__ void k_zero_pad_rows(bf16x8* Whi, bf16x8* Wlo, int G, int KS) {
-  const int RB = (G + 15) / 16;
-  const int rb = RB - 1;
-  for (int e = threadIdx.x; e < KS * 64; e += blockDim.x) {
-    const int ks = e / 64, l = e - ks * 64;
-    const int g = 16 * rb + (l & 15);
-    if (g >= G) {
-      const size_t idx = ((size_t)rb * KS + ks) * 64 + l;
-      bf16x8 z;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) z[i] = (__bf16)0.0f;
-      Whi[idx] = z;
-      Wlo[idx] = z;
-    }
-  }
 }
 
 // Reduce step for the Welford partials [nb][G][1 + 2D] = (L, m, Q), m being
@@ -1422,10 +1422,9 @@ hipError_t launch_em_fast(const float* X, int64_t N, int D, int64_t ldx, int G, 
   a.per_sample = per_sample;
   a.dev_status = dev_status;
   a.n_rec = n_recomputed;
-  hipLaunchKernelGGL(k_pre_fast, dim3(G), dim3(256), 0, st, hefts, means, covs, D, G, KS, w.prm,
-                     w.c, w.cexp, (bf16x8*)w.Bhi, (bf16x8*)w.Blo, w.c64, w.lamg64);
-  if (G % 16) hipLaunchKernelGGL(k_zero_pad_rows, dim3(1), dim3(256), 0, st, (bf16x8*)w.Bhi,
-                                 (bf16x8*)w.Blo, G, KS);
+  hipLaunchKernelGGL(k_pre_fast, dim3(16 * ((G + 15) / 16)), dim3(256), 0, st, hefts, means,
+                     covs, D, G, KS, w.prm, w.c, w.cexp, (bf16x8*)w.Bhi, (bf16x8*)w.Blo, w.c64,
+                     w.lamg64, dev_status, n_recomputed, w.counters);
   {
     ProfScope ps(mstep ? kProfEM : kProfLoglik, st);
     if (prec == GMM_PREC_BF16X3) {

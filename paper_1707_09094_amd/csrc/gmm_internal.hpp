@@ -439,7 +439,7 @@ __device__ __forceinline__ double block_sum_d(double v, double* sh) {
 // m += (m_b - m) L_b / L', Q += Q_b + (m_b - m)^2 L L_b / L'.  The running
 // totals L depend on the counts alone, so they are taken first (one thread, in
 // block order) and each block's two weights computed from them in parallel;
-// then thread d runs the chain of dimension d with the loads of eight blocks in
+// then thread d runs the chain of dimension d with the loads of 32 blocks in
 // flight.  The arithmetic is that of the plain block-by-block loop.  Needs
 // D <= NT; every thread must call it.  Returns the total L; thread d < D gets
 // its (m, Q).
@@ -481,17 +481,18 @@ __device__ double welford_combine(const double* __restrict__ base, size_t stride
     }
     __syncthreads();
     if (d < D) {
+      constexpr int kFly = 32;  // blocks whose loads are in flight together
       const double* q = base + (size_t)c0 * stride + 1 + d;
-      for (int i0 = 0; i0 < nc; i0 += 8) {
-        double mb[8], Qb[8];
+      for (int i0 = 0; i0 < nc; i0 += kFly) {
+        double mb[kFly], Qb[kFly];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < kFly; ++j) {
           const int i = min(i0 + j, nc - 1);
           mb[j] = q[(size_t)i * stride];
           Qb[j] = q[(size_t)i * stride + D];
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < kFly; ++j) {
           const int i = i0 + j;
           if (i >= nc) break;
           const int k = S.kind[i];
