@@ -13,6 +13,8 @@
  *                      Eqs. 8-14) and the variance floor (Sec. 2.2)
  *   gmm_loglik         per-sample and mean log-likelihood (Sec. 4 API:
  *                      log_p(X), avg_log_p(X))
+ *   gmm_log_p_gaussian per-sample and mean log-density under one Gaussian
+ *                      (Sec. 4 API: log_p(X, g), avg_log_p(X, g))
  *   gmm_assign         closest Gaussian per sample and its histogram
  *                      (Sec. 4 API: assign, raw_hist)
  *   gmm_*_batched      the same operations for many independent models per
@@ -149,13 +151,16 @@ int gmm_kmeans_iter(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G
  *   mean_loglik[1]  out: FP64 mean log-likelihood of the INPUT parameters
  *               (the E-step's by-product; EM makes successive values
  *               non-decreasing).
- *   n_recomputed[1] out (may be NULL): with GMM_PREC_BF16X3, number of
- *               (sample, Gaussian) log-densities recomputed in the FP32
- *               direct form (the best one of every sample plus every one
- *               within 20 nats of it); 0 with GMM_PREC_FP32.
+ *   n_recomputed[1] out (may be NULL): diagonal models with D, G <= 128 (the
+ *               one-pass kernels, either arithmetic form): number of (sample,
+ *               Gaussian) log-densities recomputed exactly, i.e. every pair
+ *               whose screened value, widened by its rounding-error bound,
+ *               comes within 30 nats of the sample's best; 0 for other shapes
+ *               (their log-densities are exact FP64 or recomputed in FP64
+ *               without being counted).
  * A Gaussian whose responsibilities sum to exactly 0 gets weight 0 and keeps
- * its mean and covariance.  Responsibilities below exp(-80) relative to the
- * sample's best component are treated as 0.
+ * its mean and covariance.  Responsibilities (normalised per sample) below
+ * exp(-40) are treated as 0.
  * Full covariances (cov = GMM_COV_FULL): Cholesky factors and log-determinants
  * in FP64; a factorisation that fails sets GMM_DEV_NOTPD. */
 int gmm_em_iter(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int32_t cov,
@@ -170,6 +175,23 @@ int gmm_loglik(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int
                const float* hefts, const float* means, const float* covs, int32_t prec,
                double* mean_loglik, float* per_sample, int32_t* dev_status, void* ws,
                size_t ws_bytes, gmm_stream_t stream);
+
+/* Log-density of X under ONE Gaussian g of a diagonal model, without its
+ * weight (Sec. 4 API log_p(X, g), avg_log_p(X, g)):
+ *   log N(x | mu_g, Sigma_g) = -1/2 (D log 2 pi + sum_d log sigma2_gd
+ *                                    + sum_d (x_d - mu_gd)^2 / sigma2_gd),
+ * computed in FP64 per sample.
+ *   g           0 <= g < G; means[D*G], dcovs[D*G] as for gmm_em_iter (only
+ *               row g is read).
+ *   mean_out[1]     out (may be NULL): FP64 average over the N samples.
+ *   per_sample[N]   out (may be NULL): FP32 value per sample.
+ * At least one of the two outputs must be given (GMM_EINVAL otherwise).  A
+ * non-finite value (e.g. a variance <= 0) sets GMM_DEV_NONFINITE.  The
+ * workspace is sized as for the same (N, D, G) with GMM_COV_DIAG. */
+int gmm_log_p_gaussian(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int32_t g,
+                       const float* means, const float* dcovs, double* mean_out,
+                       float* per_sample, int32_t* dev_status, void* ws, size_t ws_bytes,
+                       gmm_stream_t stream);
 
 /* Closest Gaussian per sample (Sec. 4 API assign / raw_hist), diagonal model.
  *   mode        GMM_ASSIGN_EUCL: nearest mean in Euclidean distance;

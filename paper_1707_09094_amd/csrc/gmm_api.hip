@@ -120,6 +120,18 @@ int gmm_loglik(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int
                                       per_sample, dev_status, w, st));
 }
 
+int gmm_log_p_gaussian(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int32_t g,
+                       const float* means, const float* dcovs, double* mean_out,
+                       float* per_sample, int32_t* dev_status, void* ws, size_t ws_bytes,
+                       gmm_stream_t stream) {
+  if (!X || !means || !dcovs || !dev_status || (!mean_out && !per_sample)) return GMM_EINVAL;
+  if (!shape_ok(N, D, ldx, G) || g < 0 || g >= G) return GMM_EINVAL;
+  Workspace w;
+  if (!ws_ok(ws, ws_bytes, N, D, G, GMM_COV_DIAG, &w)) return GMM_EINVAL;
+  return status_of(launch_log_p_gaussian(X, N, D, ldx, g, means, dcovs, mean_out, per_sample,
+                                         dev_status, w, (hipStream_t)stream));
+}
+
 int gmm_assign(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int32_t mode,
                const float* hefts, const float* means, const float* dcovs, int32_t* assign,
                int64_t* hist, int32_t* dev_status, void* ws, size_t ws_bytes,

@@ -570,6 +570,71 @@ __global__ void k_ll_finish(const double* __restrict__ ll_part, int nb, int64_t 
   }
 }
 
+// Per-Gaussian log-density (Sec. 4 API log_p(X, g), avg_log_p(X, g)) of a
+// diagonal model, without the weight: log N(x | mu_g, Sigma_g) =
+// -1/2 (D log 2 pi + sum_d log sigma2_gd + sum_d (x_d - mu_gd)^2 / sigma2_gd),
+// in FP64 per sample.  Tiles of kLT samples pass through LDS kLD dimensions at
+// a time (coalesced row segments); thread t of the workgroup owns sample t of
+// each tile and keeps its running sum of values; the workgroup's total, in a
+// fixed order, goes to part[b].
+constexpr int kLT = 256;
+constexpr int kLD = 32;
+__global__ void __launch_bounds__(kLT) k_log_p_g(const float* __restrict__ X, int64_t N, int D,
+                                                 int64_t ldx, int g,
+                                                 const float* __restrict__ means,
+                                                 const float* __restrict__ dcovs, int64_t chunk,
+                                                 float* __restrict__ per_sample,
+                                                 double* __restrict__ part,
+                                                 int32_t* __restrict__ dev_status) {
+  __shared__ float xs[kLT][kLD + 1];
+  __shared__ double lam[kLD], mu[kLD];
+  __shared__ double sh[kLT];
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x;
+  const int64_t i0 = (int64_t)b * chunk;
+  const int64_t i1 = min(N, i0 + chunk);
+  const float* mg = means + (size_t)g * D;
+  const float* vg = dcovs + (size_t)g * D;
+  // c = -1/2 (D log 2 pi + sum_d log sigma2_d), summed in a fixed order
+  double ld = 0.0;
+  for (int d = tid; d < D; d += kLT) ld += log((double)vg[d]);
+  ld = block_sum_d<kLT>(ld, sh);
+  const double c = -0.5 * ((double)D * 1.8378770664093454836 + ld);  // log 2 pi
+  double acc = 0.0;
+  bool bad = false;
+  for (int64_t t0 = i0; t0 < i1; t0 += kLT) {
+    const int nt = (int)min((int64_t)kLT, i1 - t0);
+    double q = 0.0;
+    for (int d0 = 0; d0 < D; d0 += kLD) {
+      const int nd = min(kLD, D - d0);
+      __syncthreads();  // the previous chunk's readers are done
+      for (int p = tid; p < nt * nd; p += kLT) {
+        const int t = p / nd, k = p - t * nd;
+        xs[t][k] = X[(t0 + t) * ldx + d0 + k];
+      }
+      if (tid < nd) {
+        lam[tid] = 1.0 / (double)vg[d0 + tid];
+        mu[tid] = (double)mg[d0 + tid];
+      }
+      __syncthreads();
+      if (tid < nt)
+        for (int k = 0; k < nd; ++k) {
+          const double u = (double)xs[tid][k] - mu[k];
+          q += u * u * lam[k];
+        }
+    }
+    if (tid < nt) {
+      const double a = c - 0.5 * q;
+      if (per_sample) per_sample[t0 + tid] = (float)a;
+      if (!isfinite(a)) bad = true;
+      acc += a;
+    }
+  }
+  acc = block_sum_d<kLT>(acc, sh);
+  if (tid == 0) part[b] = acc;
+  if (bad) atomicOr(dev_status, GMM_DEV_NONFINITE);
+}
+
 // LDS bytes of k_estep_diag for tile rows T (WIDE adds the parameter chunk).
 size_t estep_lds(int D, int G, int T, bool wide) {
   const size_t XS = wide ? (size_t)((D + 3) & ~3) : (size_t)D;
@@ -654,6 +719,21 @@ hipError_t launch_em_diag(const float* X, int64_t N, int D, int64_t ldx, int G, 
   hipLaunchKernelGGL(k_fin_diag, dim3(G), dim3(kNT), sizeof(double) * (2 * D + 1), st, w.partials,
                      nb, N, D, G, var_floor, hefts, means, covs, w.scalars, mean_loglik,
                      dev_status);
+  return hipGetLastError();
+}
+
+hipError_t launch_log_p_gaussian(const float* X, int64_t N, int D, int64_t ldx, int g,
+                                 const float* means, const float* dcovs, double* mean_out,
+                                 float* per_sample, int32_t* dev_status, const Workspace& w,
+                                 hipStream_t st) {
+  const int nb = partial_blocks(N, 4 * kLT);
+  const int64_t chunk = (N + nb - 1) / nb;
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, dev_status, nullptr, w.counters);
+  hipLaunchKernelGGL(k_log_p_g, dim3(nb), dim3(kLT), 0, st, X, N, D, ldx, g, means, dcovs, chunk,
+                     per_sample, w.scalars, dev_status);
+  if (mean_out)
+    hipLaunchKernelGGL(k_ll_finish, dim3(1), dim3(64), 0, st, w.scalars, nb, N, mean_out,
+                       dev_status);
   return hipGetLastError();
 }
 

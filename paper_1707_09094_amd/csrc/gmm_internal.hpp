@@ -587,6 +587,11 @@ hipError_t launch_kmeans(const float* X, int64_t N, int D, int64_t ldx, int G, i
                          int prec, int64_t* n_recomputed, int32_t* dev_status, const Workspace& w,
                          hipStream_t st);
 
+hipError_t launch_log_p_gaussian(const float* X, int64_t N, int D, int64_t ldx, int g,
+                                 const float* means, const float* dcovs, double* mean_out,
+                                 float* per_sample, int32_t* dev_status, const Workspace& w,
+                                 hipStream_t st);
+
 hipError_t launch_assign(const float* X, int64_t N, int D, int64_t ldx, int G, int mode,
                          const float* hefts, const float* means, const float* dcovs,
                          int32_t* assign, int64_t* hist, int32_t* dev_status, const Workspace& w,

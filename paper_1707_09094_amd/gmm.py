@@ -55,6 +55,8 @@ _SIGS = {
                      _vp, _sz, _vp], _i32),
     "gmm_loglik": ([_vp, _i64, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp,
                     _sz, _vp], _i32),
+    "gmm_log_p_gaussian": ([_vp, _i64, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                            _sz, _vp], _i32),
     "gmm_assign": ([_vp, _i64, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                     _vp], _i32),
     "gmm_profile_enable": ([_i32], _i32),
@@ -209,6 +211,21 @@ def gmm_loglik(X, cov, hefts, means, covs, prec, mean_loglik, per_sample, dev_st
         _ptr(per_sample, torch.float32, (N,), "per_sample", optional=True),
         _ptr(dev_status, torch.int32, (1,), "dev_status"), wp, wn, _stream(stream))
     _check("gmm_loglik", rc)
+
+
+def gmm_log_p_gaussian(X, g, means, dcovs, mean_out, per_sample, dev_status, ws, stream=None):
+    """Log-density under Gaussian g alone (no weight): mean_out (float64 [1]) and/or
+    per_sample (float32 [N]); at least one of them."""
+    xp, N, D, ldx = _xptr(X)
+    G = means.shape[0]
+    wp, wn = _ws(ws)
+    rc = library().gmm_log_p_gaussian(
+        xp, N, D, ldx, G, int(g), _ptr(means, torch.float32, (G, D), "means"),
+        _ptr(dcovs, torch.float32, (G, D), "dcovs"),
+        _ptr(mean_out, torch.float64, (1,), "mean_out", optional=True),
+        _ptr(per_sample, torch.float32, (N,), "per_sample", optional=True),
+        _ptr(dev_status, torch.int32, (1,), "dev_status"), wp, wn, _stream(stream))
+    _check("gmm_log_p_gaussian", rc)
 
 
 def gmm_assign(X, mode, hefts, means, dcovs, assign, hist, dev_status, ws, stream=None):

@@ -73,6 +73,13 @@ def test_null_and_shape_arguments_rejected_on_host():
                         None) == gmm.GMM_EINVAL
     assert L.gmm_assign(FAKE, 10, 4, 4, 2, gmm.ASSIGN_PROB, FAKE, FAKE, None, FAKE, None, FAKE,
                         ws, 1 << 30, None) == gmm.GMM_EINVAL
+    # log_p(X, g): g out of range, negative g, no output requested
+    assert L.gmm_log_p_gaussian(FAKE, 10, 4, 4, 2, 2, FAKE, FAKE, FAKE, None, FAKE, ws, 1 << 30,
+                                None) == gmm.GMM_EINVAL
+    assert L.gmm_log_p_gaussian(FAKE, 10, 4, 4, 2, -1, FAKE, FAKE, FAKE, None, FAKE, ws, 1 << 30,
+                                None) == gmm.GMM_EINVAL
+    assert L.gmm_log_p_gaussian(FAKE, 10, 4, 4, 2, 0, FAKE, FAKE, None, None, FAKE, ws, 1 << 30,
+                                None) == gmm.GMM_EINVAL
     # full covariance beyond the supported dimension
     assert L.gmm_em_iter(FAKE, 10, 200, 200, 2, gmm.COV_FULL, FAKE, FAKE, FAKE, 0.0, 0, FAKE,
                          None, FAKE, ws, 1 << 40, None) == gmm.GMM_EINVAL

@@ -371,6 +371,51 @@ def test_assign_and_hist(G_, oracle, mode):
     assert np.array_equal(hist.cpu().numpy(), np.bincount(ref, minlength=5))
 
 
+# ---------------------------------------------------------------- log_p(X, g)
+# N = 1; several tiles with a ragged tail; D = 1, one LDS dimension chunk with
+# a ragged tail (33), several chunks (100, 300); first and last Gaussian
+@pytest.mark.parametrize("N,D,G,g", [(1, 1, 1, 0), (257, 5, 3, 2), (3001, 33, 4, 3),
+                                     (10_000, 100, 7, 0), (2000, 300, 2, 1)])
+def test_log_p_gaussian(G_, oracle, N, D, G, g):
+    X, _ = synth.diag_gmm(300 + D, D, max(G, 2), N, "normal", 0.0, 4.0, "loguniform", 0.1,
+                          10.0)
+    _, mu, var = _params(7 + D, D, G, X if N >= G else None)
+    per = torch.full((N,), float("nan"), dtype=torch.float32, device=DEV)
+    mo = torch.zeros(1, dtype=torch.float64, device=DEV)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    ws = G_.workspace(N, D, G, device=DEV)
+    G_.gmm_log_p_gaussian(_t(X), g, _t(mu), _t(var), mo, per, st, ws)
+    ref = oracle.log_p_g(X, mu, var, g)
+    assert st.item() == 0
+    got = per.cpu().numpy().astype(np.float64)
+    # FP32 output of an FP64 value: half an ulp plus FP64 reordering
+    assert np.all(np.abs(got - ref) <= 2.0 ** -24 * np.abs(ref) + 1e-12), g
+    m = ref.mean()
+    assert abs(mo.item() - m) <= 1e-12 * abs(m) + 1e-12
+    # mean alone, and a row stride above D: the same mean to rounding
+    Xw = torch.zeros(N, D + 3, device=DEV)
+    Xw[:, :D] = _t(X)
+    mo2 = torch.zeros(1, dtype=torch.float64, device=DEV)
+    G_.gmm_log_p_gaussian(Xw[:, :D], g, _t(mu), _t(var), mo2, None, st, ws)
+    assert abs(mo2.item() - m) <= 1e-12 * abs(m) + 1e-12
+    with pytest.raises(G_.GmmError):
+        G_.gmm_log_p_gaussian(_t(X), G, _t(mu), _t(var), mo, per, st, ws)  # g out of range
+
+
+def test_log_p_gaussian_nonpositive_variance_sets_status(G_):
+    X = torch.zeros(100, 3, device=DEV)
+    mu = torch.zeros(2, 3, device=DEV)
+    var = torch.ones(2, 3, device=DEV)
+    var[1, 2] = 0.0
+    mo = torch.zeros(1, dtype=torch.float64, device=DEV)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    ws = G_.workspace(100, 3, 2, device=DEV)
+    G_.gmm_log_p_gaussian(X, 0, mu, var, mo, None, st, ws)
+    assert st.item() == 0
+    G_.gmm_log_p_gaussian(X, 1, mu, var, mo, None, st, ws)
+    assert st.item() & G_.GMM_DEV_NONFINITE
+
+
 # ---------------------------------------------------------------- errors
 def test_binding_raises_on_invalid(G_):
     X = torch.zeros(10, 3, device=DEV)
