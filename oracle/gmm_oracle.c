@@ -236,6 +236,48 @@ int oracle_log_p_g(const float* X, int64_t N, int D, int64_t ldx, int G, const d
   return 0;
 }
 
+/* Seeding of the initial means (Sec. 4 API seed modes static_spread /
+ * random_spread: "a maximally spread subset of the training samples"), read as
+ * farthest-first traversal.  The first seed is sample `first` (0 for
+ * static_spread, a caller-drawn index for random_spread); seed k+1 is the
+ * sample whose distance to its nearest already-chosen seed is largest, the
+ * lowest index on ties.  Distance: sum_d lam_d (x_d - y_d)^2 with lam = NULL
+ * meaning lam_d = 1 (Euclidean), each term lam_d * (u * u) added in order
+ * d = 0..D-1.  idx_out[G] receives the chosen sample indices, means_out[G*D]
+ * their coordinates. */
+int oracle_seed_spread(const float* X, int64_t N, int D, int64_t ldx, int G, const double* lam,
+                       int64_t first, int64_t* idx_out, double* means_out) {
+  if (N < 1 || D < 1 || G < 1 || ldx < D || first < 0 || first >= N) return ORC_EINVAL;
+  double* dmin = (double*)malloc(sizeof(double) * (size_t)N);
+  if (!dmin) return ORC_ENOMEM;
+  int64_t s = first;
+  for (int k = 0; k < G; ++k) {
+    const float* y = X + s * ldx;
+    idx_out[k] = s;
+    for (int d = 0; d < D; ++d) means_out[(size_t)k * D + d] = (double)y[d];
+#pragma omp parallel for schedule(static) num_threads(NTHR)
+    for (int64_t i = 0; i < N; ++i) {
+      const float* x = X + i * ldx;
+      double q = 0.0;
+      for (int d = 0; d < D; ++d) {
+        const double u = (double)x[d] - (double)y[d];
+        q += (lam ? lam[d] : 1.0) * (u * u);
+      }
+      dmin[i] = (k == 0 || q < dmin[i]) ? q : dmin[i];
+    }
+    double best = -1.0;
+    int64_t bi = 0;
+    for (int64_t i = 0; i < N; ++i)
+      if (dmin[i] > best) {
+        best = dmin[i];
+        bi = i;
+      }
+    s = bi;
+  }
+  free(dmin);
+  return 0;
+}
+
 /* Responsibilities l_{g,i} (Sec. 2, Eq. 3), exposed for tests: out[i*G+g]. */
 int oracle_responsibilities(const float* X, int64_t N, int D, int64_t ldx, int G, int full,
                             const double* hefts, const double* means, const double* covs,

@@ -61,8 +61,10 @@ def lib():
         L.oracle_kmeans_iter.argtypes = [_fp, _i64, _i32, _i64, _i32, _dp, _dp, ctypes.c_double,
                                          _dp, _dp, _dp, _i64p, _i32p, _dp, _dp]
         L.oracle_assign.argtypes = [_fp, _i64, _i32, _i64, _i32, _i32, _dp, _dp, _dp, _i32p]
+        L.oracle_seed_spread.argtypes = [_fp, _i64, _i32, _i64, _i32, _dp, _i64, _i64p, _dp]
         for f in ("oracle_loglik", "oracle_log_p_g", "oracle_responsibilities", "oracle_em_iter",
-                  "oracle_global_stats", "oracle_kmeans_iter", "oracle_assign"):
+                  "oracle_global_stats", "oracle_kmeans_iter", "oracle_assign",
+                  "oracle_seed_spread"):
             getattr(L, f).restype = _i32
         _lib = L
     return _lib
@@ -208,6 +210,18 @@ def assign(X, hefts, means, dcovs, mode):
     _check(lib().oracle_assign(_p(X, _fp), N, D, D, m.shape[0], int(mode), _p(h), _p(m), _p(c),
                                _p(out, _i32p)), "assign")
     return out
+
+
+def seed_spread(X, G, first=0, lam=None):
+    """Farthest-first seeding (Sec. 4 API static_spread / random_spread): the
+    chosen sample indices (G,) and their coordinates (G, D)."""
+    X, N, D = _X(X)
+    idx = np.zeros(G, dtype=np.int64)
+    means = np.zeros((G, D))
+    lp = _p(_d(lam)) if lam is not None else None
+    _check(lib().oracle_seed_spread(_p(X, _fp), N, D, D, int(G), lp, int(first), _p(idx, _i64p),
+                                    _p(means)), "seed_spread")
+    return idx, means
 
 
 def maha_lambda(var, var_floor):

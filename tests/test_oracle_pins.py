@@ -456,3 +456,43 @@ def test_fig1_recipe_recovery(oracle):
     assert np.all(np.abs(w - truth.hefts) < 5 * np.sqrt(truth.hefts * (1 - truth.hefts) / len(X)) + 0.01)
     assert np.all(np.abs(mu - truth.means) < 5 / np.sqrt(n)[:, None] + 0.05)
     assert np.all(np.abs(var_g - 1.0) < 5 * np.sqrt(2 / n)[:, None] + 0.1)
+
+
+# ---------------------------------------------------------------- spread seeding
+def test_seed_spread_closed_form_1d(oracle):
+    """x = 0..10 from x = 5: distances (x - 5)^2 put 0 and 10 at 25 (the lower
+    index, 0, wins), then 10 is farthest from {5, 0}, then 2, 3, 7, 8 tie at 4
+    and 2 wins: seeds 5, 0, 10, 2."""
+    X = np.arange(11, dtype=np.float32)[:, None]
+    idx, means = oracle.seed_spread(X, 4, first=5)
+    assert idx.tolist() == [5, 0, 10, 2]
+    np.testing.assert_array_equal(means[:, 0], [5.0, 0.0, 10.0, 2.0])
+
+
+@pytest.mark.parametrize("maha,first", [(False, 0), (True, 0), (True, 137)])
+def test_seed_spread_brute_force(oracle, maha, first):
+    """Greedy maximin over the full pairwise distance matrix (scipy cdist, an
+    independent evaluation of the weighted distances)."""
+    rng = _rng(23)
+    X = (rng.standard_normal((300, 4)) * [1.0, 3.0, 0.5, 2.0]).astype(np.float32)
+    lam = oracle.maha_lambda(oracle.global_stats(X)[1], 1e-10) if maha else None
+    w = np.ones(4) if lam is None else lam
+    D2 = cdist(X.astype(np.float64), X.astype(np.float64), "sqeuclidean", w=w)
+    ref = [first]
+    dmin = D2[first].copy()
+    for _ in range(11):
+        s = int(np.argmax(dmin))  # first index of the maximum
+        ref.append(s)
+        dmin = np.minimum(dmin, D2[s])
+    idx, means = oracle.seed_spread(X, 12, first=first, lam=lam)
+    assert idx.tolist() == ref
+    np.testing.assert_array_equal(means, X[ref].astype(np.float64))
+    assert len(set(ref)) == 12
+
+
+def test_seed_spread_more_seeds_than_distinct_samples(oracle):
+    """Three distinct points: once all are seeds every distance is 0 and the
+    lowest index is taken."""
+    X = np.array([[0.0], [4.0], [0.0], [9.0], [4.0]], dtype=np.float32)
+    idx, _ = oracle.seed_spread(X, 5, first=1)
+    assert idx.tolist() == [1, 3, 0, 0, 0]
