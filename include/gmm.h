@@ -13,6 +13,8 @@
  *                      Eqs. 8-14) and the variance floor (Sec. 2.2)
  *   gmm_loglik         per-sample and mean log-likelihood (Sec. 4 API:
  *                      log_p(X), avg_log_p(X))
+ *   gmm_seed_means     initial means: subset or maximally spread subset of
+ *                      the samples (Sec. 4 API seed_mode)
  *   gmm_log_p_gaussian per-sample and mean log-density under one Gaussian
  *                      (Sec. 4 API: log_p(X, g), avg_log_p(X, g))
  *   gmm_assign         closest Gaussian per sample and its histogram
@@ -78,6 +80,10 @@ extern "C" {
 /* k-means distance (Sec. 3.1 / learn() dist_mode) */
 #define GMM_DIST_EUCL 0
 #define GMM_DIST_MAHA 1
+
+/* seeding of gmm_seed_means (Sec. 4 API seed_mode) */
+#define GMM_SEED_SUBSET 0   /* static_subset / random_subset */
+#define GMM_SEED_SPREAD 1   /* static_spread / random_spread */
 
 /* assignment distance of gmm_assign (Sec. 4 API: eucl_dist / prob_dist) */
 #define GMM_ASSIGN_EUCL 0
@@ -175,6 +181,25 @@ int gmm_loglik(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int
                const float* hefts, const float* means, const float* covs, int32_t prec,
                double* mean_loglik, float* per_sample, int32_t* dev_status, void* ws,
                size_t ws_bytes, gmm_stream_t stream);
+
+/* Initial means (Sec. 4 API seed_mode), written to means[G*D].
+ *   GMM_SEED_SUBSET  means[g] = sample idx[g] (idx: device int64[G], indices
+ *                    the caller drew: random_subset), or, with idx = NULL,
+ *                    sample floor(g N / G) (static_subset).  An index outside
+ *                    [0, N) sets GMM_DEV_BADDESC and leaves that row as it was.
+ *   GMM_SEED_SPREAD  farthest-first traversal ("maximally spread"): means[0] =
+ *                    sample `first` (0: static_spread; a caller-drawn index:
+ *                    random_spread); means[k+1] = the sample whose distance to
+ *                    its nearest chosen seed is largest, lowest index on ties;
+ *                    distance sum_d lam_d (x_d - y_d)^2 in FP64, lam_d = 1
+ *                    (gvar = NULL) or 1 / max(gvar_d, var_floor) (the k-means
+ *                    Mahalanobis weights; gvar from gmm_global_stats).  One pass
+ *                    over X per seed.
+ * The workspace is sized as for the same (N, D, G) with GMM_COV_DIAG. */
+int gmm_seed_means(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int32_t mode,
+                   const double* gvar, float var_floor, int64_t first, const int64_t* idx,
+                   float* means, int32_t* dev_status, void* ws, size_t ws_bytes,
+                   gmm_stream_t stream);
 
 /* Log-density of X under ONE Gaussian g of a diagonal model, without its
  * weight (Sec. 4 API log_p(X, g), avg_log_p(X, g)):

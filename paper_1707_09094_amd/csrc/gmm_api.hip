@@ -120,6 +120,21 @@ int gmm_loglik(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int
                                       per_sample, dev_status, w, st));
 }
 
+int gmm_seed_means(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int32_t mode,
+                   const double* gvar, float var_floor, int64_t first, const int64_t* idx,
+                   float* means, int32_t* dev_status, void* ws, size_t ws_bytes,
+                   gmm_stream_t stream) {
+  if (!X || !means || !dev_status) return GMM_EINVAL;
+  if (!shape_ok(N, D, ldx, G)) return GMM_EINVAL;
+  if (mode != GMM_SEED_SUBSET && mode != GMM_SEED_SPREAD) return GMM_EINVAL;
+  if (mode == GMM_SEED_SPREAD && (first < 0 || first >= N)) return GMM_EINVAL;
+  if (!(var_floor >= 0.0f)) return GMM_EINVAL;
+  Workspace w;
+  if (!ws_ok(ws, ws_bytes, N, D, G, GMM_COV_DIAG, &w)) return GMM_EINVAL;
+  return status_of(launch_seed_means(X, N, D, ldx, G, mode, gvar, var_floor, first, idx, means,
+                                     dev_status, w, (hipStream_t)stream));
+}
+
 int gmm_log_p_gaussian(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int32_t g,
                        const float* means, const float* dcovs, double* mean_out,
                        float* per_sample, int32_t* dev_status, void* ws, size_t ws_bytes,

@@ -187,6 +187,7 @@ struct Workspace {
   double* partials;   // [B][G][P]
   double* scalars;    // [4][B] per-block FP64 sums (log-likelihood / inertia)
   int32_t* assign;    // [N] k-means assignment scratch
+  double* dmin;       // [N] spread seeding: distance to the nearest seed (same memory)
   double* lam64;      // [D] k-means distance weights (FP64)
   float* lam32;       // [D] the same rounded to FP32
   int64_t* counters;  // [8] device counters
@@ -245,7 +246,7 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   size_t o_bw = take(nfr ? sizeof(double) * (size_t)G * 16 * ((D + 15) / 16) : 0);
   size_t o_p = take(sizeof(double) * (size_t)B * G * P);
   size_t o_sc = take(sizeof(double) * 4 * (size_t)B);
-  size_t o_a = take(sizeof(int32_t) * (size_t)N);
+  size_t o_a = take(sizeof(double) * (size_t)N);  // assign, or the seeding's dmin
   size_t o_l64 = take(sizeof(double) * (size_t)D);
   size_t o_l32 = take(sizeof(float) * (size_t)D);
   size_t o_ct = take(sizeof(int64_t) * 8);
@@ -271,6 +272,7 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   w->partials = (double*)(b + o_p);
   w->scalars = (double*)(b + o_sc);
   w->assign = (int32_t*)(b + o_a);
+  w->dmin = (double*)(b + o_a);
   w->lam64 = (double*)(b + o_l64);
   w->lam32 = (float*)(b + o_l32);
   w->counters = (int64_t*)(b + o_ct);
@@ -591,6 +593,11 @@ hipError_t launch_log_p_gaussian(const float* X, int64_t N, int D, int64_t ldx, 
                                  const float* means, const float* dcovs, double* mean_out,
                                  float* per_sample, int32_t* dev_status, const Workspace& w,
                                  hipStream_t st);
+
+hipError_t launch_seed_means(const float* X, int64_t N, int D, int64_t ldx, int G, int mode,
+                             const double* gvar, float var_floor, int64_t first,
+                             const int64_t* idx, float* means, int32_t* dev_status,
+                             const Workspace& w, hipStream_t st);
 
 hipError_t launch_assign(const float* X, int64_t N, int D, int64_t ldx, int G, int mode,
                          const float* hefts, const float* means, const float* dcovs,

@@ -823,6 +823,182 @@ hipError_t launch_kmeans(const float* X, int64_t N, int D, int64_t ldx, int G, i
   return hipGetLastError();
 }
 
+namespace {
+
+// ---- seeding of the initial means (Sec. 4 API seed modes) ------------------
+
+__global__ void k_seed_init(int64_t* cur, int64_t first, int32_t* dev_status) {
+  if (threadIdx.x == 0) {
+    *cur = first;
+    *dev_status = 0;
+  }
+}
+
+// Subset modes: block g copies sample idx[g] (caller-drawn indices: random
+// subset) or floor(g N / G) (static subset) into means[g]; an index outside
+// [0, N) sets GMM_DEV_BADDESC and leaves the row unchanged.
+__global__ void __launch_bounds__(256) k_seed_subset(const float* __restrict__ X, int64_t N,
+                                                     int D, int64_t ldx, int G,
+                                                     const int64_t* __restrict__ idx,
+                                                     float* __restrict__ means,
+                                                     int32_t* __restrict__ dev_status) {
+  const int g = blockIdx.x;
+  const int64_t q = N / G, r = N % G;
+  const int64_t s = idx ? idx[g] : (int64_t)g * q + ((int64_t)g * r) / G;
+  if (s < 0 || s >= N) {
+    if (threadIdx.x == 0) atomicOr(dev_status, GMM_DEV_BADDESC);
+    return;
+  }
+  for (int d = threadIdx.x; d < D; d += 256) means[(size_t)g * D + d] = X[s * ldx + d];
+}
+
+// Spread mode (farthest-first traversal), pass k: seed k is sample *cur; its
+// row goes to means[k] and every sample's distance to its nearest seed so far,
+// dmin[i] = min(dmin[i], sum_d lam_d (x_id - y_d)^2), is updated (k = 0: set).
+// Each term lam_d * (u * u) is rounded on its own (an empty asm statement
+// keeps the compiler from fusing it into the add) and added in the order
+// d = 0..D-1, so the values, and hence the choice of the next seed, are those
+// of the plain sequential definition.  Samples
+// pass through LDS in tiles of kST, kSD dimensions at a time.  Each workgroup
+// leaves its largest dmin and the lowest sample index holding it in
+// pval/pidx[b].
+constexpr int kST = 256;
+constexpr int kSD = 32;
+__global__ void __launch_bounds__(kST) k_spread_pass(const float* __restrict__ X, int64_t N,
+                                                     int D, int64_t ldx, int64_t chunk,
+                                                     const double* __restrict__ lam, int k,
+                                                     const int64_t* __restrict__ cur,
+                                                     float* __restrict__ means,
+                                                     double* __restrict__ dmin,
+                                                     double* __restrict__ pval,
+                                                     double* __restrict__ pidx,
+                                                     int32_t* __restrict__ dev_status) {
+  __shared__ float xs[kST][kSD + 1];
+  __shared__ double ys[kSD], ls[kSD];
+  __shared__ double bv[kST];
+  __shared__ int64_t bi[kST];
+  const int tid = threadIdx.x;
+  const int64_t s = *cur;
+  const float* y = X + s * ldx;
+  if (blockIdx.x == 0)
+    for (int d = tid; d < D; d += kST) means[(size_t)k * D + d] = y[d];
+  const int64_t i0 = (int64_t)blockIdx.x * chunk;
+  const int64_t i1 = min(N, i0 + chunk);
+  double best = -1.0;
+  int64_t besti = INT64_MAX;
+  bool bad = false;
+  for (int64_t t0 = i0; t0 < i1; t0 += kST) {
+    const int nt = (int)min((int64_t)kST, i1 - t0);
+    double q = 0.0;
+    for (int d0 = 0; d0 < D; d0 += kSD) {
+      const int nd = min(kSD, D - d0);
+      __syncthreads();
+      for (int p = tid; p < nt * nd; p += kST) {
+        const int t = p / nd, c = p - t * nd;
+        xs[t][c] = X[(t0 + t) * ldx + d0 + c];
+      }
+      if (tid < nd) {
+        ys[tid] = (double)y[d0 + tid];
+        ls[tid] = lam ? lam[d0 + tid] : 1.0;
+      }
+      __syncthreads();
+      if (tid < nt)
+        for (int c = 0; c < nd; ++c) {
+          const double u = (double)xs[tid][c] - ys[c];
+          double term = ls[c] * (u * u);
+          asm volatile("" : "+v"(term));  // rounded on its own: no fused add
+          q = q + term;
+        }
+    }
+    if (tid < nt) {
+      const int64_t i = t0 + tid;
+      const double dm = (k == 0 || q < dmin[i]) ? q : dmin[i];
+      dmin[i] = dm;
+      if (!isfinite(q)) bad = true;
+      if (dm > best) {  // a thread's samples come in increasing order
+        best = dm;
+        besti = i;
+      }
+    }
+  }
+  bv[tid] = best;
+  bi[tid] = besti;
+  __syncthreads();
+  for (int h = kST / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      const double v2 = bv[tid + h];
+      const int64_t i2 = bi[tid + h];
+      if (v2 > bv[tid] || (v2 == bv[tid] && i2 < bi[tid])) {
+        bv[tid] = v2;
+        bi[tid] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    pval[blockIdx.x] = bv[0];
+    pidx[blockIdx.x] = (double)bi[0];
+  }
+  if (bad) atomicOr(dev_status, GMM_DEV_NONFINITE);
+}
+
+// The next seed: the largest of the workgroups' maxima, the earliest workgroup
+// (lowest sample index) on ties.
+__global__ void k_spread_pick(const double* __restrict__ pval, const double* __restrict__ pidx,
+                              int nb, int64_t* __restrict__ cur) {
+  if (threadIdx.x == 0) {
+    double best = -1.0;
+    double bi = 0.0;
+    for (int b = 0; b < nb; ++b)
+      if (pval[b] > best) {
+        best = pval[b];
+        bi = pidx[b];
+      }
+    *cur = (int64_t)bi;
+  }
+}
+
+// Mahalanobis weights of the seeding distance: 1 / max(global variance, floor)
+// in FP64 (Sec. 3.1, Eq. 20).
+__global__ void k_seed_lambda(const double* __restrict__ gvar, int D, float var_floor,
+                              double* __restrict__ lam) {
+  for (int d = threadIdx.x; d < D; d += blockDim.x) {
+    const double v = gvar[d] > (double)var_floor ? gvar[d] : (double)var_floor;
+    lam[d] = 1.0 / v;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_seed_means(const float* X, int64_t N, int D, int64_t ldx, int G, int mode,
+                             const double* gvar, float var_floor, int64_t first,
+                             const int64_t* idx, float* means, int32_t* dev_status,
+                             const Workspace& w, hipStream_t st) {
+  int64_t* cur = w.counters;
+  hipLaunchKernelGGL(k_seed_init, dim3(1), dim3(64), 0, st, cur, first, dev_status);
+  if (mode == GMM_SEED_SUBSET) {
+    hipLaunchKernelGGL(k_seed_subset, dim3(G), dim3(256), 0, st, X, N, D, ldx, G, idx, means,
+                       dev_status);
+    return hipGetLastError();
+  }
+  const double* lam = nullptr;
+  if (gvar) {
+    hipLaunchKernelGGL(k_seed_lambda, dim3(1), dim3(256), 0, st, gvar, D, var_floor, w.lam64);
+    lam = w.lam64;
+  }
+  const int nb = partial_blocks(N, 4 * kST);
+  const int64_t chunk = (N + nb - 1) / nb;
+  double* pval = w.scalars;
+  double* pidx = w.scalars + kMaxBlocks;
+  for (int k = 0; k < G; ++k) {
+    hipLaunchKernelGGL(k_spread_pass, dim3(nb), dim3(kST), 0, st, X, N, D, ldx, chunk, lam, k,
+                       (const int64_t*)cur, means, w.dmin, pval, pidx, dev_status);
+    if (k + 1 < G)
+      hipLaunchKernelGGL(k_spread_pick, dim3(1), dim3(64), 0, st, pval, pidx, nb, cur);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_assign(const float* X, int64_t N, int D, int64_t ldx, int G, int mode,
                          const float* hefts, const float* means, const float* dcovs,
                          int32_t* assign, int64_t* hist, int32_t* dev_status, const Workspace& w,

@@ -25,7 +25,8 @@ LIB_PATH = os.path.join(HERE, "libgmm.so")
 HEADER = os.path.join(HERE, "..", "include", "gmm.h")
 
 GMM_OK, GMM_EINVAL, GMM_EHIP = 0, -1, -2
-GMM_DEV_OK, GMM_DEV_NONFINITE, GMM_DEV_NOTPD = 0, 1, 2
+GMM_DEV_OK, GMM_DEV_NONFINITE, GMM_DEV_NOTPD, GMM_DEV_BADDESC = 0, 1, 2, 4
+SEED_SUBSET, SEED_SPREAD = 0, 1
 COV_DIAG, COV_FULL = 0, 1
 DIST_EUCL, DIST_MAHA = 0, 1
 ASSIGN_EUCL, ASSIGN_PROB = 0, 1
@@ -55,6 +56,8 @@ _SIGS = {
                      _vp, _sz, _vp], _i32),
     "gmm_loglik": ([_vp, _i64, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp,
                     _sz, _vp], _i32),
+    "gmm_seed_means": ([_vp, _i64, _i32, _i64, _i32, _i32, _vp, _f32, _i64, _vp, _vp, _vp, _vp,
+                        _sz, _vp], _i32),
     "gmm_log_p_gaussian": ([_vp, _i64, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
                             _sz, _vp], _i32),
     "gmm_assign": ([_vp, _i64, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
@@ -211,6 +214,22 @@ def gmm_loglik(X, cov, hefts, means, covs, prec, mean_loglik, per_sample, dev_st
         _ptr(per_sample, torch.float32, (N,), "per_sample", optional=True),
         _ptr(dev_status, torch.int32, (1,), "dev_status"), wp, wn, _stream(stream))
     _check("gmm_loglik", rc)
+
+
+def gmm_seed_means(X, mode, means, dev_status, ws, gvar=None, var_floor=0.0, first=0, idx=None,
+                   stream=None):
+    """Initial means into means (float32 (G, D)): SEED_SUBSET (idx: int64 (G,) device
+    indices, or None for floor(g N / G)) or SEED_SPREAD (farthest-first from sample
+    `first`; gvar: float64 (D,) global variances for the Mahalanobis weights)."""
+    xp, N, D, ldx = _xptr(X)
+    G = means.shape[0]
+    wp, wn = _ws(ws)
+    rc = library().gmm_seed_means(
+        xp, N, D, ldx, G, int(mode), _ptr(gvar, torch.float64, (D,), "gvar", optional=True),
+        float(var_floor), int(first), _ptr(idx, torch.int64, (G,), "idx", optional=True),
+        _ptr(means, torch.float32, (G, D), "means"),
+        _ptr(dev_status, torch.int32, (1,), "dev_status"), wp, wn, _stream(stream))
+    _check("gmm_seed_means", rc)
 
 
 def gmm_log_p_gaussian(X, g, means, dcovs, mean_out, per_sample, dev_status, ws, stream=None):

@@ -69,19 +69,55 @@ class Trainer:
         return self.scal[2:3]
 
 
+SEED_MODES = ("keep_existing", "static_subset", "random_subset", "static_spread",
+              "random_spread")
+
+
 def learn(X, G, dist=gmm.DIST_MAHA, init_means=None, km_iter=10, em_iter=10, var_floor=1e-10,
-          prec=gmm.PREC_FP32, cov=gmm.COV_DIAG, record=True):
-    """k-means seeding then EM (Sec. 4 learn()).  init_means: (G, D) float32
-    device tensor with the seed means (e.g. synth.static_subset)."""
+          prec=gmm.PREC_FP32, cov=gmm.COV_DIAG, record=True, seed_mode=None, rng_seed=0,
+          em_tol=None):
+    """Seeding, k-means, then EM (Sec. 4 learn()).
+
+    seed_mode: one of SEED_MODES; "keep_existing" (the default when init_means,
+    a (G, D) float32 device tensor, is given) starts from init_means; the other
+    modes seed on the device with gmm_seed_means, the random ones from indices
+    drawn on the host with NumPy's PCG64(rng_seed).  em_tol: stop EM once the
+    mean log-likelihood rises by less than em_tol from one iteration to the
+    next (each iteration reports that of its input parameters; this reads the
+    value back to the host every iteration)."""
+    import numpy as np
+
     tr = Trainer(X, G, cov, prec)
     N, D = X.shape
     dev = X.device
-    means = init_means.clone().contiguous()
+    if seed_mode is None:
+        seed_mode = "keep_existing" if init_means is not None else "static_subset"
+    if seed_mode not in SEED_MODES:
+        raise ValueError(f"seed_mode must be one of {SEED_MODES}")
+    if dist == gmm.DIST_MAHA:
+        tr.global_stats()
+    if seed_mode == "keep_existing":
+        if init_means is None:
+            raise ValueError("keep_existing needs init_means")
+        means = init_means.clone().contiguous()
+    else:
+        means = torch.zeros(G, D, dtype=torch.float32, device=dev)
+        rng = np.random.Generator(np.random.PCG64(rng_seed))
+        if seed_mode == "static_subset":
+            gmm.gmm_seed_means(X, gmm.SEED_SUBSET, means, tr.status, tr.ws)
+        elif seed_mode == "random_subset":
+            idx = rng.choice(N, G, replace=G > N)
+            gmm.gmm_seed_means(X, gmm.SEED_SUBSET, means, tr.status, tr.ws,
+                               idx=torch.as_tensor(idx, dtype=torch.int64, device=dev))
+        else:
+            first = 0 if seed_mode == "static_spread" else int(rng.integers(N))
+            gmm.gmm_seed_means(X, gmm.SEED_SPREAD, means, tr.status, tr.ws,
+                               gvar=tr.gvar if dist == gmm.DIST_MAHA else None,
+                               var_floor=var_floor, first=first)
     dcovs = torch.ones(G, D, dtype=torch.float32, device=dev)
     hefts = torch.full((G,), 1.0 / G, dtype=torch.float32, device=dev)
     log = FitLog()
-    if dist == gmm.DIST_MAHA:
-        tr.global_stats()
+    log.status |= int(tr.status[0]) if seed_mode != "keep_existing" else 0
     for _ in range(km_iter):
         tr.kmeans_iter(means, dcovs, hefts, dist, var_floor)
         if record:
@@ -93,10 +129,15 @@ def learn(X, G, dist=gmm.DIST_MAHA, init_means=None, km_iter=10, em_iter=10, var
     else:
         covs = dcovs
     model = Model(hefts, means, covs, cov)
+    prev = None
     for _ in range(em_iter):
         tr.em_iter(model, var_floor)
-        if record:
-            log.loglik.append(float(tr.scal[1]))
+        if record or em_tol is not None:
+            ll = float(tr.scal[1])
+            log.loglik.append(ll)
             log.em_recomputed.append(int(tr.i64[1]))
             log.status |= int(tr.status[0])
+            if em_tol is not None and prev is not None and ll - prev < em_tol:
+                break
+            prev = ll
     return model, log, tr

@@ -73,6 +73,13 @@ def test_null_and_shape_arguments_rejected_on_host():
                         None) == gmm.GMM_EINVAL
     assert L.gmm_assign(FAKE, 10, 4, 4, 2, gmm.ASSIGN_PROB, FAKE, FAKE, None, FAKE, None, FAKE,
                         ws, 1 << 30, None) == gmm.GMM_EINVAL
+    # seeding: unknown mode, spread start out of range, negative floor
+    assert L.gmm_seed_means(FAKE, 10, 4, 4, 2, 7, None, 0.0, 0, None, FAKE, FAKE, ws, 1 << 30,
+                            None) == gmm.GMM_EINVAL
+    assert L.gmm_seed_means(FAKE, 10, 4, 4, 2, gmm.SEED_SPREAD, None, 0.0, 10, None, FAKE, FAKE,
+                            ws, 1 << 30, None) == gmm.GMM_EINVAL
+    assert L.gmm_seed_means(FAKE, 10, 4, 4, 2, gmm.SEED_SPREAD, None, -1.0, 0, None, FAKE, FAKE,
+                            ws, 1 << 30, None) == gmm.GMM_EINVAL
     # log_p(X, g): g out of range, negative g, no output requested
     assert L.gmm_log_p_gaussian(FAKE, 10, 4, 4, 2, 2, FAKE, FAKE, FAKE, None, FAKE, ws, 1 << 30,
                                 None) == gmm.GMM_EINVAL

@@ -371,6 +371,66 @@ def test_assign_and_hist(G_, oracle, mode):
     assert np.array_equal(hist.cpu().numpy(), np.bincount(ref, minlength=5))
 
 
+# ---------------------------------------------------------------- seeding
+# one sample; several workgroups with ragged tiles; one and several LDS
+# dimension chunks; static and random starts; Euclidean and Mahalanobis
+@pytest.mark.parametrize("N,D,G,first,maha", [(1, 3, 4, 0, False), (5000, 7, 20, 0, False),
+                                              (3001, 40, 16, 123, True), (700, 100, 64, 0, True),
+                                              (20_000, 33, 8, 19_999, False)])
+def test_seed_spread(G_, oracle, N, D, G, first, maha):
+    X, _ = synth.diag_gmm(40 + D, D, 6, N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
+    gvar = oracle.global_stats(X)[1] if maha else None
+    lam = oracle.maha_lambda(gvar, 1e-10) if maha else None
+    ref_idx, _ = oracle.seed_spread(X, G, first=first, lam=lam)
+    means = torch.full((G, D), float("nan"), device=DEV)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    ws = G_.workspace(N, D, G, device=DEV)
+    G_.gmm_seed_means(_t(X), G_.SEED_SPREAD, means, st, ws,
+                      gvar=None if gvar is None else _t(gvar, torch.float64), var_floor=1e-10,
+                      first=first)
+    assert st.item() == 0
+    np.testing.assert_array_equal(means.cpu().numpy(), X[ref_idx])
+
+
+def test_seed_subset(G_):
+    X, _ = synth.diag_gmm(5, 9, 3, 1234, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
+    ws = G_.workspace(1234, 9, 37, device=DEV)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    means = torch.zeros(37, 9, device=DEV)
+    G_.gmm_seed_means(_t(X), G_.SEED_SUBSET, means, st, ws)  # static: floor(g N / G)
+    np.testing.assert_array_equal(means.cpu().numpy(), synth.static_subset(X, 37))
+    rng = np.random.Generator(np.random.PCG64(3))
+    idx = rng.choice(1234, 37, replace=False)
+    G_.gmm_seed_means(_t(X), G_.SEED_SUBSET, means, st, ws, idx=_t(idx, torch.int64))
+    np.testing.assert_array_equal(means.cpu().numpy(), X[idx])
+    assert st.item() == 0
+    idx[5] = 1234  # out of range: flagged, row kept
+    before = means.cpu().numpy().copy()
+    G_.gmm_seed_means(_t(X), G_.SEED_SUBSET, means, st, ws, idx=_t(idx, torch.int64))
+    assert st.item() & G_.GMM_DEV_BADDESC
+    np.testing.assert_array_equal(means.cpu().numpy()[5], before[5])
+
+
+@pytest.mark.parametrize("mode", ["static_subset", "random_subset", "static_spread",
+                                  "random_spread"])
+def test_learn_seed_modes_and_loglik_stop(G_, mode):
+    """The learn() driver end to end: each seed mode, then k-means and EM with
+    the log-likelihood-increase stop (EM log-likelihoods never decrease)."""
+    from paper_1707_09094_amd import train
+    X, _ = synth.diag_gmm(3, 5, 4, 4000, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
+    tol = 1e-4
+    model, log, _ = train.learn(_t(X), 4, seed_mode=mode, rng_seed=1, km_iter=5, em_iter=40,
+                                em_tol=tol)
+    assert log.status == 0
+    ll = np.array(log.loglik)
+    assert len(ll) >= 2 and np.all(np.isfinite(ll))
+    inc = np.diff(ll)
+    assert np.all(inc >= -1e-9 * np.abs(ll[1:]))
+    if len(ll) < 40:  # stopped by the rule: only the last increase is below tol
+        assert inc[-1] < tol and np.all(inc[:-1] >= tol)
+    assert abs(float(model.hefts.sum()) - 1.0) < 1e-5
+
+
 # ---------------------------------------------------------------- log_p(X, g)
 # N = 1; several tiles with a ragged tail; D = 1, one LDS dimension chunk with
 # a ragged tail (33), several chunks (100, 300); first and last Gaussian
