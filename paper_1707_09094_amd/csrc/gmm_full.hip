@@ -210,7 +210,8 @@ __device__ void logdens_full_f64(const float* __restrict__ xs, int DS, int nt, i
 // (16 rb + 4 j + l/16, 16 cb + l%16).  The tile's sums are added to the
 // component's FP64 partials q (count, first moments, packed lower triangle).
 template <int RBYM, int KC>
-__device__ void map_full_f64(const float* __restrict__ xs, int DS, int nt, int D, int G,
+__device__ void map_full_f64(const float* __restrict__ xs, int DS, int nm,
+                             const int* __restrict__ mlist, int D, int G,
                              const float* __restrict__ as, const float* __restrict__ mu_g,
                              double* __restrict__ q, int g, int lane) {
   constexpr int NB = RBYM * (RBYM + 1) / 2;  // lower-triangle blocks
@@ -225,16 +226,18 @@ __device__ void map_full_f64(const float* __restrict__ xs, int DS, int nt, int D
   f64x4 c[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) c[i] = f64x4{0.0, 0.0, 0.0, 0.0};
-  const int nks = (nt + 3) / 4;
+  // only the tile's samples with a non-zero responsibility (mlist[0..nm), in
+  // increasing order) take part: 4 per k-step
+  const int nks = (nm + 3) / 4;
   // k-steps (4 samples each) KC at a time: their fragments of y' are built,
   // then every block takes them
   for (int k0 = 0; k0 < nks; k0 += KC) {
     double yb[RBYM][KC], rr[KC];
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
-      const int t = 4 * (k0 + kk) + kb;
-      const bool ok = t < nt;
-      const int tt = ok ? t : 0;
+      const int j = 4 * (k0 + kk) + kb;
+      const bool ok = j < nm;
+      const int tt = ok ? mlist[j] : 0;
       rr[kk] = ok ? (double)as[(size_t)tt * G + g] : 0.0;
 #pragma unroll
       for (int cb = 0; cb < RBYM; ++cb) {
@@ -283,6 +286,7 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_full(
     double* __restrict__ part, double* __restrict__ ll_part, float* __restrict__ per_sample,
     int32_t* __restrict__ dev_status) {
   extern __shared__ double ldsd[];
+  __shared__ int mlist_s[kNT / kWave][64];  // per wave: a component's member samples
   const int nw = kNT / kWave;
   constexpr bool F64 = FKS > 0;
   double* as64 = ldsd;                                      // F64: [T][G] log-densities
@@ -491,11 +495,19 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_full(
     constexpr bool MAP64 = FKS == 8;  // D <= 32: the map step on the matrix cores too
     if (MSTEP && MAP64) {
       // map step (Eqs. 9-11) on the matrix cores, wave per component with a
-      // non-zero responsibility in the tile
+      // non-zero responsibility in the tile, over the list of its samples
+      // with r != 0 (T <= 64: one lane per sample)
+      int* ml = mlist_s[wid];
+      const unsigned long long lt = (1ull << lane) - 1ull;
       for (int g = wid; g < G; g += nw) {
         if (!((gbits[g >> 5] >> (g & 31)) & 1u)) continue;
-        map_full_f64<3, 4>(xs, DS, nt, D, G, as, means + (size_t)g * D, pb + (size_t)g * P, g,
-                           lane);
+        const bool mine = lane < nt && as[(size_t)lane * G + g] != 0.0f;
+        const unsigned long long mem = __ballot(mine);
+        if (mine) ml[__popcll(mem & lt)] = lane;
+        wave_lds_sync();
+        map_full_f64<3, 4>(xs, DS, __popcll(mem), ml, D, G, as, means + (size_t)g * D,
+                           pb + (size_t)g * P, g, lane);
+        wave_lds_sync();  // the list is rewritten for the next component
       }
     }
     if (MSTEP && !MAP64) {
