@@ -232,7 +232,7 @@ def cpu_baseline(X, hefts, means, dcovs):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the path runs on one GPU (one rank); --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
