@@ -213,7 +213,7 @@ template <int RBYM, int KC>
 __device__ void map_full_f64(const float* __restrict__ xs, int DS, int nm,
                              const int* __restrict__ mlist, int D, int G,
                              const float* __restrict__ as, const float* __restrict__ mu_g,
-                             double* __restrict__ q, int g, int lane) {
+                             double* __restrict__ q, int g, int lane, double* __restrict__ stg) {
   constexpr int NB = RBYM * (RBYM + 1) / 2;  // lower-triangle blocks
   const int RBY = (D + 16) / 16;             // row blocks of y'
   const int m = lane & 15, kb = lane >> 4;
@@ -269,10 +269,20 @@ __device__ void map_full_f64(const float* __restrict__ xs, int DS, int nm,
         else if (d == D && e < D) k = 1 + e;
         else if (d < D && e <= d) k = 1 + D + tri_index(d, e, D);
         // every entry has one (block, lane, register) of the one wave that
-        // owns the component: the no-return atomic add is an ordered update
-        if (k >= 0) unsafeAtomicAdd(q + k, c[i][j]);
+        // owns the component
+        if (k >= 0) {
+          if (stg) stg[k] = c[i][j];
+          else unsafeAtomicAdd(q + k, c[i][j]);  // an ordered update (one lane)
+        }
       }
     }
+  if (stg) {
+    // the staged entries go out in address order, entry k from lane k % 64:
+    // whole cache lines per atomic instruction, still one updating lane
+    wave_lds_sync();
+    const int P = 1 + D + D * (D + 1) / 2;
+    for (int k = lane; k < P; k += kWave) unsafeAtomicAdd(q + k, stg[k]);
+  }
 }
 
 // FKS: k-steps of 4 of the FP64 matrix-core log-densities (8: D <= 32, 16:
@@ -499,6 +509,10 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_full(
       // with r != 0 (T <= 64: one lane per sample)
       int* ml = mlist_s[wid];
       const unsigned long long lt = (1ull << lane) - 1ull;
+      // each wave stages a component's entries in the log-density buffer, free
+      // once the responsibilities are taken, when it is large enough
+      const int PS = (1 + D + D * (D + 1) / 2 + 1) & ~1;
+      double* stg = (size_t)T * G >= (size_t)nw * PS ? as64 + (size_t)wid * PS : nullptr;
       for (int g = wid; g < G; g += nw) {
         if (!((gbits[g >> 5] >> (g & 31)) & 1u)) continue;
         const bool mine = lane < nt && as[(size_t)lane * G + g] != 0.0f;
@@ -506,7 +520,7 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_full(
         if (mine) ml[__popcll(mem & lt)] = lane;
         wave_lds_sync();
         map_full_f64<3, 4>(xs, DS, __popcll(mem), ml, D, G, as, means + (size_t)g * D,
-                           pb + (size_t)g * P, g, lane);
+                           pb + (size_t)g * P, g, lane, stg);
         wave_lds_sync();  // the list is rewritten for the next component
       }
     }
