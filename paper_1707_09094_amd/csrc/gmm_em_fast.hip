@@ -671,11 +671,12 @@ __global__ void __launch_bounds__(256) k_fin_welford(const double* __restrict__ 
     hefts[g] = w;
     if (!isfinite(w)) bad = 1;
   }
-  if (g == 0 && threadIdx.x == 0 && mean_loglik) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += ll_part[b];
-    *mean_loglik = s / (double)N;
-    if (!isfinite(s)) bad = 1;
+  if (g == 0 && mean_loglik) {
+    const double s = ordered_sum<256>(ll_part, nb, S.lb);
+    if (threadIdx.x == 0) {
+      *mean_loglik = s / (double)N;
+      if (!isfinite(s)) bad = 1;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0 && bad) atomicOr(dev_status, GMM_DEV_NONFINITE);
@@ -719,11 +720,12 @@ __global__ void __launch_bounds__(256) k_fin_welford_batched(const gmm_model_des
       if (!isfinite(w)) bad = 1;
     }
   }
-  if (g == 0 && threadIdx.x == 0) {
-    double s = 0.0;
-    for (int k = 0; k < cnt; ++k) s += ll_part[first + k];
-    if (m.loglik) *m.loglik = s / (double)m.N;
-    if (!isfinite(s)) bad = 1;
+  if (g == 0) {
+    const double s = ordered_sum<256>(ll_part + first, cnt, S.lb);
+    if (threadIdx.x == 0) {
+      if (m.loglik) *m.loglik = s / (double)m.N;
+      if (!isfinite(s)) bad = 1;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0 && bad) atomicOr(m.dev_status, GMM_DEV_NONFINITE);

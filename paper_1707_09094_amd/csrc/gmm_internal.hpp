@@ -514,6 +514,24 @@ __device__ double welford_combine(const double* __restrict__ base, size_t stride
   return S.run;
 }
 
+// Sum of v[0..n) in index order, by thread 0, with the values staged through
+// LDS by the whole workgroup so that their loads overlap (the same arithmetic
+// as one thread's plain loop).  Every thread must call it; the sum is valid in
+// thread 0.  sh: kWcChunk doubles of LDS.
+template <int NT>
+__device__ double ordered_sum(const double* __restrict__ v, int n, double* sh) {
+  double s = 0.0;
+  for (int c0 = 0; c0 < n; c0 += kWcChunk) {
+    const int nc = min(kWcChunk, n - c0);
+    for (int i = threadIdx.x; i < nc; i += NT) sh[i] = v[c0 + i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int i = 0; i < nc; ++i) s += sh[i];
+    __syncthreads();
+  }
+  return s;
+}
+
 // ---- optional event timing of the data-pass kernels (gmm_profile.hip) ------
 
 constexpr int kProfKinds = 8;

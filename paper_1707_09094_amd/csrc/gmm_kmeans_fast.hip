@@ -435,11 +435,12 @@ __global__ void __launch_bounds__(256) k_km_fin_fast(const double* __restrict__ 
     counts[g] = (int64_t)Ltot;
     hefts[g] = (float)(Ltot / (double)N);
   }
-  if (g == 0 && threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += in_part[b];
-    *inertia = s;
-    if (!isfinite(s)) atomicOr(dev_status, GMM_DEV_NONFINITE);
+  if (g == 0) {
+    const double s = ordered_sum<256>(in_part, nb, S.lb);
+    if (threadIdx.x == 0) {
+      *inertia = s;
+      if (!isfinite(s)) atomicOr(dev_status, GMM_DEV_NONFINITE);
+    }
   }
 }
 
@@ -474,11 +475,12 @@ __global__ void __launch_bounds__(256) k_km_fin_batched(const gmm_model_desc* mo
     m.counts[g] = (int64_t)Ltot;
     m.hefts[g] = (float)(Ltot / (double)m.N);
   }
-  if (g == 0 && threadIdx.x == 0) {
-    double s = 0.0;
-    for (int k = 0; k < cnt; ++k) s += in_part[first + k];
-    if (m.inertia) *m.inertia = s;
-    if (!isfinite(s)) atomicOr(m.dev_status, GMM_DEV_NONFINITE);
+  if (g == 0) {
+    const double s = ordered_sum<256>(in_part + first, cnt, S.lb);
+    if (threadIdx.x == 0) {
+      if (m.inertia) *m.inertia = s;
+      if (!isfinite(s)) atomicOr(m.dev_status, GMM_DEV_NONFINITE);
+    }
   }
 }
 
