@@ -635,7 +635,8 @@ __global__ void __launch_bounds__(kLT) k_log_p_g(const float* __restrict__ X, in
   if (bad) atomicOr(dev_status, GMM_DEV_NONFINITE);
 }
 
-// LDS bytes of k_estep_diag for tile rows T (WIDE adds the parameter chunk).
+// LDS bytes of k_estep_diag for tile rows T (WIDE: rows of xs padded to 4,
+// rows of as padded by 8, and the per-block references rcb).
 size_t estep_lds(int D, int G, int T, bool wide) {
   const size_t XS = wide ? (size_t)((D + 3) & ~3) : (size_t)D;
   size_t b = sizeof(float) * ((size_t)T * (XS + G) + 1) + sizeof(double) * T;
@@ -644,8 +645,9 @@ size_t estep_lds(int D, int G, int T, bool wide) {
   return b;
 }
 
-// The WIDE form (register-blocked screening) is used for D <= 128 and more
-// components than the one-pass kernels take, when its tile fits in LDS.
+// The WIDE form (exact FP64 log-densities on the matrix cores) is used for
+// D <= 128 and more components than the one-pass kernels take, when its tile
+// fits in LDS.
 bool use_wide(int D, int G) {
   return D <= 128 && G > 128 && estep_lds(D, G, kWT, true) <= 159 * 1024;  // + static LDS
 }
