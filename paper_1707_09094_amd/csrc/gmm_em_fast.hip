@@ -656,7 +656,7 @@ __global__ void __launch_bounds__(256) k_fin_welford(const double* __restrict__ 
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   double m, Q;
-  const double Ltot = welford_combine<256>(part + (size_t)g * P, (size_t)G * P, nb, D, S, m, Q);
+  const double Ltot = welford_combine<256, 32>(part + (size_t)g * P, (size_t)G * P, nb, D, S, m, Q);
   const int d = threadIdx.x;
   if (d < D && Ltot > 0.0) {
     double v = Q / Ltot;
@@ -702,7 +702,7 @@ __global__ void __launch_bounds__(256) k_fin_welford_batched(const gmm_model_des
   __syncthreads();
   if (mstep) {
     double mu, Q;
-    const double Ltot = welford_combine<256>(part + ((size_t)first * Gmax + g) * P,
+    const double Ltot = welford_combine<256, 8>(part + ((size_t)first * Gmax + g) * P,
                                              (size_t)Gmax * P, cnt, D, S, mu, Q);
     const int d = threadIdx.x;
     if (d < D && Ltot > 0.0) {
@@ -720,12 +720,11 @@ __global__ void __launch_bounds__(256) k_fin_welford_batched(const gmm_model_des
       if (!isfinite(w)) bad = 1;
     }
   }
-  if (g == 0) {
-    const double s = ordered_sum<256>(ll_part + first, cnt, S.lb);
-    if (threadIdx.x == 0) {
-      if (m.loglik) *m.loglik = s / (double)m.N;
-      if (!isfinite(s)) bad = 1;
-    }
+  if (g == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < cnt; ++k) s += ll_part[first + k];
+    if (m.loglik) *m.loglik = s / (double)m.N;
+    if (!isfinite(s)) bad = 1;
   }
   __syncthreads();
   if (threadIdx.x == 0 && bad) atomicOr(m.dev_status, GMM_DEV_NONFINITE);

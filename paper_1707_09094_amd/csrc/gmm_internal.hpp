@@ -441,8 +441,9 @@ __device__ __forceinline__ double block_sum_d(double v, double* sh) {
 // m += (m_b - m) L_b / L', Q += Q_b + (m_b - m)^2 L L_b / L'.  The running
 // totals L depend on the counts alone, so they are taken first (one thread, in
 // block order) and each block's two weights computed from them in parallel;
-// then thread d runs the chain of dimension d with the loads of 32 blocks in
-// flight.  The arithmetic is that of the plain block-by-block loop.  Needs
+// then thread d runs the chain of dimension d with the loads of FLY blocks in
+// flight (32 for a few large reductions, 8 where many workgroups share the GPU
+// and registers decide occupancy).  The arithmetic is that of the plain block-by-block loop.  Needs
 // D <= NT; every thread must call it.  Returns the total L; thread d < D gets
 // its (m, Q).
 constexpr int kWcChunk = 256;  // blocks per pass
@@ -451,7 +452,7 @@ struct WelfordLds {
   int kind[kWcChunk];
   double run;
 };
-template <int NT>
+template <int NT, int FLY>
 __device__ double welford_combine(const double* __restrict__ base, size_t stride, int nb, int D,
                                   WelfordLds& S, double& m, double& Q) {
   const int tid = threadIdx.x;
@@ -483,7 +484,7 @@ __device__ double welford_combine(const double* __restrict__ base, size_t stride
     }
     __syncthreads();
     if (d < D) {
-      constexpr int kFly = 32;  // blocks whose loads are in flight together
+      constexpr int kFly = FLY;  // blocks whose loads are in flight together
       const double* q = base + (size_t)c0 * stride + 1 + d;
       for (int i0 = 0; i0 < nc; i0 += kFly) {
         double mb[kFly], Qb[kFly];

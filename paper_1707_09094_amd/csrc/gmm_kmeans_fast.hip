@@ -418,7 +418,7 @@ __global__ void __launch_bounds__(256) k_km_fin_fast(const double* __restrict__ 
   const int g = blockIdx.x;
   const int P = 2 * D + 1;
   double m, Q;
-  const double Ltot = welford_combine<256>(part + (size_t)g * P, (size_t)G * P, nb, D, S, m, Q);
+  const double Ltot = welford_combine<256, 32>(part + (size_t)g * P, (size_t)G * P, nb, D, S, m, Q);
   const int d = threadIdx.x;
   if (d < D) {
     if (Ltot > 0.0) {
@@ -457,7 +457,7 @@ __global__ void __launch_bounds__(256) k_km_fin_batched(const gmm_model_desc* mo
   if (cnt == 0 || g >= m.G) return;
   const int P = 2 * D + 1;
   double mu, Q;
-  const double Ltot = welford_combine<256>(part + ((size_t)first * Gmax + g) * P,
+  const double Ltot = welford_combine<256, 8>(part + ((size_t)first * Gmax + g) * P,
                                            (size_t)Gmax * P, cnt, D, S, mu, Q);
   const int d = threadIdx.x;
   if (d < D) {
@@ -475,12 +475,11 @@ __global__ void __launch_bounds__(256) k_km_fin_batched(const gmm_model_desc* mo
     m.counts[g] = (int64_t)Ltot;
     m.hefts[g] = (float)(Ltot / (double)m.N);
   }
-  if (g == 0) {
-    const double s = ordered_sum<256>(in_part + first, cnt, S.lb);
-    if (threadIdx.x == 0) {
-      if (m.inertia) *m.inertia = s;
-      if (!isfinite(s)) atomicOr(m.dev_status, GMM_DEV_NONFINITE);
-    }
+  if (g == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < cnt; ++k) s += in_part[first + k];
+    if (m.inertia) *m.inertia = s;
+    if (!isfinite(s)) atomicOr(m.dev_status, GMM_DEV_NONFINITE);
   }
 }
 
