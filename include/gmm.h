@@ -49,7 +49,8 @@
  * reads after synchronising: a non-finite log-likelihood or parameter
  * (GMM_DEV_NONFINITE: NaN/Inf in the data, or a covariance <= 0 on input --
  * the failure mode named at the end of Sec. 2.2) and, for full covariances, a
- * matrix that is not positive definite (GMM_DEV_NOTPD).  Outputs are then
+ * matrix that is not positive definite (GMM_DEV_NOTPD); GMM_DEV_BADDESC marks
+ * a device-side index or descriptor out of range.  Outputs are then
  * unspecified.
  */
 #ifndef GMM_H
@@ -71,7 +72,8 @@ extern "C" {
 #define GMM_DEV_OK 0
 #define GMM_DEV_NONFINITE 1
 #define GMM_DEV_NOTPD 2
-#define GMM_DEV_BADDESC 4   /* batched: descriptor disagrees with Ns/Gs; model skipped */
+#define GMM_DEV_BADDESC 4   /* batched: descriptor disagrees with Ns/Gs, model skipped;
+                               gmm_seed_means: a subset index outside [0, N) */
 
 /* covariance type (Sec. 4: diagonal covariances; full as in Eq. 2) */
 #define GMM_COV_DIAG 0
