@@ -337,21 +337,25 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_diag(
 #pragma unroll
         for (int off = 1; off < kKL; off <<= 1) M = fmaxf(M, __shfl_xor(M, off));
         M = M > -INFINITY ? M : 0.0f;
-        auto val = [&](int g) { return (float)(((double)rr[g >> 4] - (double)M) + (double)a[g]); };
+        // the value relative to M, computed once and kept in place of a - R_cb
         float dn = -INFINITY;
-        for (int g = j; g < G; g += kKL) dn = fmaxf(dn, val(g));
+        for (int g = j; g < G; g += kKL) {
+          const float v = (float)(((double)rr[g >> 4] - (double)M) + (double)a[g]);
+          a[g] = v;
+          dn = fmaxf(dn, v);
+        }
 #pragma unroll
         for (int off = 1; off < kKL; off <<= 1) dn = fmaxf(dn, __shfl_xor(dn, off));
         dn = dn > -INFINITY ? dn : 0.0f;
         double sm = 0.0;
-        for (int g = j; g < G; g += kKL) sm += (double)__expf(val(g) - dn);
+        for (int g = j; g < G; g += kKL) sm += (double)__expf(a[g] - dn);
 #pragma unroll
         for (int off = 1; off < kKL; off <<= 1) sm += __shfl_xor(sm, off);
         const double l = ((double)M + (double)dn) + log(sm);
         if (MSTEP) {
           const float dl = (float)log(sm);
           for (int g = j; g < G; g += kKL) {
-            const float z = (val(g) - dn) - dl;
+            const float z = (a[g] - dn) - dl;
             const float r = z >= -kRespCut ? __expf(z) : 0.0f;
             a[g] = r;
             if (r != 0.0f) atomicOr(&gbits[g >> 5], 1u << (g & 31));
