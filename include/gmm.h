@@ -91,14 +91,18 @@ extern "C" {
 #define GMM_ASSIGN_EUCL 0
 #define GMM_ASSIGN_PROB 1
 
-/* arithmetic of the log-density / distance contraction.
+/* arithmetic of the log-density / distance contraction of the one-pass
+ * kernels (diagonal covariances, D <= 128 and G <= 128; gmm_em_path and
+ * gmm_kmeans_path report which family a shape runs).  Other shapes compute
+ * their log-densities exactly in FP64 (matrix cores for D <= 128) or screen in
+ * FP32 with an FP64 recompute, and ignore prec.
  * GMM_PREC_FP32:   direct (x - mu)^2 form in FP32 on the vector ALUs.
  * GMM_PREC_BF16X3: the expanded form x^2 * Lambda - 2 x * (Lambda mu) + const
  *                  as a GEMM on the matrix cores with each FP32 operand split
  *                  into two BF16 parts (hi*hi + hi*lo + lo*hi, FP32 accumulate);
  *                  every sample's leading components (those within a fixed gap
- *                  of the best, see gmm_em_iter) are recomputed in the FP32
- *                  direct form, so the result carries FP32-path accuracy. */
+ *                  of the best, see gmm_em_iter) are recomputed exactly, so the
+ *                  result carries FP32-path accuracy. */
 #define GMM_PREC_FP32 0
 #define GMM_PREC_BF16X3 1
 
@@ -230,6 +234,36 @@ int gmm_assign(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int
                const float* hefts, const float* means, const float* dcovs, int32_t* assign,
                int64_t* hist, int32_t* dev_status, void* ws, size_t ws_bytes,
                gmm_stream_t stream);
+
+/* ---- kernel selection ----------------------------------------------------
+ * Which kernel family gmm_em_iter / gmm_loglik (gmm_em_path) and
+ * gmm_kmeans_iter (gmm_kmeans_path) run for a shape and arithmetic form.
+ * Pure host functions with no side effect, for tests and tools; they return
+ * GMM_EINVAL for arguments the calls would reject.
+ *   GMM_PATH_ONEPASS_BF16X3  diagonal, D <= 128, G <= 128, prec BF16X3: the
+ *                            one-pass kernel with the split-BF16 contraction
+ *                            on the matrix cores and the exact recompute of
+ *                            each sample's leading components
+ *   GMM_PATH_ONEPASS_FP32    the same shapes, prec FP32 (or a shape whose
+ *                            matrix-core fragments do not fit): the one-pass
+ *                            kernel with the FP32 direct form
+ *   GMM_PATH_WIDE_FP64       diagonal, D <= 128, G > 128: every log-density
+ *                            (distance) in FP64 on the matrix cores, whatever
+ *                            prec says
+ *   GMM_PATH_GENERIC         diagonal, D > 128: FP32 direct-form screening with
+ *                            an FP64 recompute of the near set (prec ignored)
+ *   GMM_PATH_FULL_FP64       full covariances, D <= 64: FP64 matrix cores
+ *   GMM_PATH_FULL_GENERIC    full covariances, 64 < D <= 128: FP32 screening,
+ *                            FP64 near set */
+#define GMM_PATH_ONEPASS_BF16X3 1
+#define GMM_PATH_ONEPASS_FP32 2
+#define GMM_PATH_WIDE_FP64 3
+#define GMM_PATH_GENERIC 4
+#define GMM_PATH_FULL_FP64 5
+#define GMM_PATH_FULL_GENERIC 6
+
+int gmm_em_path(int32_t D, int32_t G, int32_t cov, int32_t prec);
+int gmm_kmeans_path(int32_t D, int32_t G, int32_t prec);
 
 /* ---- many independent diagonal models in one launch sequence --------------
  * The batch is described by an array of n_models descriptors in DEVICE

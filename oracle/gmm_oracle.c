@@ -560,6 +560,27 @@ int oracle_kmeans_iter(const float* X, int64_t N, int D, int64_t ldx, int G, con
 }
 
 /* ------------------------------------------------------------------------ */
+/* Public: every k-means distance (Sec. 3, Eq. 19's argument; Sec. 3.1,       */
+/* Eq. 20's weights): out[i*G + g] = sum_d lam[d] (x_di - mu_gd)^2.          */
+/* ------------------------------------------------------------------------ */
+
+int oracle_kmeans_dists(const float* X, int64_t N, int D, int64_t ldx, int G, const double* lam,
+                        const double* means, double* out) {
+  if (N < 1 || D < 1 || G < 1 || ldx < D) return ORC_EINVAL;
+#pragma omp parallel for schedule(static) num_threads(NTHR)
+  for (int64_t i = 0; i < N; ++i)
+    for (int g = 0; g < G; ++g) {
+      double s = 0.0;
+      for (int d = 0; d < D; ++d) {
+        double t = xval(X, ldx, i, d) - means[(size_t)g * D + d];
+        s += lam[d] * t * t;
+      }
+      out[i * G + g] = s;
+    }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Public: closest Gaussian per sample (Sec. 4 API: assign(X, dist_mode)).    */
 /* mode 0 = Euclidean distance to the means; mode 1 = probabilistic:          */
 /* the Gaussian with the largest weighted likelihood.  Lowest index on ties. */

@@ -62,9 +62,10 @@ def lib():
                                          _dp, _dp, _dp, _i64p, _i32p, _dp, _dp]
         L.oracle_assign.argtypes = [_fp, _i64, _i32, _i64, _i32, _i32, _dp, _dp, _dp, _i32p]
         L.oracle_seed_spread.argtypes = [_fp, _i64, _i32, _i64, _i32, _dp, _i64, _i64p, _dp]
+        L.oracle_kmeans_dists.argtypes = [_fp, _i64, _i32, _i64, _i32, _dp, _dp, _dp]
         for f in ("oracle_loglik", "oracle_log_p_g", "oracle_responsibilities", "oracle_em_iter",
                   "oracle_global_stats", "oracle_kmeans_iter", "oracle_assign",
-                  "oracle_seed_spread"):
+                  "oracle_seed_spread", "oracle_kmeans_dists"):
             getattr(L, f).restype = _i32
         _lib = L
     return _lib
@@ -200,6 +201,18 @@ def kmeans_iter(X, means, lam, var_floor) -> KMResult:
                                   _p(inertia), _p(gap))
     _check(rc, "kmeans_iter")
     return KMResult(mo, co, ho, counts, assign, float(inertia[0]), gap, rc)
+
+
+def kmeans_dists(X, means, lam):
+    """(N, G) matrix of k-means distances sum_d lam_d (x_d - mu_gd)^2 (Eq. 19's
+    argument with Eq. 20's weights)."""
+    X, N, D = _X(X)
+    m = _d(means)
+    G = m.shape[0]
+    out = np.zeros((N, G))
+    _check(lib().oracle_kmeans_dists(_p(X, _fp), N, D, D, G, _p(_d(lam)), _p(m), _p(out)),
+           "kmeans_dists")
+    return out
 
 
 def assign(X, hefts, means, dcovs, mode):

@@ -161,6 +161,21 @@ int gmm_assign(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int
                                  dev_status, w, (hipStream_t)stream));
 }
 
+int gmm_em_path(int32_t D, int32_t G, int32_t cov, int32_t prec) {
+  if (!shape_ok(1, D, D, G)) return GMM_EINVAL;
+  if (prec != GMM_PREC_FP32 && prec != GMM_PREC_BF16X3) return GMM_EINVAL;
+  if (cov == GMM_COV_FULL)
+    return D > kMaxDFull ? GMM_EINVAL : (D <= 64 ? GMM_PATH_FULL_FP64 : GMM_PATH_FULL_GENERIC);
+  if (cov != GMM_COV_DIAG) return GMM_EINVAL;
+  return em_diag_path(D, G, prec);
+}
+
+int gmm_kmeans_path(int32_t D, int32_t G, int32_t prec) {
+  if (!shape_ok(1, D, D, G)) return GMM_EINVAL;
+  if (prec != GMM_PREC_FP32 && prec != GMM_PREC_BF16X3) return GMM_EINVAL;
+  return kmeans_path(D, G, prec);
+}
+
 // ---- many models -----------------------------------------------------------
 
 }  // extern "C"

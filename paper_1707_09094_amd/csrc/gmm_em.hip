@@ -676,6 +676,12 @@ int tile_rows(int D, int G) {
 
 }  // namespace
 
+int em_diag_path(int D, int G, int prec) {
+  if (em_fast_supported(D, G, prec))
+    return prec == GMM_PREC_BF16X3 ? GMM_PATH_ONEPASS_BF16X3 : GMM_PATH_ONEPASS_FP32;
+  return use_wide(D, G) ? GMM_PATH_WIDE_FP64 : GMM_PATH_GENERIC;
+}
+
 hipError_t launch_pre_diag(const float* hefts, const float* means, const float* covs, int D,
                            int G, const Workspace& w, hipStream_t st) {
   hipLaunchKernelGGL(k_pre_diag, dim3(G), dim3(kNT), 0, st, hefts, means, covs, D, G, w.s, w.m,
@@ -687,7 +693,8 @@ hipError_t launch_em_diag(const float* X, int64_t N, int D, int64_t ldx, int G, 
                           float* means, float* covs, float var_floor, int prec,
                           double* mean_loglik, int64_t* n_recomputed, int32_t* dev_status,
                           const Workspace& w, hipStream_t st) {
-  if (em_fast_supported(D, G, prec)) {
+  const int path = em_diag_path(D, G, prec);
+  if (path == GMM_PATH_ONEPASS_BF16X3 || path == GMM_PATH_ONEPASS_FP32) {
     int nb = 0;
     // k_pre_fast clears the status word and the counters
     hipError_t e = launch_em_fast(X, N, D, ldx, G, hefts, means, covs, prec, true, n_recomputed,
@@ -696,7 +703,7 @@ hipError_t launch_em_diag(const float* X, int64_t N, int D, int64_t ldx, int G, 
     return launch_fin_welford(nb, N, D, G, var_floor, hefts, means, covs, mean_loglik,
                               dev_status, w, st);
   }
-  const bool wide = use_wide(D, G);
+  const bool wide = path == GMM_PATH_WIDE_FP64;
   const int T = wide ? kWT : tile_rows(D, G);
   const int nb = partial_blocks(N, 4 * T);
   int64_t chunk = (N + nb - 1) / nb;
@@ -722,7 +729,12 @@ hipError_t launch_em_diag(const float* X, int64_t N, int D, int64_t ldx, int G, 
                                     (const float*)means, w.partials,
                                      w.scalars, (float*)nullptr, dev_status);
   }
-  hipLaunchKernelGGL(k_fin_diag, dim3(G), dim3(kNT), sizeof(double) * (2 * D + 1), st, w.partials,
+  // [2D + 1] FP64 totals: above the 64 KB default for D > 4095
+  const size_t fin_lds = sizeof(double) * (2 * D + 1);
+  if (fin_lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)k_fin_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)fin_lds);
+  hipLaunchKernelGGL(k_fin_diag, dim3(G), dim3(kNT), fin_lds, st, w.partials,
                      nb, N, D, G, var_floor, hefts, means, covs, w.scalars, mean_loglik,
                      dev_status);
   return hipGetLastError();
@@ -747,7 +759,8 @@ hipError_t launch_loglik_diag(const float* X, int64_t N, int D, int64_t ldx, int
                               const float* hefts, const float* means, const float* covs, int prec,
                               double* mean_loglik, float* per_sample, int32_t* dev_status,
                               const Workspace& w, hipStream_t st) {
-  if (em_fast_supported(D, G, prec)) {
+  const int path = em_diag_path(D, G, prec);
+  if (path == GMM_PATH_ONEPASS_BF16X3 || path == GMM_PATH_ONEPASS_FP32) {
     int nb = 0;
     // k_pre_fast clears the status word and the counters
     hipError_t e = launch_em_fast(X, N, D, ldx, G, hefts, means, covs, prec, false, nullptr,
@@ -757,7 +770,7 @@ hipError_t launch_loglik_diag(const float* X, int64_t N, int D, int64_t ldx, int
                        dev_status);
     return hipGetLastError();
   }
-  const bool wide = use_wide(D, G);
+  const bool wide = path == GMM_PATH_WIDE_FP64;
   const int T = wide ? kWT : tile_rows(D, G);
   const int nb = partial_blocks(N, 4 * T);
   int64_t chunk = (N + nb - 1) / nb;

@@ -695,7 +695,12 @@ hipError_t launch_em_full(const float* X, int64_t N, int D, int64_t ldx, int G, 
                        w.Wf64, w.b64, w.c, w.W64, w.c64, means, w.partials, w.scalars, nullptr,
                        dev_status);
   }
-  hipLaunchKernelGGL(k_fin_full, dim3(G), dim3(kNT), sizeof(double) * P, st, w.partials, nb, N, D,
+  // [P] FP64 totals: above the 64 KB default from D = 127 on (67 KB at D = 128)
+  const size_t fin_lds = sizeof(double) * P;
+  if (fin_lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)k_fin_full, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)fin_lds);
+  hipLaunchKernelGGL(k_fin_full, dim3(G), dim3(kNT), fin_lds, st, w.partials, nb, N, D,
                      G, var_floor, hefts, means, covs, w.scalars, mean_loglik, dev_status);
   return hipGetLastError();
 }

@@ -596,6 +596,11 @@ hipError_t launch_loglik_full(const float* X, int64_t N, int D, int64_t ldx, int
                               const Workspace& w, hipStream_t st);
 
 bool km_fast_supported(int D, int G);
+bool km2_supported(int D, int G);
+// kernel family (GMM_PATH_*) of gmm_em_iter / gmm_loglik (diagonal) and of
+// gmm_kmeans_iter; the launchers dispatch on these
+int em_diag_path(int D, int G, int prec);
+int kmeans_path(int D, int G, int prec);
 hipError_t launch_kmeans_fast(const float* X, int64_t N, int D, int64_t ldx, int G, int dist,
                               const double* gvar, float var_floor, float* means, float* dcovs,
                               float* hefts, int64_t* counts, int32_t* assign, double* inertia,

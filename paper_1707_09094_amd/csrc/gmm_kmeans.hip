@@ -744,6 +744,13 @@ void set_max_lds(const void* kern, size_t bytes) {
 
 }  // namespace
 
+int kmeans_path(int D, int G, int prec) {
+  if (km_fast_supported(D, G))
+    return prec == GMM_PREC_BF16X3 && km2_supported(D, G) ? GMM_PATH_ONEPASS_BF16X3
+                                                          : GMM_PATH_ONEPASS_FP32;
+  return km_use_wide(D, G) ? GMM_PATH_WIDE_FP64 : GMM_PATH_GENERIC;
+}
+
 hipError_t launch_kmeans(const float* X, int64_t N, int D, int64_t ldx, int G, int dist,
                          const double* gvar, float var_floor, float* means, float* dcovs,
                          float* hefts, int64_t* counts, int32_t* assign, double* inertia,

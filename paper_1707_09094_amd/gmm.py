@@ -31,6 +31,8 @@ COV_DIAG, COV_FULL = 0, 1
 DIST_EUCL, DIST_MAHA = 0, 1
 ASSIGN_EUCL, ASSIGN_PROB = 0, 1
 PREC_FP32, PREC_BF16X3 = 0, 1
+(PATH_ONEPASS_BF16X3, PATH_ONEPASS_FP32, PATH_WIDE_FP64, PATH_GENERIC, PATH_FULL_FP64,
+ PATH_FULL_GENERIC) = range(1, 7)
 
 
 class GmmError(RuntimeError):
@@ -62,6 +64,8 @@ _SIGS = {
                             _sz, _vp], _i32),
     "gmm_assign": ([_vp, _i64, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                     _vp], _i32),
+    "gmm_em_path": ([_i32, _i32, _i32, _i32], _i32),
+    "gmm_kmeans_path": ([_i32, _i32, _i32], _i32),
     "gmm_profile_enable": ([_i32], _i32),
     "gmm_profile_read": ([_i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)], _i32),
 }
@@ -259,6 +263,22 @@ def gmm_assign(X, mode, hefts, means, dcovs, assign, hist, dev_status, ws, strea
         _ptr(hist, torch.int64, (G,), "hist", optional=True),
         _ptr(dev_status, torch.int32, (1,), "dev_status"), wp, wn, _stream(stream))
     _check("gmm_assign", rc)
+
+
+def gmm_em_path(D, G, cov=COV_DIAG, prec=PREC_FP32):
+    """Kernel family (PATH_*) that gmm_em_iter / gmm_loglik run for this shape."""
+    rc = library().gmm_em_path(int(D), int(G), int(cov), int(prec))
+    if rc < 0:
+        raise GmmError("gmm_em_path", rc)
+    return rc
+
+
+def gmm_kmeans_path(D, G, prec=PREC_FP32):
+    """Kernel family (PATH_*) that gmm_kmeans_iter runs for this shape."""
+    rc = library().gmm_kmeans_path(int(D), int(G), int(prec))
+    if rc < 0:
+        raise GmmError("gmm_kmeans_path", rc)
+    return rc
 
 
 def gmm_profile_enable(on=True):

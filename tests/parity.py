@@ -48,3 +48,41 @@ def check_em(gpu, ref, N, live=None, tol=PARAM_TOL, ll_tol=LOGLIK_TOL, full=Fals
     msg = f"weights {ew:.2e} means {em:.2e} covs {ev:.2e} loglik {el:.2e}"
     assert ew <= tol and em <= tol and ev <= tol and el <= ll_tol, msg
     return dict(weights=ew, means=em, covs=ev, loglik=el)
+
+
+def check_kmeans(gk, rk, dists, N, tol=PARAM_TOL, rel_gap=1e-6):
+    """One k-means step against the oracle's (rk) on the same input means;
+    dists is the oracle's (N, G) distance matrix under those means.
+
+    Assignments are bit-exact wherever the oracle's relative gap between the
+    two nearest means is at least rel_gap; a sample below that gap
+    ("ambiguous") may take any mean of its near set, the means whose distance
+    lies within that relative gap of the nearest.  Clusters that no ambiguous
+    sample can join must then match exactly: counts equal, means/dcovs within
+    tol, weights within 1e-6 (relative to max(w, 1/N)); dead clusters'
+    resurrected means are compared when no sample is ambiguous (the donor
+    depends on the counts).  Inertia within 1e-9 relative, plus rel_gap of
+    the ambiguous samples' own distances.  Returns the number of ambiguous
+    samples."""
+    dmin = dists.min(axis=1)
+    near = (dists - dmin[:, None]) / np.maximum(dmin, 1e-300)[:, None] < rel_gap
+    amb = rk.gap < rel_gap
+    assert np.array_equal(gk["assign"][~amb], rk.assign[~amb])
+    idx = np.nonzero(amb)[0]
+    assert near[idx, gk["assign"][idx]].all(), "an ambiguous sample left its near set"
+    touched = near[idx].any(axis=0) if len(idx) else np.zeros(len(rk.counts), bool)
+    assert np.abs(gk["counts"] - rk.counts).sum() <= 2 * len(idx)
+    free = ~touched
+    np.testing.assert_array_equal(gk["counts"][free], rk.counts[free])
+    live = free & (rk.counts > 0)
+    if live.any():
+        assert rel_means(gk["means"][live], rk.means[live], rk.dcovs[live]).max() <= tol
+        assert rel_vars(gk["dcovs"][live], rk.dcovs[live]).max() <= tol
+    assert rel_weights(gk["hefts"][free], rk.hefts[free], N).max(initial=0) <= 1e-6
+    if not len(idx):
+        dead = rk.counts == 0
+        np.testing.assert_array_equal(gk["means"][dead], rk.means[dead].astype(np.float32))
+    slack = rel_gap * float(dmin[idx].sum())
+    assert abs(gk["inertia"] - rk.inertia) <= 1e-9 * abs(rk.inertia) + 1e-12 + slack, \
+        (gk["inertia"], rk.inertia)
+    return int(len(idx))

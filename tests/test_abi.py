@@ -97,3 +97,27 @@ def test_binding_refuses_host_tensors():
     X = torch.zeros(10, 4)
     with pytest.raises(ValueError):
         gmm._xptr(X)
+
+
+def test_kernel_path_selection():
+    """Which kernel family each shape runs: the one-pass kernels for D, G <= 128
+    (prec picks the arithmetic), the FP64 matrix-core kernels above 128
+    components whatever prec says, the generic ones above 128 dimensions."""
+    P = gmm
+    assert P.gmm_em_path(100, 100, P.COV_DIAG, P.PREC_BF16X3) == P.PATH_ONEPASS_BF16X3
+    assert P.gmm_em_path(100, 100, P.COV_DIAG, P.PREC_FP32) == P.PATH_ONEPASS_FP32
+    for prec in (P.PREC_FP32, P.PREC_BF16X3):
+        assert P.gmm_em_path(64, 512, P.COV_DIAG, prec) == P.PATH_WIDE_FP64
+        assert P.gmm_em_path(100, 300, P.COV_DIAG, prec) == P.PATH_WIDE_FP64
+        assert P.gmm_em_path(200, 5, P.COV_DIAG, prec) == P.PATH_GENERIC
+        assert P.gmm_em_path(32, 64, P.COV_FULL, prec) == P.PATH_FULL_FP64
+        assert P.gmm_em_path(80, 3, P.COV_FULL, prec) == P.PATH_FULL_GENERIC
+        assert P.gmm_kmeans_path(64, 512, prec) == P.PATH_WIDE_FP64
+        assert P.gmm_kmeans_path(300, 3, prec) == P.PATH_GENERIC
+    assert P.gmm_kmeans_path(100, 100, P.PREC_BF16X3) == P.PATH_ONEPASS_BF16X3
+    assert P.gmm_kmeans_path(100, 100, P.PREC_FP32) == P.PATH_ONEPASS_FP32
+    L = P.library()
+    assert L.gmm_em_path(0, 4, 0, 0) == P.GMM_EINVAL
+    assert L.gmm_em_path(4, 4, 0, 5) == P.GMM_EINVAL
+    assert L.gmm_em_path(200, 4, P.COV_FULL, 0) == P.GMM_EINVAL
+    assert L.gmm_kmeans_path(4, 0, 0) == P.GMM_EINVAL

@@ -364,6 +364,32 @@ def test_kmeans_bruteforce(oracle, maha):
     np.testing.assert_allclose(res.gap, (srt[:, 1] - srt[:, 0]) / srt[:, 0], rtol=1e-6, atol=1e-12)
 
 
+@pytest.mark.parametrize("maha", [False, True])
+def test_kmeans_dists_and_near_sets(oracle, maha):
+    """The full distance matrix against scipy's weighted squared distances; its
+    first argmin is the oracle's assignment; the near set of a sample always
+    holds its assigned mean, and holds a second mean exactly when the oracle's
+    relative gap is below the threshold (an exact tie from a duplicated mean)."""
+    rng = _rng(40 + maha)
+    N, D, G = 400, 4, 6
+    X = (rng.normal(size=(N, D)) * [1, 3, 0.5, 2]).astype(np.float32)
+    mu = X[rng.choice(N, G, replace=False)].astype(np.float64)
+    mu[5] = mu[2]  # exact ties for every sample nearest to mean 2
+    X64 = X.astype(np.float64)
+    lam = 1.0 / X64.var(0) if maha else np.ones(D)
+    d = oracle.kmeans_dists(X, mu, lam)
+    ref = cdist(X64 * np.sqrt(lam), mu * np.sqrt(lam), metric="sqeuclidean")
+    np.testing.assert_allclose(d, ref, rtol=1e-12, atol=1e-12)
+    res = oracle.kmeans_iter(X, mu, lam, 1e-10)
+    assert np.array_equal(d.argmin(axis=1), res.assign)
+    dmin = d.min(axis=1, keepdims=True)
+    near = (d - dmin) / np.maximum(dmin, 1e-300) < 1e-6
+    assert near[np.arange(N), res.assign].all()
+    assert np.array_equal(near.sum(axis=1) >= 2, res.gap < 1e-6)
+    tied = res.assign == 2
+    assert tied.any() and near[tied, 5].all() and (res.assign != 5).all()
+
+
 def test_kmeans_single_cluster_closed_form(oracle):
     """N_G = 1: every sample in cluster 0; inertia under the input mean mu0 is
     N * sum_d lam_d (var_d + (mean_d - mu0_d)^2)."""
