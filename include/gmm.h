@@ -180,6 +180,24 @@ int gmm_em_iter(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, in
                 double* mean_loglik, int64_t* n_recomputed, int32_t* dev_status, void* ws,
                 size_t ws_bytes, gmm_stream_t stream);
 
+/* gmm_em_iter for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, validation, kernels and results, without `ws`/`ws_bytes`.
+ * Its scratch space is a static device array of GMM_NOALLOC_SCRATCH_BYTES
+ * (128 MiB) per GPU, held by the library from the first load of its code on
+ * that GPU until the process ends; a shape whose gmm_workspace_bytes exceeds
+ * it (e.g. D = 64, G = 512 at any N) returns GMM_EINVAL and writes nothing.
+ * The call allocates nothing: no hipMalloc/hipFree, no events (profiling is
+ * skipped for it).  Every call on one GPU shares that GPU's array, which keeps
+ * the last call's contents (every call rewrites what it reads first): calls
+ * ordered on one stream are safe, calls that may overlap in time on one GPU
+ * (several streams or host threads) race and give undefined results. */
+#define GMM_NOALLOC_SCRATCH_BYTES (128ull << 20)
+int gmm_em_iter_noalloc(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G,
+                        int32_t cov, float* hefts, float* means, float* covs, float var_floor,
+                        int32_t prec, double* mean_loglik, int64_t* n_recomputed,
+                        int32_t* dev_status, gmm_stream_t stream);
+
 /* Log-likelihood of X under the given parameters (Sec. 4 API).
  *   mean_loglik[1]  out: FP64 average of log p(x_i | lambda)   (avg_log_p(X))
  *   per_sample[N]   out (may be NULL): FP32 log p(x_i | lambda) (log_p(X)) */

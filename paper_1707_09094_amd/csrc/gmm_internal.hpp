@@ -545,6 +545,13 @@ enum ProfKind {
   kProfBatched = GMM_PROF_BATCHED,
 };
 
+// While one of these lives on a thread, ProfScope records nothing there (for
+// entry points that must not create events).
+struct ProfSuppress {
+  ProfSuppress();
+  ~ProfSuppress();
+};
+
 // Records an event pair around its lifetime when profiling is on.
 class ProfScope {
  public:

@@ -27,7 +27,13 @@ int64_t g_n[kProfKinds];
 
 }  // namespace
 
+thread_local int tl_suppress = 0;
+
+ProfSuppress::ProfSuppress() { ++tl_suppress; }
+ProfSuppress::~ProfSuppress() { --tl_suppress; }
+
 ProfScope::ProfScope(int kind, hipStream_t st) : kind_(kind), st_(st), a_(nullptr), b_(nullptr) {
+  if (tl_suppress > 0) return;  // a caller that must not create events
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return;
   if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) {

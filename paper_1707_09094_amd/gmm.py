@@ -64,6 +64,8 @@ _SIGS = {
                             _sz, _vp], _i32),
     "gmm_assign": ([_vp, _i64, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                     _vp], _i32),
+    "gmm_em_iter_noalloc": ([_vp, _i64, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _f32, _i32, _vp,
+                             _vp, _vp, _vp], _i32),
     "gmm_em_path": ([_i32, _i32, _i32, _i32], _i32),
     "gmm_kmeans_path": ([_i32, _i32, _i32], _i32),
     "gmm_profile_enable": ([_i32], _i32),
@@ -203,6 +205,24 @@ def gmm_em_iter(X, cov, hefts, means, covs, var_floor, prec, mean_loglik, n_reco
         _ptr(n_recomputed, torch.int64, (1,), "n_recomputed", optional=True),
         _ptr(dev_status, torch.int32, (1,), "dev_status"), wp, wn, _stream(stream))
     _check("gmm_em_iter", rc)
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def gmm_em_iter_noalloc(X, cov, hefts, means, covs, var_floor, prec, mean_loglik, n_recomputed,
+                        dev_status, stream=None):
+    """gmm_em_iter without a workspace (the library's static per-GPU scratch)."""
+    xp, N, D, ldx = _xptr(X)
+    G = means.shape[0]
+    rc = library().gmm_em_iter_noalloc(
+        xp, N, D, ldx, G, int(cov), _ptr(hefts, torch.float32, (G,), "hefts"),
+        _ptr(means, torch.float32, (G, D), "means"),
+        _ptr(covs, torch.float32, _covshape(cov, G, D), "covs"), float(var_floor), int(prec),
+        _ptr(mean_loglik, torch.float64, (1,), "mean_loglik"),
+        _ptr(n_recomputed, torch.int64, (1,), "n_recomputed", optional=True),
+        _ptr(dev_status, torch.int32, (1,), "dev_status"), _stream(stream))
+    _check("gmm_em_iter_noalloc", rc)
 
 
 def gmm_loglik(X, cov, hefts, means, covs, prec, mean_loglik, per_sample, dev_status, ws,
