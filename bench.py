@@ -4,12 +4,20 @@ One step = one full training pass over the resident synthetic data set:
 global per-dimension statistics, 10 Mahalanobis k-means iterations and 10 EM
 iterations (the paper's speed-up experiment, Sec. 5.1), all through the C ABI.
 The headline value is EM iterations per second of the EM phase inside the
-timed steps; the GPU's other arithmetic form is timed separately on the same
-k-means output, and both forms' final log-likelihoods are compared.
+timed steps.  Both arithmetic forms of the EM iteration are then timed from the
+same saved k-means hand-off and their final log-likelihoods compared.
 
-Prints ONE JSON line (rank 0).  Extra keys: the roofline of the dominant
-kernel (the fused E/M pass) timed live with HIP events recorded by the library
-on the launch stream, and the FP64 CPU oracle timed on this host.
+Prints ONE JSON line (rank 0).  Extra keys:
+  roofline      the dominant kernel (the fused E/M pass) against its roofline,
+                its duration from HIP events the library records on the launch
+                stream; the bound is the slowest phase of the algorithmic work
+                (E-step contraction, M-step accumulation, one read of X)
+  kernels       the other kernels of the step (k-means pass, global statistics)
+  configs       the D=64/G=512/N=8e6 diagonal, D=32/G=64/N=2e6 full-covariance
+                and 2000-model batched workloads, each timed the same way with
+                its own roofline
+  cpu_baseline  the FP64 CPU oracle on this host: all usable cores on the full
+                data set, and one thread on a 100,000-sample slice
 """
 from __future__ import annotations
 
@@ -25,9 +33,12 @@ sys.path.insert(0, ROOT)
 D_, G_, N_ = 100, 100, 1_000_000
 KM_ITERS, EM_ITERS = 10, 10
 VAR_FLOOR = 1e-10
-FP32_VALU_PEAK_TF = 157.3     # MI355X published FP32 vector peak
-BF16_MFMA_PEAK_TF = 2500.0    # MI355X published dense BF16 matrix peak
-FP64_PEAK_TF = 78.6           # MI355X published FP64 peak (matrix and vector alike)
+# MI355X published peaks
+FP32_VALU_TF = 157.3     # FP32 vector
+BF16_MFMA_TF = 2500.0    # dense BF16 matrix
+FP64_TF = 78.6           # FP64 vector and matrix
+HBM_GBS = 8000.0
+CPU_SHARE = 16           # host threads per GPU on this pool
 
 
 def parse():
@@ -39,36 +50,150 @@ def parse():
     p.add_argument("--prec", choices=["fp32", "bf16x3"], default="bf16x3",
                    help="arithmetic form of the timed EM phase (headline)")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--workload", choices=["d100", "d64g512", "full32"], default="d100",
-                   help="d100: the headline workload (default); d64g512: D=64, G=512, N=8e6; "
-                        "full32: full covariances D=32, G=64, N=2e6")
-    p.add_argument("--no-batched", action="store_true",
-                   help="skip the many-model (2000 models, D=40) measurement")
+    p.add_argument("--no-configs", action="store_true",
+                   help="skip the D=64/G=512, full-covariance and batched workloads")
+    p.add_argument("--only", choices=["d64g512", "full32", "batched"], default=None,
+                   help="run one of the other workloads alone (for profiling)")
     p.add_argument("--profile-only", action="store_true",
                    help="run warmup + timed steps only (for rocprofv3)")
     return p.parse_args()
 
 
-def em_flops(N, D, G):
-    # algorithmic count per EM iteration: E-step 4NGD + M-step 4NGD
-    return 8.0 * N * G * D
+def roof(F_E, F_M, nbytes, t_ms, form):
+    """Roofline of one launch from its algorithmic work: E-step contraction F_E
+    and M-step accumulation F_M (flop), nbytes of HBM traffic; form picks the
+    units (bf16x3: E on the BF16 matrix cores, three split products, M on FP32
+    vector ALUs; fp32: both on FP32 vector ALUs; fp64: E on FP64 matrix cores,
+    M on FP64 vector ALUs).  The roof time is the slowest phase; achieved is
+    that phase's algorithmic work over the measured time, frac = roof / time."""
+    t = t_ms / 1e3
+    hbm = ("hbm", nbytes / 1e9, HBM_GBS, "GB/s")
+    if form == "bf16x3":
+        phases = [("mfma", 3 * F_E / 1e12, BF16_MFMA_TF, "TFLOP/s"),
+                  ("alu", F_M / 1e12, FP32_VALU_TF, "TFLOP/s"), hbm]
+    elif form == "fp32":
+        phases = [("alu", (F_E + F_M) / 1e12, FP32_VALU_TF, "TFLOP/s"), hbm]
+    else:
+        phases = [("mfma", F_E / 1e12, FP64_TF, "TFLOP/s"),
+                  ("alu", F_M / 1e12, FP64_TF, "TFLOP/s"), hbm]
+    bound, work, peak, unit = max(phases, key=lambda p: p[1] / p[2])
+    achieved = work / t
+    return {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 4), "roof_ms": round(work / peak * 1e3, 4),
+            "kernel_ms": round(t_ms, 4),
+            "algorithmic_tflops": round((F_E + F_M) / t / 1e12, 3)}
 
 
-def measured_traffic(kernel_src, key_sha="source_sha16", key_f="fetch_bytes", key_w="write_bytes"):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source; else None."""
+def measured_traffic(kernel_src, name):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_em_diag_D100_G100_N1e6.json")
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     try:
         with open(path) as f:
-            rec = json.load(f)
+            rec = json.load(f)[name]
         with open(os.path.join(ROOT, kernel_src), "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    except OSError:
+    except (OSError, KeyError, ValueError):
         return None
-    if rec.get(key_sha) != sha:
+    if rec.get("source_sha16") != sha:
         return None
-    return rec[key_f] + rec[key_w]
+    return rec["fetch_bytes"] + rec["write_bytes"]
+
+
+def ev():
+    import torch
+    e = torch.cuda.Event(enable_timing=True)
+    e.record()
+    return e
+
+
+# ---------------------------------------------------------------- other configs
+def wide_or_full(gmm, synth, torch, which, steps=1, warmup=1):
+    """D=64/G=512/N=8e6 diagonal (d64g512) or D=32/G=64/N=2e6 full covariances
+    (full32), drawn on the device from their recipes; one step = global stats +
+    10 Mahalanobis k-means + 10 EM iterations; kernel times from the library's
+    HIP events."""
+    import numpy as np
+    from paper_1707_09094_amd.train import Model, Trainer
+    dev = "cuda:0"
+    full = which == "full32"
+    if full:
+        N, D, G = 2_000_000, 32, 64
+        Xd = synth.full_gmm_device(synth.seed_for(4), D, G, N, device=dev)
+    else:
+        N, D, G = 8_000_000, 64, 512
+        Xd = synth.diag_gmm_device(synth.seed_for(3), D, G, N, 1.0, 0.05, 5.0, device=dev)
+    idx = torch.as_tensor(synth.static_subset_index(N, G), device=dev)
+    seed_means = Xd[idx].clone()
+    cov = gmm.COV_FULL if full else gmm.COV_DIAG
+    tr = Trainer(Xd, G, cov, gmm.PREC_BF16X3)
+    tr_km = Trainer(Xd, G, gmm.COV_DIAG, gmm.PREC_BF16X3) if full else tr
+
+    def fit():
+        means = seed_means.clone()
+        dcovs = torch.ones(G, D, device=dev)
+        hefts = torch.full((G,), 1.0 / G, device=dev)
+        e0 = ev()
+        tr_km.global_stats()
+        e1 = ev()
+        for _ in range(KM_ITERS):
+            tr_km.kmeans_iter(means, dcovs, hefts, gmm.DIST_MAHA, VAR_FLOOR)
+        e2 = ev()
+        covs = torch.diag_embed(dcovs).contiguous() if full else dcovs
+        model = Model(hefts, means, covs, cov)
+        for _ in range(EM_ITERS):
+            tr.em_iter(model, VAR_FLOOR)
+        e3 = ev()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e3), e1.elapsed_time(e2), e2.elapsed_time(e3), float(
+            tr.scal[1].item())
+
+    for _ in range(warmup):
+        fit()
+    gmm.gmm_profile_enable(True)
+    res = [fit() for _ in range(steps)]
+    em_ms_tot, em_n = gmm.gmm_profile_read(gmm.PROF_EM)
+    ka_ms, ka_n = gmm.gmm_profile_read(gmm.PROF_KM_ASSIGN)
+    kc_ms, kc_n = gmm.gmm_profile_read(gmm.PROF_KM_ACCUM)
+    gmm.gmm_profile_enable(False)
+    step_ms = float(np.mean([r[0] for r in res]))
+    km_ms = float(np.mean([r[1] for r in res])) / KM_ITERS
+    em_ms = float(np.mean([r[2] for r in res])) / EM_ITERS
+    k_em = em_ms_tot / max(em_n, 1)
+    nb = 4.0 * N * D
+    if full:
+        # triangular minimum of the full-covariance contraction (whitening) and
+        # of the rank update, per the survey's count
+        F_E = float(N) * G * (D * (D + 1) + 2 * D)
+        F_M = float(N) * G * (D * (D + 1) + 2 * D)
+        form = "fp64"
+        kernel = "k_estep_full (exact FP64 whitening and rank-update map step, matrix cores)"
+        work = "full-covariance GMM D=32 G=64 N=2e6 (Sigma = A A^T + 0.1 I, A_de ~ N(0, 0.3))"
+    else:
+        F_E = F_M = 4.0 * N * G * D
+        path = gmm.gmm_em_path(D, G, gmm.COV_DIAG, gmm.PREC_BF16X3)
+        form = "bf16x3" if path == gmm.PATH_ONEPASS_BF16X3 else "fp64"
+        kernel = ("k_estep_diag (exact FP64 log-densities on the matrix cores, FP64 map step)"
+                  if form == "fp64" else "BF16x3 screening kernel")
+        work = "diag GMM D=64 G=512 N=8e6 (means N(0,1), variances log-U[0.05,5])"
+    r = roof(F_E, F_M, nb, k_em, form)
+    out = {"workload": work, "N": N, "D": D, "G": G, "steps": steps,
+           "ms_per_step": round(step_ms, 3), "em_iter_ms": round(em_ms, 3),
+           "em_iter_s": round(1e3 / em_ms, 3), "km_iter_ms": round(km_ms, 3),
+           "final_loglik": res[-1][3], "dev_status": int(tr.status.item()),
+           "em_kernel": kernel, "em_form": form, "roofline": r,
+           "km_assign_ms": round(ka_ms / max(ka_n, 1), 4),
+           "km_accum_ms": round(kc_ms / max(kc_n, 1), 4) if kc_n else None,
+           "data": "synthetic, drawn on the device (torch Philox) from the stated recipe"}
+    if not full:
+        # the same kernel serves both arithmetic forms at this shape
+        out["em_path_fp32_form"] = gmm.gmm_em_path(D, G, gmm.COV_DIAG, gmm.PREC_FP32)
+        out["em_path_bf16x3_form"] = gmm.gmm_em_path(D, G, gmm.COV_DIAG, gmm.PREC_BF16X3)
+        out["roofline_vs_bf16x3_form_roof"] = roof(F_E, F_M, nb, k_em, "bf16x3")
+    del Xd, tr, tr_km
+    torch.cuda.empty_cache()
+    return out
 
 
 def batched_workload(gmm, synth, torch, dev, km_iters=KM_ITERS, em_iters=EM_ITERS):
@@ -82,157 +207,109 @@ def batched_workload(gmm, synth, torch, dev, km_iters=KM_ITERS, em_iters=EM_ITER
     import numpy as np
     Ns, Gs = synth.config5_shapes()
     D = 40
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(17079094)
     Xs, inits = [], []
-    for N, G in zip(Ns.tolist(), Gs.tolist()):
-        e = -torch.log(torch.rand(G, device=dev, generator=gen))
-        w = e / e.sum()
-        mu = 2.0 * torch.randn(G, D, device=dev, generator=gen)
-        var = torch.exp(np.log(0.1) + (np.log(10.0) - np.log(0.1)) *
-                        torch.rand(G, D, device=dev, generator=gen))
-        lab = torch.multinomial(w, N, replacement=True, generator=gen)
-        X = (mu[lab] + var[lab].sqrt() * torch.randn(N, D, device=dev, generator=gen)).contiguous()
+    for k, (N, G) in enumerate(zip(Ns.tolist(), Gs.tolist())):
+        X = synth.diag_gmm_device(synth.model5_seed(k) % (1 << 62), D, G, N, 4.0, 0.1, 10.0,
+                                  device=dev)
         Xs.append(X)
-        inits.append(X[(torch.arange(G, device=dev) * N) // G].clone())
+        inits.append(X[torch.as_tensor(synth.static_subset_index(N, G), device=dev)].clone())
     b = gmm.ModelBatch(Xs, Gs.tolist(), device=dev)
     ws = b.workspace(1024)
     chunk = gmm.gmm_batched_autotune(b, gmm.PREC_BF16X3, ws)
     sum_ng = float(np.sum(Ns.astype(np.float64) * Gs))
+    sum_n = float(np.sum(Ns))
 
     def step():
         for m, mu0 in enumerate(inits):
             b.means[m].copy_(mu0)
         gmm.gmm_global_stats_batched(b, b.gmean, b.gvar)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e2 = torch.cuda.Event(enable_timing=True)
-        e0.record()
+        e0 = ev()
         for _ in range(km_iters):
             gmm.gmm_kmeans_iter_batched(b, gmm.DIST_MAHA, VAR_FLOOR, chunk, ws)
-        e1.record()
+        e1 = ev()
         for _ in range(em_iters):
             gmm.gmm_em_iter_batched(b, VAR_FLOOR, gmm.PREC_BF16X3, chunk, ws)
-        e2.record()
+        e2 = ev()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / km_iters, e1.elapsed_time(e2) / em_iters
 
     step()  # warm-up
+    gmm.gmm_profile_enable(True)
     km_ms, em_ms = step()
+    bt_ms, bt_n = gmm.gmm_profile_read(gmm.PROF_BATCHED)
+    gmm.gmm_profile_enable(False)
+    # one batched EM kernel and one batched k-means kernel per iteration: the
+    # EM kernel's share is its phase time minus the per-model reduce
     status = int((b.dev_status != 0).sum().item())
-    return {"models": len(Ns), "D": D, "sum_N": int(Ns.sum()), "sum_NG": sum_ng, "chunk": chunk,
-            "km_iter_ms": round(km_ms, 3), "em_iter_ms": round(em_ms, 3),
-            "em_sample_components_per_s": round(sum_ng / (em_ms / 1e3), 1),
-            "km_sample_components_per_s": round(sum_ng / (km_ms / 1e3), 1),
-            "models_with_status": status,
-            "data": "synthetic, drawn on the device (torch Philox) from the stated recipe"}
+    F = 4.0 * D * sum_ng
+    out = {"workload": "2000 diagonal GMMs, D=40, G_k in {8,16,32,64}, N_k log-U[500,2e5]",
+           "models": len(Ns), "D": D, "sum_N": int(sum_n), "sum_NG": sum_ng, "chunk": chunk,
+           "km_iter_ms": round(km_ms, 3), "em_iter_ms": round(em_ms, 3),
+           "em_sample_components_per_s": round(sum_ng / (em_ms / 1e3), 1),
+           "km_sample_components_per_s": round(sum_ng / (km_ms / 1e3), 1),
+           "batched_kernels_ms_per_launch": round(bt_ms / max(bt_n, 1), 4),
+           "models_with_status": status,
+           # whole EM iteration (batched kernel + constants + reduce) vs the roof
+           "roofline": roof(F, F, 4.0 * D * sum_n, em_ms, "bf16x3"),
+           "data": "synthetic, drawn on the device (torch Philox) from the stated recipe"}
+    del Xs, b, ws
+    torch.cuda.empty_cache()
+    return out
 
 
-def other_workload(args, gmm, synth, torch, np):
-    """D=64/G=512/N=8e6 (diagonal) or full covariances D=32/G=64/N=2e6: one step =
-    global stats + 10 Mahalanobis k-means + 10 EM iterations, timed with HIP events;
-    the same JSON layout as the headline line."""
-    from paper_1707_09094_amd.train import Model, Trainer
-    dev = "cuda:0"
-    full = args.workload == "full32"
-    if full:
-        X, _ = synth.config4(N=args.N if args.N != N_ else 2_000_000)
-        G = 64
-    else:
-        X, _ = synth.config3(N=args.N if args.N != N_ else 8_000_000)
-        G = 512
-    N, D = X.shape
-    Xd = torch.as_tensor(X).to(dev)
-    seed_means = torch.as_tensor(synth.static_subset(X, G)).to(dev)
-    head = gmm.PREC_BF16X3 if args.prec == "bf16x3" else gmm.PREC_FP32
-    cov = gmm.COV_FULL if full else gmm.COV_DIAG
-    tr = Trainer(Xd, G, cov, head)
-    tr_km = Trainer(Xd, G, gmm.COV_DIAG, head) if full else tr
-
-    def fit(em_prec):
-        means = seed_means.clone()
-        dcovs = torch.ones(G, D, device=dev)
-        hefts = torch.full((G,), 1.0 / G, device=dev)
-        tr_km.global_stats()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e2 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(KM_ITERS):
-            tr_km.kmeans_iter(means, dcovs, hefts, gmm.DIST_MAHA, VAR_FLOOR, prec=head)
-        e1.record()
-        covs = torch.diag_embed(dcovs).contiguous() if full else dcovs
-        model = Model(hefts, means, covs, cov)
-        for _ in range(EM_ITERS):
-            tr.em_iter(model, VAR_FLOOR, prec=em_prec)
-        e2.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1), e1.elapsed_time(e2), float(tr.scal[1].item())
-
-    for _ in range(args.warmup):
-        fit(head)
-    kms, ems, lls = [], [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        a, b, ll = fit(head)
-        kms.append(a)
-        ems.append(b)
-        lls.append(ll)
-    wall = time.perf_counter() - t0
-    _, em_fp32, ll32 = fit(gmm.PREC_FP32)
-    em_ms = float(np.mean(ems)) / EM_ITERS
-    # both kernels compute in FP64 (E-step on the matrix cores; map step on the
-    # matrix cores for full covariances, on the FP64 vector ALUs for diagonal
-    # ones), and the two FP64 peaks are equal
-    if full:
-        F = float(N) * G * (2 * D * (D + 1) + 4 * D)
-        work = "full-covariance GMM D=32 G=64 N=2e6 (Sigma = A A^T + 0.1 I, A_de ~ N(0, 0.3))"
-        kernel = ("k_estep_full: exact FP64 log-densities Z = X W^T - W mu and the map step as "
-                  "an FP64 rank update, both on the matrix cores")
-    else:
-        F = em_flops(N, D, G)
-        work = "diag GMM D=64 G=512 N=8e6 (means N(0,1), variances log-U[0.05,5])"
-        kernel = ("k_estep_diag (more than 128 components): exact FP64 log-densities of the "
-                  "expanded form on the matrix cores, FP64 map step on the vector ALUs")
-    achieved = F / (em_ms / 1e3) / 1e12
-    out = {
-        "metric": "EM iter/s", "value": round(1e3 / em_ms, 3), "unit": "EM iter/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(float(np.mean(np.array(kms) + np.array(ems))), 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": work + "; step = global stats + 10 Mahalanobis k-means + 10 EM",
-                   "N": N, "D": D, "G": G, "em_prec": args.prec,
-                   "kernel": kernel},
-        "em_iter_ms": round(em_ms, 3), "km_iter_ms": round(float(np.mean(kms)) / KM_ITERS, 3),
-        "em_iter_ms_fp32_form": round(em_fp32 / EM_ITERS, 3),
-        "final_loglik": lls[-1], "final_loglik_fp32_form": ll32, "wall_s": round(wall, 3),
-        "dev_status": int(tr.status.item()),
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TF,
-                     "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TF, 4),
-                     "traffic": None},
-    }
-    print(json.dumps(out))
+# ---------------------------------------------------------------- CPU oracle
+def host_info():
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return info
 
 
 def cpu_baseline(X, hefts, means, dcovs):
-    """One EM iteration of the FP64 oracle over the full data set on the host."""
+    """The FP64 oracle's EM iteration on this host from the GPU's k-means
+    hand-off: on all usable cores (up to the pool's 16 host threads per GPU)
+    over the full data set, and on one thread over the first 100,000 samples
+    (scaled to the full N)."""
     from oracle import oracle
-    ncpu = os.cpu_count() or 1
-    threads = min(16, ncpu)
+    host = host_info()
+    threads = max(1, min(CPU_SHARE, host.get("affinity", host["nproc"] or 1)))
     oracle.set_threads(threads)
     t0 = time.perf_counter()
     oracle.em_iter(X, hefts, means, dcovs, VAR_FLOOR)
     dt = time.perf_counter() - t0
+    n1 = min(100_000, X.shape[0])
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.em_iter(X[:n1], hefts, means, dcovs, VAR_FLOOR)
+    dt1 = (time.perf_counter() - t0) * X.shape[0] / n1
+    oracle.set_threads(threads)
     return {"value": round(1.0 / dt, 5), "unit": "EM iter/s", "cores": threads, "kind": "oracle",
-            "sample": f"1 EM iteration on the full {X.shape[0]}x{X.shape[1]} data set, G={len(hefts)}"
-                      f" ({dt:.2f} s, FP64, OpenMP {threads} threads)"}
+            "sample": f"1 EM iteration on the full {X.shape[0]}x{X.shape[1]} data set, "
+                      f"G={len(hefts)}, FP64, OpenMP {threads} threads ({dt:.2f} s)",
+            "single_thread": {"value": round(1.0 / dt1, 5), "unit": "EM iter/s", "cores": 1,
+                              "sample": f"1 EM iteration on the first {n1} samples, scaled to "
+                                        f"N={X.shape[0]} ({dt1:.1f} s extrapolated)"},
+            "host": host,
+            "paper_context": "paper, Sec. 5.1: about 27 s for 10 k-means + 10 EM iterations on "
+                             "16 Xeon E5-2620 v4 cores, FP64 (other hardware)"}
 
 
+# ---------------------------------------------------------------- headline
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: the path runs on one GPU (one rank); --gpus must be 1", file=sys.stderr)
+        print("bench.py: this build runs on one GPU (one rank); --gpus must be 1",
+              file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -242,8 +319,12 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    if args.workload != "d100":
-        other_workload(args, gmm, synth, torch, np)
+    if args.only in ("d64g512", "full32"):
+        print(json.dumps(wide_or_full(gmm, synth, torch, args.only, steps=args.steps,
+                                      warmup=args.warmup)))
+        return
+    if args.only == "batched":
+        print(json.dumps(batched_workload(gmm, synth, torch, dev)))
         return
     X, _ = synth.config2(N=args.N)
     N, D = X.shape
@@ -254,51 +335,39 @@ def main():
     tr = Trainer(Xd, G, gmm.COV_DIAG, head)
     torch.cuda.synchronize()
 
-    last_handoff = [None]
-
-    def fit(em_prec, record=False, keep_handoff=False):
+    def fit(em_prec):
         means = seed_means.clone()
         dcovs = torch.ones(G, D, device=dev)
         hefts = torch.full((G,), 1.0 / G, device=dev)
+        e0 = ev()
         tr.global_stats()
+        ek = ev()
         for _ in range(KM_ITERS):
             tr.kmeans_iter(means, dcovs, hefts, gmm.DIST_MAHA, VAR_FLOOR, prec=head)
-        ev_km = torch.cuda.Event(enable_timing=True)
-        ev_km.record()
-        if keep_handoff:
-            last_handoff[0] = (hefts.cpu().numpy(), means.cpu().numpy(), dcovs.cpu().numpy())
+        e1 = ev()
+        handoff = (hefts.clone(), means.clone(), dcovs.clone())
         model = Model(hefts, means, dcovs, gmm.COV_DIAG)
-        lls = []
         for _ in range(EM_ITERS):
             tr.em_iter(model, VAR_FLOOR, prec=em_prec)
-            if record:
-                lls.append(tr.scal[1].clone())
-        ev_em = torch.cuda.Event(enable_timing=True)
-        ev_em.record()
-        return ev_km, ev_em, model, lls
+        e2 = ev()
+        return e0, ek, e1, e2, handoff
 
     for _ in range(args.warmup):
         fit(head)
     torch.cuda.synchronize()
 
     gmm.gmm_profile_enable(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record()
-    marks = []
-    for _ in range(args.steps):
-        start = torch.cuda.Event(enable_timing=True)
-        start.record()
-        ev_km, ev_em, model, _ = fit(head)
-        marks.append((start, ev_km, ev_em))
+    marks = [fit(head)[:4] for _ in range(args.steps)]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     em_ms_tot, em_launches = gmm.gmm_profile_read(gmm.PROF_EM)
     km_ms_tot, km_launches = gmm.gmm_profile_read(gmm.PROF_KM_ASSIGN)
+    st_ms_tot, st_launches = gmm.gmm_profile_read(gmm.PROF_STATS)
     gmm.gmm_profile_enable(False)
-    step_ms = [s.elapsed_time(e) for s, _, e in marks]
-    em_phase_ms = [k.elapsed_time(e) for _, k, e in marks]
+    step_ms = [a.elapsed_time(d) for a, _, _, d in marks]
+    em_phase_ms = [c.elapsed_time(d) for _, _, c, d in marks]
+    km_phase_ms = [b.elapsed_time(c) for _, b, c, _ in marks]
     if args.profile_only:
         # calibration for HBM byte counters: one plain device copy of 256 MiB
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -313,49 +382,63 @@ def main():
     ms_per_step = float(np.mean(step_ms))
     status = int(tr.status.item())
 
-    # the two arithmetic forms from the same k-means output
+    # the two arithmetic forms, each timed over EM_ITERS iterations from the
+    # same saved k-means hand-off
+    *_, handoff = fit(head)
+    torch.cuda.synchronize()
     forms = {}
-    handoff = None
     for name, pr in (("fp32", gmm.PREC_FP32), ("bf16x3", gmm.PREC_BF16X3)):
-        _, _, m, lls = fit(pr, record=True, keep_handoff=handoff is None)
-        if handoff is None:
-            handoff = last_handoff[0]
+        model = Model(*(t.clone() for t in handoff), gmm.COV_DIAG)
+        tr.em_iter(model, VAR_FLOOR, prec=pr)  # first iteration: recompute count
         torch.cuda.synchronize()
-        ev_a = torch.cuda.Event(enable_timing=True)
-        ev_b = torch.cuda.Event(enable_timing=True)
-        # time EM_ITERS iterations of this form from a copy of the hand-off
-        mm = Model(m.hefts.clone(), m.means.clone(), m.covs.clone(), gmm.COV_DIAG)
-        ev_a.record()
+        nrec_first = int(tr.i64[1].item())
+        model = Model(*(t.clone() for t in handoff), gmm.COV_DIAG)
+        torch.cuda.synchronize()
+        a = ev()
+        lls = []
         for _ in range(EM_ITERS):
-            tr.em_iter(mm, VAR_FLOOR, prec=pr)
-        ev_b.record()
+            tr.em_iter(model, VAR_FLOOR, prec=pr)
+            lls.append(tr.scal[1].clone())
+        b = ev()
         torch.cuda.synchronize()
-        forms[name] = {"em_iter_s": EM_ITERS / (ev_a.elapsed_time(ev_b) / 1e3),
-                       "final_loglik": float(lls[-1].item()),
-                       "em_recomputed": int(tr.i64[1].item())}
+        # the log-likelihood of the final parameters
+        final = float(tr.loglik(model, prec=pr).item())
+        torch.cuda.synchronize()
+        forms[name] = {"em_iter_s": EM_ITERS / (a.elapsed_time(b) / 1e3),
+                       "final_loglik": final, "last_iter_loglik": float(lls[-1].item()),
+                       "em_recomputed_first_iter": nrec_first}
     dl = abs(forms["bf16x3"]["final_loglik"] - forms["fp32"]["final_loglik"]) / abs(
         forms["fp32"]["final_loglik"])
 
-    F = em_flops(N, D, G)
+    F_E = F_M = 4.0 * N * G * D
     em_kernel_ms = em_ms_tot / max(em_launches, 1)
-    achieved_tf = F / (em_kernel_ms / 1e3) / 1e12
-    if head == gmm.PREC_BF16X3:
-        # E-step contraction on the BF16 matrix cores (algorithmic 4NGD at the
-        # dense BF16 peak) + M-step map on FP32 vector ALUs (4NGD at the FP32
-        # peak): the shortest possible time of the algorithmic work.
-        t_min = 4.0 * N * G * D / (BF16_MFMA_PEAK_TF * 1e12) + 4.0 * N * G * D / (FP32_VALU_PEAK_TF * 1e12)
-        peak = F / t_min / 1e12
-        bound = "mfma"
-    else:
-        peak = FP32_VALU_PEAK_TF
-        bound = "alu"
-    traffic = measured_traffic("paper_1707_09094_amd/csrc/gmm_em_fast.hip") if N == N_ else None
-    roof = {"bound": bound, "achieved": round(achieved_tf, 3), "peak": round(peak, 2),
-            "unit": "TFLOP/s", "frac": round(achieved_tf / peak, 4),
-            "traffic": None if traffic is None else round(traffic),
-            "kernel": "k_em2 (fused E-step + M-step map, sample-major BF16x3 MFMA)"
-                      if head == gmm.PREC_BF16X3 else "k_em_fast (fused E-step + M-step map, FP32)",
-            "kernel_ms": round(em_kernel_ms, 4), "launches": em_launches}
+    form = "bf16x3" if head == gmm.PREC_BF16X3 else "fp32"
+    r = roof(F_E, F_M, 4.0 * N * D, em_kernel_ms, form)
+    src = "paper_1707_09094_amd/csrc/gmm_em_fast.hip"
+    traffic = measured_traffic(src, "k_em2" if form == "bf16x3" else "k_em_fast") \
+        if N == N_ else None
+    roofline = {k: r[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+    roofline["traffic"] = None if traffic is None else round(traffic)
+    roofline.update({
+        "kernel": "k_em2 (fused E-step + M-step map, sample-major BF16x3 MFMA)"
+                  if form == "bf16x3" else "k_em_fast (fused E-step + M-step map, FP32)",
+        "kernel_ms": r["kernel_ms"], "roof_ms": r["roof_ms"], "launches": em_launches,
+        "algorithmic_tflops": r["algorithmic_tflops"],
+        "per_unit": f"one sample against G={G} components: E 4GD + M 4GD flop, 4D bytes; "
+                    f"a launch processes all N={N} samples"})
+    km_kernel_ms = km_ms_tot / max(km_launches, 1)
+    st_kernel_ms = st_ms_tot / max(st_launches, 1)
+    kernels = {
+        "k_km2": {"ms": round(km_kernel_ms, 4), "bound": "hbm",
+                  "achieved_GBs": round(4.0 * N * D / (km_kernel_ms / 1e3) / 1e9, 1),
+                  "peak_GBs": HBM_GBS,
+                  "frac": round(4.0 * N * D / (km_kernel_ms / 1e3) / 1e9 / HBM_GBS, 4),
+                  "algorithmic_tflops": round(3.0 * N * G * D / (km_kernel_ms / 1e3) / 1e12, 3)},
+        "global_stats": {"ms": round(st_kernel_ms, 4), "bound": "hbm",
+                         "achieved_GBs": round(4.0 * N * D / (st_kernel_ms / 1e3) / 1e9, 1),
+                         "peak_GBs": HBM_GBS,
+                         "frac": round(4.0 * N * D / (st_kernel_ms / 1e3) / 1e9 / HBM_GBS, 4)},
+    }
 
     out = {
         "metric": "EM iter/s & GFLOP/s at D=100 N_G=100 N=1e6; BF16-MFMA vs FP32 at equal loglik",
@@ -374,25 +457,29 @@ def main():
                                "log-U[0.1,10], Dirichlet(1) weights); step = global stats + 10 "
                                "Mahalanobis k-means + 10 EM iterations",
                    "N": N, "D": D, "G": G, "em_prec": args.prec},
-        "gflops": round(F * em_iter_s / 1e9, 1),
+        "gflops": round((F_E + F_M) * em_iter_s / 1e9, 1),
         "em_iter_s_fp32": round(forms["fp32"]["em_iter_s"], 3),
         "em_iter_s_bf16x3": round(forms["bf16x3"]["em_iter_s"], 3),
         "bf16x3_speedup": round(forms["bf16x3"]["em_iter_s"] / forms["fp32"]["em_iter_s"], 3),
         "final_loglik_fp32": forms["fp32"]["final_loglik"],
+        "final_loglik_bf16x3": forms["bf16x3"]["final_loglik"],
         "final_loglik_rel_delta": dl,
-        "em_recomputed_bf16x3": forms["bf16x3"]["em_recomputed"],
-        "km_assign_ms": round(km_ms_tot / max(km_launches, 1), 4),
+        "em_recomputed_bf16x3_first_iter": forms["bf16x3"]["em_recomputed_first_iter"],
+        "km_iter_ms": round(float(np.mean(km_phase_ms)) / KM_ITERS, 4),
         "wall_s": round(wall, 3),
         "dev_status": status,
-        "roofline": roof,
+        "roofline": roofline,
+        "kernels": kernels,
     }
-    if not args.no_batched:
-        del Xd, tr
-        torch.cuda.empty_cache()
-        out["batched"] = batched_workload(gmm, synth, torch, dev)
+    del Xd, tr
+    torch.cuda.empty_cache()
+    if not args.no_configs:
+        out["configs"] = {"d64g512": wide_or_full(gmm, synth, torch, "d64g512"),
+                          "full32": wide_or_full(gmm, synth, torch, "full32"),
+                          "batched": batched_workload(gmm, synth, torch, dev)}
     if not args.no_cpu_baseline:
-        # the CPU oracle runs one EM iteration from the GPU's k-means hand-off
-        out["cpu_baseline"] = cpu_baseline(X, *handoff)
+        h = [t.cpu().numpy() for t in handoff]
+        out["cpu_baseline"] = cpu_baseline(X, *h)
     print(json.dumps(out))
 
 

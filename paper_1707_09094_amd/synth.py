@@ -138,6 +138,59 @@ def fig1_recipe(N=10_000, d=5, seed=seed_for(0)):
     return X, Truth(np.array([2 / 3, 1 / 3]), np.stack([m1, m2]), np.ones((2, d)), None, lab)
 
 
+# --- the same recipes drawn on the device (torch Philox), for data sets too
+# large to draw on the host inside a benchmark run ---------------------------
+
+def diag_gmm_device(seed, D, G, N, mean_var, var_lo, var_hi, device="cuda"):
+    """Device twin of diag_gmm(seed, D, G, N, "normal", 0, mean_var, "loguniform",
+    var_lo, var_hi): the same recipe and generation order (weights, means,
+    variances, labels, noise) with torch's generator, so a different draw."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    e = -torch.log(torch.rand(G, device=device, generator=gen, dtype=torch.float64))
+    w = e / e.sum()
+    mu = float(np.sqrt(mean_var)) * torch.randn(G, D, device=device, generator=gen,
+                                                dtype=torch.float64)
+    lv = np.log(var_lo) + (np.log(var_hi) - np.log(var_lo)) * torch.rand(
+        G, D, device=device, generator=gen, dtype=torch.float64)
+    sd = torch.exp(0.5 * lv)
+    lab = torch.multinomial(w, N, replacement=True, generator=gen)
+    X = torch.empty(N, D, device=device, dtype=torch.float32)
+    for s in range(0, N, CHUNK):
+        e_ = min(N, s + CHUNK)
+        z = torch.randn(e_ - s, D, device=device, generator=gen, dtype=torch.float64)
+        X[s:e_] = (mu[lab[s:e_]] + sd[lab[s:e_]] * z).to(torch.float32)
+    return X
+
+
+def full_gmm_device(seed, D, G, N, mean_var=4.0, a_var=0.3, ridge=0.1, device="cuda"):
+    """Device twin of full_gmm: Sigma_g = A A^T + ridge I, A_de ~ N(0, a_var)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    e = -torch.log(torch.rand(G, device=device, generator=gen, dtype=torch.float64))
+    w = e / e.sum()
+    mu = float(np.sqrt(mean_var)) * torch.randn(G, D, device=device, generator=gen,
+                                                dtype=torch.float64)
+    A = float(np.sqrt(a_var)) * torch.randn(G, D, D, device=device, generator=gen,
+                                            dtype=torch.float64)
+    S = A @ A.transpose(1, 2) + ridge * torch.eye(D, device=device, dtype=torch.float64)
+    Lc = torch.linalg.cholesky(S)
+    lab = torch.multinomial(w, N, replacement=True, generator=gen)
+    X = torch.empty(N, D, device=device, dtype=torch.float32)
+    for s in range(0, N, CHUNK):
+        e_ = min(N, s + CHUNK)
+        z = torch.randn(e_ - s, D, 1, device=device, generator=gen, dtype=torch.float64)
+        X[s:e_] = (mu[lab[s:e_]] + (Lc[lab[s:e_]] @ z)[..., 0]).to(torch.float32)
+    return X
+
+
+def static_subset_index(N, G):
+    """Indices floor(g*N/G), g = 0..G-1, of the static_subset seed mode."""
+    return (np.arange(G, dtype=np.int64) * N) // G
+
+
 def static_subset(X, G):
     """Initial means = samples floor(g*N/G), g = 0..G-1 (a repeatable subset of
     the training samples, the static_subset seed mode)."""
