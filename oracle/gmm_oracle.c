@@ -27,8 +27,9 @@
  * sequential loop over samples i = 0..N-1.  Results are therefore bit-identical
  * for any thread count.
  *
- * Data layout (Sec. 4 API: one sample per column): X is D x N column-major
- * float32, sample i at X + i*ldx.  Samples are promoted exactly to double.
+ * Data layout (Sec. 4 API: one sample per column): X is D x N column-major,
+ * sample i at X + i*ldx, float32 (oracle_*) or float64 (oracle_*_f64, the
+ * gmm_diag precision); float32 samples are promoted exactly to double.
  * Parameters are double: hefts[G], means[g*D + d], dcovs[g*D + d] (diagonal),
  * covs[g*D*D + e*D + d] (full, column-major per component).
  */
@@ -60,8 +61,19 @@ int oracle_get_threads(void) {
 #define NTHR (g_threads > 0 ? g_threads : omp_get_max_threads())
 #endif
 
-static inline double xval(const float* X, int64_t ldx, int64_t i, int d) {
-  return (double)X[i * ldx + d];
+/* Samples are FP32 (the fgmm_diag precision, Sec. 4) or FP64 (gmm_diag, and
+ * the precision of the speed-up experiment, Sec. 5.1).  FP32 values are
+ * promoted exactly to double where they are read, so every computation below
+ * is the same FP64 arithmetic for both, and FP32 data given as FP64 gives
+ * bit-identical results. */
+typedef struct {
+  const float* f;  /* FP32 samples, or NULL */
+  const double* d; /* FP64 samples when f is NULL */
+  int64_t ldx;
+} samples_t;
+
+static inline double xval(const samples_t* S, int64_t i, int d) {
+  return S->f ? (double)S->f[i * S->ldx + d] : S->d[i * S->ldx + d];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -76,12 +88,21 @@ static double log_det_diag(const double* s2, int D) {
   return logdet;
 }
 
-static double log_gauss_diag(const float* x, const double* mu, const double* s2, double logdet,
-                             int D) {
+static double log_gauss_diag(const samples_t* S, int64_t i, const double* mu, const double* s2,
+                             double logdet, int D) {
   double maha = 0.0;
-  for (int d = 0; d < D; ++d) {
-    double t = (double)x[d] - mu[d];
-    maha += t * t / s2[d];
+  if (S->f) {
+    const float* x = S->f + i * S->ldx;
+    for (int d = 0; d < D; ++d) {
+      double t = (double)x[d] - mu[d];
+      maha += t * t / s2[d];
+    }
+  } else {
+    const double* x = S->d + i * S->ldx;
+    for (int d = 0; d < D; ++d) {
+      double t = x[d] - mu[d];
+      maha += t * t / s2[d];
+    }
   }
   return -0.5 * ((double)D * LOG_2PI + logdet) - 0.5 * maha;
 }
@@ -107,11 +128,11 @@ static int cholesky(const double* S, double* L, int D) {
 
 /* Full covariance Eq. 15 with log|Sigma| = 2 sum log L_dd and the Mahalanobis
  * term as ||z||^2, L z = x - mu (forward substitution). */
-static double log_gauss_full(const float* x, const double* mu, const double* L, double logdet,
-                             int D, double* z) {
+static double log_gauss_full(const samples_t* S, int64_t i, const double* mu, const double* L,
+                             double logdet, int D, double* z) {
   double maha = 0.0;
   for (int d = 0; d < D; ++d) {
-    double t = (double)x[d] - mu[d];
+    double t = xval(S, i, d) - mu[d];
     for (int k = 0; k < d; ++k) t -= L[k * D + d] * z[k];
     z[d] = t / L[d * D + d];
     maha += z[d] * z[d];
@@ -135,7 +156,7 @@ static double log_sum_exp(const double* a, int G) {
 /* E-step: a[i*G+g] = log w_g + log N(x_i | g), lse[i] = log p(x_i | lambda). */
 /* ------------------------------------------------------------------------ */
 
-static int estep_diag(const float* X, int64_t N, int D, int64_t ldx, int G, const double* hefts,
+static int estep_diag(const samples_t* S, int64_t N, int D, int G, const double* hefts,
                       const double* means, const double* dcovs, double* a, double* lse) {
   double* logdet = (double*)malloc(sizeof(double) * G);
   if (!logdet) return ORC_ENOMEM;
@@ -144,7 +165,7 @@ static int estep_diag(const float* X, int64_t N, int D, int64_t ldx, int G, cons
   for (int64_t i = 0; i < N; ++i) {
     double* ai = a + i * G;
     for (int g = 0; g < G; ++g)
-      ai[g] = log(hefts[g]) + log_gauss_diag(X + i * ldx, means + (size_t)g * D,
+      ai[g] = log(hefts[g]) + log_gauss_diag(S, i, means + (size_t)g * D,
                                              dcovs + (size_t)g * D, logdet[g], D);
     lse[i] = log_sum_exp(ai, G);
   }
@@ -152,7 +173,7 @@ static int estep_diag(const float* X, int64_t N, int D, int64_t ldx, int G, cons
   return 0;
 }
 
-static int estep_full(const float* X, int64_t N, int D, int64_t ldx, int G, const double* hefts,
+static int estep_full(const samples_t* S, int64_t N, int D, int G, const double* hefts,
                       const double* means, const double* covs, double* a, double* lse) {
   size_t DD = (size_t)D * D;
   double* L = (double*)malloc(sizeof(double) * DD * G);
@@ -179,7 +200,7 @@ static int estep_full(const float* X, int64_t N, int D, int64_t ldx, int G, cons
       for (int64_t i = 0; i < N; ++i) {
         double* ai = a + i * G;
         for (int g = 0; g < G; ++g)
-          ai[g] = log(hefts[g]) + log_gauss_full(X + i * ldx, means + (size_t)g * D, L + DD * g,
+          ai[g] = log(hefts[g]) + log_gauss_full(S, i, means + (size_t)g * D, L + DD * g,
                                                  logdet[g], D, z);
         lse[i] = log_sum_exp(ai, G);
       }
@@ -201,10 +222,10 @@ static double mean_of(const double* v, int64_t N) {
 /* Public: log-likelihood (Sec. 4 API: log_p(X) per sample, avg_log_p(X)).   */
 /* ------------------------------------------------------------------------ */
 
-int oracle_loglik(const float* X, int64_t N, int D, int64_t ldx, int G, int full,
+static int loglik_s(const samples_t* S, int64_t N, int D, int G, int full,
                   const double* hefts, const double* means, const double* covs,
                   double* mean_loglik, double* per_sample /* N or NULL */) {
-  if (N < 1 || D < 1 || G < 1 || ldx < D) return ORC_EINVAL;
+  if (N < 1 || D < 1 || G < 1 || S->ldx < D) return ORC_EINVAL;
   double* a = (double*)malloc(sizeof(double) * (size_t)N * G);
   double* lse = (double*)malloc(sizeof(double) * (size_t)N);
   if (!a || !lse) {
@@ -212,8 +233,8 @@ int oracle_loglik(const float* X, int64_t N, int D, int64_t ldx, int G, int full
     free(lse);
     return ORC_ENOMEM;
   }
-  int rc = full ? estep_full(X, N, D, ldx, G, hefts, means, covs, a, lse)
-                : estep_diag(X, N, D, ldx, G, hefts, means, covs, a, lse);
+  int rc = full ? estep_full(S, N, D, G, hefts, means, covs, a, lse)
+                : estep_diag(S, N, D, G, hefts, means, covs, a, lse);
   if (rc == 0) {
     *mean_loglik = mean_of(lse, N);
     if (per_sample) memcpy(per_sample, lse, sizeof(double) * (size_t)N);
@@ -226,13 +247,13 @@ int oracle_loglik(const float* X, int64_t N, int D, int64_t ldx, int G, int full
 
 /* Per-Gaussian log-likelihood log N(x_i | g) without the weight
  * (Sec. 4 API: log_p(X, g)). */
-int oracle_log_p_g(const float* X, int64_t N, int D, int64_t ldx, int G, const double* means,
+static int log_p_g_s(const samples_t* S, int64_t N, int D, int G, const double* means,
                    const double* dcovs, int g, double* out /* N */) {
-  if (N < 1 || D < 1 || G < 1 || ldx < D || g < 0 || g >= G) return ORC_EINVAL;
+  if (N < 1 || D < 1 || G < 1 || S->ldx < D || g < 0 || g >= G) return ORC_EINVAL;
   double logdet = log_det_diag(dcovs + (size_t)g * D, D);
 #pragma omp parallel for schedule(static) num_threads(NTHR)
   for (int64_t i = 0; i < N; ++i)
-    out[i] = log_gauss_diag(X + i * ldx, means + (size_t)g * D, dcovs + (size_t)g * D, logdet, D);
+    out[i] = log_gauss_diag(S, i, means + (size_t)g * D, dcovs + (size_t)g * D, logdet, D);
   return 0;
 }
 
@@ -245,22 +266,21 @@ int oracle_log_p_g(const float* X, int64_t N, int D, int64_t ldx, int G, const d
  * meaning lam_d = 1 (Euclidean), each term lam_d * (u * u) added in order
  * d = 0..D-1.  idx_out[G] receives the chosen sample indices, means_out[G*D]
  * their coordinates. */
-int oracle_seed_spread(const float* X, int64_t N, int D, int64_t ldx, int G, const double* lam,
+static int seed_spread_s(const samples_t* S, int64_t N, int D, int G, const double* lam,
                        int64_t first, int64_t* idx_out, double* means_out) {
-  if (N < 1 || D < 1 || G < 1 || ldx < D || first < 0 || first >= N) return ORC_EINVAL;
+  if (N < 1 || D < 1 || G < 1 || S->ldx < D || first < 0 || first >= N) return ORC_EINVAL;
   double* dmin = (double*)malloc(sizeof(double) * (size_t)N);
   if (!dmin) return ORC_ENOMEM;
   int64_t s = first;
   for (int k = 0; k < G; ++k) {
-    const float* y = X + s * ldx;
     idx_out[k] = s;
-    for (int d = 0; d < D; ++d) means_out[(size_t)k * D + d] = (double)y[d];
+    for (int d = 0; d < D; ++d) means_out[(size_t)k * D + d] = xval(S, s, d);
+    const double* y = means_out + (size_t)k * D;
 #pragma omp parallel for schedule(static) num_threads(NTHR)
     for (int64_t i = 0; i < N; ++i) {
-      const float* x = X + i * ldx;
       double q = 0.0;
       for (int d = 0; d < D; ++d) {
-        const double u = (double)x[d] - (double)y[d];
+        const double u = xval(S, i, d) - y[d];
         q += (lam ? lam[d] : 1.0) * (u * u);
       }
       dmin[i] = (k == 0 || q < dmin[i]) ? q : dmin[i];
@@ -279,14 +299,14 @@ int oracle_seed_spread(const float* X, int64_t N, int D, int64_t ldx, int G, con
 }
 
 /* Responsibilities l_{g,i} (Sec. 2, Eq. 3), exposed for tests: out[i*G+g]. */
-int oracle_responsibilities(const float* X, int64_t N, int D, int64_t ldx, int G, int full,
+static int responsibilities_s(const samples_t* S, int64_t N, int D, int G, int full,
                             const double* hefts, const double* means, const double* covs,
                             double* out) {
-  if (N < 1 || D < 1 || G < 1 || ldx < D) return ORC_EINVAL;
+  if (N < 1 || D < 1 || G < 1 || S->ldx < D) return ORC_EINVAL;
   double* lse = (double*)malloc(sizeof(double) * (size_t)N);
   if (!lse) return ORC_ENOMEM;
-  int rc = full ? estep_full(X, N, D, ldx, G, hefts, means, covs, out, lse)
-                : estep_diag(X, N, D, ldx, G, hefts, means, covs, out, lse);
+  int rc = full ? estep_full(S, N, D, G, hefts, means, covs, out, lse)
+                : estep_diag(S, N, D, G, hefts, means, covs, out, lse);
   if (rc == 0) {
 #pragma omp parallel for schedule(static) num_threads(NTHR)
     for (int64_t i = 0; i < N; ++i)
@@ -306,11 +326,11 @@ int oracle_responsibilities(const float* X, int64_t N, int D, int64_t ldx, int G
 /* returns L_g.                                                               */
 /* ------------------------------------------------------------------------ */
 
-int oracle_em_iter(const float* X, int64_t N, int D, int64_t ldx, int G, int full,
+static int em_iter_s(const samples_t* S, int64_t N, int D, int G, int full,
                    const double* hefts, const double* means, const double* covs, double var_floor,
                    double* hefts_out, double* means_out, double* covs_out, double* mean_loglik,
                    double* L_out) {
-  if (N < 1 || D < 1 || G < 1 || ldx < D) return ORC_EINVAL;
+  if (N < 1 || D < 1 || G < 1 || S->ldx < D) return ORC_EINVAL;
   size_t csz = full ? (size_t)D * D : (size_t)D;
   double* l = (double*)malloc(sizeof(double) * (size_t)N * G);
   double* lse = (double*)malloc(sizeof(double) * (size_t)N);
@@ -319,8 +339,8 @@ int oracle_em_iter(const float* X, int64_t N, int D, int64_t ldx, int G, int ful
     free(lse);
     return ORC_ENOMEM;
   }
-  int rc = full ? estep_full(X, N, D, ldx, G, hefts, means, covs, l, lse)
-                : estep_diag(X, N, D, ldx, G, hefts, means, covs, l, lse);
+  int rc = full ? estep_full(S, N, D, G, hefts, means, covs, l, lse)
+                : estep_diag(S, N, D, G, hefts, means, covs, l, lse);
   if (rc != 0) {
     free(l);
     free(lse);
@@ -356,7 +376,7 @@ int oracle_em_iter(const float* X, int64_t N, int D, int64_t ldx, int G, int ful
     for (int d = 0; d < D; ++d) s[d] = 0.0;
     for (int64_t i = 0; i < N; ++i) {
       double li = l[i * G + g];
-      for (int d = 0; d < D; ++d) s[d] += xval(X, ldx, i, d) * li;
+      for (int d = 0; d < D; ++d) s[d] += xval(S, i, d) * li;
     }
     for (int d = 0; d < D; ++d) mu[d] = s[d] / Lg;
     /* Eq. 7, centred on the new mean; second pass over the samples. */
@@ -365,7 +385,7 @@ int oracle_em_iter(const float* X, int64_t N, int D, int64_t ldx, int G, int ful
       for (int64_t i = 0; i < N; ++i) {
         double li = l[i * G + g];
         for (int d = 0; d < D; ++d) {
-          double t = xval(X, ldx, i, d) - mu[d];
+          double t = xval(S, i, d) - mu[d];
           s[d] += t * t * li;
         }
       }
@@ -378,9 +398,9 @@ int oracle_em_iter(const float* X, int64_t N, int D, int64_t ldx, int G, int ful
       for (int64_t i = 0; i < N; ++i) {
         double li = l[i * G + g];
         for (int e = 0; e < D; ++e) {
-          double te = xval(X, ldx, i, e) - mu[e];
+          double te = xval(S, i, e) - mu[e];
           for (int d = e; d < D; ++d)
-            s[(size_t)e * D + d] += (xval(X, ldx, i, d) - mu[d]) * te * li;
+            s[(size_t)e * D + d] += (xval(S, i, d) - mu[d]) * te * li;
         }
       }
       for (int e = 0; e < D; ++e)
@@ -406,19 +426,19 @@ int oracle_em_iter(const float* X, int64_t N, int D, int64_t ldx, int G, int ful
 /* Population variance (divide by N), two-pass.                              */
 /* ------------------------------------------------------------------------ */
 
-int oracle_global_stats(const float* X, int64_t N, int D, int64_t ldx, double* mean,
+static int global_stats_s(const samples_t* S, int64_t N, int D, double* mean,
                         double* var) {
-  if (N < 1 || D < 1 || ldx < D) return ORC_EINVAL;
+  if (N < 1 || D < 1 || S->ldx < D) return ORC_EINVAL;
   /* Sequential sums over i for each dimension; the sample loop is outermost so
      memory is read in order. */
   for (int d = 0; d < D; ++d) mean[d] = 0.0;
   for (int64_t i = 0; i < N; ++i)
-    for (int d = 0; d < D; ++d) mean[d] += xval(X, ldx, i, d);
+    for (int d = 0; d < D; ++d) mean[d] += xval(S, i, d);
   for (int d = 0; d < D; ++d) mean[d] /= (double)N;
   for (int d = 0; d < D; ++d) var[d] = 0.0;
   for (int64_t i = 0; i < N; ++i)
     for (int d = 0; d < D; ++d) {
-      double t = xval(X, ldx, i, d) - mean[d];
+      double t = xval(S, i, d) - mean[d];
       var[d] += t * t;
     }
   for (int d = 0; d < D; ++d) var[d] /= (double)N;
@@ -450,11 +470,11 @@ int oracle_global_stats(const float* X, int64_t N, int D, int64_t ldx, double* m
 /* the best and second-best distance (+inf when G == 1).                      */
 /* ------------------------------------------------------------------------ */
 
-int oracle_kmeans_iter(const float* X, int64_t N, int D, int64_t ldx, int G, const double* lam,
+static int kmeans_iter_s(const samples_t* S, int64_t N, int D, int G, const double* lam,
                        const double* means, double var_floor, double* means_out,
                        double* dcovs_out, double* hefts_out, int64_t* counts_out,
                        int32_t* assign_out, double* inertia, double* gap /* N or NULL */) {
-  if (N < 1 || D < 1 || G < 1 || ldx < D) return ORC_EINVAL;
+  if (N < 1 || D < 1 || G < 1 || S->ldx < D) return ORC_EINVAL;
   double* best = (double*)malloc(sizeof(double) * (size_t)N);
   int64_t* rem = (int64_t*)malloc(sizeof(int64_t) * (size_t)G);
   int64_t* taken = (int64_t*)calloc((size_t)G, sizeof(int64_t));
@@ -473,7 +493,7 @@ int oracle_kmeans_iter(const float* X, int64_t N, int D, int64_t ldx, int G, con
     for (int g = 0; g < G; ++g) {
       double s = 0.0;
       for (int d = 0; d < D; ++d) {
-        double t = xval(X, ldx, i, d) - means[(size_t)g * D + d];
+        double t = xval(S, i, d) - means[(size_t)g * D + d];
         s += lam[d] * t * t;
       }
       if (s < d1) {
@@ -513,13 +533,13 @@ int oracle_kmeans_iter(const float* X, int64_t N, int D, int64_t ldx, int G, con
     for (int d = 0; d < D; ++d) s[d] = 0.0;
     for (int64_t i = 0; i < N; ++i)
       if (assign_out[i] == g)
-        for (int d = 0; d < D; ++d) s[d] += xval(X, ldx, i, d);
+        for (int d = 0; d < D; ++d) s[d] += xval(S, i, d);
     for (int d = 0; d < D; ++d) mu[d] = s[d] / (double)c;
     for (int d = 0; d < D; ++d) s[d] = 0.0;
     for (int64_t i = 0; i < N; ++i)
       if (assign_out[i] == g)
         for (int d = 0; d < D; ++d) {
-          double t = xval(X, ldx, i, d) - mu[d];
+          double t = xval(S, i, d) - mu[d];
           s[d] += t * t;
         }
     for (int d = 0; d < D; ++d) {
@@ -548,7 +568,7 @@ int oracle_kmeans_iter(const float* X, int64_t N, int D, int64_t ldx, int G, con
         ++seen;
       }
     if (pick < 0) continue;
-    for (int d = 0; d < D; ++d) means_out[(size_t)g * D + d] = xval(X, ldx, pick, d);
+    for (int d = 0; d < D; ++d) means_out[(size_t)g * D + d] = xval(S, pick, d);
     taken[q] += 1;
     rem[q] -= 1;
   }
@@ -564,15 +584,15 @@ int oracle_kmeans_iter(const float* X, int64_t N, int D, int64_t ldx, int G, con
 /* Eq. 20's weights): out[i*G + g] = sum_d lam[d] (x_di - mu_gd)^2.          */
 /* ------------------------------------------------------------------------ */
 
-int oracle_kmeans_dists(const float* X, int64_t N, int D, int64_t ldx, int G, const double* lam,
+static int kmeans_dists_s(const samples_t* S, int64_t N, int D, int G, const double* lam,
                         const double* means, double* out) {
-  if (N < 1 || D < 1 || G < 1 || ldx < D) return ORC_EINVAL;
+  if (N < 1 || D < 1 || G < 1 || S->ldx < D) return ORC_EINVAL;
 #pragma omp parallel for schedule(static) num_threads(NTHR)
   for (int64_t i = 0; i < N; ++i)
     for (int g = 0; g < G; ++g) {
       double s = 0.0;
       for (int d = 0; d < D; ++d) {
-        double t = xval(X, ldx, i, d) - means[(size_t)g * D + d];
+        double t = xval(S, i, d) - means[(size_t)g * D + d];
         s += lam[d] * t * t;
       }
       out[i * G + g] = s;
@@ -586,10 +606,10 @@ int oracle_kmeans_dists(const float* X, int64_t N, int D, int64_t ldx, int G, co
 /* the Gaussian with the largest weighted likelihood.  Lowest index on ties. */
 /* ------------------------------------------------------------------------ */
 
-int oracle_assign(const float* X, int64_t N, int D, int64_t ldx, int G, int mode,
+static int assign_s(const samples_t* S, int64_t N, int D, int G, int mode,
                   const double* hefts, const double* means, const double* dcovs,
                   int32_t* out) {
-  if (N < 1 || D < 1 || G < 1 || ldx < D || (mode != 0 && mode != 1)) return ORC_EINVAL;
+  if (N < 1 || D < 1 || G < 1 || S->ldx < D || (mode != 0 && mode != 1)) return ORC_EINVAL;
   double* logdet = (double*)malloc(sizeof(double) * G);
   if (!logdet) return ORC_ENOMEM;
   for (int g = 0; g < G; ++g) logdet[g] = mode == 1 ? log_det_diag(dcovs + (size_t)g * D, D) : 0.0;
@@ -602,12 +622,12 @@ int oracle_assign(const float* X, int64_t N, int D, int64_t ldx, int G, int mode
       if (mode == 0) {
         double s = 0.0;
         for (int d = 0; d < D; ++d) {
-          double t = xval(X, ldx, i, d) - means[(size_t)g * D + d];
+          double t = xval(S, i, d) - means[(size_t)g * D + d];
           s += t * t;
         }
         v = -s;
       } else {
-        v = log(hefts[g]) + log_gauss_diag(X + i * ldx, means + (size_t)g * D,
+        v = log(hefts[g]) + log_gauss_diag(S, i, means + (size_t)g * D,
                                            dcovs + (size_t)g * D, logdet[g], D);
       }
       if (g == 0 || v > best) {
@@ -620,3 +640,52 @@ int oracle_assign(const float* X, int64_t N, int D, int64_t ldx, int G, int mode
   free(logdet);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Public entry points: FP32 samples (oracle_*) and FP64 samples             */
+/* (oracle_*_f64), both D x N column-major with row stride ldx.              */
+/* ------------------------------------------------------------------------ */
+
+#define ORC_PAIR(NAME, PARAMS, ARGS)                                                   \
+  int oracle_##NAME(const float* X, int64_t N, int D, int64_t ldx, PARAMS) {          \
+    samples_t S = {X, NULL, ldx};                                                      \
+    return NAME##_s(&S, N, D, ARGS);                                                   \
+  }                                                                                    \
+  int oracle_##NAME##_f64(const double* X, int64_t N, int D, int64_t ldx, PARAMS) {   \
+    samples_t S = {NULL, X, ldx};                                                      \
+    return NAME##_s(&S, N, D, ARGS);                                                   \
+  }
+#define P_(...) __VA_ARGS__
+
+ORC_PAIR(loglik,
+         P_(int G, int full, const double* hefts, const double* means, const double* covs,
+            double* mean_loglik, double* per_sample),
+         P_(G, full, hefts, means, covs, mean_loglik, per_sample))
+ORC_PAIR(log_p_g, P_(int G, const double* means, const double* dcovs, int g, double* out),
+         P_(G, means, dcovs, g, out))
+ORC_PAIR(seed_spread,
+         P_(int G, const double* lam, int64_t first, int64_t* idx_out, double* means_out),
+         P_(G, lam, first, idx_out, means_out))
+ORC_PAIR(responsibilities,
+         P_(int G, int full, const double* hefts, const double* means, const double* covs,
+            double* out),
+         P_(G, full, hefts, means, covs, out))
+ORC_PAIR(em_iter,
+         P_(int G, int full, const double* hefts, const double* means, const double* covs,
+            double var_floor, double* hefts_out, double* means_out, double* covs_out,
+            double* mean_loglik, double* L_out),
+         P_(G, full, hefts, means, covs, var_floor, hefts_out, means_out, covs_out, mean_loglik,
+            L_out))
+ORC_PAIR(global_stats, P_(double* mean, double* var), P_(mean, var))
+ORC_PAIR(kmeans_iter,
+         P_(int G, const double* lam, const double* means, double var_floor, double* means_out,
+            double* dcovs_out, double* hefts_out, int64_t* counts_out, int32_t* assign_out,
+            double* inertia, double* gap),
+         P_(G, lam, means, var_floor, means_out, dcovs_out, hefts_out, counts_out, assign_out,
+            inertia, gap))
+ORC_PAIR(kmeans_dists, P_(int G, const double* lam, const double* means, double* out),
+         P_(G, lam, means, out))
+ORC_PAIR(assign,
+         P_(int G, int mode, const double* hefts, const double* means, const double* dcovs,
+            int32_t* out),
+         P_(G, mode, hefts, means, dcovs, out))

@@ -3,9 +3,11 @@
 TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
 benchmark's CPU-baseline leg, never by the product library.
 
-All functions take numpy arrays on the host.  Samples are float32, D x N
-column-major, i.e. a C-contiguous (N, D) array whose row i is sample i
-(one sample per column of the paper's data matrix, Sec. 4 API).  Parameters
+All functions take numpy arrays on the host.  Samples are D x N column-major,
+i.e. a C-contiguous (N, D) array whose row i is sample i (one sample per
+column of the paper's data matrix, Sec. 4 API): float64 arrays go to the
+FP64-sample entry points (the paper's gmm_diag precision), anything else is
+taken as float32.  Parameters
 are promoted to float64: ``means`` and ``dcovs`` are (G, D) arrays (row g is
 the paper's column g), full covariances are (G, D, D).
 """
@@ -67,6 +69,10 @@ def lib():
                   "oracle_global_stats", "oracle_kmeans_iter", "oracle_assign",
                   "oracle_seed_spread", "oracle_kmeans_dists"):
             getattr(L, f).restype = _i32
+            # FP64-sample twin: the same arguments with X as double*
+            g64 = getattr(L, f + "_f64")
+            g64.argtypes = [_dp] + list(getattr(L, f).argtypes[1:])
+            g64.restype = _i32
         _lib = L
     return _lib
 
@@ -84,10 +90,20 @@ class OracleError(RuntimeError):
 
 
 def _X(X):
-    X = np.ascontiguousarray(X, dtype=np.float32)
+    """Samples as a C-contiguous (N, D) array: float64 input stays FP64 (the
+    *_f64 entry points), anything else becomes float32."""
+    X = np.asarray(X)
+    X = np.ascontiguousarray(X, dtype=np.float64 if X.dtype == np.float64 else np.float32)
     if X.ndim != 2:
         raise ValueError("X must be (N, D)")
     return X, X.shape[0], X.shape[1]
+
+
+def _call(name, X, *args):
+    """Call the entry point for X's precision (name, or name_f64 for FP64)."""
+    if X.dtype == np.float64:
+        return getattr(lib(), name + "_f64")(X.ctypes.data_as(_dp), *args)
+    return getattr(lib(), name)(X.ctypes.data_as(_fp), *args)
 
 
 def _d(a):
@@ -117,7 +133,7 @@ def loglik(X, hefts, means, covs, full=False, per_sample=False):
     h, m, c = _d(hefts), _d(means), _d(covs)
     out = np.zeros(1)
     ps = np.zeros(N) if per_sample else None
-    rc = lib().oracle_loglik(_p(X, _fp), N, D, D, G, int(full), _p(h), _p(m), _p(c), _p(out),
+    rc = _call("oracle_loglik", X, N, D, D, G, int(full), _p(h), _p(m), _p(c), _p(out),
                              _p(ps) if per_sample else None)
     _check(rc, "loglik")
     return (float(out[0]), ps) if per_sample else float(out[0])
@@ -127,7 +143,7 @@ def log_p_g(X, means, dcovs, g):
     X, N, D = _X(X)
     m, c = _d(means), _d(dcovs)
     out = np.zeros(N)
-    _check(lib().oracle_log_p_g(_p(X, _fp), N, D, D, m.shape[0], _p(m), _p(c), int(g), _p(out)),
+    _check(_call("oracle_log_p_g", X, N, D, D, m.shape[0], _p(m), _p(c), int(g), _p(out)),
            "log_p_g")
     return out
 
@@ -137,7 +153,7 @@ def responsibilities(X, hefts, means, covs, full=False):
     G = len(hefts)
     h, m, c = _d(hefts), _d(means), _d(covs)
     out = np.zeros((N, G))
-    _check(lib().oracle_responsibilities(_p(X, _fp), N, D, D, G, int(full), _p(h), _p(m), _p(c),
+    _check(_call("oracle_responsibilities", X, N, D, D, G, int(full), _p(h), _p(m), _p(c),
                                          _p(out)), "responsibilities")
     return out
 
@@ -159,7 +175,7 @@ def em_iter(X, hefts, means, covs, var_floor, full=False) -> EMResult:
     ho, mo, co = np.zeros_like(h), np.zeros_like(m), np.zeros_like(c)
     ll = np.zeros(1)
     L = np.zeros(G)
-    rc = lib().oracle_em_iter(_p(X, _fp), N, D, D, G, int(full), _p(h), _p(m), _p(c),
+    rc = _call("oracle_em_iter", X, N, D, D, G, int(full), _p(h), _p(m), _p(c),
                               float(var_floor), _p(ho), _p(mo), _p(co), _p(ll), _p(L))
     _check(rc, "em_iter")
     return EMResult(ho, mo, co, float(ll[0]), L, rc)
@@ -168,7 +184,7 @@ def em_iter(X, hefts, means, covs, var_floor, full=False) -> EMResult:
 def global_stats(X):
     X, N, D = _X(X)
     mean, var = np.zeros(D), np.zeros(D)
-    _check(lib().oracle_global_stats(_p(X, _fp), N, D, D, _p(mean), _p(var)), "global_stats")
+    _check(_call("oracle_global_stats", X, N, D, D, _p(mean), _p(var)), "global_stats")
     return mean, var
 
 
@@ -196,7 +212,7 @@ def kmeans_iter(X, means, lam, var_floor) -> KMResult:
     assign = np.zeros(N, dtype=np.int32)
     inertia = np.zeros(1)
     gap = np.zeros(N)
-    rc = lib().oracle_kmeans_iter(_p(X, _fp), N, D, D, G, _p(lam), _p(m), float(var_floor),
+    rc = _call("oracle_kmeans_iter", X, N, D, D, G, _p(lam), _p(m), float(var_floor),
                                   _p(mo), _p(co), _p(ho), _p(counts, _i64p), _p(assign, _i32p),
                                   _p(inertia), _p(gap))
     _check(rc, "kmeans_iter")
@@ -210,7 +226,7 @@ def kmeans_dists(X, means, lam):
     m = _d(means)
     G = m.shape[0]
     out = np.zeros((N, G))
-    _check(lib().oracle_kmeans_dists(_p(X, _fp), N, D, D, G, _p(_d(lam)), _p(m), _p(out)),
+    _check(_call("oracle_kmeans_dists", X, N, D, D, G, _p(_d(lam)), _p(m), _p(out)),
            "kmeans_dists")
     return out
 
@@ -220,7 +236,7 @@ def assign(X, hefts, means, dcovs, mode):
     X, N, D = _X(X)
     h, m, c = _d(hefts), _d(means), _d(dcovs)
     out = np.zeros(N, dtype=np.int32)
-    _check(lib().oracle_assign(_p(X, _fp), N, D, D, m.shape[0], int(mode), _p(h), _p(m), _p(c),
+    _check(_call("oracle_assign", X, N, D, D, m.shape[0], int(mode), _p(h), _p(m), _p(c),
                                _p(out, _i32p)), "assign")
     return out
 
@@ -232,7 +248,7 @@ def seed_spread(X, G, first=0, lam=None):
     idx = np.zeros(G, dtype=np.int64)
     means = np.zeros((G, D))
     lp = _p(_d(lam)) if lam is not None else None
-    _check(lib().oracle_seed_spread(_p(X, _fp), N, D, D, int(G), lp, int(first), _p(idx, _i64p),
+    _check(_call("oracle_seed_spread", X, N, D, D, int(G), lp, int(first), _p(idx, _i64p),
                                     _p(means)), "seed_spread")
     return idx, means
 

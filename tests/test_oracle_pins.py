@@ -522,3 +522,82 @@ def test_seed_spread_more_seeds_than_distinct_samples(oracle):
     X = np.array([[0.0], [4.0], [0.0], [9.0], [4.0]], dtype=np.float32)
     idx, _ = oracle.seed_spread(X, 5, first=1)
     assert idx.tolist() == [1, 3, 0, 0, 0]
+
+
+# ------------------------------------------------------- FP64 samples (gmm_diag)
+def _f64_data(seed, N, D, offset=1e6, scale=1e-3):
+    """FP64 samples that FP32 cannot hold: a large offset plus deviations far
+    below the FP32 spacing at that offset (0.0625 at 1e6)."""
+    rng = _rng(seed)
+    return offset + rng.normal(size=(N, D)) * scale * rng.uniform(0.5, 2.0, size=D)
+
+
+@pytest.mark.parametrize("D,N", [(1, 40), (4, 3000)])
+def test_f64_single_component_closed_form(oracle, D, N):
+    """FP64 samples, N_G = 1: the EM step gives numpy's FP64 mean and population
+    variance, the k-means step the same mean; the same data rounded to FP32
+    would have lost the deviations entirely."""
+    X = _f64_data(3 + D, N, D)
+    rng = _rng(D)
+    res = oracle.em_iter(X, [1.0], rng.normal(size=(1, D)) + 1e6, np.full((1, D), 1e-6), 1e-30)
+    np.testing.assert_allclose(res.means[0], X.mean(axis=0), rtol=1e-15)
+    np.testing.assert_allclose(res.covs[0], X.var(axis=0), rtol=1e-8)
+    km = oracle.kmeans_iter(X, X[:1], np.ones(D), 1e-30)
+    np.testing.assert_allclose(km.means[0], X.mean(axis=0), rtol=1e-15)
+    np.testing.assert_allclose(km.dcovs[0], X.var(axis=0), rtol=1e-8)
+    m, v = oracle.global_stats(X)
+    np.testing.assert_allclose(m, X.mean(axis=0), rtol=1e-15)
+    np.testing.assert_allclose(v, X.var(axis=0), rtol=1e-8)
+    assert np.all(X.astype(np.float32).astype(np.float64).var(axis=0) == 0.0)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_f64_bruteforce_linear_domain_decimal(oracle, seed):
+    """FP64 samples through the log domain == Eqs. 1-3 in 50-digit decimals."""
+    rng = _rng(200 + seed)
+    N, D, G = 6, 2, 3
+    X = rng.normal(size=(N, D)) * 1.5 + 1e-9 * rng.normal(size=(N, D))
+    w = rng.dirichlet(np.ones(G))
+    mu = rng.normal(size=(G, D))
+    var = rng.uniform(0.3, 2.0, size=(G, D))
+    ref_lp, ref_r = _dec_lin_mixture(X, w, mu, var)
+    _, ps = oracle.loglik(X, w, mu, var, per_sample=True)
+    np.testing.assert_allclose(ps, ref_lp, rtol=1e-14, atol=1e-14)
+    np.testing.assert_allclose(oracle.responsibilities(X, w, mu, var), ref_r, rtol=1e-13,
+                               atol=1e-15)
+
+
+@pytest.mark.parametrize("maha", [False, True])
+def test_f64_kmeans_bruteforce(oracle, maha):
+    """FP64 samples: Eq. 19 / Eq. 20 by brute force with scipy's distances."""
+    rng = _rng(300 + maha)
+    N, D, G = 500, 3, 4
+    X = rng.normal(size=(N, D)) * [1, 10, 0.1] + 5e5
+    mu = X[rng.choice(N, G, replace=False)] + rng.normal(size=(G, D)) * 0.01
+    if maha:
+        var = X.var(0)
+        lam, dist = 1.0 / var, cdist(X, mu, metric="seuclidean", V=var) ** 2
+    else:
+        lam, dist = np.ones(D), cdist(X, mu, metric="sqeuclidean")
+    res = oracle.kmeans_iter(X, mu, lam, 1e-30)
+    assert np.array_equal(res.assign, dist.argmin(axis=1))
+    for g in range(G):
+        sel = X[res.assign == g]
+        np.testing.assert_allclose(res.means[g], sel.mean(0), rtol=1e-15)
+        np.testing.assert_allclose(res.dcovs[g], sel.var(0), rtol=1e-7)
+    np.testing.assert_allclose(oracle.kmeans_dists(X, mu, lam), dist, rtol=1e-7)
+
+
+def test_f64_entry_points_agree_with_fp32_on_fp32_data(oracle):
+    """FP32 samples handed over as FP64 give bit-identical results (each value
+    is promoted exactly in both)."""
+    X, _ = synth.config1(N=3000)
+    X64 = X.astype(np.float64)
+    mu = synth.static_subset(X, 4).astype(np.float64)
+    w, v = np.full(4, 0.25), np.ones((4, 4))
+    a, b = oracle.em_iter(X, w, mu, v, 1e-10), oracle.em_iter(X64, w, mu, v, 1e-10)
+    assert np.array_equal(a.means, b.means) and np.array_equal(a.covs, b.covs)
+    assert a.mean_loglik == b.mean_loglik
+    ka, kb = oracle.kmeans_iter(X, mu, np.ones(4), 1e-10), oracle.kmeans_iter(X64, mu, np.ones(4), 1e-10)
+    assert np.array_equal(ka.assign, kb.assign) and ka.inertia == kb.inertia
+    assert np.array_equal(oracle.global_stats(X)[1], oracle.global_stats(X64)[1])
