@@ -253,6 +253,39 @@ int gmm_assign(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int
                int64_t* hist, int32_t* dev_status, void* ws, size_t ws_bytes,
                gmm_stream_t stream);
 
+/* ---- FP64 data (the paper's gmm_diag<double>, Sec. 4; the precision of its
+ * speed-up experiment, Sec. 5.1) ---------------------------------------------
+ * The same operations on FP64 samples with FP64 parameters, diagonal
+ * covariances.  Layouts, conventions and semantics are those of the FP32
+ * calls above, with double in place of float for X, hefts, means, dcovs,
+ * per_sample and var_floor.  Supported shapes: D <= 128 and G up to what the
+ * 32-sample tile of FP64 log-densities holds in LDS (about 480 components at
+ * D = 128, 540 at D = 64); gmm_workspace_bytes_f64 returns 0 and the calls
+ * return GMM_EINVAL beyond that.  Arithmetic: FP64 throughout.  The E-step
+ * computes every log-density on the FP64 matrix cores (expanded form) and
+ * then recomputes, in the FP64 direct form, every pair within 41 nats of the
+ * sample's largest value, so every responsibility above exp(-40) and every
+ * log-likelihood is as exact as FP64 rounding of the plain definition
+ * (responsibilities below exp(-80), not exp(-40), are treated as 0); the
+ * k-means assignment is the FP64 argmin (re-decided in the direct form when
+ * the two smallest matrix-core distances are within their rounding bound). */
+size_t gmm_workspace_bytes_f64(int64_t N, int32_t D, int32_t G);
+int gmm_global_stats_f64(const double* X, int64_t N, int32_t D, int64_t ldx, double* mean_out,
+                         double* var_out, void* ws, size_t ws_bytes, gmm_stream_t stream);
+int gmm_kmeans_iter_f64(const double* X, int64_t N, int32_t D, int64_t ldx, int32_t G,
+                        int32_t dist, const double* gvar, double var_floor, double* means,
+                        double* dcovs, double* hefts, int64_t* counts, int32_t* assign,
+                        double* inertia, int64_t* n_recomputed, int32_t* dev_status, void* ws,
+                        size_t ws_bytes, gmm_stream_t stream);
+int gmm_em_iter_f64(const double* X, int64_t N, int32_t D, int64_t ldx, int32_t G,
+                    double* hefts, double* means, double* dcovs, double var_floor,
+                    double* mean_loglik, int32_t* dev_status, void* ws, size_t ws_bytes,
+                    gmm_stream_t stream);
+int gmm_loglik_f64(const double* X, int64_t N, int32_t D, int64_t ldx, int32_t G,
+                   const double* hefts, const double* means, const double* dcovs,
+                   double* mean_loglik, double* per_sample, int32_t* dev_status, void* ws,
+                   size_t ws_bytes, gmm_stream_t stream);
+
 /* ---- kernel selection ----------------------------------------------------
  * Which kernel family gmm_em_iter / gmm_loglik (gmm_em_path) and
  * gmm_kmeans_iter (gmm_kmeans_path) run for a shape and arithmetic form.

@@ -161,6 +161,66 @@ int gmm_assign(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G, int
                                  dev_status, w, (hipStream_t)stream));
 }
 
+// ---- FP64 data ---------------------------------------------------------------
+
+size_t gmm_workspace_bytes_f64(int64_t N, int32_t D, int32_t G) {
+  if (!shape_ok(N, D, D, G) || !em_f64_supported(D, G)) return 0;
+  Workspace w;
+  carve(nullptr, 0, N, D, G, GMM_COV_DIAG, &w);
+  return w.bytes;
+}
+
+int gmm_global_stats_f64(const double* X, int64_t N, int32_t D, int64_t ldx, double* mean_out,
+                         double* var_out, void* ws, size_t ws_bytes, gmm_stream_t stream) {
+  if (!X || !mean_out || !var_out || !shape_ok(N, D, ldx, 1)) return GMM_EINVAL;
+  Workspace w;
+  if (!ws_ok(ws, ws_bytes, N, D, 1, GMM_COV_DIAG, &w)) return GMM_EINVAL;
+  return status_of(
+      launch_global_stats_f64(X, N, D, ldx, mean_out, var_out, w, (hipStream_t)stream));
+}
+
+int gmm_kmeans_iter_f64(const double* X, int64_t N, int32_t D, int64_t ldx, int32_t G,
+                        int32_t dist, const double* gvar, double var_floor, double* means,
+                        double* dcovs, double* hefts, int64_t* counts, int32_t* assign,
+                        double* inertia, int64_t* n_recomputed, int32_t* dev_status, void* ws,
+                        size_t ws_bytes, gmm_stream_t stream) {
+  if (!X || !means || !dcovs || !hefts || !counts || !inertia || !dev_status) return GMM_EINVAL;
+  if (!shape_ok(N, D, ldx, G) || !em_f64_supported(D, G)) return GMM_EINVAL;
+  if (dist != GMM_DIST_EUCL && dist != GMM_DIST_MAHA) return GMM_EINVAL;
+  if (dist == GMM_DIST_MAHA && !gvar) return GMM_EINVAL;
+  if (!(var_floor >= 0.0)) return GMM_EINVAL;
+  Workspace w;
+  if (!ws_ok(ws, ws_bytes, N, D, G, GMM_COV_DIAG, &w)) return GMM_EINVAL;
+  return status_of(launch_kmeans_f64(X, N, D, ldx, G, dist, gvar, var_floor, means, dcovs, hefts,
+                                     counts, assign, inertia, n_recomputed, dev_status, w,
+                                     (hipStream_t)stream));
+}
+
+int gmm_em_iter_f64(const double* X, int64_t N, int32_t D, int64_t ldx, int32_t G,
+                    double* hefts, double* means, double* dcovs, double var_floor,
+                    double* mean_loglik, int32_t* dev_status, void* ws, size_t ws_bytes,
+                    gmm_stream_t stream) {
+  if (!X || !hefts || !means || !dcovs || !mean_loglik || !dev_status) return GMM_EINVAL;
+  if (!shape_ok(N, D, ldx, G) || !em_f64_supported(D, G)) return GMM_EINVAL;
+  if (!(var_floor >= 0.0)) return GMM_EINVAL;
+  Workspace w;
+  if (!ws_ok(ws, ws_bytes, N, D, G, GMM_COV_DIAG, &w)) return GMM_EINVAL;
+  return status_of(launch_em_diag_f64(X, N, D, ldx, G, hefts, means, dcovs, var_floor,
+                                      mean_loglik, dev_status, w, (hipStream_t)stream));
+}
+
+int gmm_loglik_f64(const double* X, int64_t N, int32_t D, int64_t ldx, int32_t G,
+                   const double* hefts, const double* means, const double* dcovs,
+                   double* mean_loglik, double* per_sample, int32_t* dev_status, void* ws,
+                   size_t ws_bytes, gmm_stream_t stream) {
+  if (!X || !hefts || !means || !dcovs || !mean_loglik || !dev_status) return GMM_EINVAL;
+  if (!shape_ok(N, D, ldx, G) || !em_f64_supported(D, G)) return GMM_EINVAL;
+  Workspace w;
+  if (!ws_ok(ws, ws_bytes, N, D, G, GMM_COV_DIAG, &w)) return GMM_EINVAL;
+  return status_of(launch_loglik_diag_f64(X, N, D, ldx, G, hefts, means, dcovs, mean_loglik,
+                                          per_sample, dev_status, w, (hipStream_t)stream));
+}
+
 int gmm_em_path(int32_t D, int32_t G, int32_t cov, int32_t prec) {
   if (!shape_ok(1, D, D, G)) return GMM_EINVAL;
   if (prec != GMM_PREC_FP32 && prec != GMM_PREC_BF16X3) return GMM_EINVAL;

@@ -37,10 +37,12 @@ __global__ void k_init(int32_t* dev_status, int64_t* n_recomputed, int64_t* coun
   if (threadIdx.x < 8) counters[threadIdx.x] = 0;
 }
 
-// One workgroup per component g.
-__global__ void __launch_bounds__(kNT) k_pre_diag(const float* __restrict__ hefts,
-                                                  const float* __restrict__ means,
-                                                  const float* __restrict__ covs, int D, int G,
+// One workgroup per component g.  XT: the parameters' type (FP32, or FP64 for
+// FP64 data).
+template <typename XT>
+__global__ void __launch_bounds__(kNT) k_pre_diag(const XT* __restrict__ hefts,
+                                                  const XT* __restrict__ means,
+                                                  const XT* __restrict__ covs, int D, int G,
                                                   float* __restrict__ s_out,
                                                   float* __restrict__ m_out,
                                                   float* __restrict__ c_out,
@@ -77,7 +79,8 @@ __global__ void __launch_bounds__(kNT) k_pre_diag(const float* __restrict__ heft
 // (kr = lane / 16) holding -lam_gk / 2 for k < dpad4(D) (x_k^2) and
 // lam mu for k - dpad4(D) (x); zero for padding components and dimensions.
 // Also c0_g = c_g - Q_g / 2 and Q_g = sum_d lam mu^2 in FP64.
-__global__ void __launch_bounds__(kNT) k_frag_diag64(const float* __restrict__ means,
+template <typename XT>
+__global__ void __launch_bounds__(kNT) k_frag_diag64(const XT* __restrict__ means,
                                                      const double* __restrict__ lam64,
                                                      const double* __restrict__ c64, int D, int G,
                                                      double* __restrict__ Bx64,
@@ -129,13 +132,13 @@ __global__ void __launch_bounds__(kNT) k_frag_diag64(const float* __restrict__ m
 // the expanded form run side by side (x^2 times -lam/2, x times lam mu: four
 // independent accumulator chains).  XH = 0: any D <= 128, the operand is
 // rebuilt from LDS per component block.
-template <int XH>
-__device__ __forceinline__ void logdens_diag_f64(const float* __restrict__ xs, int XS, int nt, int D, int G,
+template <int XH, typename XT>
+__device__ __forceinline__ void logdens_diag_f64(const XT* __restrict__ xs, int XS, int nt, int D, int G,
                                  const double* __restrict__ Bx64,
                                  const double* __restrict__ cq64,
                                  const double* __restrict__ c64,
                                  const double* __restrict__ lam64,
-                                 const float* __restrict__ means, float* __restrict__ as,
+                                 const XT* __restrict__ means, XT* __restrict__ as,
                                  int AS, float* __restrict__ rcb, int RS, int wid, int nw,
                                  int lane) {
   const int DP4 = XS;           // dimensions padded to 4 (zeros in xs)
@@ -228,7 +231,7 @@ __device__ __forceinline__ void logdens_diag_f64(const float* __restrict__ xs, i
           if (!(ek * (base + (T1 + 0.5 * Q)) <= 1e-9) &&
               !(ek * (base + sqrt(2.0 * T1 * Q)) <= 1e-9)) {
             // extreme data (or non-finite): FP64 direct form
-            const float* x = xs + (size_t)t * XS;
+            const XT* x = xs + (size_t)t * XS;
             double q = 0.0;
             for (int d = 0; d < D; ++d) {
               const double u = (double)x[d] - (double)means[(size_t)g * D + d];
@@ -245,7 +248,7 @@ __device__ __forceinline__ void logdens_diag_f64(const float* __restrict__ xs, i
         v = fmaxf(v, dpp_f<0x124>(v));
         v = fmaxf(v, dpp_f<0x128>(v));
         if (t < nt) {
-          if (gv) as[(size_t)t * AS + g] = v > -INFINITY ? (float)(a - (double)v) : -INFINITY;
+          if (gv) as[(size_t)t * AS + g] = v > -INFINITY ? (XT)(a - (double)v) : -INFINITY;
           if (m == 0) rcb[(size_t)t * RS + cb] = v;
         }
       }
@@ -258,19 +261,33 @@ __device__ __forceinline__ void logdens_diag_f64(const float* __restrict__ xs, i
 // responsibilities, lse[T], the tile's component mask (WIDE: then rcb[T][NCB],
 // a reference per sample and block of 16 components).  T is chosen on the host
 // so the tile fits in LDS.
-template <bool MSTEP, bool WIDE>
+// XT: the type of the samples and parameters.  FP32 data as above.  FP64 data
+// (WIDE only): xs and as hold FP64 values, and in the log-sum-exp every pair
+// within kExactGap nats of the sample's largest matrix-core value is computed
+// again in the FP64 direct form before the responsibilities are taken, so
+// every responsibility above exp(-40) comes from a log-density good to FP64
+// rounding (the matrix-core values alone carry up to their rounding bound,
+// 1e-9 nats, which moves a responsibility below exp(-41) by a relative 1e-9).
+// Responsibilities below exp(-80) are set to 0 (FP32 data: exp(-40)): at the
+// FP64 bar a component made of one sample has a variance that far samples'
+// tiny responsibilities still move at 1e-11 with the FP32 cut.
+constexpr double kExactGap = 41.0;
+constexpr double kRespCut64 = 80.0;
+template <bool MSTEP, bool WIDE, typename XT>
 __global__ void __launch_bounds__(kNT, 2) k_estep_diag(
-    const float* __restrict__ X, int64_t N, int D, int64_t ldx, int G, int T, int64_t chunk,
+    const XT* __restrict__ X, int64_t N, int D, int64_t ldx, int G, int T, int64_t chunk,
     const float* __restrict__ sT, const float* __restrict__ mT, const float* __restrict__ cc,
     const double* __restrict__ c64, const double* __restrict__ lam64,
     const double* __restrict__ Bx64, const double* __restrict__ cq64,
-    const float* __restrict__ means, double* __restrict__ part, double* __restrict__ ll_part,
-    float* __restrict__ per_sample, int32_t* __restrict__ dev_status) {
-  extern __shared__ float lds[];
+    const XT* __restrict__ means, double* __restrict__ part, double* __restrict__ ll_part,
+    XT* __restrict__ per_sample, int32_t* __restrict__ dev_status) {
+  static_assert(WIDE || sizeof(XT) == 4, "FP64 data takes the matrix-core form");
+  constexpr bool F64 = sizeof(XT) == 8;
+  extern __shared__ double lds_d[];
   const int XS = WIDE ? ((D + 3) & ~3) : D;  // row stride of xs
   const int AS = WIDE ? G + 8 : G;            // row stride of as
-  float* xs = lds;                   // [T][XS]
-  float* as = xs + (size_t)T * XS;   // [T][AS]
+  XT* xs = (XT*)lds_d;                // [T][XS]
+  XT* as = xs + (size_t)T * XS;       // [T][AS]
   double* lse = (double*)(as + (size_t)T * AS + ((T * AS) & 1));  // [T]
   uint32_t* gbits = (uint32_t*)(lse + T);  // [G/32]: component has a non-zero r in the tile
   const int RS = (G + 15) / 16;  // WIDE: row stride of rcb
@@ -298,11 +315,11 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_diag(
     const int nt = (int)min((int64_t)T, i1 - t0);
     for (int p = tid; p < nt * XS; p += kNT) {
       const int t = p / XS, d = p - t * XS;
-      xs[p] = d < D ? X[(t0 + t) * ldx + d] : 0.0f;
+      xs[p] = d < D ? X[(t0 + t) * ldx + d] : (XT)0;
     }
     for (int p = tid; p < NGB; p += kNT) gbits[p] = 0u;
     __syncthreads();
-    if (!WIDE) {
+    if constexpr (!WIDE) {
       // a_gi: one (sample, component) pair per thread iteration.
       for (int p = tid; p < nt * G; p += kNT) {
         const int t = p / G, g = p - t * G;
@@ -324,7 +341,64 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_diag(
                             wid, nw, lane);
     }
     __syncthreads();
-    if (WIDE) {
+    if constexpr (WIDE && F64) {
+      // FP64 data: log-sum-exp (Eqs. 16-18) about M = max_cb R_cb from the
+      // values (R_cb - M) + (a - R_cb), after the pairs within kExactGap nats of
+      // the largest are recomputed in the FP64 direct form; kKL threads per
+      // sample
+      const int ts = tid / kKL, j = tid % kKL;
+      if (ts < nt) {  // uniform over the kKL threads of a sample
+        XT* a = as + (size_t)ts * AS;
+        const float* rr = rcb + (size_t)ts * RS;
+        float Mf = -INFINITY;
+        for (int c = j; c < RS; c += kKL) Mf = fmaxf(Mf, rr[c]);
+#pragma unroll
+        for (int off = 1; off < kKL; off <<= 1) Mf = fmaxf(Mf, __shfl_xor(Mf, off));
+        const double M = Mf > -INFINITY ? (double)Mf : 0.0;
+        double dn = -INFINITY;
+        for (int g = j; g < G; g += kKL) {
+          const double v = ((double)rr[g >> 4] - M) + (double)a[g];
+          a[g] = v;
+          dn = fmax(dn, v);
+        }
+#pragma unroll
+        for (int off = 1; off < kKL; off <<= 1) dn = fmax(dn, __shfl_xor(dn, off));
+        const XT* x = xs + (size_t)ts * XS;
+        double dx = -INFINITY;
+        for (int g = j; g < G; g += kKL)
+          if (a[g] >= dn - kExactGap) {
+            double q = 0.0;
+            for (int d = 0; d < D; ++d) {
+              const double u = (double)x[d] - (double)means[(size_t)g * D + d];
+              q += u * u * lam64[(size_t)g * D + d];
+            }
+            a[g] = (c64[g] - 0.5 * q) - M;
+            dx = fmax(dx, (double)a[g]);
+          }
+#pragma unroll
+        for (int off = 1; off < kKL; off <<= 1) dx = fmax(dx, __shfl_xor(dx, off));
+        dx = dx > -INFINITY ? dx : 0.0;
+        double sm = 0.0;
+        for (int g = j; g < G; g += kKL) sm += exp((double)a[g] - dx);
+#pragma unroll
+        for (int off = 1; off < kKL; off <<= 1) sm += __shfl_xor(sm, off);
+        const double ls = log(sm);
+        const double l = (M + dx) + ls;
+        if (MSTEP) {
+          for (int g = j; g < G; g += kKL) {
+            const double z = ((double)a[g] - dx) - ls;
+            const double r = z >= -kRespCut64 ? exp(z) : 0.0;
+            a[g] = r;
+            if (r != 0.0) atomicOr(&gbits[g >> 5], 1u << (g & 31));
+          }
+        }
+        if (j == 0) {
+          lse[ts] = l;
+          if (!isfinite(l)) bad = 1;
+          if (per_sample) per_sample[t0 + ts] = (XT)l;
+        }
+      }
+    } else if constexpr (WIDE) {
       // log-sum-exp (Eqs. 16-18) about M = max_cb R_cb, each value taken as
       // (R_cb - M) + (a - R_cb) in FP64, and responsibilities; kKL threads per
       // sample
@@ -474,19 +548,20 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_diag(
         unsigned long long mk[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-          mk[k] = k < nq ? __ballot(lane < nt && as[(size_t)lane * AS + gq[k]] != 0.0f) : 0ull;
+          mk[k] = k < nq ? __ballot(lane < nt && as[(size_t)lane * AS + gq[k]] != (XT)0) : 0ull;
         double cnt[4] = {0.0, 0.0, 0.0, 0.0};
         for (int d = lane; d < D; d += kWave) {
-          float mu[4];
+          XT mu[4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) mu[k] = k < nq ? means[(size_t)gq[k] * D + d] : 0.0f;
+          for (int k = 0; k < 4; ++k) mu[k] = k < nq ? means[(size_t)gq[k] * D + d] : (XT)0;
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             if (k >= nq) break;
             double s1 = 0.0, s2 = 0.0, l = 0.0;
             for (unsigned long long mm = mk[k]; mm; mm &= mm - 1) {
               const int t = __ffsll((long long)mm) - 1;
-              const float r = as[(size_t)t * AS + gq[k]];
+              const XT r = as[(size_t)t * AS + gq[k]];
+              // FP32 data: the difference of two FP32 values; FP64 data: FP64
               const double y = (double)(xs[(size_t)t * XS + d] - mu[k]);
               const double ry = (double)r * y;
               s1 += ry;
@@ -517,11 +592,12 @@ __global__ void __launch_bounds__(kNT, 2) k_estep_diag(
 
 // Reduce step: one workgroup per component.  Thread j sums column j of the
 // partials over blocks 0..nb-1 in order.
+template <typename XT>
 __global__ void __launch_bounds__(kNT) k_fin_diag(const double* __restrict__ part, int nb, int64_t N,
-                                                  int D, int G, float var_floor,
-                                                  float* __restrict__ hefts,
-                                                  float* __restrict__ means,
-                                                  float* __restrict__ covs,
+                                                  int D, int G, double var_floor,
+                                                  XT* __restrict__ hefts,
+                                                  XT* __restrict__ means,
+                                                  XT* __restrict__ covs,
                                                   const double* __restrict__ ll_part,
                                                   double* __restrict__ mean_loglik,
                                                   int32_t* __restrict__ dev_status) {
@@ -538,7 +614,7 @@ __global__ void __launch_bounds__(kNT) k_fin_diag(const double* __restrict__ par
   __syncthreads();
   const double L = tot[0];
   if (threadIdx.x == 0) {
-    const float w = (float)(L / (double)N);  // Eq. 5
+    const XT w = (XT)(L / (double)N);  // Eq. 5
     hefts[g] = w;
     if (!isfinite(w)) bad = 1;
   }
@@ -548,9 +624,9 @@ __global__ void __launch_bounds__(kNT) k_fin_diag(const double* __restrict__ par
       const double mu = (double)means[(size_t)g * D + d] + dm;
       double v = tot[1 + D + d] / L - dm * dm;           // Eq. 7 about the new mean
       v = v > 0.0 ? v : 0.0;
-      v = v > (double)var_floor ? v : (double)var_floor;  // floor, Sec. 2.2
-      means[(size_t)g * D + d] = (float)mu;
-      covs[(size_t)g * D + d] = (float)v;
+      v = v > var_floor ? v : var_floor;  // floor, Sec. 2.2
+      means[(size_t)g * D + d] = (XT)mu;
+      covs[(size_t)g * D + d] = (XT)v;
       if (!isfinite(mu) || !isfinite(v)) bad = 1;
     }
   }
@@ -640,12 +716,14 @@ __global__ void __launch_bounds__(kLT) k_log_p_g(const float* __restrict__ X, in
 }
 
 // LDS bytes of k_estep_diag for tile rows T (WIDE: rows of xs padded to 4,
-// rows of as padded by 8, and the per-block references rcb).
-size_t estep_lds(int D, int G, int T, bool wide) {
+// rows of as padded by 8, and the per-block references rcb); esz: bytes of a
+// sample value (4, or 8 for FP64 data).
+size_t estep_lds(int D, int G, int T, bool wide, size_t esz = sizeof(float)) {
   const size_t XS = wide ? (size_t)((D + 3) & ~3) : (size_t)D;
-  size_t b = sizeof(float) * ((size_t)T * (XS + G) + 1) + sizeof(double) * T;
+  const size_t AS = wide ? (size_t)G + 8 : (size_t)G;
+  size_t b = esz * ((size_t)T * (XS + AS) + 1) + sizeof(double) * T;
   b += sizeof(uint32_t) * (((size_t)(G + 31) / 32 + 3) / 4 * 4);
-  if (wide) b += sizeof(float) * 8 * (size_t)T + sizeof(float) * (size_t)T * ((G + 15) / 16);
+  if (wide) b += sizeof(float) * (size_t)T * ((G + 15) / 16);
   return b;
 }
 
@@ -656,9 +734,9 @@ bool use_wide(int D, int G) {
   return D <= 128 && G > 128 && estep_lds(D, G, kWT, true) <= 159 * 1024;  // + static LDS
 }
 
-template <bool MSTEP, bool WIDE, typename... Args>
+template <bool MSTEP, bool WIDE, typename XT, typename... Args>
 void launch_estep_diag(int nb, size_t lds, hipStream_t st, Args... args) {
-  auto kern = k_estep_diag<MSTEP, WIDE>;
+  auto kern = k_estep_diag<MSTEP, WIDE, XT>;
   // dynamic LDS above the 64 KB default: raise the kernel's limit to exactly
   // this launch's size (limit plus static LDS must fit the CU's 160 KB)
   if (lds > 64 * 1024)
@@ -674,6 +752,57 @@ int tile_rows(int D, int G) {
   return T;
 }
 
+// EM iteration (mstep) or log-likelihood of the tile kernels: WIDE (FP64
+// matrix cores, the only form for FP64 data) or the FP32 direct form.
+template <typename XT>
+hipError_t em_tiles(const XT* X, int64_t N, int D, int64_t ldx, int G, const XT* hefts_in,
+                    XT* hefts, XT* means, XT* covs, double var_floor, bool wide, bool mstep,
+                    double* mean_loglik, XT* per_sample, int64_t* n_recomputed,
+                    int32_t* dev_status, const Workspace& w, hipStream_t st) {
+  const int T = wide ? kWT : tile_rows(D, G);
+  const int nb = partial_blocks(N, 4 * T);
+  int64_t chunk = (N + nb - 1) / nb;
+  const size_t lds = estep_lds(D, G, T, wide, sizeof(XT));
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, dev_status, n_recomputed, w.counters);
+  hipLaunchKernelGGL(k_pre_diag<XT>, dim3(G), dim3(kNT), 0, st, hefts_in, (const XT*)means,
+                     (const XT*)covs, D, G, w.s, w.m, w.c, w.c64, w.lamg64);
+  if (wide)
+    hipLaunchKernelGGL(k_frag_diag64<XT>, dim3(16 * ((G + 15) / 16)), dim3(kNT), 0, st,
+                       (const XT*)means, (const double*)w.lamg64, (const double*)w.c64, D, G,
+                       w.Bx64, w.cq64);
+  {
+    ProfScope ps(mstep ? kProfEM : kProfLoglik, st);
+#define GMM_ESTEP_ARGS                                                                      \
+  nb, lds, st, X, N, D, ldx, G, T, chunk, (const float*)w.s, (const float*)w.m,             \
+      (const float*)w.c, (const double*)w.c64, (const double*)w.lamg64,                     \
+      (const double*)w.Bx64, (const double*)w.cq64, (const XT*)means, w.partials, w.scalars, \
+      per_sample, dev_status
+    if constexpr (sizeof(XT) == 8) {
+      if (mstep) launch_estep_diag<true, true, XT>(GMM_ESTEP_ARGS);
+      else launch_estep_diag<false, true, XT>(GMM_ESTEP_ARGS);
+    } else {
+      if (wide && mstep) launch_estep_diag<true, true, XT>(GMM_ESTEP_ARGS);
+      else if (wide) launch_estep_diag<false, true, XT>(GMM_ESTEP_ARGS);
+      else if (mstep) launch_estep_diag<true, false, XT>(GMM_ESTEP_ARGS);
+      else launch_estep_diag<false, false, XT>(GMM_ESTEP_ARGS);
+    }
+#undef GMM_ESTEP_ARGS
+  }
+  if (!mstep) {
+    hipLaunchKernelGGL(k_ll_finish, dim3(1), dim3(64), 0, st, w.scalars, nb, N, mean_loglik,
+                       dev_status);
+    return hipGetLastError();
+  }
+  // [2D + 1] FP64 totals: above the 64 KB default for D > 4095
+  const size_t fin_lds = sizeof(double) * (2 * D + 1);
+  if (fin_lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)k_fin_diag<XT>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)fin_lds);
+  hipLaunchKernelGGL(k_fin_diag<XT>, dim3(G), dim3(kNT), fin_lds, st, w.partials, nb, N, D, G,
+                     var_floor, hefts, means, covs, w.scalars, mean_loglik, dev_status);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 int em_diag_path(int D, int G, int prec) {
@@ -682,10 +811,15 @@ int em_diag_path(int D, int G, int prec) {
   return use_wide(D, G) ? GMM_PATH_WIDE_FP64 : GMM_PATH_GENERIC;
 }
 
+bool em_f64_supported(int D, int G) {
+  return D >= 1 && D <= 128 && G >= 1 &&
+         estep_lds(D, G, kWT, true, sizeof(double)) <= 159 * 1024;
+}
+
 hipError_t launch_pre_diag(const float* hefts, const float* means, const float* covs, int D,
                            int G, const Workspace& w, hipStream_t st) {
-  hipLaunchKernelGGL(k_pre_diag, dim3(G), dim3(kNT), 0, st, hefts, means, covs, D, G, w.s, w.m,
-                     w.c, w.c64, w.lamg64);
+  hipLaunchKernelGGL(k_pre_diag<float>, dim3(G), dim3(kNT), 0, st, hefts, means, covs, D, G, w.s,
+                     w.m, w.c, w.c64, w.lamg64);
   return hipGetLastError();
 }
 
@@ -703,41 +837,25 @@ hipError_t launch_em_diag(const float* X, int64_t N, int D, int64_t ldx, int G, 
     return launch_fin_welford(nb, N, D, G, var_floor, hefts, means, covs, mean_loglik,
                               dev_status, w, st);
   }
-  const bool wide = path == GMM_PATH_WIDE_FP64;
-  const int T = wide ? kWT : tile_rows(D, G);
-  const int nb = partial_blocks(N, 4 * T);
-  int64_t chunk = (N + nb - 1) / nb;
-  const size_t lds = estep_lds(D, G, T, wide);
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, dev_status, n_recomputed, w.counters);
-  hipLaunchKernelGGL(k_pre_diag, dim3(G), dim3(kNT), 0, st, hefts, means, covs, D, G, w.s, w.m,
-                     w.c, w.c64, w.lamg64);
-  if (wide)
-    hipLaunchKernelGGL(k_frag_diag64, dim3(16 * ((G + 15) / 16)), dim3(kNT), 0, st, means,
-                       w.lamg64, w.c64, D, G, w.Bx64, w.cq64);
-  {
-    ProfScope ps(kProfEM, st);
-    if (wide)
-      launch_estep_diag<true, true>(nb, lds, st, X, N, D, ldx, G, T, chunk, (const float*)w.s,
-                                    (const float*)w.m, (const float*)w.c, (const double*)w.c64,
-                                    (const double*)w.lamg64, (const double*)w.Bx64, (const double*)w.cq64,
-                                    (const float*)means, w.partials,
-                                    w.scalars, (float*)nullptr, dev_status);
-    else
-      launch_estep_diag<true, false>(nb, lds, st, X, N, D, ldx, G, T, chunk, (const float*)w.s,
-                                     (const float*)w.m, (const float*)w.c, (const double*)w.c64,
-                                     (const double*)w.lamg64, (const double*)w.Bx64, (const double*)w.cq64,
-                                    (const float*)means, w.partials,
-                                     w.scalars, (float*)nullptr, dev_status);
-  }
-  // [2D + 1] FP64 totals: above the 64 KB default for D > 4095
-  const size_t fin_lds = sizeof(double) * (2 * D + 1);
-  if (fin_lds > 64 * 1024)
-    (void)hipFuncSetAttribute((const void*)k_fin_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)fin_lds);
-  hipLaunchKernelGGL(k_fin_diag, dim3(G), dim3(kNT), fin_lds, st, w.partials,
-                     nb, N, D, G, var_floor, hefts, means, covs, w.scalars, mean_loglik,
-                     dev_status);
-  return hipGetLastError();
+  return em_tiles<float>(X, N, D, ldx, G, hefts, hefts, means, covs, (double)var_floor,
+                         path == GMM_PATH_WIDE_FP64, true, mean_loglik, nullptr, n_recomputed,
+                         dev_status, w, st);
+}
+
+hipError_t launch_em_diag_f64(const double* X, int64_t N, int D, int64_t ldx, int G,
+                              double* hefts, double* means, double* covs, double var_floor,
+                              double* mean_loglik, int32_t* dev_status, const Workspace& w,
+                              hipStream_t st) {
+  return em_tiles<double>(X, N, D, ldx, G, hefts, hefts, means, covs, var_floor, true, true,
+                          mean_loglik, nullptr, nullptr, dev_status, w, st);
+}
+
+hipError_t launch_loglik_diag_f64(const double* X, int64_t N, int D, int64_t ldx, int G,
+                                  const double* hefts, const double* means, const double* covs,
+                                  double* mean_loglik, double* per_sample, int32_t* dev_status,
+                                  const Workspace& w, hipStream_t st) {
+  return em_tiles<double>(X, N, D, ldx, G, hefts, nullptr, (double*)means, (double*)covs, 0.0,
+                          true, false, mean_loglik, per_sample, nullptr, dev_status, w, st);
 }
 
 hipError_t launch_log_p_gaussian(const float* X, int64_t N, int D, int64_t ldx, int g,
@@ -770,35 +888,9 @@ hipError_t launch_loglik_diag(const float* X, int64_t N, int D, int64_t ldx, int
                        dev_status);
     return hipGetLastError();
   }
-  const bool wide = path == GMM_PATH_WIDE_FP64;
-  const int T = wide ? kWT : tile_rows(D, G);
-  const int nb = partial_blocks(N, 4 * T);
-  int64_t chunk = (N + nb - 1) / nb;
-  const size_t lds = estep_lds(D, G, T, wide);
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, dev_status, nullptr, w.counters);
-  hipLaunchKernelGGL(k_pre_diag, dim3(G), dim3(kNT), 0, st, hefts, means, covs, D, G, w.s, w.m,
-                     w.c, w.c64, w.lamg64);
-  if (wide)
-    hipLaunchKernelGGL(k_frag_diag64, dim3(16 * ((G + 15) / 16)), dim3(kNT), 0, st, means,
-                       w.lamg64, w.c64, D, G, w.Bx64, w.cq64);
-  {
-    ProfScope ps(kProfLoglik, st);
-    if (wide)
-      launch_estep_diag<false, true>(nb, lds, st, X, N, D, ldx, G, T, chunk, (const float*)w.s,
-                                     (const float*)w.m, (const float*)w.c, (const double*)w.c64,
-                                     (const double*)w.lamg64, (const double*)w.Bx64, (const double*)w.cq64,
-                                    (const float*)means, w.partials,
-                                     w.scalars, per_sample, dev_status);
-    else
-      launch_estep_diag<false, false>(nb, lds, st, X, N, D, ldx, G, T, chunk, (const float*)w.s,
-                                      (const float*)w.m, (const float*)w.c, (const double*)w.c64,
-                                      (const double*)w.lamg64, (const double*)w.Bx64, (const double*)w.cq64,
-                                    (const float*)means, w.partials,
-                                      w.scalars, per_sample, dev_status);
-  }
-  hipLaunchKernelGGL(k_ll_finish, dim3(1), dim3(64), 0, st, w.scalars, nb, N, mean_loglik,
-                     dev_status);
-  return hipGetLastError();
+  return em_tiles<float>(X, N, D, ldx, G, hefts, nullptr, (float*)means, (float*)covs, 0.0,
+                         path == GMM_PATH_WIDE_FP64, false, mean_loglik, per_sample, nullptr,
+                         dev_status, w, st);
 }
 
 }  // namespace gmm

@@ -592,6 +592,26 @@ hipError_t launch_loglik_diag(const float* X, int64_t N, int D, int64_t ldx, int
                               double* mean_loglik, float* per_sample, int32_t* dev_status,
                               const Workspace& w, hipStream_t st);
 
+// FP64 data (diagonal): the tile kernels in FP64 throughout
+bool em_f64_supported(int D, int G);
+hipError_t launch_em_diag_f64(const double* X, int64_t N, int D, int64_t ldx, int G,
+                              double* hefts, double* means, double* covs, double var_floor,
+                              double* mean_loglik, int32_t* dev_status, const Workspace& w,
+                              hipStream_t st);
+hipError_t launch_loglik_diag_f64(const double* X, int64_t N, int D, int64_t ldx, int G,
+                                  const double* hefts, const double* means, const double* covs,
+                                  double* mean_loglik, double* per_sample, int32_t* dev_status,
+                                  const Workspace& w, hipStream_t st);
+
+hipError_t launch_global_stats_f64(const double* X, int64_t N, int D, int64_t ldx, double* mean,
+                                   double* var, const Workspace& w, hipStream_t st);
+bool kmeans_f64_supported(int D);
+hipError_t launch_kmeans_f64(const double* X, int64_t N, int D, int64_t ldx, int G, int dist,
+                             const double* gvar, double var_floor, double* means, double* dcovs,
+                             double* hefts, int64_t* counts, int32_t* assign, double* inertia,
+                             int64_t* n_recomputed, int32_t* dev_status, const Workspace& w,
+                             hipStream_t st);
+
 hipError_t launch_em_full(const float* X, int64_t N, int D, int64_t ldx, int G, float* hefts,
                           float* means, float* covs, float var_floor, double* mean_loglik,
                           int64_t* n_recomputed, int32_t* dev_status, const Workspace& w,

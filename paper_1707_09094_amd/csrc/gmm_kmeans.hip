@@ -145,12 +145,13 @@ __global__ void __launch_bounds__(kNT) k_km_accum(const float* __restrict__ X, i
 // Reduce step, one workgroup per component.  The inertia term of the
 // component, sum_d lam_d sum_i (x_id - mu_gd)^2 about the input mean, comes
 // from the same partials and is left in ig[g] for k_km_inertia.
+template <typename XT>
 __global__ void __launch_bounds__(kNT) k_km_fin(const double* __restrict__ part, int nb, int64_t N,
-                                                int D, int G, float var_floor,
+                                                int D, int G, double var_floor,
                                                 const double* __restrict__ lam64,
-                                                float* __restrict__ means,
-                                                float* __restrict__ dcovs,
-                                                float* __restrict__ hefts,
+                                                XT* __restrict__ means,
+                                                XT* __restrict__ dcovs,
+                                                XT* __restrict__ hefts,
                                                 int64_t* __restrict__ counts,
                                                 double* __restrict__ ig) {
   extern __shared__ double tot[];
@@ -166,7 +167,7 @@ __global__ void __launch_bounds__(kNT) k_km_fin(const double* __restrict__ part,
   const double c = tot[0];
   if (threadIdx.x == 0) {
     counts[g] = (int64_t)c;
-    hefts[g] = (float)(c / (double)N);
+    hefts[g] = (XT)(c / (double)N);
   }
   double in = 0.0;
   for (int d = threadIdx.x; d < D; d += kNT) {
@@ -175,11 +176,11 @@ __global__ void __launch_bounds__(kNT) k_km_fin(const double* __restrict__ part,
       const double dm = tot[1 + d] / c;
       double v = tot[1 + D + d] / c - dm * dm;
       v = v > 0.0 ? v : 0.0;
-      v = v > (double)var_floor ? v : (double)var_floor;
-      means[(size_t)g * D + d] = (float)((double)means[(size_t)g * D + d] + dm);
-      dcovs[(size_t)g * D + d] = (float)v;
+      v = v > var_floor ? v : var_floor;
+      means[(size_t)g * D + d] = (XT)((double)means[(size_t)g * D + d] + dm);
+      dcovs[(size_t)g * D + d] = (XT)v;
     } else {
-      dcovs[(size_t)g * D + d] = 1.0f;
+      dcovs[(size_t)g * D + d] = (XT)1;
     }
   }
   in = block_sum_d<kNT>(in, sh);
@@ -199,11 +200,12 @@ __global__ void k_km_inertia(const double* __restrict__ ig, int G, double* __res
 
 // Dead-mean resurrection (Sec. 3.1), one workgroup.  rem/taken live in the
 // (now free) partials area.
-__global__ void __launch_bounds__(kRT) k_km_resurrect(const float* __restrict__ X, int64_t N,
+template <typename XT>
+__global__ void __launch_bounds__(kRT) k_km_resurrect(const XT* __restrict__ X, int64_t N,
                                                       int D, int64_t ldx, int G,
                                                       const int64_t* __restrict__ counts,
                                                       const int32_t* __restrict__ assign,
-                                                      float* __restrict__ means,
+                                                      XT* __restrict__ means,
                                                       int64_t* __restrict__ scratch) {
   __shared__ int any_dead;
   __shared__ long long s_val[kRT];
@@ -405,8 +407,9 @@ __global__ void __launch_bounds__(kNT) k_assign(const float* __restrict__ X, int
 // X2 = sum_d lam_d x_d^2, since sum_d |lam mu x| <= sqrt(Q X2).
 
 // Fragments and Q_g; block 16 cb + n writes mean g = 16 cb + n (zero past G).
+template <typename XT>
 __global__ void __launch_bounds__(kNT) k_km_pre_f64(const double* __restrict__ lam64,
-                                                    const float* __restrict__ means, int D, int G,
+                                                    const XT* __restrict__ means, int D, int G,
                                                     double* __restrict__ Bk,
                                                     double* __restrict__ Qg) {
   __shared__ double sh[kNT];
@@ -452,14 +455,14 @@ __device__ __forceinline__ void km_merge_dpp(double& v1, int& g1, double& v2) {
 // then the 16 lanes of a row, then the waves through LDS); a sample whose gap
 // v2 - v1 exceeds twice the bound is decided, the others are re-decided over
 // all means in the FP64 direct form, first minimum wins.
-template <int KQM>
+template <int KQM, typename XT>
 __global__ void __launch_bounds__(kWNT) k_km_assign_f64(
-    const float* __restrict__ X, int64_t N, int D, int64_t ldx, int G, int64_t chunk,
+    const XT* __restrict__ X, int64_t N, int D, int64_t ldx, int G, int64_t chunk,
     const double* __restrict__ Bk, const double* __restrict__ Qg,
-    const float* __restrict__ means, const double* __restrict__ lam64,
+    const XT* __restrict__ means, const double* __restrict__ lam64,
     int32_t* __restrict__ assign, int64_t* __restrict__ n_recomputed) {
   constexpr int NW = kWNT / kWave;
-  __shared__ float xs[kWT * 129];
+  __shared__ XT xs[kWT * 129];
   __shared__ double l64[128];
   __shared__ double wv1[NW][kWT], wv2[NW][kWT];
   __shared__ int wg1[NW][kWT];
@@ -489,7 +492,7 @@ __global__ void __launch_bounds__(kWNT) k_km_assign_f64(
     const int nt = (int)min((int64_t)kWT, i1 - t0);
     for (int p = tid; p < nt * XS; p += kWNT) {
       const int t = p / XS, d = p - t * XS;
-      xs[p] = d < D ? X[(t0 + t) * ldx + d] : 0.0f;
+      xs[p] = d < D ? X[(t0 + t) * ldx + d] : (XT)0;
     }
     __syncthreads();
     double xa[2][KQM];
@@ -557,7 +560,7 @@ __global__ void __launch_bounds__(kWNT) k_km_assign_f64(
       double V1 = wv1[0][t], V2 = wv2[0][t];
       int G1 = wg1[0][t];
       for (int w = 1; w < NW; ++w) km_merge(V1, G1, V2, wv1[w][t], wg1[w][t], wv2[w][t]);
-      const float* x = xs + t * XS;
+      const XT* x = xs + t * XS;
       double X2 = 0.0;
       for (int d = 0; d < D; ++d) X2 += l64[d] * (double)x[d] * (double)x[d];
       const double e = 1.01 * (D + 8.0) * 0x1p-52 * (Qmax + 2.0 * sqrt(Qmax * X2));
@@ -567,7 +570,7 @@ __global__ void __launch_bounds__(kWNT) k_km_assign_f64(
         double best = INFINITY;
         arg = 0;
         for (int g = 0; g < G; ++g) {
-          const float* mu = means + (size_t)g * D;
+          const XT* mu = means + (size_t)g * D;
           double q = 0.0;
           for (int d = 0; d < D; ++d) {
             const double u = (double)x[d] - (double)mu[d];
@@ -605,11 +608,11 @@ __global__ void __launch_bounds__(kWNT) k_km_assign_f64(
 // deterministic.  Output: partials [range][G][2D+1] as the generic kernel.
 constexpr int kAT = 1024;   // threads of the grouped accumulation
 constexpr int kASL = 1024;  // assignments staged per slice
-template <int DPL>
-__global__ void __launch_bounds__(kAT) k_km_accum_grp(const float* __restrict__ X, int64_t N,
+template <int DPL, typename XT>
+__global__ void __launch_bounds__(kAT) k_km_accum_grp(const XT* __restrict__ X, int64_t N,
                                                       int D, int64_t ldx, int G, int GG,
                                                       int64_t chunk,
-                                                      const float* __restrict__ means,
+                                                      const XT* __restrict__ means,
                                                       const int32_t* __restrict__ assign,
                                                       double* __restrict__ part) {
   extern __shared__ double lacc[];
@@ -617,7 +620,7 @@ __global__ void __launch_bounds__(kAT) k_km_accum_grp(const float* __restrict__ 
   const int g0 = blockIdx.y * GG;
   const int gn = min(GG, G - g0);
   const int P = 2 * D + 1;
-  float* mu = (float*)(lacc + (size_t)GG * P);  // [GG][D]
+  XT* mu = (XT*)(lacc + (size_t)GG * P);  // [GG][D]
   int* sa = (int*)(mu + (size_t)GG * D);         // [kASL] group-relative component or -1
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -644,25 +647,25 @@ __global__ void __launch_bounds__(kAT) k_km_accum_grp(const float* __restrict__ 
     int mrel = 0;   // lane p: its group-relative component
     auto flush = [&]() {
       for (int k0 = 0; k0 < cnt; k0 += 8) {
-        float xv[8][DPL];
+        XT xv[8][DPL];
         int rr[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int k = min(k0 + u, cnt - 1);
           const int off = __builtin_amdgcn_readlane(midx, k);
           rr[u] = __builtin_amdgcn_readlane(mrel, k);
-          const float* xr = X + (s0 + off) * ldx;
+          const XT* xr = X + (s0 + off) * ldx;
 #pragma unroll
           for (int j = 0; j < DPL; ++j) {
             const int d = lane + kWave * j;
-            xv[u][j] = d < D ? xr[d] : 0.0f;
+            xv[u][j] = d < D ? xr[d] : (XT)0;
           }
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           if (k0 + u >= cnt) break;
           double* q = lacc + (size_t)rr[u] * P;
-          const float* m = mu + (size_t)rr[u] * D;
+          const XT* m = mu + (size_t)rr[u] * D;
 #pragma unroll
           for (int j = 0; j < DPL; ++j) {
             const int d = lane + kWave * j;
@@ -713,9 +716,8 @@ __global__ void __launch_bounds__(kAT) k_km_accum_grp(const float* __restrict__ 
   for (int p = tid; p < gn * P; p += kAT) pb[p] = lacc[p];
 }
 
-size_t km_accum_grp_lds(int D, int GG) {
-  return sizeof(double) * (size_t)GG * (2 * D + 1) + sizeof(float) * (size_t)GG * D +
-         sizeof(int) * kASL;
+size_t km_accum_grp_lds(int D, int GG, size_t esz = sizeof(float)) {
+  return sizeof(double) * (size_t)GG * (2 * D + 1) + esz * (size_t)GG * D + sizeof(int) * kASL;
 }
 
 __global__ void k_zero_i64(int64_t* p, int n, int32_t* dev_status) {
@@ -728,8 +730,8 @@ __global__ void k_zero_i64(int64_t* p, int n, int32_t* dev_status) {
 bool km_use_wide(int D, int G) { return D <= 128 && G > 128; }
 
 // Largest component group of the grouped map step that fits in LDS (0: none).
-int km_accum_group_max(int D) {
-  const size_t per = sizeof(double) * (2 * (size_t)D + 1) + sizeof(float) * (size_t)D;
+int km_accum_group_max(int D, size_t esz = sizeof(float)) {
+  const size_t per = sizeof(double) * (2 * (size_t)D + 1) + esz * (size_t)D;
   const size_t avail = 160 * 1024 - sizeof(int) * kASL;
   return (int)(avail / per);
 }
@@ -751,6 +753,82 @@ int kmeans_path(int D, int G, int prec) {
   return km_use_wide(D, G) ? GMM_PATH_WIDE_FP64 : GMM_PATH_GENERIC;
 }
 
+namespace {
+
+// The tile kernels of one k-means iteration: assignment (FP64 matrix cores when
+// wide, the only form for FP64 data; else the FP32 direct form with its FP64
+// re-decision), the map step, the reduce step, inertia and resurrection.
+template <typename XT>
+hipError_t kmeans_tiles(const XT* X, int64_t N, int D, int64_t ldx, int G, int dist,
+                        const double* gvar, double var_floor, XT* means, XT* dcovs, XT* hefts,
+                        int64_t* counts, int32_t* asg, double* inertia, bool wide,
+                        int64_t* n_recomputed, int32_t* dev_status, const Workspace& w,
+                        hipStream_t st) {
+  const int nb = partial_blocks(N, 256);
+  const int64_t chunk = (N + nb - 1) / nb;
+  int64_t* nrec = n_recomputed ? n_recomputed : w.counters;
+  hipLaunchKernelGGL(k_km_init, dim3(1), dim3(64), 0, st, dev_status, n_recomputed);
+  hipLaunchKernelGGL(k_km_pre, dim3((D + 255) / 256), dim3(256), 0, st, gvar, D, (float)var_floor,
+                     dist, w.lam64, w.lam32);
+  if (wide) {
+    hipLaunchKernelGGL(k_km_pre_f64<XT>, dim3(16 * ((G + 15) / 16)), dim3(kNT), 0, st,
+                       (const double*)w.lam64, (const XT*)means, D, G, w.Bx64, w.cq64);
+    ProfScope ps(kProfKmAssign, st);
+    if (D <= 64)
+      hipLaunchKernelGGL((k_km_assign_f64<16, XT>), dim3(nb), dim3(kWNT), 0, st, X, N, D, ldx, G,
+                         chunk, (const double*)w.Bx64, (const double*)w.cq64, (const XT*)means,
+                         (const double*)w.lam64, asg, nrec);
+    else
+      hipLaunchKernelGGL((k_km_assign_f64<32, XT>), dim3(nb), dim3(kWNT), 0, st, X, N, D, ldx, G,
+                         chunk, (const double*)w.Bx64, (const double*)w.cq64, (const XT*)means,
+                         (const double*)w.lam64, asg, nrec);
+  } else if constexpr (sizeof(XT) == 4) {
+    ProfScope ps(kProfKmAssign, st);
+    hipLaunchKernelGGL(k_km_assign, dim3(nb), dim3(kNT), 0, st, X, N, D, ldx, G, chunk, means,
+                       w.lam32, w.lam64, asg, nrec);
+  }
+  int nba = nb;  // partial sets of the map step
+  {
+    ProfScope ps(kProfKmAccum, st);
+    const int GGmax = D <= 4 * kWave ? km_accum_group_max(D, sizeof(XT)) : 0;
+    if (GGmax >= 1) {
+      const int ngrp = (G + GGmax - 1) / GGmax;
+      const int GG = (G + ngrp - 1) / ngrp;
+      // about 2048 blocks in all, at least 64 sample ranges (fewer when N is small)
+      const int want = std::max(64, (2048 + ngrp - 1) / ngrp);
+      nba = std::min(partial_blocks(N, 2048), want);
+      const int64_t ach = (N + nba - 1) / nba;
+      const size_t lds = km_accum_grp_lds(D, GG, sizeof(XT));
+      if (D <= kWave) {
+        set_max_lds((const void*)k_km_accum_grp<1, XT>, lds);
+        hipLaunchKernelGGL((k_km_accum_grp<1, XT>), dim3(nba, ngrp), dim3(kAT), lds, st, X, N, D,
+                           ldx, G, GG, ach, (const XT*)means, (const int32_t*)asg, w.partials);
+      } else if (D <= 2 * kWave) {
+        set_max_lds((const void*)k_km_accum_grp<2, XT>, lds);
+        hipLaunchKernelGGL((k_km_accum_grp<2, XT>), dim3(nba, ngrp), dim3(kAT), lds, st, X, N, D,
+                           ldx, G, GG, ach, (const XT*)means, (const int32_t*)asg, w.partials);
+      } else {
+        set_max_lds((const void*)k_km_accum_grp<4, XT>, lds);
+        hipLaunchKernelGGL((k_km_accum_grp<4, XT>), dim3(nba, ngrp), dim3(kAT), lds, st, X, N, D,
+                           ldx, G, GG, ach, (const XT*)means, (const int32_t*)asg, w.partials);
+      }
+    } else if constexpr (sizeof(XT) == 4) {
+      hipLaunchKernelGGL(k_km_accum, dim3(nb), dim3(kNT), 0, st, X, N, D, ldx, G, chunk, means,
+                         asg, w.partials);
+    }
+  }
+  // per-component inertia terms in c64 (unused by k-means)
+  hipLaunchKernelGGL(k_km_fin<XT>, dim3(G), dim3(kNT), sizeof(double) * (2 * D + 1), st,
+                     w.partials, nba, N, D, G, var_floor, (const double*)w.lam64, means, dcovs,
+                     hefts, counts, w.c64);
+  hipLaunchKernelGGL(k_km_inertia, dim3(1), dim3(64), 0, st, w.c64, G, inertia, dev_status);
+  hipLaunchKernelGGL(k_km_resurrect<XT>, dim3(1), dim3(kRT), 0, st, X, N, D, ldx, G,
+                     (const int64_t*)counts, (const int32_t*)asg, means, (int64_t*)w.partials);
+  return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_kmeans(const float* X, int64_t N, int D, int64_t ldx, int G, int dist,
                          const double* gvar, float var_floor, float* means, float* dcovs,
                          float* hefts, int64_t* counts, int32_t* assign, double* inertia,
@@ -766,68 +844,25 @@ hipError_t launch_kmeans(const float* X, int64_t N, int D, int64_t ldx, int G, i
                                       n_recomputed ? n_recomputed : w.counters, dev_status, w, st,
                                       prec);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_km_resurrect, dim3(1), dim3(kRT), 0, st, X, N, D, ldx, G, counts, asg,
-                       means, (int64_t*)w.partials);
+    hipLaunchKernelGGL(k_km_resurrect<float>, dim3(1), dim3(kRT), 0, st, X, N, D, ldx, G,
+                       (const int64_t*)counts, (const int32_t*)asg, means, (int64_t*)w.partials);
     return hipGetLastError();
   }
-  const int nb = partial_blocks(N, 256);
-  const int64_t chunk = (N + nb - 1) / nb;
-  int64_t* nrec = n_recomputed ? n_recomputed : w.counters;
-  hipLaunchKernelGGL(k_km_init, dim3(1), dim3(64), 0, st, dev_status, n_recomputed);
-  hipLaunchKernelGGL(k_km_pre, dim3((D + 255) / 256), dim3(256), 0, st, gvar, D, var_floor, dist,
-                     w.lam64, w.lam32);
-  if (km_use_wide(D, G)) {
-    hipLaunchKernelGGL(k_km_pre_f64, dim3(16 * ((G + 15) / 16)), dim3(kNT), 0, st, w.lam64, means,
-                       D, G, w.Bx64, w.cq64);
-    ProfScope ps(kProfKmAssign, st);
-    if (D <= 64)
-      hipLaunchKernelGGL(k_km_assign_f64<16>, dim3(nb), dim3(kWNT), 0, st, X, N, D, ldx, G, chunk,
-                         w.Bx64, w.cq64, means, w.lam64, asg, nrec);
-    else
-      hipLaunchKernelGGL(k_km_assign_f64<32>, dim3(nb), dim3(kWNT), 0, st, X, N, D, ldx, G, chunk,
-                         w.Bx64, w.cq64, means, w.lam64, asg, nrec);
-  } else {
-    ProfScope ps(kProfKmAssign, st);
-    hipLaunchKernelGGL(k_km_assign, dim3(nb), dim3(kNT), 0, st, X, N, D, ldx, G, chunk, means,
-                       w.lam32, w.lam64, asg, nrec);
-  }
-  int nba = nb;  // partial sets of the map step
-  {
-    ProfScope ps(kProfKmAccum, st);
-    const int GGmax = D <= 4 * kWave ? km_accum_group_max(D) : 0;
-    if (GGmax >= 1) {
-      const int ngrp = (G + GGmax - 1) / GGmax;
-      const int GG = (G + ngrp - 1) / ngrp;
-      // about 2048 blocks in all, at least 64 sample ranges (fewer when N is small)
-      const int want = std::max(64, (2048 + ngrp - 1) / ngrp);
-      nba = std::min(partial_blocks(N, 2048), want);
-      const int64_t ach = (N + nba - 1) / nba;
-      const size_t lds = km_accum_grp_lds(D, GG);
-      if (D <= kWave) {
-        set_max_lds((const void*)k_km_accum_grp<1>, lds);
-        hipLaunchKernelGGL(k_km_accum_grp<1>, dim3(nba, ngrp), dim3(kAT), lds, st, X, N, D, ldx,
-                           G, GG, ach, means, asg, w.partials);
-      } else if (D <= 2 * kWave) {
-        set_max_lds((const void*)k_km_accum_grp<2>, lds);
-        hipLaunchKernelGGL(k_km_accum_grp<2>, dim3(nba, ngrp), dim3(kAT), lds, st, X, N, D, ldx,
-                           G, GG, ach, means, asg, w.partials);
-      } else {
-        set_max_lds((const void*)k_km_accum_grp<4>, lds);
-        hipLaunchKernelGGL(k_km_accum_grp<4>, dim3(nba, ngrp), dim3(kAT), lds, st, X, N, D, ldx,
-                           G, GG, ach, means, asg, w.partials);
-      }
-    } else {
-      hipLaunchKernelGGL(k_km_accum, dim3(nb), dim3(kNT), 0, st, X, N, D, ldx, G, chunk, means,
-                         asg, w.partials);
-    }
-  }
-  // per-component inertia terms in c64 (unused by k-means)
-  hipLaunchKernelGGL(k_km_fin, dim3(G), dim3(kNT), sizeof(double) * (2 * D + 1), st, w.partials,
-                     nba, N, D, G, var_floor, w.lam64, means, dcovs, hefts, counts, w.c64);
-  hipLaunchKernelGGL(k_km_inertia, dim3(1), dim3(64), 0, st, w.c64, G, inertia, dev_status);
-  hipLaunchKernelGGL(k_km_resurrect, dim3(1), dim3(kRT), 0, st, X, N, D, ldx, G, counts, asg,
-                     means, (int64_t*)w.partials);
-  return hipGetLastError();
+  return kmeans_tiles<float>(X, N, D, ldx, G, dist, gvar, (double)var_floor, means, dcovs, hefts,
+                             counts, asg, inertia, km_use_wide(D, G), n_recomputed, dev_status,
+                             w, st);
+}
+
+bool kmeans_f64_supported(int D) { return D >= 1 && D <= 128; }
+
+hipError_t launch_kmeans_f64(const double* X, int64_t N, int D, int64_t ldx, int G, int dist,
+                             const double* gvar, double var_floor, double* means, double* dcovs,
+                             double* hefts, int64_t* counts, int32_t* assign, double* inertia,
+                             int64_t* n_recomputed, int32_t* dev_status, const Workspace& w,
+                             hipStream_t st) {
+  return kmeans_tiles<double>(X, N, D, ldx, G, dist, gvar, var_floor, means, dcovs, hefts, counts,
+                              assign ? assign : w.assign, inertia, true, n_recomputed, dev_status,
+                              w, st);
 }
 
 namespace {

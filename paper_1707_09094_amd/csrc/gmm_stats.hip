@@ -25,8 +25,9 @@ namespace {
 constexpr int kNT = 512;  // threads of k_gstats (two workgroups per CU)
 constexpr int kUnroll = 8;  // loads in flight per thread
 
-template <int VEC>
-__global__ void __launch_bounds__(kNT) k_gstats(const float* __restrict__ X, int64_t N, int D,
+// XT: float (VEC 4 or 1) or double (VEC 2 or 1) samples; VEC values per load.
+template <typename XT, int VEC>
+__global__ void __launch_bounds__(kNT) k_gstats(const XT* __restrict__ X, int64_t N, int D,
                                                 int64_t ldx, int64_t chunk,
                                                 double* __restrict__ part) {
   __shared__ double sh[2 * VEC * kNT];  // [row][group][VEC][S1, S2]
@@ -44,10 +45,10 @@ __global__ void __launch_bounds__(kNT) k_gstats(const float* __restrict__ X, int
 #pragma unroll
   for (int k = 0; k < VEC; ++k) s1[k] = s2[k] = 0.0;
   if (r < R) {
-    float sh0[VEC];
+    XT sh0[VEC];
 #pragma unroll
     for (int k = 0; k < VEC; ++k) sh0[k] = X[min(d0 + k, D - 1)];
-    auto add = [&](const float* v) {
+    auto add = [&](const XT* v) {
 #pragma unroll
       for (int k = 0; k < VEC; ++k) {
         const double t = (double)v[k] - (double)sh0[k];
@@ -55,28 +56,32 @@ __global__ void __launch_bounds__(kNT) k_gstats(const float* __restrict__ X, int
         s2[k] = fma(t, t, s2[k]);
       }
     };
-    auto load = [&](int64_t i, float* v) {
-      const float* p = X + i * ldx + d0;
-      if (VEC == 4) {
+    auto load = [&](int64_t i, XT* v) {
+      const XT* p = X + i * ldx + d0;
+      if constexpr (VEC == 4) {
         const float4 q = *(const float4*)p;
         v[0] = q.x;
         v[1] = q.y;
         v[2] = q.z;
         v[3] = q.w;
+      } else if constexpr (VEC == 2) {
+        const double2 q = *(const double2*)p;
+        v[0] = q.x;
+        v[1] = q.y;
       } else {
         v[0] = *p;
       }
     };
     int64_t i = i0 + r;
     for (; i + (kUnroll - 1) * (int64_t)R < i1; i += kUnroll * (int64_t)R) {
-      float v[kUnroll][VEC];
+      XT v[kUnroll][VEC];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) load(i + u * (int64_t)R, v[u]);
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) add(v[u]);
     }
     for (; i < i1; i += R) {
-      float v[VEC];
+      XT v[VEC];
       load(i, v);
       add(v);
     }
@@ -102,17 +107,29 @@ __global__ void __launch_bounds__(kNT) k_gstats(const float* __restrict__ X, int
 }
 
 // mean_d = s_d + S1_d / N, var_d = S2_d / N - (S1_d / N)^2, the workgroups'
-// partials summed in order.
-__global__ void __launch_bounds__(kNT) k_gstats_finish(const float* __restrict__ X,
+// partials summed in order.  One workgroup per dimension: its threads load the
+// nb partials into LDS together, then one thread adds them in order (the
+// arithmetic of a plain sequential loop, without its chain of dependent
+// loads).
+constexpr int kFT = 256;
+template <typename XT>
+__global__ void __launch_bounds__(kFT) k_gstats_finish(const XT* __restrict__ X,
                                                        const double* __restrict__ part, int nb,
                                                        int D, int64_t N,
                                                        double* __restrict__ mean,
                                                        double* __restrict__ var) {
-  for (int d = blockIdx.x * kNT + threadIdx.x; d < D; d += gridDim.x * kNT) {
+  __shared__ double s1[kMaxBlocks], s2[kMaxBlocks];
+  const int d = blockIdx.x;
+  for (int b = threadIdx.x; b < nb; b += kFT) {
+    s1[b] = part[(size_t)b * 2 * D + d];
+    s2[b] = part[(size_t)b * 2 * D + D + d];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
     double a = 0.0, e = 0.0;
     for (int b = 0; b < nb; ++b) {
-      a += part[(size_t)b * 2 * D + d];
-      e += part[(size_t)b * 2 * D + D + d];
+      a += s1[b];
+      e += s2[b];
     }
     const double m1 = a / (double)N;
     const double v = e / (double)N - m1 * m1;
@@ -121,24 +138,38 @@ __global__ void __launch_bounds__(kNT) k_gstats_finish(const float* __restrict__
   }
 }
 
+template <typename XT>
+hipError_t global_stats_t(const XT* X, int64_t N, int D, int64_t ldx, double* mean, double* var,
+                          const Workspace& w, hipStream_t st) {
+  // the partial region holds kMaxBlocks x (2D + 1) doubles
+  const int nb = partial_blocks(N, 1024);
+  const int64_t chunk = (N + nb - 1) / nb;
+  constexpr int V = sizeof(XT) == 4 ? 4 : 2;  // 16-byte loads
+  const bool vec = D % V == 0 && ldx % V == 0 && ((uintptr_t)X) % 16 == 0;
+  const int C = vec ? D / V : D;
+  const dim3 grid(nb, (C + kNT - 1) / kNT);
+  ProfScope ps(kProfStats, st);
+  if (vec)
+    hipLaunchKernelGGL((k_gstats<XT, V>), grid, dim3(kNT), 0, st, X, N, D, ldx, chunk,
+                       w.partials);
+  else
+    hipLaunchKernelGGL((k_gstats<XT, 1>), grid, dim3(kNT), 0, st, X, N, D, ldx, chunk,
+                       w.partials);
+  hipLaunchKernelGGL(k_gstats_finish<XT>, dim3(D), dim3(kFT), 0, st, X,
+                     (const double*)w.partials, nb, D, N, mean, var);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_global_stats(const float* X, int64_t N, int D, int64_t ldx, double* mean,
                                double* var, const Workspace& w, hipStream_t st) {
-  // the partial region holds kMaxBlocks x (2D + 1) doubles
-  const int nb = partial_blocks(N, 1024);
-  const int64_t chunk = (N + nb - 1) / nb;
-  const bool v4 = D % 4 == 0 && ldx % 4 == 0 && ((uintptr_t)X) % 16 == 0;
-  const int C = v4 ? D / 4 : D;
-  const dim3 grid(nb, (C + kNT - 1) / kNT);
-  ProfScope ps(kProfStats, st);
-  if (v4)
-    hipLaunchKernelGGL(k_gstats<4>, grid, dim3(kNT), 0, st, X, N, D, ldx, chunk, w.partials);
-  else
-    hipLaunchKernelGGL(k_gstats<1>, grid, dim3(kNT), 0, st, X, N, D, ldx, chunk, w.partials);
-  hipLaunchKernelGGL(k_gstats_finish, dim3((D + kNT - 1) / kNT), dim3(kNT), 0, st, X, w.partials,
-                     nb, D, N, mean, var);
-  return hipGetLastError();
+  return global_stats_t<float>(X, N, D, ldx, mean, var, w, st);
+}
+
+hipError_t launch_global_stats_f64(const double* X, int64_t N, int D, int64_t ldx, double* mean,
+                                   double* var, const Workspace& w, hipStream_t st) {
+  return global_stats_t<double>(X, N, D, ldx, mean, var, w, st);
 }
 
 }  // namespace gmm

@@ -66,6 +66,14 @@ _SIGS = {
                     _vp], _i32),
     "gmm_em_iter_noalloc": ([_vp, _i64, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _f32, _i32, _vp,
                              _vp, _vp, _vp], _i32),
+    "gmm_workspace_bytes_f64": ([_i64, _i32, _i32], _sz),
+    "gmm_global_stats_f64": ([_vp, _i64, _i32, _i64, _vp, _vp, _vp, _sz, _vp], _i32),
+    "gmm_kmeans_iter_f64": ([_vp, _i64, _i32, _i64, _i32, _i32, _vp, ctypes.c_double, _vp, _vp,
+                             _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
+    "gmm_em_iter_f64": ([_vp, _i64, _i32, _i64, _i32, _vp, _vp, _vp, ctypes.c_double, _vp, _vp,
+                         _vp, _sz, _vp], _i32),
+    "gmm_loglik_f64": ([_vp, _i64, _i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
+                        _vp], _i32),
     "gmm_em_path": ([_i32, _i32, _i32, _i32], _i32),
     "gmm_kmeans_path": ([_i32, _i32, _i32], _i32),
     "gmm_profile_enable": ([_i32], _i32),
@@ -283,6 +291,76 @@ def gmm_assign(X, mode, hefts, means, dcovs, assign, hist, dev_status, ws, strea
         _ptr(hist, torch.int64, (G,), "hist", optional=True),
         _ptr(dev_status, torch.int32, (1,), "dev_status"), wp, wn, _stream(stream))
     _check("gmm_assign", rc)
+
+
+# ---- FP64 data (gmm_*_f64): X float64 (N, D), parameters float64 -----------
+
+def _xptr64(X):
+    if not isinstance(X, torch.Tensor) or not X.is_cuda or X.dtype != torch.float64 or X.dim() != 2:
+        raise ValueError("X must be a float64 (N, D) device tensor")
+    N, D = X.shape
+    ldx = X.stride(0) if N > 1 else D
+    if (D > 1 and X.stride(1) != 1) or ldx < D:
+        raise ValueError("X rows must be contiguous samples with row stride >= D")
+    return ctypes.c_void_p(X.data_ptr()), int(N), int(D), int(ldx)
+
+
+def gmm_workspace_bytes_f64(N, D, G):
+    return int(library().gmm_workspace_bytes_f64(int(N), int(D), int(G)))
+
+
+def workspace_f64(N, D, G, device="cuda"):
+    n = gmm_workspace_bytes_f64(N, D, G)
+    if n == 0:
+        raise GmmError("gmm_workspace_bytes_f64", GMM_EINVAL)
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def gmm_global_stats_f64(X, mean_out, var_out, ws, stream=None):
+    xp, N, D, ldx = _xptr64(X)
+    wp, wn = _ws(ws)
+    _check("gmm_global_stats_f64", library().gmm_global_stats_f64(
+        xp, N, D, ldx, _ptr(mean_out, torch.float64, (D,), "mean_out"),
+        _ptr(var_out, torch.float64, (D,), "var_out"), wp, wn, _stream(stream)))
+
+
+def gmm_kmeans_iter_f64(X, dist, gvar, var_floor, means, dcovs, hefts, counts, assign, inertia,
+                        n_recomputed, dev_status, ws, stream=None):
+    xp, N, D, ldx = _xptr64(X)
+    G = means.shape[0]
+    wp, wn = _ws(ws)
+    f = torch.float64
+    _check("gmm_kmeans_iter_f64", library().gmm_kmeans_iter_f64(
+        xp, N, D, ldx, G, int(dist), _ptr(gvar, f, (D,), "gvar", optional=True),
+        float(var_floor), _ptr(means, f, (G, D), "means"), _ptr(dcovs, f, (G, D), "dcovs"),
+        _ptr(hefts, f, (G,), "hefts"), _ptr(counts, torch.int64, (G,), "counts"),
+        _ptr(assign, torch.int32, (N,), "assign", optional=True),
+        _ptr(inertia, f, (1,), "inertia"),
+        _ptr(n_recomputed, torch.int64, (1,), "n_recomputed", optional=True),
+        _ptr(dev_status, torch.int32, (1,), "dev_status"), wp, wn, _stream(stream)))
+
+
+def gmm_em_iter_f64(X, hefts, means, dcovs, var_floor, mean_loglik, dev_status, ws, stream=None):
+    xp, N, D, ldx = _xptr64(X)
+    G = means.shape[0]
+    wp, wn = _ws(ws)
+    f = torch.float64
+    _check("gmm_em_iter_f64", library().gmm_em_iter_f64(
+        xp, N, D, ldx, G, _ptr(hefts, f, (G,), "hefts"), _ptr(means, f, (G, D), "means"),
+        _ptr(dcovs, f, (G, D), "dcovs"), float(var_floor), _ptr(mean_loglik, f, (1,), "mean_loglik"),
+        _ptr(dev_status, torch.int32, (1,), "dev_status"), wp, wn, _stream(stream)))
+
+
+def gmm_loglik_f64(X, hefts, means, dcovs, mean_loglik, per_sample, dev_status, ws, stream=None):
+    xp, N, D, ldx = _xptr64(X)
+    G = means.shape[0]
+    wp, wn = _ws(ws)
+    f = torch.float64
+    _check("gmm_loglik_f64", library().gmm_loglik_f64(
+        xp, N, D, ldx, G, _ptr(hefts, f, (G,), "hefts"), _ptr(means, f, (G, D), "means"),
+        _ptr(dcovs, f, (G, D), "dcovs"), _ptr(mean_loglik, f, (1,), "mean_loglik"),
+        _ptr(per_sample, f, (N,), "per_sample", optional=True),
+        _ptr(dev_status, torch.int32, (1,), "dev_status"), wp, wn, _stream(stream)))
 
 
 def gmm_em_path(D, G, cov=COV_DIAG, prec=PREC_FP32):

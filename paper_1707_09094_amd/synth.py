@@ -31,19 +31,20 @@ class Truth:
     labels: np.ndarray | None = field(default=None, repr=False)
 
 
-def _draw(rng, N, hefts, means, scale_fn):
+def _draw(rng, N, hefts, means, scale_fn, dtype=np.float32):
     G, D = means.shape
     labels = rng.choice(G, size=N, p=hefts).astype(np.int32)
-    X = np.empty((N, D), dtype=np.float32)
+    X = np.empty((N, D), dtype=dtype)
     for s in range(0, N, CHUNK):
         e = min(N, s + CHUNK)
         z = rng.standard_normal((e - s, D))
-        X[s:e] = (means[labels[s:e]] + scale_fn(labels[s:e], z)).astype(np.float32)
+        X[s:e] = (means[labels[s:e]] + scale_fn(labels[s:e], z)).astype(dtype)
     return X, labels
 
 
-def diag_gmm(seed, D, G, N, mean_kind, mean_a, mean_b, var_kind, var_a, var_b):
-    """Ground-truth diagonal GMM and N samples from it.
+def diag_gmm(seed, D, G, N, mean_kind, mean_a, mean_b, var_kind, var_a, var_b, dtype=np.float32):
+    """Ground-truth diagonal GMM and N samples from it (float32, or float64 for
+    the FP64-data path: the same draw without the final rounding).
 
     Generation order: weights -> means -> variances -> labels -> noise.
     mean_kind 'uniform' draws U[mean_a, mean_b]; 'normal' draws N(mean_a, mean_b).
@@ -65,7 +66,7 @@ def diag_gmm(seed, D, G, N, mean_kind, mean_a, mean_b, var_kind, var_a, var_b):
     else:
         raise ValueError(var_kind)
     sd = np.sqrt(var)
-    X, labels = _draw(rng, N, w, mu, lambda lab, z: sd[lab] * z)
+    X, labels = _draw(rng, N, w, mu, lambda lab, z: sd[lab] * z, dtype)
     return X, Truth(w, mu, var, None, labels)
 
 
@@ -87,14 +88,14 @@ def seed_for(cfg_index: int) -> int:
     return 1707 * 10 + cfg_index
 
 
-def config1(N=10_000):
+def config1(N=10_000, dtype=np.float32):
     """D=4, G=4, N=1e4: means U[-5,5], std U[0.5,2], weights Dirichlet(1)."""
-    return diag_gmm(seed_for(1), 4, 4, N, "uniform", -5.0, 5.0, "std_uniform", 0.5, 2.0)
+    return diag_gmm(seed_for(1), 4, 4, N, "uniform", -5.0, 5.0, "std_uniform", 0.5, 2.0, dtype)
 
 
-def config2(N=1_000_000, D=100, G=100):
+def config2(N=1_000_000, D=100, G=100, dtype=np.float32):
     """D=100, G=100, N=1e6: means N(0,4), variances log-U[0.1,10], weights Dirichlet(1)."""
-    return diag_gmm(seed_for(2), D, G, N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
+    return diag_gmm(seed_for(2), D, G, N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0, dtype)
 
 
 def config3(N=8_000_000, D=64, G=512):
@@ -196,7 +197,7 @@ def static_subset(X, G):
     the training samples, the static_subset seed mode)."""
     N = X.shape[0]
     idx = (np.arange(G, dtype=np.int64) * N) // G
-    return np.array(X[idx], dtype=np.float32)
+    return np.array(X[idx], dtype=X.dtype if X.dtype == np.float64 else np.float32)
 
 
 def random_params(rng, D, G, var_lo=0.2, var_hi=3.0, mean_scale=3.0):
