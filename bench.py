@@ -141,13 +141,14 @@ def wide_or_full(gmm, synth, torch, which, steps=1, warmup=1):
             tr_km.kmeans_iter(means, dcovs, hefts, gmm.DIST_MAHA, VAR_FLOOR)
         e2 = ev()
         covs = torch.diag_embed(dcovs).contiguous() if full else dcovs
+        handoff = (hefts.clone(), means.clone(), covs.clone())
         model = Model(hefts, means, covs, cov)
         for _ in range(EM_ITERS):
             tr.em_iter(model, VAR_FLOOR)
         e3 = ev()
         torch.cuda.synchronize()
         return e0.elapsed_time(e3), e1.elapsed_time(e2), e2.elapsed_time(e3), float(
-            tr.scal[1].item())
+            tr.scal[1].item()), handoff
 
     for _ in range(warmup):
         fit()
@@ -173,9 +174,12 @@ def wide_or_full(gmm, synth, torch, which, steps=1, warmup=1):
     else:
         F_E = F_M = 4.0 * N * G * D
         path = gmm.gmm_em_path(D, G, gmm.COV_DIAG, gmm.PREC_BF16X3)
-        form = "bf16x3" if path == gmm.PATH_ONEPASS_BF16X3 else "fp64"
+        form = "bf16x3" if path in (gmm.PATH_ONEPASS_BF16X3, gmm.PATH_SLICED_BF16X3) else "fp64"
         kernel = ("k_estep_diag (exact FP64 log-densities on the matrix cores, FP64 map step)"
-                  if form == "fp64" else "BF16x3 screening kernel")
+                  if form == "fp64" else
+                  "k_em2s x3 (split-BF16 screening over 4 slices of 128 Gaussians: slice "
+                  "maxima; FP64 near pairs and slice sums; responsibilities and Welford map "
+                  "step)")
         work = "diag GMM D=64 G=512 N=8e6 (means N(0,1), variances log-U[0.05,5])"
     r = roof(F_E, F_M, nb, k_em, form)
     out = {"workload": work, "N": N, "D": D, "G": G, "steps": steps,
@@ -187,10 +191,42 @@ def wide_or_full(gmm, synth, torch, which, steps=1, warmup=1):
            "km_accum_ms": round(kc_ms / max(kc_n, 1), 4) if kc_n else None,
            "data": "synthetic, drawn on the device (torch Philox) from the stated recipe"}
     if not full:
-        # the same kernel serves both arithmetic forms at this shape
-        out["em_path_fp32_form"] = gmm.gmm_em_path(D, G, gmm.COV_DIAG, gmm.PREC_FP32)
-        out["em_path_bf16x3_form"] = gmm.gmm_em_path(D, G, gmm.COV_DIAG, gmm.PREC_BF16X3)
-        out["roofline_vs_bf16x3_form_roof"] = roof(F_E, F_M, nb, k_em, "bf16x3")
+        # the two arithmetic forms, EM_ITERS iterations each from the last
+        # step's k-means hand-off: the FP32 form runs the exact FP64
+        # matrix-core kernel at this G, the BF16x3 form the sliced kernels
+        handoff = res[-1][4]
+        forms = {}
+        for name, pr in (("fp32", gmm.PREC_FP32), ("bf16x3", gmm.PREC_BF16X3)):
+            model = Model(*(t.clone() for t in handoff), cov)
+            tr.em_iter(model, VAR_FLOOR, prec=pr)  # first iteration: recompute count
+            torch.cuda.synchronize()
+            nrec = int(tr.i64[1].item())
+            model = Model(*(t.clone() for t in handoff), cov)
+            torch.cuda.synchronize()
+            gmm.gmm_profile_enable(True)
+            a = ev()
+            for _ in range(EM_ITERS):
+                tr.em_iter(model, VAR_FLOOR, prec=pr)
+            b = ev()
+            torch.cuda.synchronize()
+            ms_k, n_k = gmm.gmm_profile_read(gmm.PROF_EM)
+            gmm.gmm_profile_enable(False)
+            final = float(tr.loglik(model, prec=pr).item())
+            torch.cuda.synchronize()
+            kms = ms_k / max(n_k, 1)
+            fm = "fp64" if name == "fp32" else "bf16x3"
+            forms[name] = {"em_path": gmm.gmm_em_path(D, G, gmm.COV_DIAG, pr),
+                           "em_iter_ms": round(a.elapsed_time(b) / EM_ITERS, 3),
+                           "em_kernel_ms": round(kms, 4), "final_loglik": final,
+                           "em_recomputed_first_iter": nrec,
+                           "recompute_fraction": nrec / (float(N) * G),
+                           "roofline": roof(F_E, F_M, nb, kms, fm)}
+        out["forms"] = forms
+        out["bf16x3_vs_fp32_final_loglik_rel_delta"] = abs(
+            forms["bf16x3"]["final_loglik"] - forms["fp32"]["final_loglik"]) / abs(
+            forms["fp32"]["final_loglik"])
+        out["bf16x3_em_speedup"] = round(
+            forms["fp32"]["em_kernel_ms"] / forms["bf16x3"]["em_kernel_ms"], 3)
     del Xd, tr, tr_km
     torch.cuda.empty_cache()
     return out

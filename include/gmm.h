@@ -92,10 +92,11 @@ extern "C" {
 #define GMM_ASSIGN_PROB 1
 
 /* arithmetic of the log-density / distance contraction of the one-pass
- * kernels (diagonal covariances, D <= 128 and G <= 128; gmm_em_path and
- * gmm_kmeans_path report which family a shape runs).  Other shapes compute
- * their log-densities exactly in FP64 (matrix cores for D <= 128) or screen in
- * FP32 with an FP64 recompute, and ignore prec.
+ * kernels (diagonal covariances, D <= 128 and G <= 128) and, for EM and the
+ * log-likelihood, of the sliced kernels (diagonal, D <= 128, G > 128, prec
+ * BF16X3); gmm_em_path and gmm_kmeans_path report which family a shape runs.
+ * Other shapes compute their log-densities exactly in FP64 (matrix cores for
+ * D <= 128) or screen in FP32 with an FP64 recompute, and ignore prec.
  * GMM_PREC_FP32:   direct (x - mu)^2 form in FP32 on the vector ALUs.
  * GMM_PREC_BF16X3: the expanded form x^2 * Lambda - 2 x * (Lambda mu) + const
  *                  as a GEMM on the matrix cores with each FP32 operand split
@@ -164,10 +165,11 @@ int gmm_kmeans_iter(const float* X, int64_t N, int32_t D, int64_t ldx, int32_t G
  *               (the E-step's by-product; EM makes successive values
  *               non-decreasing).
  *   n_recomputed[1] out (may be NULL): diagonal models with D, G <= 128 (the
- *               one-pass kernels, either arithmetic form): number of (sample,
- *               Gaussian) log-densities recomputed exactly, i.e. every pair
- *               whose screened value, widened by its rounding-error bound,
- *               comes within 30 nats of the sample's best; 0 for other shapes
+ *               one-pass kernels, either arithmetic form) or D <= 128 with
+ *               prec BF16X3 (the sliced kernels): number of (sample, Gaussian)
+ *               log-densities recomputed exactly, i.e. every pair whose
+ *               screened value, widened by its rounding-error bound, comes
+ *               within 30 nats of the sample's best; 0 for other shapes
  *               (their log-densities are exact FP64 or recomputed in FP64
  *               without being counted).
  * A Gaussian whose responsibilities sum to exactly 0 gets weight 0 and keeps
@@ -298,9 +300,15 @@ int gmm_loglik_f64(const double* X, int64_t N, int32_t D, int64_t ldx, int32_t G
  *   GMM_PATH_ONEPASS_FP32    the same shapes, prec FP32 (or a shape whose
  *                            matrix-core fragments do not fit): the one-pass
  *                            kernel with the FP32 direct form
- *   GMM_PATH_WIDE_FP64       diagonal, D <= 128, G > 128: every log-density
- *                            (distance) in FP64 on the matrix cores, whatever
- *                            prec says
+ *   GMM_PATH_WIDE_FP64       diagonal, D <= 128, G > 128, prec FP32 (and
+ *                            k-means with either prec): every log-density
+ *                            (distance) in FP64 on the matrix cores
+ *   GMM_PATH_SLICED_BF16X3   EM / log-likelihood, diagonal, D <= 128, G > 128,
+ *                            prec BF16X3: the one-pass kernel's split-BF16
+ *                            screening over slices of at most 128 Gaussians,
+ *                            in three passes (slice maxima; near pairs
+ *                            recomputed in FP64 and slice sums; responsibilities
+ *                            and the map step)
  *   GMM_PATH_GENERIC         diagonal, D > 128: FP32 direct-form screening with
  *                            an FP64 recompute of the near set (prec ignored)
  *   GMM_PATH_FULL_FP64       full covariances, D <= 64: FP64 matrix cores
@@ -312,6 +320,7 @@ int gmm_loglik_f64(const double* X, int64_t N, int32_t D, int64_t ldx, int32_t G
 #define GMM_PATH_GENERIC 4
 #define GMM_PATH_FULL_FP64 5
 #define GMM_PATH_FULL_GENERIC 6
+#define GMM_PATH_SLICED_BF16X3 7
 
 int gmm_em_path(int32_t D, int32_t G, int32_t cov, int32_t prec);
 int gmm_kmeans_path(int32_t D, int32_t G, int32_t prec);

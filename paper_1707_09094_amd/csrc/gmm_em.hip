@@ -808,6 +808,7 @@ hipError_t em_tiles(const XT* X, int64_t N, int D, int64_t ldx, int G, const XT*
 int em_diag_path(int D, int G, int prec) {
   if (em_fast_supported(D, G, prec))
     return prec == GMM_PREC_BF16X3 ? GMM_PATH_ONEPASS_BF16X3 : GMM_PATH_ONEPASS_FP32;
+  if (prec == GMM_PREC_BF16X3 && G > 128 && em2s_supported(D, G)) return GMM_PATH_SLICED_BF16X3;
   return use_wide(D, G) ? GMM_PATH_WIDE_FP64 : GMM_PATH_GENERIC;
 }
 
@@ -833,6 +834,14 @@ hipError_t launch_em_diag(const float* X, int64_t N, int D, int64_t ldx, int G, 
     // k_pre_fast clears the status word and the counters
     hipError_t e = launch_em_fast(X, N, D, ldx, G, hefts, means, covs, prec, true, n_recomputed,
                                   nullptr, dev_status, w, st, &nb);
+    if (e != hipSuccess) return e;
+    return launch_fin_welford(nb, N, D, G, var_floor, hefts, means, covs, mean_loglik,
+                              dev_status, w, st);
+  }
+  if (path == GMM_PATH_SLICED_BF16X3) {
+    int nb = 0;
+    hipError_t e = launch_em_sliced(X, N, D, ldx, G, hefts, means, covs, true, n_recomputed,
+                                    nullptr, dev_status, w, st, &nb);
     if (e != hipSuccess) return e;
     return launch_fin_welford(nb, N, D, G, var_floor, hefts, means, covs, mean_loglik,
                               dev_status, w, st);
@@ -883,6 +892,15 @@ hipError_t launch_loglik_diag(const float* X, int64_t N, int D, int64_t ldx, int
     // k_pre_fast clears the status word and the counters
     hipError_t e = launch_em_fast(X, N, D, ldx, G, hefts, means, covs, prec, false, nullptr,
                                   per_sample, dev_status, w, st, &nb);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ll_finish, dim3(1), dim3(64), 0, st, w.scalars, nb, N, mean_loglik,
+                       dev_status);
+    return hipGetLastError();
+  }
+  if (path == GMM_PATH_SLICED_BF16X3) {
+    int nb = 0;
+    hipError_t e = launch_em_sliced(X, N, D, ldx, G, hefts, means, covs, false, nullptr,
+                                    per_sample, dev_status, w, st, &nb);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_ll_finish, dim3(1), dim3(64), 0, st, w.scalars, nb, N, mean_loglik,
                        dev_status);

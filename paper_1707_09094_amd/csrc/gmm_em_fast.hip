@@ -72,6 +72,12 @@ struct FastArgs {
   float* per_sample;        // [N] or null
   int32_t* dev_status;
   int64_t* n_rec;           // or null
+  // component slices (sliced passes only): the pass works on components
+  // g0 .. g0 + G - 1 of Gt; per-sample, per-slice arrays [S][NS]
+  int g0, Gt, Gs, sl, S;
+  int64_t NS;
+  float* wM;                // bounded maximum of the slice's values
+  float* wS;                // sum over the slice of exp(value - M), M the global bound
 };
 
 // LDS layout of k_em_fast: the direct-form parameters are staged (ps, pm); the
@@ -821,12 +827,26 @@ __device__ inline Lds2 carve_lds2(char* base, int G, int KS) {
 
 // Fragments are laid out for KST = 4 DPL k-steps (16 dimensions each, zero
 // past D), so every LDS offset below is a compile-time immediate.
-template <int CPW, int DPL, bool MSTEP>
+//
+// MODE 0: one pass over all G components (G <= 128).  With more components
+// than one workgroup's LDS holds, three passes over slices of them, each
+// workgroup (b, slice) screening its slice for its sample range:
+//   MODE 1  the slice's bounded maximum per sample -> wM[slice][n];
+//   MODE 2  the global bound M = max over slices, the slice's near pairs
+//           recomputed exactly, sum over the slice of exp(value - M)
+//           -> wS[slice][n];
+//   MODE 3  log-sum-exp M + log(sum over slices of wS) (Eqs. 16-18),
+//           the responsibilities and the map step of the slice's components.
+// Near pairs are the same in MODES 2 and 3 (same bound, same M) and always
+// recomputed in FP64, so both passes see the same exact values.
+template <int CPW, int DPL, bool MSTEP, int MODE = 0>
 __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t i1, int b,
                                           char* lds_raw) {
   constexpr int RBT = (CPW + 1) / 2;  // row blocks of 16 components
   constexpr int KST = 4 * DPL;        // k-steps of 16 dimensions
   const int D = a.D, G = a.G;
+  const int g0 = MODE ? a.g0 : 0;   // first component of the slice
+  const int Gt = MODE ? a.Gt : G;   // components of the model
   const int DP = D + 1;
   const int P = 2 * D + 1;
   const int RB = (G + 15) / 16;
@@ -837,20 +857,25 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
   const int KSr = (2 * D + 31) / 32;  // k-steps holding data
   const float ecoef = err_expanded_coef(KSr);
 
-  for (int p = tid; p < RB * KST * 64; p += kThreads) {
-    L.wh[p] = a.Whi[p];
-    L.wl[p] = a.Wlo[p];
+  {
+    const bf16x8* const whs = a.Whi + (size_t)(g0 / 16) * KST * 64;
+    const bf16x8* const wls = a.Wlo + (size_t)(g0 / 16) * KST * 64;
+    for (int p = tid; p < RB * KST * 64; p += kThreads) {
+      L.wh[p] = whs[p];
+      L.wl[p] = wls[p];
+    }
   }
   for (int g = tid; g < 16 * RB; g += kThreads) {
     float* q = L.cq + 8 * g;
     if (g < G) {
-      const float c = a.cc[g];
-      const float Q = 2.0f * ((c + a.cc[G + g]) - (a.cexp[g] + a.cexp[G + g]));
+      const int gg = g0 + g;
+      const float c = a.cc[gg];
+      const float Q = 2.0f * ((c + a.cc[Gt + gg]) - (a.cexp[gg] + a.cexp[Gt + gg]));
       q[0] = c;
       q[1] = isfinite(Q) ? 1.0001f * fmaxf(Q, 0.0f) : 0.0f;
-      q[2] = a.cc[G + g];
-      q[3] = a.cexp[g];
-      q[4] = a.cexp[G + g];
+      q[2] = a.cc[Gt + gg];
+      q[3] = a.cexp[gg];
+      q[4] = a.cexp[Gt + gg];
     } else {  // padding component: value -inf
       q[0] = 0.0f;
       q[1] = 0.0f;
@@ -859,7 +884,9 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
       q[4] = 0.0f;
     }
   }
-  if (tid < 2) L.need[tid] = 0;
+  if (MODE == 0 || MODE == 3) {
+    if (tid < 2) L.need[tid] = 0;
+  }
 
   // owner accumulators: component g = w + 8 c, dimension d = lane + 64 j
   float Lc[CPW], S1[CPW][DPL], S2[CPW][DPL];
@@ -956,12 +983,32 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
       for (int j = 0; j < 4; ++j) {
         const float v = vj[j] ? (acc[cb][j] + eh) + el : -INFINITY;
         acc[cb][j] = v;
-        M[j] = fmaxf(M[j], v - err_expanded(2.0f * (ch - v), Qg, ch, ecoef));
+        if (MODE < 2) M[j] = fmaxf(M[j], v - err_expanded(2.0f * (ch - v), Qg, ch, ecoef));
       }
       __builtin_amdgcn_sched_barrier(0);
     }
+    if constexpr (MODE < 2) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) M[j] = row16_max(M[j]);
+      for (int j = 0; j < 4; ++j) M[j] = row16_max(M[j]);
+    } else {
+      // the bound over all slices
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (vj[j]) {
+          const float* pm = a.wM + s0 + 4 * rowq + j;
+          float m = -INFINITY;
+          for (int q = 0; q < a.S; ++q) m = fmaxf(m, pm[(size_t)q * a.NS]);
+          M[j] = m;
+        }
+    }
+    if constexpr (MODE == 1) {
+      if (colc == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (vj[j]) a.wM[(size_t)a.sl * a.NS + s0 + 4 * rowq + j] = M[j];
+      }
+      continue;
+    }
     uint32_t nearb = 0;  // bit 4 cb + j
 #pragma unroll
     for (int cb = 0; cb < RBT; ++cb) {
@@ -993,7 +1040,7 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
         }
       }
     }
-    nrec += np;
+    if (MODE != 2) nrec += np;
 
     // 4. exact values of the near pairs, kCapR at a time
     for (int c0 = 0; c0 < np; c0 += kCapR) {
@@ -1018,14 +1065,15 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
           const int n = code & 15, g = code >> 8;
           const float* xr = a.X + (s0 + n) * a.ldx;
           const float Mn = mw[n];
-          bool ex64 = cw[n] >= 2;
+          const int gg = g0 + g;
+          bool ex64 = MODE != 0 || cw[n] >= 2;
           float xv[NE];
 #pragma unroll
           for (int i = 0; i < NE; ++i) xv[i] = xr[min(l16 + 16 * i, D - 1)];
           double val = 0.0;
           if (!ex64) {
-            const float* sg = a.prm + (size_t)g * DP;
-            const float* mg = a.prm + (size_t)G * DP + (size_t)g * DP;
+            const float* sg = a.prm + (size_t)gg * DP;
+            const float* mg = a.prm + (size_t)Gt * DP + (size_t)gg * DP;
             float sv[NE], mv[NE];
 #pragma unroll
             for (int i = 0; i < NE; ++i) {
@@ -1045,8 +1093,8 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
             ex64 = !(err_direct(q, qg[1], qg[0], D) <= kExactTol);
           }
           if (ex64) {
-            const float* mu_g = a.means + (size_t)g * D;
-            const double* lg = a.lam64 + (size_t)g * D;
+            const float* mu_g = a.means + (size_t)gg * D;
+            const double* lg = a.lam64 + (size_t)gg * D;
             float mv[NE];
             double lv[NE];
 #pragma unroll
@@ -1062,7 +1110,7 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
               q = l16 + 16 * i < D ? q + u * u * lv[i] : q;
             }
             q = row16_sum(q);
-            val = a.c64[g] - 0.5 * q;
+            val = a.c64[gg] - 0.5 * q;
           }
           if (l16 == 0) rval[p] = (float)(val - (double)Mn);
         }
@@ -1081,8 +1129,47 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
     }
 
     // 5. log-sum-exp about M + max(near - M) (Eqs. 16-18) and responsibilities
+    if constexpr (MODE == 2) {
+      // the slice's sum of exp(value - M)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double sm = 0.0;
+#pragma unroll
+        for (int cb = 0; cb < RBT; ++cb) {
+          const bool nr = (nearb >> (4 * cb + j)) & 1u;
+          sm += (double)__expf(nr ? acc[cb][j] : acc[cb][j] - M[j]);
+        }
+        sm = row16_sum(sm);
+        if (vj[j] && colc == 0) a.wS[(size_t)a.sl * a.NS + s0 + 4 * rowq + j] = (float)sm;
+      }
+      continue;
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
+      if constexpr (MODE == 3) {
+        // lse = M + log(sum over slices, in slice order)
+        double tot = 0.0;
+        if (vj[j]) {
+          const float* ps = a.wS + s0 + 4 * rowq + j;
+          for (int q = 0; q < a.S; ++q) tot += (double)ps[(size_t)q * a.NS];
+        }
+        const double lsd = log(tot);
+        const float dl = (float)lsd;
+        const double lse = (double)M[j] + lsd;
+        if (vj[j] && colc == 0 && g0 == 0) {
+          llacc += lse;
+          if (!isfinite(lse)) bad = 1;
+          if (a.per_sample) a.per_sample[s0 + 4 * rowq + j] = (float)lse;
+        }
+#pragma unroll
+        for (int cb = 0; cb < RBT; ++cb) {
+          const bool nr = (nearb >> (4 * cb + j)) & 1u;
+          const float z = (nr ? acc[cb][j] : acc[cb][j] - M[j]) - dl;
+          acc[cb][j] = (vj[j] && z >= -kRespCut) ? __expf(z) : 0.0f;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        continue;
+      }
       float dm = -INFINITY;
 #pragma unroll
       for (int cb = 0; cb < RBT; ++cb)
@@ -1194,7 +1281,7 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
           for (int c = 0; c < CPW; ++c) {
             const int cc = cnt[c];
             if (cc > 0) {
-              const int g = wo + kNW * c;
+              const int g = g0 + wo + kNW * c;
               float mu[DPL];
 #pragma unroll
               for (int jd = 0; jd < DPL; ++jd)
@@ -1240,8 +1327,9 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
     }
   }
 
+  if constexpr (MODE == 1 || MODE == 2) return;
   if (MSTEP) {
-    double* pb = a.part + (size_t)b * G * P;
+    double* pb = a.part + (size_t)b * Gt * P + (size_t)g0 * P;
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
       const int g = w + kNW * c;
@@ -1258,6 +1346,9 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
       }
     }
   }
+  if (a.n_rec && lane == 0 && nrec)
+    atomicAdd((unsigned long long*)a.n_rec, (unsigned long long)nrec);
+  if (MODE == 3 && g0 != 0) return;  // the first slice holds the log-likelihood
   {
     const double v = wave_sum_d(llacc);
     if (lane == 0) L.llw[w] = v;
@@ -1270,7 +1361,6 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
     a.ll_part[b] = s;
   }
   if (bad) atomicOr(a.dev_status, GMM_DEV_NONFINITE);
-  if (a.n_rec && lane == 0 && nrec) atomicAdd((unsigned long long*)a.n_rec, (unsigned long long)nrec);
 }
 
 template <int CPW, int DPL, bool MSTEP>
@@ -1280,6 +1370,57 @@ __global__ void __launch_bounds__(kThreads) k_em2(FastArgs a) {
   const int64_t i0 = (int64_t)b * a.chunk;
   const int64_t i1 = min(a.N, i0 + a.chunk);
   em2_range<CPW, DPL, MSTEP>(a, i0, i1, b, lds_raw);
+}
+
+// One sliced pass (MODE 1, 2 or 3): grid (work ranges, slices); slice s holds
+// components Gs s .. min(Gs (s + 1), Gt) - 1.
+template <int DPL, int MODE>
+__global__ void __launch_bounds__(kThreads) k_em2s(FastArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const int b = blockIdx.x;
+  FastArgs s = a;
+  s.sl = blockIdx.y;
+  s.g0 = s.sl * s.Gs;
+  s.G = min(s.Gs, s.Gt - s.g0);
+  const int64_t i0 = (int64_t)b * a.chunk;
+  const int64_t i1 = min(a.N, i0 + a.chunk);
+  em2_range<16, DPL, MODE == 3, MODE>(s, i0, i1, b, lds_raw);
+}
+
+// Log-likelihood of the sliced passes without the map step: per sample
+// lse = M + log(sum over slices of wS) (the arithmetic of MODE 3), the
+// workgroup's samples summed per thread and the threads in order.
+constexpr int kWllT = 256;
+__global__ void __launch_bounds__(kWllT) k_wll(const float* __restrict__ wM,
+                                               const float* __restrict__ wS, int S, int64_t NS,
+                                               int64_t N, int64_t chunk,
+                                               float* __restrict__ per_sample,
+                                               double* __restrict__ ll_part,
+                                               int32_t* __restrict__ dev_status) {
+  __shared__ double sh[kWllT];
+  const int b = blockIdx.x;
+  const int64_t i0 = (int64_t)b * chunk;
+  const int64_t i1 = min(N, i0 + chunk);
+  double acc = 0.0;
+  int bad = 0;
+  for (int64_t n = i0 + threadIdx.x; n < i1; n += kWllT) {
+    float m = -INFINITY;
+    double tot = 0.0;
+    for (int q = 0; q < S; ++q) m = fmaxf(m, wM[(size_t)q * NS + n]);
+    for (int q = 0; q < S; ++q) tot += (double)wS[(size_t)q * NS + n];
+    const double lse = (double)m + log(tot);
+    acc += lse;
+    if (!isfinite(lse)) bad = 1;
+    if (per_sample) per_sample[n] = (float)lse;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < kWllT; ++i) t += sh[i];
+    ll_part[b] = t;
+  }
+  if (bad) atomicOr(dev_status, GMM_DEV_NONFINITE);
 }
 
 template <int CPW, int DPL, bool MSTEP>
@@ -1381,19 +1522,121 @@ void dispatch_em2(const FastArgs& a, int nb, size_t lds, hipStream_t st) {
   }
 }
 
-}  // namespace
-
-bool em_fast_supported(int D, int G, int prec) {
-  if (D < 1 || D > 128 || G < 1 || G > 128) return false;
-  if (prec == GMM_PREC_BF16X3) return em2_lds_bytes(G, em2_ks(D)) <= 160 * 1024;
-  return fast_lds_bytes(D, G) <= 160 * 1024;
+// LDS of the sliced passes: MODE 1 uses the fragments and constants, MODE 2
+// also the near-pair buffers, MODE 3 all of it.
+size_t em2s_lds_bytes(int Gs, int KS, int mode) {
+  const int upto = mode == 1 ? 3 : (mode == 2 ? 7 : -1);
+  if (upto < 0) return em2_lds_bytes(Gs, KS);
+  size_t r = 0;
+  lds2_walk(Gs, KS, [&](int which, size_t off) {
+    if (which == upto) r = off;
+  });
+  return r * 4 + 64;
 }
+
+template <int DPL, int MODE>
+void launch_em2s_one(const FastArgs& a, int nb, hipStream_t st) {
+  auto kern = k_em2s<DPL, MODE>;
+  static bool attr_set = false;  // benign race: setting the attribute twice is harmless
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(nb, a.S), dim3(kThreads), em2s_lds_bytes(a.Gs, a.KS, MODE), st,
+                     a);
+}
+
+}  // namespace
 
 int em_fast_blocks(int64_t N) {
   int64_t b = (N + kT * 4 - 1) / (kT * 4);
   if (b < 1) b = 1;
   if (b > 256) b = 256;
   return (int)b;
+}
+
+// components per slice: the largest multiple of 16 (at most 128) whose LDS
+// fits one CU, then evened out over the slices
+int em2s_slice_max(int D) {
+  if (D < 1 || D > 128) return 0;
+  for (int gs = 128; gs >= 16; gs -= 16)
+    if (em2_lds_bytes(gs, em2_ks(D)) <= 160 * 1024) return gs;
+  return 0;
+}
+
+bool em2s_supported(int D, int G) { return G >= 1 && em2s_slice_max(D) > 0; }
+
+int em2s_slices(int D, int G) {
+  const int gm = em2s_slice_max(D);
+  return gm > 0 && G >= 1 ? (G + gm - 1) / gm : 0;
+}
+
+hipError_t launch_em_sliced(const float* X, int64_t N, int D, int64_t ldx, int G,
+                            const float* hefts, const float* means, const float* covs, bool mstep,
+                            int64_t* n_recomputed, float* per_sample, int32_t* dev_status,
+                            const Workspace& w, hipStream_t st, int* nb_out) {
+  const int KS = em2_ks(D);
+  const int S = em2s_slices(D, G);
+  if (S < 1 || !w.wM || !w.wS) return hipErrorInvalidValue;
+  const int Gs = 16 * (((G + S - 1) / S + 15) / 16);
+  const int nb0 = em_fast_blocks(N);
+  FastArgs a;
+  a.X = X;
+  a.N = N;
+  a.ldx = ldx;
+  a.chunk = ((N + nb0 - 1) / nb0 + kRoundN - 1) / kRoundN * kRoundN;
+  const int nb = (int)((N + a.chunk - 1) / a.chunk);
+  a.D = D;
+  a.G = Gs;
+  a.KS = KS;
+  a.prm = w.prm;
+  a.cc = w.c;
+  a.cexp = w.cexp;
+  a.Whi = (const bf16x8*)w.Bhi;
+  a.Wlo = (const bf16x8*)w.Blo;
+  a.c64 = w.c64;
+  a.lam64 = w.lamg64;
+  a.means = means;
+  a.part = w.partials;
+  a.ll_part = w.scalars;
+  a.per_sample = per_sample;
+  a.dev_status = dev_status;
+  a.n_rec = n_recomputed;
+  a.g0 = 0;
+  a.Gt = G;
+  a.Gs = Gs;
+  a.sl = 0;
+  a.S = S;
+  a.NS = N;
+  a.wM = w.wM;
+  a.wS = w.wS;
+  hipLaunchKernelGGL(k_pre_fast, dim3(16 * ((G + 15) / 16)), dim3(256), 0, st, hefts, means,
+                     covs, D, G, KS, w.prm, w.c, w.cexp, (bf16x8*)w.Bhi, (bf16x8*)w.Blo, w.c64,
+                     w.lamg64, dev_status, n_recomputed, w.counters);
+  {
+    ProfScope ps(mstep ? kProfEM : kProfLoglik, st);
+    if (D <= 64) {
+      launch_em2s_one<1, 1>(a, nb, st);
+      launch_em2s_one<1, 2>(a, nb, st);
+      if (mstep) launch_em2s_one<1, 3>(a, nb, st);
+    } else {
+      launch_em2s_one<2, 1>(a, nb, st);
+      launch_em2s_one<2, 2>(a, nb, st);
+      if (mstep) launch_em2s_one<2, 3>(a, nb, st);
+    }
+    if (!mstep)
+      hipLaunchKernelGGL(k_wll, dim3(nb), dim3(kWllT), 0, st, (const float*)w.wM,
+                         (const float*)w.wS, S, N, N, a.chunk, per_sample, w.scalars, dev_status);
+  }
+  *nb_out = nb;
+  return hipGetLastError();
+}
+
+bool em_fast_supported(int D, int G, int prec) {
+  if (D < 1 || D > 128 || G < 1 || G > 128) return false;
+  if (prec == GMM_PREC_BF16X3) return em2_lds_bytes(G, em2_ks(D)) <= 160 * 1024;
+  return fast_lds_bytes(D, G) <= 160 * 1024;
 }
 
 hipError_t launch_em_fast(const float* X, int64_t N, int D, int64_t ldx, int G, const float* hefts,

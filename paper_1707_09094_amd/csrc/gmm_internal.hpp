@@ -191,8 +191,14 @@ struct Workspace {
   double* lam64;      // [D] k-means distance weights (FP64)
   float* lam32;       // [D] the same rounded to FP32
   int64_t* counters;  // [8] device counters
+  float* wM;          // sliced BF16x3 E-step: [S][N] per-slice bounded maxima
+  float* wS;          // [S][N] per-slice sums of exp(value - M)
   size_t bytes;
 };
+
+// component slices of the sliced BF16x3 E-step (0: the shape has no such path)
+int em2s_slices(int D, int G);
+bool em_fast_supported(int D, int G, int prec);
 
 // expanded-form depth (features) of the MFMA fragments: 128 or 256 for the
 // one-pass kernels (D <= 64 / D <= 128), padded to 32 beyond
@@ -250,6 +256,12 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   size_t o_l64 = take(sizeof(double) * (size_t)D);
   size_t o_l32 = take(sizeof(float) * (size_t)D);
   size_t o_ct = take(sizeof(int64_t) * 8);
+  // per-slice arrays of the sliced BF16x3 E-step (diagonal, more components
+  // than the one-pass kernel holds)
+  const int nsl = cov == GMM_COV_DIAG && !em_fast_supported(D, G, GMM_PREC_BF16X3)
+                      ? em2s_slices(D, G) : 0;
+  size_t o_wm = take(sizeof(float) * (size_t)nsl * N);
+  size_t o_ws = take(sizeof(float) * (size_t)nsl * N);
   w->bytes = off;
   if (!base) return true;
   if (avail < off) return false;
@@ -276,6 +288,8 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   w->lam64 = (double*)(b + o_l64);
   w->lam32 = (float*)(b + o_l32);
   w->counters = (int64_t*)(b + o_ct);
+  w->wM = nsl ? (float*)(b + o_wm) : nullptr;
+  w->wS = nsl ? (float*)(b + o_ws) : nullptr;
   return true;
 }
 
@@ -577,6 +591,14 @@ hipError_t launch_em_fast(const float* X, int64_t N, int D, int64_t ldx, int G, 
                           const float* means, const float* covs, int prec, bool mstep,
                           int64_t* n_recomputed, float* per_sample, int32_t* dev_status,
                           const Workspace& w, hipStream_t st, int* nb_out);
+
+// EM / log-likelihood over component slices (BF16x3, D <= 128, any G): see
+// em2_range; nb_out: work ranges of the partials
+bool em2s_supported(int D, int G);
+hipError_t launch_em_sliced(const float* X, int64_t N, int D, int64_t ldx, int G,
+                            const float* hefts, const float* means, const float* covs, bool mstep,
+                            int64_t* n_recomputed, float* per_sample, int32_t* dev_status,
+                            const Workspace& w, hipStream_t st, int* nb_out);
 
 hipError_t launch_fin_welford(int nb, int64_t N, int D, int G, float var_floor, float* hefts,
                               float* means, float* covs, double* mean_loglik, int32_t* dev_status,

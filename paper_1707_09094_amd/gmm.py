@@ -32,7 +32,7 @@ DIST_EUCL, DIST_MAHA = 0, 1
 ASSIGN_EUCL, ASSIGN_PROB = 0, 1
 PREC_FP32, PREC_BF16X3 = 0, 1
 (PATH_ONEPASS_BF16X3, PATH_ONEPASS_FP32, PATH_WIDE_FP64, PATH_GENERIC, PATH_FULL_FP64,
- PATH_FULL_GENERIC) = range(1, 7)
+ PATH_FULL_GENERIC, PATH_SLICED_BF16X3) = range(1, 8)
 
 
 class GmmError(RuntimeError):

@@ -107,8 +107,10 @@ def test_kernel_path_selection():
     assert P.gmm_em_path(100, 100, P.COV_DIAG, P.PREC_BF16X3) == P.PATH_ONEPASS_BF16X3
     assert P.gmm_em_path(100, 100, P.COV_DIAG, P.PREC_FP32) == P.PATH_ONEPASS_FP32
     for prec in (P.PREC_FP32, P.PREC_BF16X3):
-        assert P.gmm_em_path(64, 512, P.COV_DIAG, prec) == P.PATH_WIDE_FP64
-        assert P.gmm_em_path(100, 300, P.COV_DIAG, prec) == P.PATH_WIDE_FP64
+        want = P.PATH_SLICED_BF16X3 if prec == P.PREC_BF16X3 else P.PATH_WIDE_FP64
+        assert P.gmm_em_path(64, 512, P.COV_DIAG, prec) == want
+        assert P.gmm_em_path(100, 300, P.COV_DIAG, prec) == want
+        assert P.gmm_em_path(128, 129, P.COV_DIAG, prec) == want
         assert P.gmm_em_path(200, 5, P.COV_DIAG, prec) == P.PATH_GENERIC
         assert P.gmm_em_path(32, 64, P.COV_FULL, prec) == P.PATH_FULL_FP64
         assert P.gmm_em_path(80, 3, P.COV_FULL, prec) == P.PATH_FULL_GENERIC

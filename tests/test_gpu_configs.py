@@ -111,14 +111,18 @@ def test_headline_size_kmeans_and_em_steps(G_, oracle):
 # ------------------------------------------------ D=64, G=512 on 512 workgroups
 def test_wide_config_on_full_grid_and_determinism(G_, oracle):
     """The D=64/G=512 recipe at N=65,536 (the 512-workgroup grid of the FP64
-    matrix-core kernels): a Mahalanobis k-means step and an EM step from its
-    hand-off against the oracle, and the EM step run twice bit for bit (its
-    map step adds FP64 partials with order-fixed atomics)."""
+    matrix-core kernels): a Mahalanobis k-means step and an EM step of each
+    arithmetic form from its hand-off against the oracle (FP32 form: the FP64
+    matrix-core kernel; BF16x3 form: the sliced split-BF16 kernels, four
+    slices of 128), the two forms' log-likelihoods within 1e-7 of each other,
+    and each EM step run twice bit for bit (the FP64 kernel's map step adds
+    partials with order-fixed atomics)."""
     X, _ = synth.config3(N=65_536)
     N, D = X.shape
     G = 512
+    assert G_.gmm_em_path(D, G, G_.COV_DIAG, 0) == G_.PATH_WIDE_FP64
+    assert G_.gmm_em_path(D, G, G_.COV_DIAG, 1) == G_.PATH_SLICED_BF16X3
     for prec in (0, 1):
-        assert G_.gmm_em_path(D, G, G_.COV_DIAG, prec) == G_.PATH_WIDE_FP64
         assert G_.gmm_kmeans_path(D, G, prec) == G_.PATH_WIDE_FP64
     r = Runner(G_, X, G)
     _, gv = oracle.global_stats(X)
@@ -129,11 +133,17 @@ def test_wide_config_on_full_grid_and_determinism(G_, oracle):
     assert gk["status"] == 0
     check_kmeans(gk, oracle.kmeans_iter(X, mu, lam, 1e-10), oracle.kmeans_dists(X, mu, lam), N)
     w, mu1, var = gk["hefts"], gk["means"], gk["dcovs"]
-    a = r.em(w, mu1, var)
-    assert a["status"] == 0
-    check_em(a, oracle.em_iter(X, w, mu1, var, 1e-10), N)
-    b = r.em(w, mu1, var)
-    _same(a, b)
+    ref = oracle.em_iter(X, w, mu1, var, 1e-10)
+    out = {}
+    for prec in (0, 1):
+        a = r.em(w, mu1, var, prec=prec)
+        assert a["status"] == 0
+        check_em(a, ref, N)
+        b = r.em(w, mu1, var, prec=prec)
+        _same(a, b)
+        out[prec] = a
+    assert abs(out[0]["loglik"] - out[1]["loglik"]) <= 1e-7 * abs(ref.mean_loglik)
+    assert out[1]["nrec"] >= N
 
 
 # ------------------------------------------------ full covariances

@@ -114,26 +114,35 @@ def test_em_step_diag(G_, oracle, N, D, G, prec):
     check_em(gpu, ref, N)
 
 
-# shapes outside the one-pass envelope: their kernels ignore the arithmetic
-# form (asserted through the dispatch query), so each runs once
+# shapes outside the one-pass envelope: G > 128 runs the FP64 matrix-core
+# kernel for the FP32 form and the sliced split-BF16 kernels for the BF16x3
+# form; D > 128 runs the generic kernel for both (asserted through the
+# dispatch query)
 EM_OTHER = [
     (1500, 200, 5, "generic"),
     (2500, 8, 150, "wide"),
     (5000, 64, 512, "wide"),
     (3001, 100, 300, "wide"),
+    (3001, 128, 200, "wide"),   # two dimensions per lane, slices below 128
+    (129, 33, 129, "wide"),     # slices of 80 and 49, ragged round
 ]
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
 @pytest.mark.parametrize("N,D,G,path", EM_OTHER)
-def test_em_step_diag_beyond_onepass(G_, oracle, N, D, G, path):
-    want = G_.PATH_WIDE_FP64 if path == "wide" else G_.PATH_GENERIC
-    for prec in (0, 1):
-        assert G_.gmm_em_path(D, G, G_.COV_DIAG, prec) == want
+def test_em_step_diag_beyond_onepass(G_, oracle, N, D, G, path, prec):
+    if path == "generic":
+        want = G_.PATH_GENERIC
+    else:
+        want = G_.PATH_SLICED_BF16X3 if prec else G_.PATH_WIDE_FP64
+    assert G_.gmm_em_path(D, G, G_.COV_DIAG, prec) == want
     X, _ = synth.diag_gmm(1000 + N + D, D, max(G, 2), N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
     w, mu, var = _params(N * 7 + G, D, G, X if N >= G else None)
-    gpu = gpu_em_step(G_, X, w, mu, var, 1e-10, prec=1)
+    gpu = gpu_em_step(G_, X, w, mu, var, 1e-10, prec=prec)
     assert gpu["status"] == 0
     check_em(gpu, oracle.em_iter(X, w, mu, var, 1e-10), N)
+    if want == G_.PATH_SLICED_BF16X3:
+        assert gpu["nrec"] >= N  # every sample's best component is recomputed
 
 
 @pytest.mark.parametrize("N,D,G", [(200_000, 100, 100), (50_000, 40, 64)])
@@ -288,7 +297,8 @@ def test_em_row_stride(G_, oracle):
 # ---------------------------------------------------------------- loglik
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
 @pytest.mark.parametrize("N,D,G", [(10_000, 4, 4), (777, 33, 9), (1, 2, 1), (3000, 100, 100),
-                                   (900, 150, 3), (3001, 64, 300), (2000, 100, 260)])
+                                   (900, 150, 3), (3001, 64, 300), (2000, 100, 260),
+                                   (1, 5, 140)])
 def test_loglik_diag(G_, oracle, N, D, G, prec):
     X, _ = synth.diag_gmm(77 + N, D, max(G, 2), N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
     w, mu, var = _params(8, D, G, X if N >= G else None)
