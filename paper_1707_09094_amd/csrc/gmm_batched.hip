@@ -1,6 +1,7 @@
 // gmm_batched.hip -- shared pieces of the many-model entry points: the
 // on-device work list (a model's samples cut into consecutive items of
-// `chunk` samples, models in index order) and per-model status reset.
+// `chunk` samples, grouped by the model's component-block count, largest
+// first) and per-model status reset.
 // Building the list on the device keeps an iteration free of host copies,
 // so a sequence of batched calls can be captured into a graph.
 #include "gmm_internal.hpp"
@@ -9,51 +10,82 @@ namespace gmm {
 
 namespace {
 
-// One workgroup.  mitems[m] = (first item, item count); items in model order.
-// A model whose descriptor is unusable gets no items; if the descriptors ask
-// for more items than the host sized (`cap`), no model gets any.
+// One workgroup.  mitems[m] = (first item, item count).  Items are grouped
+// by the model's block count RB = ceil(G / 16), largest first: an item's cost
+// grows with RB, so the persistent grid takes the longest items first and
+// neighbouring workgroups run the same kernel variant; models keep index
+// order within a group and a model's items stay consecutive.  A model whose
+// descriptor is unusable gets no items; if the descriptors ask for more items
+// than the host sized (`cap`), no model gets any.
 __global__ void __launch_bounds__(1024) k_batch_plan(const gmm_model_desc* models, int n_models,
                                                      int Gmax, int64_t chunk, int cap,
                                                      BatchItemDev* items, int2* mitems,
                                                      int* n_items) {
   __shared__ int part_sum[1024];
   __shared__ int overflow;
+  __shared__ int run_sh;
   const int tid = threadIdx.x;
   // per-thread contiguous block of models
   const int per = (n_models + 1023) / 1024;
   const int m0 = min(n_models, tid * per), m1 = min(n_models, m0 + per);
+  auto count = [&](int m) -> int64_t {
+    return batch_desc_ok(models[m], Gmax) ? (models[m].N + chunk - 1) / chunk : 0;
+  };
   int64_t local = 0;
-  for (int m = m0; m < m1; ++m)
-    if (batch_desc_ok(models[m], Gmax)) local += (models[m].N + chunk - 1) / chunk;
+  for (int m = m0; m < m1; ++m) local += count(m);
   part_sum[tid] = (int)min(local, (int64_t)cap + 1);
   __syncthreads();
   if (tid == 0) {
     int64_t run = 0;
-    for (int t = 0; t < 1024; ++t) {
-      const int v = part_sum[t];
-      part_sum[t] = (int)min(run, (int64_t)cap);
-      run += v;
-    }
+    for (int t = 0; t < 1024; ++t) run += part_sum[t];
     overflow = run > cap;
     *n_items = run > cap ? 0 : (int)run;
+    run_sh = 0;
   }
   __syncthreads();
-  int first = part_sum[tid];
+  const bool ovf = overflow != 0;
   for (int m = m0; m < m1; ++m) {
     const gmm_model_desc& md = models[m];
-    const bool ok = batch_desc_ok(md, Gmax) && !overflow;
-    const int cnt = ok ? (int)((md.N + chunk - 1) / chunk) : 0;
-    mitems[m] = make_int2(first, cnt);
-    for (int k = 0; k < cnt; ++k) {
-      BatchItemDev it;
-      it.model = m;
-      it.first_of_model = first;
-      it.i0 = (int64_t)k * chunk;
-      it.i1 = min(md.N, (int64_t)(k + 1) * chunk);
-      items[first + k] = it;
-    }
+    const bool ok = batch_desc_ok(md, Gmax) && !ovf;
+    if (!ok) mitems[m] = make_int2(0, 0);
     if (md.dev_status) *md.dev_status = ok ? 0 : GMM_DEV_BADDESC;
-    first += cnt;
+  }
+  if (ovf) return;
+  const int RBmax = (Gmax + 15) / 16;
+  for (int rb = RBmax; rb >= 1; --rb) {
+    auto in_group = [&](int m) { return (models[m].G + 15) / 16 == rb; };
+    int mine = 0;
+    for (int m = m0; m < m1; ++m)
+      if (in_group(m)) mine += (int)count(m);
+    part_sum[tid] = mine;
+    __syncthreads();
+    if (tid == 0) {
+      int run = run_sh;
+      for (int t = 0; t < 1024; ++t) {
+        const int v = part_sum[t];
+        part_sum[t] = run;
+        run += v;
+      }
+      run_sh = run;
+    }
+    __syncthreads();
+    int first = part_sum[tid];
+    for (int m = m0; m < m1; ++m) {
+      if (!in_group(m)) continue;
+      const gmm_model_desc& md = models[m];
+      const int cnt = (int)count(m);
+      mitems[m] = make_int2(first, cnt);
+      for (int k = 0; k < cnt; ++k) {
+        BatchItemDev it;
+        it.model = m;
+        it.first_of_model = first;
+        it.i0 = (int64_t)k * chunk;
+        it.i1 = min(md.N, (int64_t)(k + 1) * chunk);
+        items[first + k] = it;
+      }
+      first += cnt;
+    }
+    __syncthreads();
   }
 }
 

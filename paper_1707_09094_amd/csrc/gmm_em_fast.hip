@@ -77,7 +77,8 @@ struct FastArgs {
   int g0, Gt, Gs, sl, S;
   int64_t NS;
   float* wM;                // bounded maximum of the slice's values
-  float* wS;                // sum over the slice of exp(value - M), M the global bound
+  float* wD;                // reference of the slice's sum: largest exact near value - M
+  float* wS;                // sum over the slice of exp(value - M - wD)
 };
 
 // LDS layout of k_em_fast: the direct-form parameters are staged (ps, pm); the
@@ -825,6 +826,20 @@ __device__ inline Lds2 carve_lds2(char* base, int G, int KS) {
   return L;
 }
 
+// A sample's log-sum-exp less M from its per-slice references D_q and sums
+// S_q: D* = max_q D_q (returned) and log(sum over slices of S_q exp(D_q - D*))
+// (in ls); the total is D* + ls.
+__device__ __forceinline__ float slice_lse(const float* pd, const float* ps, int S, int64_t NS,
+                                           double& ls) {
+  float dstar = -INFINITY;
+  for (int q = 0; q < S; ++q) dstar = fmaxf(dstar, pd[(size_t)q * NS]);
+  double tot = 0.0;
+  for (int q = 0; q < S; ++q)
+    tot += (double)ps[(size_t)q * NS] * exp((double)pd[(size_t)q * NS] - (double)dstar);
+  ls = log(tot);
+  return dstar;
+}
+
 // Fragments are laid out for KST = 4 DPL k-steps (16 dimensions each, zero
 // past D), so every LDS offset below is a compile-time immediate.
 //
@@ -833,10 +848,12 @@ __device__ inline Lds2 carve_lds2(char* base, int G, int KS) {
 // workgroup (b, slice) screening its slice for its sample range:
 //   MODE 1  the slice's bounded maximum per sample -> wM[slice][n];
 //   MODE 2  the global bound M = max over slices, the slice's near pairs
-//           recomputed exactly, sum over the slice of exp(value - M)
-//           -> wS[slice][n];
-//   MODE 3  log-sum-exp M + log(sum over slices of wS) (Eqs. 16-18),
-//           the responsibilities and the map step of the slice's components.
+//           recomputed exactly, their largest value less M (0 without near
+//           pairs) -> wD[slice][n] and the slice's sum of
+//           exp(value - M - wD) -> wS[slice][n];
+//   MODE 3  log-sum-exp M + D* + log(sum over slices of
+//           wS exp(wD - D*)), D* = max over slices of wD (Eqs. 16-18), the
+//           responsibilities and the map step of the slice's components.
 // Near pairs are the same in MODES 2 and 3 (same bound, same M) and always
 // recomputed in FP64, so both passes see the same exact values.
 template <int CPW, int DPL, bool MSTEP, int MODE = 0>
@@ -887,6 +904,7 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
   if (MODE == 0 || MODE == 3) {
     if (tid < 2) L.need[tid] = 0;
   }
+
 
   // owner accumulators: component g = w + 8 c, dimension d = lane + 64 j
   float Lc[CPW], S1[CPW][DPL], S2[CPW][DPL];
@@ -1130,32 +1148,41 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
 
     // 5. log-sum-exp about M + max(near - M) (Eqs. 16-18) and responsibilities
     if constexpr (MODE == 2) {
-      // the slice's sum of exp(value - M)
+      // the slice's sum about its largest exact near value (an exact value
+      // can lie far above M when its screening bound is wide)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
+        float dm = -INFINITY;
+#pragma unroll
+        for (int cb = 0; cb < RBT; ++cb)
+          if ((nearb >> (4 * cb + j)) & 1u) dm = fmaxf(dm, acc[cb][j]);
+        dm = row16_max(dm);
+        const float dn = dm > -INFINITY ? dm : 0.0f;
         double sm = 0.0;
 #pragma unroll
         for (int cb = 0; cb < RBT; ++cb) {
           const bool nr = (nearb >> (4 * cb + j)) & 1u;
-          sm += (double)__expf(nr ? acc[cb][j] : acc[cb][j] - M[j]);
+          sm += (double)__expf((nr ? acc[cb][j] : acc[cb][j] - M[j]) - dn);
         }
         sm = row16_sum(sm);
-        if (vj[j] && colc == 0) a.wS[(size_t)a.sl * a.NS + s0 + 4 * rowq + j] = (float)sm;
+        if (vj[j] && colc == 0) {
+          const size_t o = (size_t)a.sl * a.NS + s0 + 4 * rowq + j;
+          a.wD[o] = dn;
+          a.wS[o] = (float)sm;
+        }
       }
       continue;
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if constexpr (MODE == 3) {
-        // lse = M + log(sum over slices, in slice order)
-        double tot = 0.0;
-        if (vj[j]) {
-          const float* ps = a.wS + s0 + 4 * rowq + j;
-          for (int q = 0; q < a.S; ++q) tot += (double)ps[(size_t)q * a.NS];
-        }
-        const double lsd = log(tot);
-        const float dl = (float)lsd;
-        const double lse = (double)M[j] + lsd;
+        // lse = M + D* + log(sum over slices in slice order)
+        double lsd = 0.0;
+        float dstar = 0.0f;
+        if (vj[j])
+          dstar = slice_lse(a.wD + s0 + 4 * rowq + j, a.wS + s0 + 4 * rowq + j, a.S, a.NS, lsd);
+        const float ls = (float)lsd;
+        const double lse = ((double)M[j] + (double)dstar) + lsd;
         if (vj[j] && colc == 0 && g0 == 0) {
           llacc += lse;
           if (!isfinite(lse)) bad = 1;
@@ -1164,7 +1191,7 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
 #pragma unroll
         for (int cb = 0; cb < RBT; ++cb) {
           const bool nr = (nearb >> (4 * cb + j)) & 1u;
-          const float z = (nr ? acc[cb][j] : acc[cb][j] - M[j]) - dl;
+          const float z = ((nr ? acc[cb][j] : acc[cb][j] - M[j]) - dstar) - ls;
           acc[cb][j] = (vj[j] && z >= -kRespCut) ? __expf(z) : 0.0f;
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -1388,10 +1415,11 @@ __global__ void __launch_bounds__(kThreads) k_em2s(FastArgs a) {
 }
 
 // Log-likelihood of the sliced passes without the map step: per sample
-// lse = M + log(sum over slices of wS) (the arithmetic of MODE 3), the
+// lse = M + slice_lse (the arithmetic of MODE 3), the
 // workgroup's samples summed per thread and the threads in order.
 constexpr int kWllT = 256;
 __global__ void __launch_bounds__(kWllT) k_wll(const float* __restrict__ wM,
+                                               const float* __restrict__ wD,
                                                const float* __restrict__ wS, int S, int64_t NS,
                                                int64_t N, int64_t chunk,
                                                float* __restrict__ per_sample,
@@ -1405,10 +1433,10 @@ __global__ void __launch_bounds__(kWllT) k_wll(const float* __restrict__ wM,
   int bad = 0;
   for (int64_t n = i0 + threadIdx.x; n < i1; n += kWllT) {
     float m = -INFINITY;
-    double tot = 0.0;
     for (int q = 0; q < S; ++q) m = fmaxf(m, wM[(size_t)q * NS + n]);
-    for (int q = 0; q < S; ++q) tot += (double)wS[(size_t)q * NS + n];
-    const double lse = (double)m + log(tot);
+    double ls;
+    const float dstar = slice_lse(wD + n, wS + n, S, NS, ls);
+    const double lse = ((double)m + (double)dstar) + ls;
     acc += lse;
     if (!isfinite(lse)) bad = 1;
     if (per_sample) per_sample[n] = (float)lse;
@@ -1454,7 +1482,11 @@ __global__ void __launch_bounds__(kThreads) k_em2_batched(FastArgs base,
     a.per_sample = nullptr;
     a.dev_status = m.dev_status;
     a.n_rec = nullptr;
-    em2_range<CPW, DPL, MSTEP>(a, item.i0, item.i1, 0, lds_raw);
+    // the smallest component-block template that holds the model's G
+    if (CPW > 2 && a.G <= 16) em2_range<(CPW > 2 ? 2 : CPW), DPL, MSTEP>(a, item.i0, item.i1, 0, lds_raw);
+    else if (CPW > 4 && a.G <= 32) em2_range<(CPW > 4 ? 4 : CPW), DPL, MSTEP>(a, item.i0, item.i1, 0, lds_raw);
+    else if (CPW > 8 && a.G <= 64) em2_range<(CPW > 8 ? 8 : CPW), DPL, MSTEP>(a, item.i0, item.i1, 0, lds_raw);
+    else em2_range<CPW, DPL, MSTEP>(a, item.i0, item.i1, 0, lds_raw);
     __syncthreads();
   }
 }
@@ -1578,7 +1610,7 @@ hipError_t launch_em_sliced(const float* X, int64_t N, int D, int64_t ldx, int G
                             const Workspace& w, hipStream_t st, int* nb_out) {
   const int KS = em2_ks(D);
   const int S = em2s_slices(D, G);
-  if (S < 1 || !w.wM || !w.wS) return hipErrorInvalidValue;
+  if (S < 1 || !w.wM || !w.wD || !w.wS) return hipErrorInvalidValue;
   const int Gs = 16 * (((G + S - 1) / S + 15) / 16);
   const int nb0 = em_fast_blocks(N);
   FastArgs a;
@@ -1610,6 +1642,7 @@ hipError_t launch_em_sliced(const float* X, int64_t N, int D, int64_t ldx, int G
   a.S = S;
   a.NS = N;
   a.wM = w.wM;
+  a.wD = w.wD;
   a.wS = w.wS;
   hipLaunchKernelGGL(k_pre_fast, dim3(16 * ((G + 15) / 16)), dim3(256), 0, st, hefts, means,
                      covs, D, G, KS, w.prm, w.c, w.cexp, (bf16x8*)w.Bhi, (bf16x8*)w.Blo, w.c64,
@@ -1627,7 +1660,8 @@ hipError_t launch_em_sliced(const float* X, int64_t N, int D, int64_t ldx, int G
     }
     if (!mstep)
       hipLaunchKernelGGL(k_wll, dim3(nb), dim3(kWllT), 0, st, (const float*)w.wM,
-                         (const float*)w.wS, S, N, N, a.chunk, per_sample, w.scalars, dev_status);
+                         (const float*)w.wD, (const float*)w.wS, S, N, N, a.chunk, per_sample,
+                         w.scalars, dev_status);
   }
   *nb_out = nb;
   return hipGetLastError();

@@ -192,7 +192,8 @@ struct Workspace {
   float* lam32;       // [D] the same rounded to FP32
   int64_t* counters;  // [8] device counters
   float* wM;          // sliced BF16x3 E-step: [S][N] per-slice bounded maxima
-  float* wS;          // [S][N] per-slice sums of exp(value - M)
+  float* wD;          // [S][N] per-slice references of the sums
+  float* wS;          // [S][N] per-slice sums of exp(value - M - reference)
   size_t bytes;
 };
 
@@ -261,6 +262,7 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   const int nsl = cov == GMM_COV_DIAG && !em_fast_supported(D, G, GMM_PREC_BF16X3)
                       ? em2s_slices(D, G) : 0;
   size_t o_wm = take(sizeof(float) * (size_t)nsl * N);
+  size_t o_wd = take(sizeof(float) * (size_t)nsl * N);
   size_t o_ws = take(sizeof(float) * (size_t)nsl * N);
   w->bytes = off;
   if (!base) return true;
@@ -289,6 +291,7 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   w->lam32 = (float*)(b + o_l32);
   w->counters = (int64_t*)(b + o_ct);
   w->wM = nsl ? (float*)(b + o_wm) : nullptr;
+  w->wD = nsl ? (float*)(b + o_wd) : nullptr;
   w->wS = nsl ? (float*)(b + o_ws) : nullptr;
   return true;
 }

@@ -1237,7 +1237,11 @@ __global__ void __launch_bounds__(kThreads) k_km2_batched(Km2Args base,
     a.in_part = base.in_part + it;
     a.n_rec = nullptr;
     a.dev_status = m.dev_status;
-    km2_range<CPW, DPL>(a, item.i0, item.i1, 0, lds_raw);
+    // the smallest component-block template that holds the model's G
+    if (CPW > 2 && a.G <= 16) km2_range<(CPW > 2 ? 2 : CPW), DPL>(a, item.i0, item.i1, 0, lds_raw);
+    else if (CPW > 4 && a.G <= 32) km2_range<(CPW > 4 ? 4 : CPW), DPL>(a, item.i0, item.i1, 0, lds_raw);
+    else if (CPW > 8 && a.G <= 64) km2_range<(CPW > 8 ? 8 : CPW), DPL>(a, item.i0, item.i1, 0, lds_raw);
+    else km2_range<CPW, DPL>(a, item.i0, item.i1, 0, lds_raw);
     __syncthreads();
   }
 }
