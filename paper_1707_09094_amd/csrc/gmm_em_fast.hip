@@ -35,7 +35,10 @@
 //      (the old means sit in LDS);
 //      for every sample with a non-zero responsibility r, in sample order,
 //        L' = L + r, delta = y - m, m += delta r / L', Q += delta^2 r L / L'
-//      (the first sample sets m = y exactly).  m is the block's weighted mean of
+//      except that a sample carrying more than half of L' sets
+//      m = y - delta L / L' (rounded relative to its own y, not to a mean
+//      that earlier, far-off samples of tiny weight have set; the first
+//      sample sets m = y exactly).  m is the block's weighted mean of
 //      y and Q its weighted sum of squared deviations from it; neither update
 //      subtracts two large accumulated sums, so the one-pass covariance of
 //      Eq. 8 loses nothing to cancellation (one sample gives Q = 0 exactly).
@@ -399,7 +402,9 @@ __device__ __forceinline__ void em_range(const FastArgs& a, int64_t i0, int64_t 
             const float Lo = Lc[c];
             const float Ln = Lo + r;
             const float inv = r / Ln;
+            const float wo = Lo / Ln;
             const float w2 = inv * Lo;
+            const bool dom = inv > 0.5f;  // the sample outweighs the run so far
             Lc[c] = Ln;
 #pragma unroll
             for (int j = 0; j < DPL; ++j) {
@@ -410,7 +415,7 @@ __device__ __forceinline__ void em_range(const FastArgs& a, int64_t i0, int64_t 
                   S1[c][j] = y;
                 } else {
                   const float dl = y - S1[c][j];
-                  S1[c][j] = fmaf(inv, dl, S1[c][j]);
+                  S1[c][j] = dom ? fmaf(-wo, dl, y) : fmaf(inv, dl, S1[c][j]);
                   S2[c][j] = fmaf(w2 * dl, dl, S2[c][j]);
                 }
               }
@@ -828,15 +833,16 @@ __device__ inline Lds2 carve_lds2(char* base, int G, int KS) {
 
 // A sample's log-sum-exp less M from its per-slice references D_q and sums
 // S_q: D* = max_q D_q (returned) and log(sum over slices of S_q exp(D_q - D*))
-// (in ls); the total is D* + ls.
+// (in ls); the total is D* + ls.  The rescaling and the logarithm are taken in
+// FP32, as the one-pass kernel takes its logarithm (about 1e-7 nats).
 __device__ __forceinline__ float slice_lse(const float* pd, const float* ps, int S, int64_t NS,
                                            double& ls) {
   float dstar = -INFINITY;
   for (int q = 0; q < S; ++q) dstar = fmaxf(dstar, pd[(size_t)q * NS]);
   double tot = 0.0;
   for (int q = 0; q < S; ++q)
-    tot += (double)ps[(size_t)q * NS] * exp((double)pd[(size_t)q * NS] - (double)dstar);
-  ls = log(tot);
+    tot += (double)(ps[(size_t)q * NS] * __expf(pd[(size_t)q * NS] - dstar));
+  ls = (double)__logf((float)tot);
   return dstar;
 }
 
@@ -1330,14 +1336,18 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
                   if (r != 0.0f) {
                     const float Lo = Lc[c];
                     const float Ln = Lo + r;
-                    const float inv = r * __builtin_amdgcn_rcpf(Ln);
+                    const float rc = __builtin_amdgcn_rcpf(Ln);
+                    const float inv = r * rc;
+                    const float wo = Lo * rc;
                     const float w2 = inv * Lo;
+                    // a sample outweighing the run so far takes the mean from
+                    // its own side (the first sample sets it exactly: wo = 0)
+                    const bool dom = inv > 0.5f;
                     Lc[c] = Ln;
 #pragma unroll
                     for (int jd = 0; jd < DPL; ++jd) {
                       const float dl = y[i][jd] - S1[c][jd];
-                      // the first sample sets the mean exactly (Lo = 0: inv = 1)
-                      S1[c][jd] = Lo == 0.0f ? y[i][jd] : fmaf(inv, dl, S1[c][jd]);
+                      S1[c][jd] = dom ? fmaf(-wo, dl, y[i][jd]) : fmaf(inv, dl, S1[c][jd]);
                       S2[c][jd] = fmaf(w2 * dl, dl, S2[c][jd]);
                     }
                   }

@@ -145,6 +145,25 @@ def test_em_step_diag_beyond_onepass(G_, oracle, N, D, G, path, prec):
         assert gpu["nrec"] >= N  # every sample's best component is recomputed
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
+@pytest.mark.parametrize("N,D,G", [(777, 64, 128), (777, 64, 130), (777, 64, 200)])
+def test_em_heavy_sample_after_tiny_weights(G_, oracle, N, D, G, prec):
+    """Unfitted components that collapse onto one or two samples: far-off
+    samples with responsibilities ~1e-11 can open a component's run in a
+    workgroup, and the heavy sample that follows must not inherit their
+    rounding in the running mean (variances of ~1e-6 against a data spread of
+    ~16; one-pass kernels at G <= 128, sliced kernels beyond, FP64 kernel for
+    the FP32 form beyond)."""
+    X, _ = synth.diag_gmm(7000 + 13 + D, D, G, N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
+    rng = np.random.Generator(np.random.PCG64(7000 + 13 + D + 1))
+    w = rng.dirichlet(np.ones(G)).astype(np.float32)
+    mu = X[rng.choice(N, G, replace=False)].astype(np.float32)
+    var = np.exp(rng.uniform(np.log(0.5), np.log(5.0), size=(G, D))).astype(np.float32)
+    gpu = gpu_em_step(G_, X, w, mu, var, 1e-10, prec=prec)
+    assert gpu["status"] == 0
+    check_em(gpu, oracle.em_iter(X, w, mu, var, 1e-10), N)
+
+
 @pytest.mark.parametrize("N,D,G", [(200_000, 100, 100), (50_000, 40, 64)])
 def test_em_forms_agree_on_fitted_model(G_, oracle, N, D, G):
     """From a k-means hand-off (the realistic regime: most samples have one
