@@ -82,6 +82,8 @@ struct FastArgs {
   float* wM;                // bounded maximum of the slice's values
   float* wD;                // reference of the slice's sum: largest exact near value - M
   float* wS;                // sum over the slice of exp(value - M - wD)
+  float* wR;                // [S][NG][kCapR] exact near values of MODE 2 (value - M), read by MODE 3
+  int64_t NG;               // 16-sample groups: ceil(N / 16)
 };
 
 // LDS layout of k_em_fast: the direct-form parameters are staged (ps, pm); the
@@ -760,7 +762,7 @@ __global__ void __launch_bounds__(256) k_fin_welford_batched(const gmm_model_des
 
 constexpr int kGS = 16;             // samples per wave group
 constexpr int kRoundN = kNW * kGS;  // samples per block round
-constexpr int kCapM = 32;           // pairs per (source, owner) list per pass
+constexpr int kCapM = 16;           // pairs per (source, owner) list per pass
 constexpr int kCapR = 64;           // near pairs recomputed per chunk per wave
 
 struct Lds2 {
@@ -771,8 +773,8 @@ struct Lds2 {
   int* cw;       // [NW][16] per-sample near count
   int* rcode;    // [NW][kCapR] near pair: sample | component << 8
   float* rval;   // [NW][kCapR] exact value - maximum bound
-  int2* sub;     // [NW source][NW owner][kCapM] (sample | component << 8, r)
-  int* subn;     // [NW source][NW owner] pairs of the round
+  int2* sub;     // [2][NW source][NW owner][kCapM] (sample | component << 8, r), by round parity
+  int* subn;     // [2][NW source][NW owner] pairs of the round
   int* need;     // [2] largest list of the round
   double* llw;   // [NW]
   int2* osort;   // [NW][64] an owner's pairs ordered by component slot
@@ -794,8 +796,8 @@ __host__ __device__ inline size_t lds2_walk(int G, int KS, F&& at) {
   put(4, kNW * 16, 1);
   put(5, kNW * kCapR, 1);
   put(6, kNW * kCapR, 1);
-  put(7, (size_t)kNW * kNW * kCapM * 2, 2);
-  put(8, kNW * kNW, 1);
+  put(7, 2 * (size_t)kNW * kNW * kCapM * 2, 2);
+  put(8, 2 * kNW * kNW, 1);
   put(9, 2, 1);
   put(10, 2 * kNW, 2);
   put(11, kNW * 64 * 2, 2);
@@ -860,8 +862,10 @@ __device__ __forceinline__ float slice_lse(const float* pd, const float* ps, int
 //   MODE 3  log-sum-exp M + D* + log(sum over slices of
 //           wS exp(wD - D*)), D* = max over slices of wD (Eqs. 16-18), the
 //           responsibilities and the map step of the slice's components.
-// Near pairs are the same in MODES 2 and 3 (same bound, same M) and always
-// recomputed in FP64, so both passes see the same exact values.
+// Near pairs are the same in MODES 2 and 3 (same bound, same M, same order)
+// and always taken in FP64: MODE 2 stores the first kCapR exact values of
+// each 16-sample group and slice (wR), MODE 3 reads them and recomputes only
+// beyond kCapR.
 template <int CPW, int DPL, bool MSTEP, int MODE = 0>
 __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t i1, int b,
                                           char* lds_raw) {
@@ -906,9 +910,6 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
       q[3] = -INFINITY;
       q[4] = 0.0f;
     }
-  }
-  if (MODE == 0 || MODE == 3) {
-    if (tid < 2) L.need[tid] = 0;
   }
 
 
@@ -1067,7 +1068,22 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
     if (MODE != 2) nrec += np;
 
     // 4. exact values of the near pairs, kCapR at a time
+    float* const wrg =
+        MODE >= 2 ? a.wR + ((size_t)a.sl * a.NG + (size_t)(s0 / kGS)) * kCapR : nullptr;
     for (int c0 = 0; c0 < np; c0 += kCapR) {
+      if (MODE == 3 && c0 == 0) {
+        // the near-pair pass's values, in the same order
+        int k = mybase;
+#pragma unroll
+        for (int cb = 0; cb < RBT; ++cb)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if ((nearb >> (4 * cb + j)) & 1u) {
+              if (k < kCapR) acc[cb][j] = wrg[k];
+              ++k;
+            }
+        continue;
+      }
       int k = mybase - c0;
 #pragma unroll
       for (int cb = 0; cb < RBT; ++cb)
@@ -1136,7 +1152,11 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
             q = row16_sum(q);
             val = a.c64[gg] - 0.5 * q;
           }
-          if (l16 == 0) rval[p] = (float)(val - (double)Mn);
+          if (l16 == 0) {
+            const float rv = (float)(val - (double)Mn);
+            rval[p] = rv;
+            if (MODE == 2 && c0 == 0) wrg[p] = rv;
+          }
         }
       }
       wave_lds_sync();
@@ -1248,17 +1268,16 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
           if (acc[cb][j] != 0.0f) nzb |= 1u << (4 * cb + j);
       int mine = 0;
       const int cbase = wave_prefix_small(__popc(nzb), lt, cls, &mine);
-      if (lane < kNW) L.subn[w * kNW + lane] = mine;
-      int mx = mine;
-      mx = max(mx, __builtin_amdgcn_update_dpp(0, mx, 0xB1, 0xF, 0xF, false));
-      mx = max(mx, __builtin_amdgcn_update_dpp(0, mx, 0x4E, 0xF, 0xF, false));
-      mx = max(mx, __builtin_amdgcn_update_dpp(0, mx, 0x124, 0xF, 0xF, false));  // row_ror:4
-      if (lane == 0) atomicMax(&L.need[round & 1], mx);
-      __syncthreads();
-      const int need = L.need[round & 1];
-      if (tid == 0) L.need[(round + 1) & 1] = 0;
-      for (int pass = 0; pass * kCapM < need; ++pass) {
-        int2* const dst = L.sub + (size_t)(w * kNW + (lane & 7)) * kCapM;
+      // lists and counts alternate between two buffers by round parity: a
+      // wave writes round r + 2's lists only after the barrier of round r + 1,
+      // which every owner reaches after its map step of round r, so a round
+      // whose lists fit kCapM takes one barrier
+      int2* const subb = L.sub + (size_t)(round & 1) * kNW * kNW * kCapM;
+      int* const subnb = L.subn + (round & 1) * kNW * kNW;
+      if (lane < kNW) subnb[w * kNW + lane] = mine;
+      int need = 0;  // longest list of the round (known after the first barrier)
+      for (int pass = 0;; ++pass) {
+        int2* const dst = subb + (size_t)(w * kNW + (lane & 7)) * kCapM;
         int k = cbase - pass * kCapM;
 #pragma unroll
         for (int cb = 0; cb < RBT; ++cb)
@@ -1271,13 +1290,22 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
               ++k;
             }
         __syncthreads();
+        if (pass == 0) {
+          need = subnb[lane];  // the 64 counts, one per lane
+          need = max(need, __shfl_xor(need, 1));
+          need = max(need, __shfl_xor(need, 2));
+          need = max(need, __shfl_xor(need, 4));
+          need = max(need, __shfl_xor(need, 8));
+          need = max(need, __shfl_xor(need, 16));
+          need = max(need, __shfl_xor(need, 32));
+        }
         // owner w: the map step (Eqs. 9-11) in West's weighted Welford form on
         // y = x - mu_old, lists taken in source-wave order
         int pre[kNW + 1];
         pre[0] = 0;
 #pragma unroll
         for (int src = 0; src < kNW; ++src)
-          pre[src + 1] = pre[src] + max(0, min(kCapM, L.subn[src * kNW + w] - pass * kCapM));
+          pre[src + 1] = pre[src] + max(0, min(kCapM, subnb[src * kNW + w] - pass * kCapM));
         const int tot = pre[kNW];
         int2* const os = L.osort + w * 64;
         for (int k0 = 0; k0 < tot; k0 += 64) {
@@ -1288,7 +1316,7 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
           int src = 0;
 #pragma unroll
           for (int t = 1; t < kNW; ++t) src = k >= pre[t] ? t : src;
-          const int2 e = ok ? L.sub[(size_t)(src * kNW + w) * kCapM + (k - pre[src])]
+          const int2 e = ok ? subb[(size_t)(src * kNW + w) * kCapM + (k - pre[src])]
                             : make_int2(0, 0);
           const int cs = ok ? (e.x >> 11) : -1;
           int cnt[CPW];
@@ -1358,9 +1386,9 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
           }
           wave_lds_sync();
         }
-        __syncthreads();
+        if ((pass + 1) * kCapM >= need) break;
+        __syncthreads();  // this buffer is refilled by the next pass
       }
-      if (need == 0) __syncthreads();
     }
   }
 
@@ -1620,7 +1648,7 @@ hipError_t launch_em_sliced(const float* X, int64_t N, int D, int64_t ldx, int G
                             const Workspace& w, hipStream_t st, int* nb_out) {
   const int KS = em2_ks(D);
   const int S = em2s_slices(D, G);
-  if (S < 1 || !w.wM || !w.wD || !w.wS) return hipErrorInvalidValue;
+  if (S < 1 || !w.wM || !w.wD || !w.wS || !w.wR) return hipErrorInvalidValue;
   const int Gs = 16 * (((G + S - 1) / S + 15) / 16);
   const int nb0 = em_fast_blocks(N);
   FastArgs a;
@@ -1654,6 +1682,8 @@ hipError_t launch_em_sliced(const float* X, int64_t N, int D, int64_t ldx, int G
   a.wM = w.wM;
   a.wD = w.wD;
   a.wS = w.wS;
+  a.wR = w.wR;
+  a.NG = (N + kGS - 1) / kGS;
   hipLaunchKernelGGL(k_pre_fast, dim3(16 * ((G + 15) / 16)), dim3(256), 0, st, hefts, means,
                      covs, D, G, KS, w.prm, w.c, w.cexp, (bf16x8*)w.Bhi, (bf16x8*)w.Blo, w.c64,
                      w.lamg64, dev_status, n_recomputed, w.counters);

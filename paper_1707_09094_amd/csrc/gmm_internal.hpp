@@ -194,6 +194,7 @@ struct Workspace {
   float* wM;          // sliced BF16x3 E-step: [S][N] per-slice bounded maxima
   float* wD;          // [S][N] per-slice references of the sums
   float* wS;          // [S][N] per-slice sums of exp(value - M - reference)
+  float* wR;          // [S][ceil(N/16)][64] exact near values passed between the passes
   size_t bytes;
 };
 
@@ -264,6 +265,7 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   size_t o_wm = take(sizeof(float) * (size_t)nsl * N);
   size_t o_wd = take(sizeof(float) * (size_t)nsl * N);
   size_t o_ws = take(sizeof(float) * (size_t)nsl * N);
+  size_t o_wr = take(sizeof(float) * (size_t)nsl * ((N + 15) / 16) * 64);
   w->bytes = off;
   if (!base) return true;
   if (avail < off) return false;
@@ -292,6 +294,7 @@ inline bool carve(void* base, size_t avail, int64_t N, int D, int G, int cov, Wo
   w->counters = (int64_t*)(b + o_ct);
   w->wM = nsl ? (float*)(b + o_wm) : nullptr;
   w->wD = nsl ? (float*)(b + o_wd) : nullptr;
+  w->wR = nsl ? (float*)(b + o_wr) : nullptr;
   w->wS = nsl ? (float*)(b + o_ws) : nullptr;
   return true;
 }
