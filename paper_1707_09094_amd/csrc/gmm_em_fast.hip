@@ -883,6 +883,7 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
   const int w = tid / kWave;
   const int KSr = (2 * D + 31) / 32;  // k-steps holding data
   const float ecoef = err_expanded_coef(KSr);
+  const float B2 = 2.0f * ecoef;
 
   {
     const bf16x8* const whs = a.Whi + (size_t)(g0 / 16) * KST * 64;
@@ -898,17 +899,25 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
       const int gg = g0 + g;
       const float c = a.cc[gg];
       const float Q = 2.0f * ((c + a.cc[Gt + gg]) - (a.cexp[gg] + a.cexp[Gt + gg]));
+      const float Qb = isfinite(Q) ? 1.0001f * fmaxf(Q, 0.0f) : 0.0f;
       q[0] = c;
-      q[1] = isfinite(Q) ? 1.0001f * fmaxf(Q, 0.0f) : 0.0f;
+      q[1] = Qb;
       q[2] = a.cc[Gt + gg];
       q[3] = a.cexp[gg];
       q[4] = a.cexp[Gt + gg];
+      // err_expanded(2 (c - v), Q, c) = coef (2 max(c - v, 0) + Q) + K is
+      // E0 - 2 coef min(v, c) with E0 = coef (2c + Q) + K; the slack covers
+      // the FP32 evaluation of E0 and of that product
+      const float K = 1.01f * 0x1p-23f * (fabsf(c) + 0.5f * Qb);
+      const float e0 = ecoef * (2.0f * c + Qb) + K;
+      q[5] = isfinite(e0) ? e0 + 0x1p-20f * (2.0f * ecoef * fabsf(c) + ecoef * Qb + K) : 0.0f;
     } else {  // padding component: value -inf
       q[0] = 0.0f;
       q[1] = 0.0f;
       q[2] = 0.0f;
       q[3] = -INFINITY;
       q[4] = 0.0f;
+      q[5] = 0.0f;
     }
   }
 
@@ -1002,13 +1011,13 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
     for (int cb = 0; cb < RBT; ++cb) {
       const float* q = cql + 8 * 16 * cb;
       const bool vg = cb < RB;
-      const float ch = vg ? q[0] : 0.0f, Qg = vg ? q[1] : 0.0f;
+      const float ch = vg ? q[0] : 0.0f, E0 = vg ? q[5] : 0.0f;
       const float eh = vg ? q[3] : -INFINITY, el = vg ? q[4] : 0.0f;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const float v = vj[j] ? (acc[cb][j] + eh) + el : -INFINITY;
         acc[cb][j] = v;
-        if (MODE < 2) M[j] = fmaxf(M[j], v - err_expanded(2.0f * (ch - v), Qg, ch, ecoef));
+        if (MODE < 2) M[j] = fmaxf(M[j], v - fmaf(-B2, fminf(v, ch), E0));
       }
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -1039,11 +1048,11 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
     for (int cb = 0; cb < RBT; ++cb) {
       const float* q = cql + 8 * 16 * cb;
       const bool vg = cb < RB;
-      const float ch = vg ? q[0] : 0.0f, Qg = vg ? q[1] : 0.0f;
+      const float ch = vg ? q[0] : 0.0f, E0 = vg ? q[5] : 0.0f;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const float v = acc[cb][j];
-        if (v > -INFINITY && v + err_expanded(2.0f * (ch - v), Qg, ch, ecoef) >= M[j] - kNearGap)
+        if (v > -INFINITY && v + fmaf(-B2, fminf(v, ch), E0) >= M[j] - kNearGap)
           nearb |= 1u << (4 * cb + j);
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -1184,13 +1193,13 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
           if ((nearb >> (4 * cb + j)) & 1u) dm = fmaxf(dm, acc[cb][j]);
         dm = row16_max(dm);
         const float dn = dm > -INFINITY ? dm : 0.0f;
-        double sm = 0.0;
+        float sf = 0.0f;  // this lane's few terms in FP32, the row's total in FP64
 #pragma unroll
         for (int cb = 0; cb < RBT; ++cb) {
           const bool nr = (nearb >> (4 * cb + j)) & 1u;
-          sm += (double)__expf((nr ? acc[cb][j] : acc[cb][j] - M[j]) - dn);
+          sf += __expf((nr ? acc[cb][j] : acc[cb][j] - M[j]) - dn);
         }
-        sm = row16_sum(sm);
+        const double sm = row16_sum((double)sf);
         if (vj[j] && colc == 0) {
           const size_t o = (size_t)a.sl * a.NS + s0 + 4 * rowq + j;
           a.wD[o] = dn;
@@ -1229,14 +1238,14 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
         if ((nearb >> (4 * cb + j)) & 1u) dm = fmaxf(dm, acc[cb][j]);
       dm = row16_max(dm);
       const float dn = dm > -INFINITY ? dm : 0.0f;
-      double sm = 0.0;
+      float sf = 0.0f;  // this lane's few terms in FP32, the row's total in FP64
 #pragma unroll
       for (int cb = 0; cb < RBT; ++cb) {
         const bool nr = (nearb >> (4 * cb + j)) & 1u;
         const float t = nr ? acc[cb][j] - dn : (acc[cb][j] - M[j]) - dn;
-        sm += (double)__expf(t);
+        sf += __expf(t);
       }
-      sm = row16_sum(sm);
+      const double sm = row16_sum((double)sf);
       const float ls = __logf((float)sm);
       const double lse = ((double)M[j] + (double)dn) + (double)ls;
       if (vj[j] && colc == 0) {

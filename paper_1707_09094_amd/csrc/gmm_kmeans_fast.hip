@@ -667,7 +667,7 @@ __global__ void k_zero_status_batched(const gmm_model_desc* models, int n_models
 
 constexpr int kKGS = 16;              // samples per wave group
 constexpr int kKRound = kNW * kKGS;   // samples per block round
-constexpr int kKCapM = 32;            // pairs per (source, owner) list per pass
+constexpr int kKCapM = 16;            // pairs per (source, owner) list per pass (= kKGS: one pass)
 constexpr int kCandMax = 8;           // candidate list per sample (more: all means)
 
 struct Km2Args {
@@ -699,8 +699,8 @@ struct KLds {
   float* un;     // [NW][16] |u| of each sample (bound)
   int* cand;     // [NW][16][kCandMax]
   int* ccnt;     // [NW][16]
-  int2* sub;     // [NW][NW][kKCapM]
-  int* subn;     // [NW][NW]
+  int2* sub;     // [2][NW][NW][kKCapM], by round parity
+  int* subn;     // [2][NW][NW]
   int* need;     // [2]
   int2* osort;   // [NW][64]
   double* inw;   // [NW]
@@ -724,8 +724,8 @@ __host__ __device__ inline size_t km2_lds_walk(int D, int G, int KSK, F&& at) {
   put(6, kNW * 16, 1);
   put(7, kNW * 16 * kCandMax, 1);
   put(8, kNW * 16, 1);
-  put(9, (size_t)kNW * kNW * kKCapM * 2, 2);
-  put(10, kNW * kNW, 1);
+  put(9, 2 * (size_t)kNW * kNW * kKCapM * 2, 2);
+  put(10, 2 * kNW * kNW, 1);
   put(11, 2, 1);
   put(12, kNW * 64 * 2, 2);
   put(13, 2 * kNW, 2);
@@ -791,7 +791,6 @@ __device__ __forceinline__ void km2_range(const Km2Args& a, int64_t i0, int64_t 
     L.lam[d] = a.lam64[d];
     L.sd[d] = a.sd[d];
   }
-  if (tid < 2) L.need[tid] = 0;
 
   float Lc[CPW], S1[CPW][DPL], S2[CPW][DPL];
 #pragma unroll
@@ -980,25 +979,32 @@ __device__ __forceinline__ void km2_range(const Km2Args& a, int64_t i0, int64_t 
       // row-rotation maximum below reads lanes 0-15
       if ((lane & 7) == o) mine = __popcll(m);
     }
-    if (lane < kNW) L.subn[w * kNW + lane] = mine;
-    int mx = mine;
-    mx = max(mx, __builtin_amdgcn_update_dpp(0, mx, 0xB1, 0xF, 0xF, false));
-    mx = max(mx, __builtin_amdgcn_update_dpp(0, mx, 0x4E, 0xF, 0xF, false));
-    mx = max(mx, __builtin_amdgcn_update_dpp(0, mx, 0x124, 0xF, 0xF, false));
-    if (lane == 0) atomicMax(&L.need[round & 1], mx);
-    __syncthreads();
-    const int need = L.need[round & 1];
-    if (tid == 0) L.need[(round + 1) & 1] = 0;
-    for (int pass = 0; pass * kKCapM < need; ++pass) {
+    // lists and counts alternate between two buffers by round parity (a wave
+    // writes round r + 2's lists only after the barrier of round r + 1, which
+    // every owner reaches after its map step of round r): one barrier a round
+    int2* const subb = L.sub + (size_t)(round & 1) * kNW * kNW * kKCapM;
+    int* const subnb = L.subn + (round & 1) * kNW * kNW;
+    if (lane < kNW) subnb[w * kNW + lane] = mine;
+    int need = 0;  // longest list of the round (at most kKGS = kKCapM)
+    for (int pass = 0;; ++pass) {
       const int k = mypos - pass * kKCapM;
       if (has && k >= 0 && k < kKCapM)
-        L.sub[(size_t)(w * kNW + own) * kKCapM + k] = make_int2(na | (best << 8), 0);
+        subb[(size_t)(w * kNW + own) * kKCapM + k] = make_int2(na | (best << 8), 0);
       __syncthreads();
+      if (pass == 0) {
+        need = subnb[lane];  // the 64 counts, one per lane
+        need = max(need, __shfl_xor(need, 1));
+        need = max(need, __shfl_xor(need, 2));
+        need = max(need, __shfl_xor(need, 4));
+        need = max(need, __shfl_xor(need, 8));
+        need = max(need, __shfl_xor(need, 16));
+        need = max(need, __shfl_xor(need, 32));
+      }
       int pre[kNW + 1];
       pre[0] = 0;
 #pragma unroll
       for (int src = 0; src < kNW; ++src)
-        pre[src + 1] = pre[src] + max(0, min(kKCapM, L.subn[src * kNW + w] - pass * kKCapM));
+        pre[src + 1] = pre[src] + max(0, min(kKCapM, subnb[src * kNW + w] - pass * kKCapM));
       const int tot = pre[kNW];
       int2* const os = L.osort + w * 64;
       for (int k0 = 0; k0 < tot; k0 += 64) {
@@ -1007,7 +1013,7 @@ __device__ __forceinline__ void km2_range(const Km2Args& a, int64_t i0, int64_t 
         int src = 0;
 #pragma unroll
         for (int t = 1; t < kNW; ++t) src = kk >= pre[t] ? t : src;
-        const int2 e = ok ? L.sub[(size_t)(src * kNW + w) * kKCapM + (kk - pre[src])]
+        const int2 e = ok ? subb[(size_t)(src * kNW + w) * kKCapM + (kk - pre[src])]
                           : make_int2(0, 0);
         const int cs = ok ? (e.x >> 11) : -1;
         int cnt[CPW];
@@ -1068,9 +1074,9 @@ __device__ __forceinline__ void km2_range(const Km2Args& a, int64_t i0, int64_t 
         }
         wave_lds_sync();
       }
-      __syncthreads();
+      if ((pass + 1) * kKCapM >= need) break;
+      __syncthreads();  // this buffer is refilled by the next pass
     }
-    if (need == 0) __syncthreads();
   }
 
   double* pb = a.part + (size_t)b * G * P;
