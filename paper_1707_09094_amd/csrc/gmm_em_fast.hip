@@ -962,7 +962,6 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
     // acc[cb][j] (sample 4 rowq + j, component 16 cb + colc).
     float acc[RBT][4];
     {
-      bf16x8 ah[KST], al[KST];
       const int64_t ia = s0 + na;
       const bool va = ia < i1;
       const float* xr = a.X + (va ? ia : i0) * a.ldx + 4 * kg;
@@ -970,6 +969,58 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
       // opaque per round, so the bound tests are not hoisted out of the round
       // loop (they would stay live in registers for the whole kernel)
       asm volatile("" : "+v"(dl));
+      if constexpr (MODE != 1) {
+      // every load of the group's samples first; then k-step by k-step, the
+      // step's split operands built and multiplied into all component blocks
+      // (one independent accumulator per block, each summed in k order)
+      float xv[KST][4];
+#pragma unroll
+      for (int ks = 0; ks < KST; ++ks)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          xv[ks][q] = (va && 16 * ks + q < dl) ? xr[16 * ks + q] : 0.0f;
+      f32x4 c[RBT];
+#pragma unroll
+      for (int cb = 0; cb < RBT; ++cb) c[cb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      // an opaque zero per round: the fragment loads below are loop-invariant
+      // where the round stores nothing to LDS, and hoisted they would hold
+      // every fragment in registers
+      int kof = 0;
+      asm volatile("" : "+v"(kof));
+#pragma unroll
+      for (int ks = 0; ks < KST; ++ks) {
+        bf16x8 ah, al;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float x = xv[ks][i >> 1];
+          const float v = (i & 1) ? x * x : x;
+          const __bf16 h = (__bf16)v;
+          ah[i] = h;
+          al[i] = (__bf16)(v - (float)h);
+        }
+#pragma unroll
+        for (int cb = 0; cb < RBT; ++cb) {
+          if (cb < RB) {
+            const bf16x8 bh = whl[kof + (cb * KST + ks) * 64];
+            const bf16x8 bl = wll[kof + (cb * KST + ks) * 64];
+            c[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c[cb], 0, 0, 0);
+            c[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c[cb], 0, 0, 0);
+            c[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c[cb], 0, 0, 0);
+          }
+        }
+        // one k-step's operand loads in flight at a time (unbounded, the
+        // scheduler hoists them all and the registers spill)
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int cb = 0; cb < RBT; ++cb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[cb][j] = c[cb][j];
+      } else {
+      // the slice-maximum pass: all split operands first, then block by
+      // block (in this short round the k-outer order above is compiled into
+      // spilling branchy code); the same products in the same order
+      bf16x8 ah[KST], al[KST];
 #pragma unroll
       for (int ks = 0; ks < KST; ++ks) {
         float xv[4];
@@ -999,6 +1050,7 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[cb][j] = c[j];
+      }
       }
     }
 
