@@ -389,6 +389,20 @@ int gmm_batched_autotune(const gmm_model_desc* models, int32_t n_models, const i
                          const int32_t* Gs, int32_t D, int32_t prec, void* ws, size_t ws_bytes,
                          gmm_stream_t stream, int32_t* best_chunk);
 
+/* The autotune cache.  gmm_batched_autotune keeps each choice in a
+ * per-process table keyed by (GPU architecture, D, largest G, floor(log2) of
+ * the batch's total N, floor(log2) of the model count, arithmetic form,
+ * covariance type) and returns a cached choice (one the workspace can hold)
+ * without timing or launching anything.  When the environment variable
+ * GMM_AUTOTUNE_CACHE names a file, the table is filled from it (lines "key
+ * chunk") at the first call after a clear, and every new choice is appended
+ * to it.  The table is guarded by a mutex.
+ * Number of entries in the table: */
+int gmm_autotune_cache_size(void);
+/* Empties the table (the file is left as it is; it is read again at the next
+ * gmm_batched_autotune). */
+int gmm_autotune_cache_clear(void);
+
 /* ---- instrumentation -----------------------------------------------------
  * When enabled, every launch of a data-pass kernel (one that reads all of X)
  * is bracketed by a pair of HIP events recorded on the caller's stream, and

@@ -3,6 +3,13 @@
 // enqueue, so a rejected call writes nothing), workspace carving, dispatch.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
 #include "gmm_internal.hpp"
 
 using namespace gmm;
@@ -24,6 +31,70 @@ bool ws_ok(void* ws, size_t ws_bytes, int64_t N, int D, int G, int cov, Workspac
   if (!ws) return false;
   if (((uintptr_t)ws) % 256 != 0) return false;
   return carve(ws, ws_bytes, N, D, G, cov, w);
+}
+
+// ---- autotune cache: key -> chosen work-item size ---------------------------
+// Keyed by (GPU architecture, D, largest G, log2 of the batch's total N, log2
+// of the model count, arithmetic form, covariance type).  Loaded from the file
+// named by GMM_AUTOTUNE_CACHE at first use after a clear; new entries are
+// appended to it as "key chunk" lines.
+std::mutex g_tune_mu;
+std::map<std::string, int32_t> g_tune;
+bool g_tune_loaded = false;
+
+int ilog2_floor(int64_t v) {
+  int r = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++r;
+  }
+  return r;
+}
+
+bool tune_key(int32_t n_models, const int64_t* Ns, const int32_t* Gs, int32_t D, int32_t prec,
+              std::string* key) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return false;
+  int64_t sumN = 0;
+  int32_t gmax = 0;
+  for (int m = 0; m < n_models; ++m) {
+    sumN += Ns[m];
+    gmax = Gs[m] > gmax ? Gs[m] : gmax;
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s|D%d|G%d|N%d|M%d|p%d|diag", prop.gcnArchName, (int)D,
+                (int)gmax, ilog2_floor(sumN), ilog2_floor(n_models), (int)prec);
+  for (char* c = buf; *c; ++c)
+    if (*c == ' ') *c = '_';
+  *key = buf;
+  return true;
+}
+
+// with g_tune_mu held
+void tune_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("GMM_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char k[256];
+  int v = 0;
+  while (std::fscanf(f, "%255s %d", k, &v) == 2)
+    if (v > 0) g_tune[k] = v;
+  std::fclose(f);
+}
+
+void tune_store(const std::string& key, int32_t chunk) {
+  g_tune[key] = chunk;
+  const char* path = std::getenv("GMM_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d\n", key.c_str(), (int)chunk);
+  std::fclose(f);
 }
 
 }  // namespace
@@ -341,8 +412,20 @@ int gmm_global_stats_batched(const gmm_model_desc* models, int32_t n_models, int
 int gmm_batched_autotune(const gmm_model_desc* models, int32_t n_models, const int64_t* Ns,
                          const int32_t* Gs, int32_t D, int32_t prec, void* ws, size_t ws_bytes,
                          gmm_stream_t stream, int32_t* best_chunk) {
-  if (!best_chunk) return GMM_EINVAL;
+  if (!best_chunk || !Ns || !Gs || n_models < 1) return GMM_EINVAL;
   static const int32_t cand[] = {1024, 2048, 4096, 8192, 16384};
+  std::string key;
+  if (!tune_key(n_models, Ns, Gs, D, prec, &key)) return GMM_EHIP;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end() && ws_bytes >= gmm_batched_workspace_bytes(n_models, Ns, Gs, D,
+                                                                       it->second)) {
+      *best_chunk = it->second;
+      return GMM_OK;
+    }
+  }
   hipStream_t st = (hipStream_t)stream;
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess) return GMM_EHIP;
@@ -376,7 +459,23 @@ int gmm_batched_autotune(const gmm_model_desc* models, int32_t n_models, const i
   (void)hipEventDestroy(b);
   if (rc != GMM_OK) return rc;
   if (pick == 0) return GMM_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_store(key, pick);
+  }
   *best_chunk = pick;
+  return GMM_OK;
+}
+
+int gmm_autotune_cache_size(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return (int)g_tune.size();
+}
+
+int gmm_autotune_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+  g_tune_loaded = false;
   return GMM_OK;
 }
 

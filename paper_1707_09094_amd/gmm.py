@@ -411,6 +411,8 @@ _SIGS.update({
     "gmm_global_stats_batched": ([_vp, _i32, _i32, _vp, _vp, _vp], _i32),
     "gmm_batched_autotune": ([_vp, _i32, _vp, _vp, _i32, _i32, _vp, _sz, _vp,
                               ctypes.POINTER(_i32)], _i32),
+    "gmm_autotune_cache_size": ([], _i32),
+    "gmm_autotune_cache_clear": ([], _i32),
 })
 
 
@@ -545,3 +547,11 @@ def gmm_batched_autotune(batch, prec, ws, stream=None):
                                         ctypes.byref(best))
     _check("gmm_batched_autotune", rc)
     return int(best.value)
+
+
+def gmm_autotune_cache_size():
+    return int(library().gmm_autotune_cache_size())
+
+
+def gmm_autotune_cache_clear():
+    _check("gmm_autotune_cache_clear", library().gmm_autotune_cache_clear())

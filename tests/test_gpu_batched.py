@@ -297,3 +297,43 @@ def test_batched_binding_raises(G_):
     big = G_.ModelBatch([torch.zeros(10, 129, device=DEV)], [2], device=DEV)
     with pytest.raises(G_.GmmError):
         G_.gmm_em_iter_batched(big, 1e-10, 0, 1024, ws)  # D beyond the batched envelope
+
+
+def test_autotune_cache(G_, tmp_path, monkeypatch):
+    """gmm_batched_autotune keeps its choice per (arch, D, largest G, N and
+    model-count buckets, form, covariance type): a repeated call launches
+    nothing and returns the same work-item size; the cache file named by
+    GMM_AUTOTUNE_CACHE gets one "key chunk" line per new choice and refills
+    the table after a clear."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("GMM_AUTOTUNE_CACHE", str(path))
+    G_.gmm_autotune_cache_clear()
+    assert G_.gmm_autotune_cache_size() == 0
+    Xs, params = _data(97, 40, SHAPES_D40[:6])
+    b = _batch(G_, Xs, params)
+    ws = b.workspace(1024)
+    c1 = G_.gmm_batched_autotune(b, 1, ws)
+    assert c1 in (1024, 2048, 4096, 8192, 16384)
+    assert G_.gmm_autotune_cache_size() == 1
+    (line,) = path.read_text().splitlines()
+    key, val = line.split()
+    assert int(val) == c1 and "|D40|G64|" in key and key.endswith("|p1|diag")
+
+    def launches(fn):
+        G_.gmm_profile_enable(True)
+        out = fn()
+        torch.cuda.synchronize()
+        n = G_.gmm_profile_read(G_.PROF_BATCHED)[1]
+        G_.gmm_profile_enable(False)
+        return out, n
+
+    c2, n2 = launches(lambda: G_.gmm_batched_autotune(b, 1, ws))
+    assert c2 == c1 and n2 == 0
+    G_.gmm_autotune_cache_clear()
+    c3, n3 = launches(lambda: G_.gmm_batched_autotune(b, 1, ws))
+    assert c3 == c1 and n3 == 0 and G_.gmm_autotune_cache_size() == 1
+    # the other arithmetic form is another key: timed, then cached
+    c4, n4 = launches(lambda: G_.gmm_batched_autotune(b, 0, ws))
+    assert n4 > 0 and G_.gmm_autotune_cache_size() == 2
+    assert len(path.read_text().splitlines()) == 2
+    G_.gmm_autotune_cache_clear()
