@@ -922,6 +922,18 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
   }
 
 
+  // the owner's old means in registers when they take few (they are read by
+  // every map-step chunk); otherwise reloaded per chunk
+  constexpr bool kMuReg = MSTEP && CPW * DPL <= 8;
+  float mur[kMuReg ? CPW : 1][DPL];
+#pragma unroll
+  for (int c = 0; c < (kMuReg ? CPW : 1); ++c)
+#pragma unroll
+    for (int jd = 0; jd < DPL; ++jd) {
+      const int g = w + kNW * c;
+      mur[c][jd] = kMuReg && g < G ? a.means[(size_t)(g0 + g) * D + min(lane + kWave * jd, D - 1)]
+                                   : 0.0f;
+    }
   // owner accumulators: component g = w + 8 c, dimension d = lane + 64 j
   float Lc[CPW], S1[CPW][DPL], S2[CPW][DPL];
 #pragma unroll
@@ -1407,7 +1419,8 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
               float mu[DPL];
 #pragma unroll
               for (int jd = 0; jd < DPL; ++jd)
-                mu[jd] = a.means[(size_t)g * D + min(lane + kWave * jd, D - 1)];
+                mu[jd] = kMuReg ? mur[kMuReg ? c : 0][jd]
+                                : a.means[(size_t)g * D + min(lane + kWave * jd, D - 1)];
               for (int q0 = 0; q0 < cc; q0 += 4) {
                 float rq[4], y[4][DPL];
 #pragma unroll
