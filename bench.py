@@ -251,6 +251,12 @@ def batched_workload(gmm, synth, torch, dev, km_iters=KM_ITERS, em_iters=EM_ITER
         inits.append(X[torch.as_tensor(synth.static_subset_index(N, G), device=dev)].clone())
     b = gmm.ModelBatch(Xs, Gs.tolist(), device=dev)
     ws = b.workspace(1024)
+    # the tuner times the log-likelihood pass on the models' parameters: give
+    # it the state EM starts from (seeded means, one k-means pass)
+    for m, mu0 in enumerate(inits):
+        b.means[m].copy_(mu0)
+    gmm.gmm_global_stats_batched(b, b.gmean, b.gvar)
+    gmm.gmm_kmeans_iter_batched(b, gmm.DIST_MAHA, VAR_FLOOR, 4096, ws)
     chunk = gmm.gmm_batched_autotune(b, gmm.PREC_BF16X3, ws)
     sum_ng = float(np.sum(Ns.astype(np.float64) * Gs))
     sum_n = float(np.sum(Ns))

@@ -384,6 +384,9 @@ int gmm_global_stats_batched(const gmm_model_desc* models, int32_t n_models, int
 /* Chooses `chunk` for a batch: times gmm_loglik_batched (which leaves the
  * models unchanged) for each candidate chunk in {1024, 2048, 4096, 8192,
  * 16384} (those the workspace can hold) and writes the fastest to *best_chunk.
+ * The pass costs what the models' current parameters make it cost (how many
+ * near pairs each sample has), so call it once they hold a fitted state, for
+ * example after the k-means seeding, not on zeroed parameters.
  * Synchronises with the host; not for use under graph capture. */
 int gmm_batched_autotune(const gmm_model_desc* models, int32_t n_models, const int64_t* Ns,
                          const int32_t* Gs, int32_t D, int32_t prec, void* ws, size_t ws_bytes,

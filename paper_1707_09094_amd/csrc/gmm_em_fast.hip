@@ -753,12 +753,15 @@ __global__ void __launch_bounds__(256) k_fin_welford_batched(const gmm_model_des
 // work range).  Output lane l, register j is (sample 4 (l/16) + j, component
 // 16 cb + l%16), so every per-sample reduction (bounded maximum, near count,
 // log-sum-exp) is a butterfly over the 16 lanes of a lane row.  Near pairs are
-// recomputed exactly (FP64, or the FP32 direct form under its bound) by
-// 16-lane rows reading the sample and parameters from global memory.  The
-// map step of component g is done by wave g % 8 (its "owner"), which keeps
-// (L, m, Q) of its components in registers; every 128 samples the waves pass
-// their non-zero responsibilities to the owners through LDS lists, in a fixed
-// order, with two barriers per 128 samples.
+// recomputed exactly, in FP64 from the FP32 parameters, two pairs per 16-lane
+// row at a time (all loads of both issued first).  The map step of component g
+// is done by wave g % 8 (its "owner"), which keeps (L, m, Q) of its components
+// in registers; every 128 samples the waves pass their non-zero
+// responsibilities to the owners through LDS lists, in a fixed order, with one
+// barrier per 128 samples when the lists fit.  Where LDS has room (D <= 64, few
+// components) the staged form also keeps each round's samples and the
+// components' FP64 constants in LDS, so the recompute and the map step read no
+// global memory.
 
 constexpr int kGS = 16;             // samples per wave group
 constexpr int kRoundN = kNW * kGS;  // samples per block round
@@ -810,6 +813,21 @@ __host__ __device__ inline size_t em2_lds_bytes(int G, int KS) {
 
 // k-steps of the sample-major fragment layout (compile-time in the kernel)
 __host__ __device__ inline int em2_ks(int D) { return D <= 64 ? 4 : 8; }
+
+// Staged form (D <= 64): after the layout above, each round's samples
+// [2 by round parity][128][D] (floats), the precisions lam [G][D] (doubles),
+// the constants c [G] (doubles) and the means [G][D] (floats), so the near-pair
+// recompute and the map step read LDS only.
+__host__ __device__ inline size_t em2_stage_off(int G, int KS) {
+  return (em2_lds_bytes(G, KS) + 15) / 16 * 16;
+}
+__host__ __device__ inline size_t em2_stage_lds_bytes(int D, int G) {
+  return em2_stage_off(G, 4) + (size_t)4 * 2 * kRoundN * D + (size_t)8 * G * D +
+         (size_t)8 * G + (size_t)4 * G * D;
+}
+inline bool em2_stage_fits(int D, int G) {
+  return D <= 64 && em2_stage_lds_bytes(D, G) <= 160 * 1024;
+}
 
 __device__ inline Lds2 carve_lds2(char* base, int G, int KS) {
   Lds2 L;
@@ -866,15 +884,15 @@ __device__ __forceinline__ float slice_lse(const float* pd, const float* ps, int
 // and always taken in FP64: MODE 2 stores the first kCapR exact values of
 // each 16-sample group and slice (wR), MODE 3 reads them and recomputes only
 // beyond kCapR.
-template <int CPW, int DPL, bool MSTEP, int MODE = 0>
+template <int CPW, int DPL, bool MSTEP, int MODE = 0, bool STG = false>
 __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t i1, int b,
                                           char* lds_raw) {
+  static_assert(!STG || (MODE == 0 && DPL == 1), "staged form: one pass, D <= 64");
   constexpr int RBT = (CPW + 1) / 2;  // row blocks of 16 components
   constexpr int KST = 4 * DPL;        // k-steps of 16 dimensions
   const int D = a.D, G = a.G;
   const int g0 = MODE ? a.g0 : 0;   // first component of the slice
   const int Gt = MODE ? a.Gt : G;   // components of the model
-  const int DP = D + 1;
   const int P = 2 * D + 1;
   const int RB = (G + 15) / 16;
   const Lds2 L = carve_lds2(lds_raw, G, KST);
@@ -922,6 +940,20 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
   }
 
 
+  // staged form: the FP64 constants and the means of all G components (one
+  // pass, so g0 = 0) and each round's samples in LDS
+  float* const xs = STG ? (float*)(lds_raw + em2_stage_off(G, KST)) : nullptr;
+  double* const slam = STG ? (double*)(xs + 2 * kRoundN * D) : nullptr;
+  double* const sc64 = STG ? slam + G * D : nullptr;
+  float* const smu = STG ? (float*)(sc64 + G) : nullptr;
+  if constexpr (STG) {
+    for (int i = tid; i < G * D; i += kThreads) {
+      slam[i] = a.lam64[i];
+      smu[i] = a.means[i];
+    }
+    for (int g = tid; g < G; g += kThreads) sc64[g] = a.c64[g];
+  }
+
   // the owner's old means in registers when they take few (they are read by
   // every map-step chunk); otherwise reloaded per chunk
   constexpr bool kMuReg = MSTEP && CPW * DPL <= 8;
@@ -967,6 +999,22 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
   int round = 0;
   for (int64_t base = i0; base < i1; base += kRoundN, ++round) {
     const int64_t s0 = base + (int64_t)kGS * w;
+    // staged form: this wave's 16 rows of the round, zero past i1.  Buffers
+    // alternate by round parity: an owner reads them until its map step ends,
+    // before the next round's barrier, and this wave refills a buffer only
+    // two rounds later, after that barrier.
+    float* const xsr = STG ? xs + (size_t)(round & 1) * kRoundN * D : nullptr;
+    if constexpr (STG) {
+      float* const dst = xsr + (size_t)kGS * w * D;
+      float v[kGS];
+#pragma unroll
+      for (int n = 0; n < kGS; ++n)
+        v[n] = (lane < D && s0 + n < i1) ? a.X[(s0 + n) * a.ldx + lane] : 0.0f;
+#pragma unroll
+      for (int n = 0; n < kGS; ++n)
+        if (lane < D) dst[n * D + lane] = v[n];
+      wave_lds_sync();
+    }
 
     // 1-2. screening on the matrix cores.  A fragments: the group's samples,
     // features [x_d, x_d^2] interleaved, split into BF16 hi + lo; each block
@@ -1168,67 +1216,61 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
           }
       wave_lds_sync();
       {
-        // one pair per 16-lane row; lane l16 of the row takes dimensions
-        // l16 + 16 i, and every load of the pair is issued before any use
+        // PU pairs per 16-lane row at a time (p, p + 4, ...); lane l16 of the
+        // row takes dimensions l16 + 16 i, and every load of those pairs is
+        // issued before any use.  The value is c - q/2 in FP64 from the FP32
+        // sample and parameters (q summed over the row in FP64).  Two pairs
+        // in flight where D <= 64; one where 128 dimensions per row would
+        // take twice the registers.
         constexpr int NE = 4 * DPL;  // dimensions per lane (D <= 64 NE)
+        constexpr int PU = DPL == 1 ? 2 : 1;
         const int rid = lane >> 4, l16 = lane & 15;
         const int nc = min(kCapR, np - c0);
-        for (int p = rid; p < nc; p += 4) {
-          const int code = rcode[p];
-          const int n = code & 15, g = code >> 8;
-          const float* xr = a.X + (s0 + n) * a.ldx;
-          const float Mn = mw[n];
-          const int gg = g0 + g;
-          bool ex64 = MODE != 0 || cw[n] >= 2;
-          float xv[NE];
+        for (int p = rid; p < nc; p += 4 * PU) {
+          int n[PU], g[PU];
+          bool has[PU];
+          float xv[PU][NE], mv[PU][NE];
+          double lv[PU][NE], cg[PU];
 #pragma unroll
-          for (int i = 0; i < NE; ++i) xv[i] = xr[min(l16 + 16 * i, D - 1)];
-          double val = 0.0;
-          if (!ex64) {
-            const float* sg = a.prm + (size_t)gg * DP;
-            const float* mg = a.prm + (size_t)Gt * DP + (size_t)gg * DP;
-            float sv[NE], mv[NE];
-#pragma unroll
-            for (int i = 0; i < NE; ++i) {
-              const int dc = min(l16 + 16 * i, D - 1);
-              sv[i] = sg[dc];
-              mv[i] = mg[dc];
-            }
-            float q = 0.0f;
-#pragma unroll
-            for (int i = 0; i < NE; ++i) {
-              const float u = fmaf(xv[i], sv[i], -mv[i]);
-              q = l16 + 16 * i < D ? fmaf(u, u, q) : q;
-            }
-            q = (float)row16_sum((double)q);
-            const float* qg = L.cq + 8 * g;
-            val = ((double)qg[0] + (double)qg[2]) - 0.5 * (double)q;
-            ex64 = !(err_direct(q, qg[1], qg[0], D) <= kExactTol);
-          }
-          if (ex64) {
-            const float* mu_g = a.means + (size_t)gg * D;
-            const double* lg = a.lam64 + (size_t)gg * D;
-            float mv[NE];
-            double lv[NE];
+          for (int h = 0; h < PU; ++h) {
+            has[h] = p + 4 * h < nc;
+            const int code = rcode[has[h] ? p + 4 * h : p];
+            n[h] = code & 15;
+            g[h] = code >> 8;
+            const int gg = g0 + g[h];
+            const float* xr = STG ? xsr + (kGS * w + n[h]) * D : a.X + (s0 + n[h]) * a.ldx;
+            const float* mu_g = STG ? smu + g[h] * D : a.means + (size_t)gg * D;
+            const double* lg = STG ? slam + g[h] * D : a.lam64 + (size_t)gg * D;
 #pragma unroll
             for (int i = 0; i < NE; ++i) {
               const int dc = min(l16 + 16 * i, D - 1);
-              mv[i] = mu_g[dc];
-              lv[i] = lg[dc];
+              xv[h][i] = xr[dc];
+              mv[h][i] = mu_g[dc];
+              lv[h][i] = lg[dc];
             }
-            double q = 0.0;
+            cg[h] = STG ? sc64[g[h]] : a.c64[gg];
+          }
+          double q[PU];
+#pragma unroll
+          for (int h = 0; h < PU; ++h) {
+            q[h] = 0.0;
 #pragma unroll
             for (int i = 0; i < NE; ++i) {
-              const double u = (double)xv[i] - (double)mv[i];
-              q = l16 + 16 * i < D ? q + u * u * lv[i] : q;
+              const double u = (double)xv[h][i] - (double)mv[h][i];
+              q[h] = l16 + 16 * i < D ? q[h] + u * u * lv[h][i] : q[h];
             }
-            q = row16_sum(q);
-            val = a.c64[gg] - 0.5 * q;
           }
+#pragma unroll
+          for (int h = 0; h < PU; ++h) q[h] = row16_sum(q[h]);
           if (l16 == 0) {
-            const float rv = (float)(val - (double)Mn);
-            rval[p] = rv;
-            if (MODE == 2 && c0 == 0) wrg[p] = rv;
+#pragma unroll
+            for (int h = 0; h < PU; ++h)
+              if (has[h]) {
+                const double val = cg[h] - 0.5 * q[h];
+                const float rv = (float)(val - (double)mw[n[h]]);
+                rval[p + 4 * h] = rv;
+                if (MODE == 2 && c0 == 0) wrg[p + 4 * h] = rv;
+              }
           }
         }
       }
@@ -1420,6 +1462,7 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
 #pragma unroll
               for (int jd = 0; jd < DPL; ++jd)
                 mu[jd] = kMuReg ? mur[kMuReg ? c : 0][jd]
+                         : STG  ? smu[g * D + min(lane + kWave * jd, D - 1)]
                                 : a.means[(size_t)g * D + min(lane + kWave * jd, D - 1)];
               for (int q0 = 0; q0 < cc; q0 += 4) {
                 float rq[4], y[4][DPL];
@@ -1427,7 +1470,8 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
                 for (int i = 0; i < 4; ++i) {
                   const int2 e2 = os[o + min(q0 + i, cc - 1)];
                   rq[i] = q0 + i < cc ? __int_as_float(e2.y) : 0.0f;
-                  const float* xr = a.X + (base + (e2.x & 0xFF)) * a.ldx;
+                  const float* xr = STG ? xsr + (e2.x & 0xFF) * D
+                                        : a.X + (base + (e2.x & 0xFF)) * a.ldx;
 #pragma unroll
                   for (int jd = 0; jd < DPL; ++jd)
                     y[i][jd] = xr[min(lane + kWave * jd, D - 1)] - mu[jd];
@@ -1502,13 +1546,13 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
   if (bad) atomicOr(a.dev_status, GMM_DEV_NONFINITE);
 }
 
-template <int CPW, int DPL, bool MSTEP>
+template <int CPW, int DPL, bool MSTEP, bool STG>
 __global__ void __launch_bounds__(kThreads) k_em2(FastArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds_raw[];
   const int b = blockIdx.x;
   const int64_t i0 = (int64_t)b * a.chunk;
   const int64_t i1 = min(a.N, i0 + a.chunk);
-  em2_range<CPW, DPL, MSTEP>(a, i0, i1, b, lds_raw);
+  em2_range<CPW, DPL, MSTEP, 0, STG>(a, i0, i1, b, lds_raw);
 }
 
 // One sliced pass (MODE 1, 2 or 3): grid (work ranges, slices); slice s holds
@@ -1563,7 +1607,7 @@ __global__ void __launch_bounds__(kWllT) k_wll(const float* __restrict__ wM,
   if (bad) atomicOr(dev_status, GMM_DEV_NONFINITE);
 }
 
-template <int CPW, int DPL, bool MSTEP>
+template <int CPW, int DPL, bool MSTEP, bool STG>
 __global__ void __launch_bounds__(kThreads) k_em2_batched(FastArgs base,
                                                           const gmm_model_desc* models,
                                                           const BatchItemDev* items,
@@ -1595,10 +1639,13 @@ __global__ void __launch_bounds__(kThreads) k_em2_batched(FastArgs base,
     a.dev_status = m.dev_status;
     a.n_rec = nullptr;
     // the smallest component-block template that holds the model's G
-    if (CPW > 2 && a.G <= 16) em2_range<(CPW > 2 ? 2 : CPW), DPL, MSTEP>(a, item.i0, item.i1, 0, lds_raw);
-    else if (CPW > 4 && a.G <= 32) em2_range<(CPW > 4 ? 4 : CPW), DPL, MSTEP>(a, item.i0, item.i1, 0, lds_raw);
-    else if (CPW > 8 && a.G <= 64) em2_range<(CPW > 8 ? 8 : CPW), DPL, MSTEP>(a, item.i0, item.i1, 0, lds_raw);
-    else em2_range<CPW, DPL, MSTEP>(a, item.i0, item.i1, 0, lds_raw);
+    if (CPW > 2 && a.G <= 16)
+      em2_range<(CPW > 2 ? 2 : CPW), DPL, MSTEP, 0, STG>(a, item.i0, item.i1, 0, lds_raw);
+    else if (CPW > 4 && a.G <= 32)
+      em2_range<(CPW > 4 ? 4 : CPW), DPL, MSTEP, 0, STG>(a, item.i0, item.i1, 0, lds_raw);
+    else if (CPW > 8 && a.G <= 64)
+      em2_range<(CPW > 8 ? 8 : CPW), DPL, MSTEP, 0, STG>(a, item.i0, item.i1, 0, lds_raw);
+    else em2_range<CPW, DPL, MSTEP, 0, STG>(a, item.i0, item.i1, 0, lds_raw);
     __syncthreads();
   }
 }
@@ -1636,9 +1683,9 @@ void dispatch_cpw(const FastArgs& a, int nb, size_t lds, hipStream_t st) {
   }
 }
 
-template <int CPW, int DPL, bool MSTEP>
+template <int CPW, int DPL, bool MSTEP, bool STG = false>
 void launch_em2_one(const FastArgs& a, int nb, size_t lds, hipStream_t st) {
-  auto kern = k_em2<CPW, DPL, MSTEP>;
+  auto kern = k_em2<CPW, DPL, MSTEP, STG>;
   static bool attr_set = false;  // benign race: setting the attribute twice is harmless
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1649,9 +1696,15 @@ void launch_em2_one(const FastArgs& a, int nb, size_t lds, hipStream_t st) {
 }
 
 template <bool MSTEP>
-void dispatch_em2(const FastArgs& a, int nb, size_t lds, hipStream_t st) {
+void dispatch_em2(const FastArgs& a, int nb, size_t lds, hipStream_t st, bool stg) {
   const int cpw = (a.G + kNW - 1) / kNW;
-  if (a.D <= 64) {
+  if (stg) {
+    if (cpw <= 2) launch_em2_one<2, 1, MSTEP, true>(a, nb, lds, st);
+    else if (cpw <= 4) launch_em2_one<4, 1, MSTEP, true>(a, nb, lds, st);
+    else if (cpw <= 8) launch_em2_one<8, 1, MSTEP, true>(a, nb, lds, st);
+    else if (cpw <= 13) launch_em2_one<13, 1, MSTEP, true>(a, nb, lds, st);
+    else launch_em2_one<16, 1, MSTEP, true>(a, nb, lds, st);
+  } else if (a.D <= 64) {
     if (cpw <= 2) launch_em2_one<2, 1, MSTEP>(a, nb, lds, st);
     else if (cpw <= 4) launch_em2_one<4, 1, MSTEP>(a, nb, lds, st);
     else if (cpw <= 8) launch_em2_one<8, 1, MSTEP>(a, nb, lds, st);
@@ -1824,9 +1877,10 @@ hipError_t launch_em_fast(const float* X, int64_t N, int D, int64_t ldx, int G, 
       const int64_t ch = ((N + nb - 1) / nb + kRoundN - 1) / kRoundN * kRoundN;
       a.chunk = ch;
       const int nb2 = (int)((N + ch - 1) / ch);
-      const size_t lds = em2_lds_bytes(G, KS);
-      if (mstep) dispatch_em2<true>(a, nb2, lds, st);
-      else dispatch_em2<false>(a, nb2, lds, st);
+      const bool stg = em2_stage_fits(D, G);
+      const size_t lds = stg ? em2_stage_lds_bytes(D, G) : em2_lds_bytes(G, KS);
+      if (mstep) dispatch_em2<true>(a, nb2, lds, st, stg);
+      else dispatch_em2<false>(a, nb2, lds, st, stg);
       *nb_out = nb2;
       return hipGetLastError();
     }
@@ -1862,11 +1916,11 @@ void launch_batched_one(const FastArgs& base, const gmm_model_desc* models, cons
                      bw.n_items, bc);
 }
 
-template <bool MSTEP, int CPW, int DPL>
+template <bool MSTEP, int CPW, int DPL, bool STG = false>
 void launch_em2_batched_one(const FastArgs& base, const gmm_model_desc* models,
                             const BatchWorkspace& bw, const BatchConst& bc, int grid, size_t lds,
                             hipStream_t st) {
-  auto kern = k_em2_batched<CPW, DPL, MSTEP>;
+  auto kern = k_em2_batched<CPW, DPL, MSTEP, STG>;
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1880,9 +1934,14 @@ void launch_em2_batched_one(const FastArgs& base, const gmm_model_desc* models,
 template <bool MSTEP>
 void dispatch_em2_batched(const FastArgs& base, const gmm_model_desc* models,
                           const BatchWorkspace& bw, const BatchConst& bc, int grid, size_t lds,
-                          hipStream_t st) {
+                          hipStream_t st, bool stg) {
   const int cpw = (bw.Gmax + kNW - 1) / kNW;
-  if (bw.D <= 64) {
+  if (stg) {
+    if (cpw <= 2) launch_em2_batched_one<MSTEP, 2, 1, true>(base, models, bw, bc, grid, lds, st);
+    else if (cpw <= 4) launch_em2_batched_one<MSTEP, 4, 1, true>(base, models, bw, bc, grid, lds, st);
+    else if (cpw <= 8) launch_em2_batched_one<MSTEP, 8, 1, true>(base, models, bw, bc, grid, lds, st);
+    else launch_em2_batched_one<MSTEP, 16, 1, true>(base, models, bw, bc, grid, lds, st);
+  } else if (bw.D <= 64) {
     if (cpw <= 2) launch_em2_batched_one<MSTEP, 2, 1>(base, models, bw, bc, grid, lds, st);
     else if (cpw <= 4) launch_em2_batched_one<MSTEP, 4, 1>(base, models, bw, bc, grid, lds, st);
     else if (cpw <= 8) launch_em2_batched_one<MSTEP, 8, 1>(base, models, bw, bc, grid, lds, st);
@@ -1939,14 +1998,16 @@ hipError_t launch_em_batched(const gmm_model_desc* models, int n_models, int n_i
   base.ll_part = bw.sparts;
   hipLaunchKernelGGL(k_pre_fast_batched, dim3(16 * bw.RBmax, n_models), dim3(256), 0, st, models,
                      D, bc);
-  const size_t lds = prec == GMM_PREC_BF16X3 ? em2_lds_bytes(bw.Gmax, em2_ks(D))
-                                             : fast_lds_bytes(D, bw.Gmax);
+  const bool stg = prec == GMM_PREC_BF16X3 && em2_stage_fits(D, bw.Gmax);
+  const size_t lds = prec == GMM_PREC_BF16X3
+                         ? (stg ? em2_stage_lds_bytes(D, bw.Gmax) : em2_lds_bytes(bw.Gmax, em2_ks(D)))
+                         : fast_lds_bytes(D, bw.Gmax);
   const int grid = n_items_host < 256 ? (n_items_host < 1 ? 1 : n_items_host) : 256;
   {
     ProfScope ps(kProfBatched, st);
     if (prec == GMM_PREC_BF16X3) {
-      if (mstep) dispatch_em2_batched<true>(base, models, bw, bc, grid, lds, st);
-      else dispatch_em2_batched<false>(base, models, bw, bc, grid, lds, st);
+      if (mstep) dispatch_em2_batched<true>(base, models, bw, bc, grid, lds, st, stg);
+      else dispatch_em2_batched<false>(base, models, bw, bc, grid, lds, st, stg);
     } else {
       if (mstep) dispatch_batched<true>(base, models, bw, bc, grid, lds, st);
       else dispatch_batched<false>(base, models, bw, bc, grid, lds, st);
