@@ -817,16 +817,26 @@ __host__ __device__ inline int em2_ks(int D) { return D <= 64 ? 4 : 8; }
 // Staged form (D <= 64): after the layout above, each round's samples
 // [2 by round parity][128][D] (floats), the precisions lam [G][D] (doubles),
 // the constants c [G] (doubles) and the means [G][D] (floats), so the near-pair
-// recompute and the map step read LDS only.
+// recompute and the map step read LDS only.  With G <= 16 the same bytes
+// later hold the 8 waves' map-step states [8][G][2D + 1] (floats).
 __host__ __device__ inline size_t em2_stage_off(int G, int KS) {
   return (em2_lds_bytes(G, KS) + 15) / 16 * 16;
 }
 __host__ __device__ inline size_t em2_stage_lds_bytes(int D, int G) {
-  return em2_stage_off(G, 4) + (size_t)4 * 2 * kRoundN * D + (size_t)8 * G * D +
-         (size_t)8 * G + (size_t)4 * G * D;
+  const size_t st = (size_t)4 * 2 * kRoundN * D + (size_t)8 * G * D + (size_t)8 * G +
+                    (size_t)4 * G * D;
+  const size_t mg = G <= 16 ? (size_t)4 * kNW * G * (2 * D + 1) : 0;
+  return em2_stage_off(G, 4) + (st > mg ? st : mg);
+}
+// LDS of the staged form for models of up to G components (a batch item
+// with G' <= G components uses its own, smaller layout, whose map-step states
+// for G' <= 16 must fit as well)
+inline size_t em2_stage_lds_max(int D, int G) {
+  const size_t a = em2_stage_lds_bytes(D, G), b = em2_stage_lds_bytes(D, G < 16 ? G : 16);
+  return a > b ? a : b;
 }
 inline bool em2_stage_fits(int D, int G) {
-  return D <= 64 && em2_stage_lds_bytes(D, G) <= 160 * 1024;
+  return D <= 64 && em2_stage_lds_max(D, G) <= 160 * 1024;
 }
 
 __device__ inline Lds2 carve_lds2(char* base, int G, int KS) {
@@ -956,7 +966,21 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
 
   // the owner's old means in registers when they take few (they are read by
   // every map-step chunk); otherwise reloaded per chunk
-  constexpr bool kMuReg = MSTEP && CPW * DPL <= 8;
+  // private map step (staged form, G <= 16): every wave keeps (L, m, Q) of
+  // all G components for its own samples, so no list passes between waves and
+  // a round takes no barrier; the 8 states are combined at the end of the
+  // range.  Otherwise each component has one owner wave.
+  constexpr bool kPriv = MSTEP && STG && CPW <= 2;
+  constexpr int kPG = kPriv ? 16 : 1;
+  float Lp[kPG], P1[kPG], P2[kPG], mup[kPG];
+#pragma unroll
+  for (int g = 0; g < kPG; ++g) {
+    Lp[g] = 0.0f;
+    P1[g] = 0.0f;
+    P2[g] = 0.0f;
+    mup[g] = kPriv && g < G ? a.means[(size_t)g * D + min(lane, D - 1)] : 0.0f;
+  }
+  constexpr bool kMuReg = MSTEP && !kPriv && CPW * DPL <= 8;
   float mur[kMuReg ? CPW : 1][DPL];
 #pragma unroll
   for (int c = 0; c < (kMuReg ? CPW : 1); ++c)
@@ -996,23 +1020,30 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
   const bf16x8* const wll = L.wl + lane;
   const float* const cql = L.cq + 8 * colc;
 
+  // staged form: the next round's rows of this wave, one row per register
+  // (lane d holds dimension d), loaded a round ahead
+  float pf[STG ? kGS : 1];
+  if constexpr (STG) {
+    const int64_t s0n = i0 + (int64_t)kGS * w;
+#pragma unroll
+    for (int n = 0; n < kGS; ++n)
+      pf[n] = (lane < D && s0n + n < i1) ? a.X[(s0n + n) * a.ldx + lane] : 0.0f;
+  }
+
   int round = 0;
   for (int64_t base = i0; base < i1; base += kRoundN, ++round) {
     const int64_t s0 = base + (int64_t)kGS * w;
-    // staged form: this wave's 16 rows of the round, zero past i1.  Buffers
-    // alternate by round parity: an owner reads them until its map step ends,
-    // before the next round's barrier, and this wave refills a buffer only
-    // two rounds later, after that barrier.
+    // staged form: this wave's 16 rows of the round (loaded into registers
+    // during the previous round, zero past i1) go to LDS.  Buffers alternate
+    // by round parity: an owner reads them until its map step ends, before
+    // the next round's barrier, and this wave refills a buffer only two rounds
+    // later, after that barrier.
     float* const xsr = STG ? xs + (size_t)(round & 1) * kRoundN * D : nullptr;
     if constexpr (STG) {
       float* const dst = xsr + (size_t)kGS * w * D;
-      float v[kGS];
 #pragma unroll
       for (int n = 0; n < kGS; ++n)
-        v[n] = (lane < D && s0 + n < i1) ? a.X[(s0 + n) * a.ldx + lane] : 0.0f;
-#pragma unroll
-      for (int n = 0; n < kGS; ++n)
-        if (lane < D) dst[n * D + lane] = v[n];
+        if (lane < D) dst[n * D + lane] = pf[n];
       wave_lds_sync();
     }
 
@@ -1023,8 +1054,9 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
     float acc[RBT][4];
     {
       const int64_t ia = s0 + na;
-      const bool va = ia < i1;
-      const float* xr = a.X + (va ? ia : i0) * a.ldx + 4 * kg;
+      // the staged rows are zero past i1
+      const bool va = STG || ia < i1;
+      const float* xr = STG ? xsr + (kGS * w + na) * D + 4 * kg : a.X + (va ? ia : i0) * a.ldx + 4 * kg;
       int dl = D - 4 * kg;  // this lane's dimensions are 16 ks + q < dl
       // opaque per round, so the bound tests are not hoisted out of the round
       // loop (they would stay live in registers for the whole kernel)
@@ -1114,6 +1146,13 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
       }
     }
 
+    if constexpr (STG) {
+      // the next round's rows, in flight during the rest of this round
+      const int64_t s0n = s0 + kRoundN;
+#pragma unroll
+      for (int n = 0; n < kGS; ++n)
+        pf[n] = (lane < D && s0n + n < i1) ? a.X[(s0n + n) * a.ldx + lane] : 0.0f;
+    }
     // 3. values, their error bounds, per-sample bounded maximum M and near set
     bool vj[4];
 #pragma unroll
@@ -1370,7 +1409,45 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
       __builtin_amdgcn_sched_barrier(0);
     }
 
-    if (MSTEP) {
+    if constexpr (kPriv) {
+      // 6'. the wave's own samples in order, each sample's components in
+      // order.  Sample 4 q + j's responsibility of component g sits in lane
+      // 16 q + g of acc[0][j]; four ballots mark the non-zero ones.
+      unsigned long long nzm[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) nzm[j] = __ballot(acc[0][j] != 0.0f);
+      for (int q = 0; q < 4; ++q) {
+        float xv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xv[j] = xsr[(kGS * w + 4 * q + j) * D + min(lane, D - 1)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const unsigned m16 = (unsigned)(nzm[j] >> (16 * q)) & 0xFFFFu;
+          if (m16 == 0u) continue;
+#pragma unroll
+          for (int g = 0; g < 16; ++g) {
+            if ((m16 >> g) & 1u) {
+              const float r = __int_as_float(
+                  __builtin_amdgcn_readlane(__float_as_int(acc[0][j]), 16 * q + g));
+              const float y = xv[j] - mup[g];
+              const float Lo = Lp[g];
+              const float Ln = Lo + r;
+              const float rc = __builtin_amdgcn_rcpf(Ln);
+              const float inv = r * rc;
+              const float wo = Lo * rc;
+              const float w2 = inv * Lo;
+              // the owner form's update (a dominant sample sets the mean
+              // from its own side)
+              const bool dom = inv > 0.5f;
+              Lp[g] = Ln;
+              const float dl = y - P1[g];
+              P1[g] = dom ? fmaf(-wo, dl, y) : fmaf(inv, dl, P1[g]);
+              P2[g] = fmaf(w2 * dl, dl, P2[g]);
+            }
+          }
+        }
+      }
+    } else if (MSTEP) {
       // 6. hand the non-zero responsibilities to their owners (the owner of
       // component 16 cb + colc is wave colc % 8 = lane % 8)
       // non-zero responsibilities, lane-major within each owner class (lanes
@@ -1511,7 +1588,45 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
   }
 
   if constexpr (MODE == 1 || MODE == 2) return;
-  if (MSTEP) {
+  if constexpr (kPriv) {
+    // the 8 waves' states of each component, combined in wave order by the
+    // pairwise update of (L, m, Q) in FP64 (as across work ranges); the
+    // round buffers and the FP64 constants are free here
+    __syncthreads();
+    float* const mb = xs;  // [8][G][2D + 1]
+#pragma unroll
+    for (int g = 0; g < 16; ++g)
+      if (g < G) {
+        float* const o = mb + (size_t)(w * G + g) * P;
+        if (lane == 0) o[0] = Lp[g];
+        if (lane < D) {
+          o[1 + lane] = P1[g];
+          o[1 + D + lane] = P2[g];
+        }
+      }
+    __syncthreads();
+    double* pb = a.part + (size_t)b * Gt * P;
+    for (int g = w; g < G; g += kNW) {
+      double Lt = 0.0, mt = 0.0, Qt = 0.0;
+      for (int q = 0; q < kNW; ++q) {
+        const float* const o = mb + (size_t)(q * G + g) * P;
+        const double Lb = (double)o[0];
+        if (Lb == 0.0) continue;
+        const double mbq = lane < D ? (double)o[1 + lane] : 0.0;
+        const double Qb = lane < D ? (double)o[1 + D + lane] : 0.0;
+        const double Ln = Lt + Lb;
+        const double dl = mbq - mt;
+        mt += dl * (Lb / Ln);
+        Qt += Qb + dl * dl * (Lt * Lb / Ln);
+        Lt = Ln;
+      }
+      if (lane == 0) pb[(size_t)g * P] = Lt;
+      if (lane < D) {
+        pb[(size_t)g * P + 1 + lane] = mt;
+        pb[(size_t)g * P + 1 + D + lane] = Qt;
+      }
+    }
+  } else if (MSTEP) {
     double* pb = a.part + (size_t)b * Gt * P + (size_t)g0 * P;
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
@@ -1878,7 +1993,7 @@ hipError_t launch_em_fast(const float* X, int64_t N, int D, int64_t ldx, int G, 
       a.chunk = ch;
       const int nb2 = (int)((N + ch - 1) / ch);
       const bool stg = em2_stage_fits(D, G);
-      const size_t lds = stg ? em2_stage_lds_bytes(D, G) : em2_lds_bytes(G, KS);
+      const size_t lds = stg ? em2_stage_lds_max(D, G) : em2_lds_bytes(G, KS);
       if (mstep) dispatch_em2<true>(a, nb2, lds, st, stg);
       else dispatch_em2<false>(a, nb2, lds, st, stg);
       *nb_out = nb2;
@@ -2000,7 +2115,7 @@ hipError_t launch_em_batched(const gmm_model_desc* models, int n_models, int n_i
                      D, bc);
   const bool stg = prec == GMM_PREC_BF16X3 && em2_stage_fits(D, bw.Gmax);
   const size_t lds = prec == GMM_PREC_BF16X3
-                         ? (stg ? em2_stage_lds_bytes(D, bw.Gmax) : em2_lds_bytes(bw.Gmax, em2_ks(D)))
+                         ? (stg ? em2_stage_lds_max(D, bw.Gmax) : em2_lds_bytes(bw.Gmax, em2_ks(D)))
                          : fast_lds_bytes(D, bw.Gmax);
   const int grid = n_items_host < 256 ? (n_items_host < 1 ? 1 : n_items_host) : 256;
   {
