@@ -739,6 +739,27 @@ __host__ __device__ inline size_t km2_lds_bytes(int D, int G, int KSK) {
 // k-steps (32 dimensions each) of the k-means fragment layout
 __host__ __device__ inline int km2_ks(int D) { return D <= 64 ? 2 : 4; }
 
+// Staged form (D <= 64): after the layout above, each round's samples
+// [2 by round parity][128][D] (floats), written from the registers that
+// already hold them, so the map step reads LDS; with G <= 16 the same bytes
+// later hold the 8 waves' map-step states [8][G][2D + 1] (floats).
+__host__ __device__ inline size_t km2_stage_off(int D, int G) {
+  return (km2_lds_bytes(D, G, 2) + 15) / 16 * 16;
+}
+__host__ __device__ inline size_t km2_stage_lds_bytes(int D, int G) {
+  const size_t st = (size_t)4 * 2 * kKRound * D;
+  const size_t mg = G <= 16 ? (size_t)4 * kNW * G * (2 * D + 1) : 0;
+  return km2_stage_off(D, G) + (st > mg ? st : mg);
+}
+// for models of up to G means (a batch item with fewer uses its own layout)
+inline size_t km2_stage_lds_max(int D, int G) {
+  const size_t a = km2_stage_lds_bytes(D, G), b = km2_stage_lds_bytes(D, G < 16 ? G : 16);
+  return a > b ? a : b;
+}
+inline bool km2_stage_fits(int D, int G) {
+  return D <= 64 && km2_stage_lds_max(D, G) <= 160 * 1024;
+}
+
 __device__ inline KLds carve_klds(char* base, int D, int G, int KSK) {
   KLds L;
   float* f = (float*)base;
@@ -763,9 +784,10 @@ __device__ inline KLds carve_klds(char* base, int D, int G, int KSK) {
   return L;
 }
 
-template <int CPW, int DPL>
+template <int CPW, int DPL, bool STG = false>
 __device__ __forceinline__ void km2_range(const Km2Args& a, int64_t i0, int64_t i1, int b,
                                           char* lds_raw) {
+  static_assert(!STG || DPL == 1, "staged form: D <= 64");
   constexpr int RBT = (CPW + 1) / 2;  // row blocks of 16 means
   constexpr int KSK = 2 * DPL;        // k-steps of 32 dimensions
   const int D = a.D, G = a.G;
@@ -792,6 +814,21 @@ __device__ __forceinline__ void km2_range(const Km2Args& a, int64_t i0, int64_t 
     L.sd[d] = a.sd[d];
   }
 
+  float* const xs = STG ? (float*)(lds_raw + km2_stage_off(D, G)) : nullptr;
+  // private map step (staged form, G <= 16): every wave keeps (count, m, Q)
+  // of all G means for its own samples, so no list passes between waves and
+  // a round takes no barrier; the 8 states are combined at the end of the
+  // range.  Otherwise each mean has one owner wave.
+  constexpr bool kPriv = STG && CPW <= 2;
+  constexpr int kPG = kPriv ? 16 : 1;
+  float Lp[kPG], P1[kPG], P2[kPG], mup[kPG];
+#pragma unroll
+  for (int g = 0; g < kPG; ++g) {
+    Lp[g] = 0.0f;
+    P1[g] = 0.0f;
+    P2[g] = 0.0f;
+    mup[g] = kPriv && g < G ? a.means[(size_t)g * D + min(lane, D - 1)] : 0.0f;
+  }
   float Lc[CPW], S1[CPW][DPL], S2[CPW][DPL];
 #pragma unroll
   for (int c = 0; c < CPW; ++c) {
@@ -833,6 +870,17 @@ __device__ __forceinline__ void km2_range(const Km2Args& a, int64_t i0, int64_t 
       for (int ks = 0; ks < KSK; ++ks)
 #pragma unroll
         for (int i = 0; i < 8; ++i) xv[ks][i] = (va && 32 * ks + i < dl) ? xr[32 * ks + i] : 0.0f;
+      if constexpr (STG) {
+        // the round's rows to LDS (zero past i1).  Buffers alternate by round
+        // parity: an owner reads them until its map step ends, before the next
+        // round's barrier, and this wave refills a buffer two rounds later.
+        float* const dst = xs + (size_t)(round & 1) * kKRound * D + (size_t)(kKGS * w + na) * D;
+#pragma unroll
+        for (int ks = 0; ks < KSK; ++ks)
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            if (32 * ks + 8 * kg + i < D) dst[32 * ks + 8 * kg + i] = xv[ks][i];
+      }
       bf16x8 ah[KSK], al[KSK];
       float usq = 0.0f;
 #pragma unroll
@@ -967,8 +1015,37 @@ __device__ __forceinline__ void km2_range(const Km2Args& a, int64_t i0, int64_t 
       }
     }
 
-    // 4. hand (sample, chosen mean) to the mean's owner wave best % 8
     const bool has = va && kg == 0 && best >= 0;
+    if constexpr (kPriv) {
+      // 4'. the wave's samples in order; sample n's chosen mean is in lane n
+      const float* const xsr = xs + (size_t)(round & 1) * kKRound * D;
+      for (int q = 0; q < 4; ++q) {
+        float xq[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xq[j] = xsr[(kKGS * w + 4 * q + j) * D + min(lane, D - 1)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int g = __builtin_amdgcn_readlane(has ? best : -1, 4 * q + j);
+          if (g < 0) continue;
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            if (g == k) {
+              const float y = xq[j] - mup[k];
+              const float Lo = Lp[k];
+              const float Ln = Lo + 1.0f;
+              const float inv = __builtin_amdgcn_rcpf(Ln);
+              const float w2 = inv * Lo;
+              Lp[k] = Ln;
+              const float dlt = y - P1[k];
+              P1[k] = Lo == 0.0f ? y : fmaf(inv, dlt, P1[k]);
+              P2[k] = fmaf(w2 * dlt, dlt, P2[k]);
+            }
+          }
+        }
+      }
+      continue;
+    }
+    // 4. hand (sample, chosen mean) to the mean's owner wave best % 8
     const int own = has ? (best & 7) : 0;
     int mypos = 0, mine = 0;
 #pragma unroll
@@ -1047,7 +1124,8 @@ __device__ __forceinline__ void km2_range(const Km2Args& a, int64_t i0, int64_t 
               for (int i = 0; i < 4; ++i) {
                 const int2 e2 = os[o + min(q0 + i, cc - 1)];
                 okq[i] = q0 + i < cc;
-                const float* xr = a.X + (base + (e2.x & 0xFF)) * a.ldx;
+                const float* xr = STG ? xs + (size_t)(round & 1) * kKRound * D + (e2.x & 0xFF) * D
+                                      : a.X + (base + (e2.x & 0xFF)) * a.ldx;
 #pragma unroll
                 for (int jd = 0; jd < DPL; ++jd)
                   y[i][jd] = xr[min(lane + kWave * jd, D - 1)] - mu[jd];
@@ -1080,8 +1158,45 @@ __device__ __forceinline__ void km2_range(const Km2Args& a, int64_t i0, int64_t 
   }
 
   double* pb = a.part + (size_t)b * G * P;
+  if constexpr (kPriv) {
+    // the 8 waves' states of each mean, combined in wave order by the
+    // pairwise update of (count, m, Q) in FP64 (as across work ranges)
+    __syncthreads();
+    float* const mb = xs;  // [8][G][2D + 1]
 #pragma unroll
-  for (int c = 0; c < CPW; ++c) {
+    for (int g = 0; g < 16; ++g)
+      if (g < G) {
+        float* const o = mb + (size_t)(w * G + g) * P;
+        if (lane == 0) o[0] = Lp[g];
+        if (lane < D) {
+          o[1 + lane] = P1[g];
+          o[1 + D + lane] = P2[g];
+        }
+      }
+    __syncthreads();
+    for (int g = w; g < G; g += kNW) {
+      double Lt = 0.0, mt = 0.0, Qt = 0.0;
+      for (int q = 0; q < kNW; ++q) {
+        const float* const o = mb + (size_t)(q * G + g) * P;
+        const double Lb = (double)o[0];
+        if (Lb == 0.0) continue;
+        const double mbq = lane < D ? (double)o[1 + lane] : 0.0;
+        const double Qb = lane < D ? (double)o[1 + D + lane] : 0.0;
+        const double Ln = Lt + Lb;
+        const double dl = mbq - mt;
+        mt += dl * (Lb / Ln);
+        Qt += Qb + dl * dl * (Lt * Lb / Ln);
+        Lt = Ln;
+      }
+      if (lane == 0) pb[(size_t)g * P] = Lt;
+      if (lane < D) {
+        pb[(size_t)g * P + 1 + lane] = mt;
+        pb[(size_t)g * P + 1 + D + lane] = Qt;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < (kPriv ? 0 : CPW); ++c) {
     const int g = w + kNW * c;
     if (g < G) {
       if (lane == 0) pb[(size_t)g * P] = (double)Lc[c];
@@ -1113,13 +1228,13 @@ __device__ __forceinline__ void km2_range(const Km2Args& a, int64_t i0, int64_t 
   }
 }
 
-template <int CPW, int DPL>
+template <int CPW, int DPL, bool STG>
 __global__ void __launch_bounds__(kThreads) k_km2(Km2Args a) {
   extern __shared__ __attribute__((aligned(16))) char lds_raw[];
   const int b = blockIdx.x;
   const int64_t i0 = (int64_t)b * a.chunk;
   const int64_t i1 = min(a.N, i0 + a.chunk);
-  km2_range<CPW, DPL>(a, i0, i1, b, lds_raw);
+  km2_range<CPW, DPL, STG>(a, i0, i1, b, lds_raw);
 }
 
 // Per-mean constants: block g < 16 RB.  lam and s = sqrt(lam) per dimension
@@ -1213,7 +1328,7 @@ __global__ void __launch_bounds__(256) k_km2_pre_batched(const gmm_model_desc* m
                kb.cq + (size_t)mi * kb.kps);
 }
 
-template <int CPW, int DPL>
+template <int CPW, int DPL, bool STG>
 __global__ void __launch_bounds__(kThreads) k_km2_batched(Km2Args base,
                                                           const gmm_model_desc* models,
                                                           const BatchItemDev* items,
@@ -1244,10 +1359,13 @@ __global__ void __launch_bounds__(kThreads) k_km2_batched(Km2Args base,
     a.n_rec = nullptr;
     a.dev_status = m.dev_status;
     // the smallest component-block template that holds the model's G
-    if (CPW > 2 && a.G <= 16) km2_range<(CPW > 2 ? 2 : CPW), DPL>(a, item.i0, item.i1, 0, lds_raw);
-    else if (CPW > 4 && a.G <= 32) km2_range<(CPW > 4 ? 4 : CPW), DPL>(a, item.i0, item.i1, 0, lds_raw);
-    else if (CPW > 8 && a.G <= 64) km2_range<(CPW > 8 ? 8 : CPW), DPL>(a, item.i0, item.i1, 0, lds_raw);
-    else km2_range<CPW, DPL>(a, item.i0, item.i1, 0, lds_raw);
+    if (CPW > 2 && a.G <= 16)
+      km2_range<(CPW > 2 ? 2 : CPW), DPL, STG>(a, item.i0, item.i1, 0, lds_raw);
+    else if (CPW > 4 && a.G <= 32)
+      km2_range<(CPW > 4 ? 4 : CPW), DPL, STG>(a, item.i0, item.i1, 0, lds_raw);
+    else if (CPW > 8 && a.G <= 64)
+      km2_range<(CPW > 8 ? 8 : CPW), DPL, STG>(a, item.i0, item.i1, 0, lds_raw);
+    else km2_range<CPW, DPL, STG>(a, item.i0, item.i1, 0, lds_raw);
     __syncthreads();
   }
 }
@@ -1264,9 +1382,9 @@ void km_launch_one(const KmArgs& a, int nb, size_t lds, hipStream_t st) {
   hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), lds, st, a);
 }
 
-template <int CPW, int DPL>
+template <int CPW, int DPL, bool STG = false>
 void km2_launch_one(const Km2Args& a, int nb, size_t lds, hipStream_t st) {
-  auto kern = k_km2<CPW, DPL>;
+  auto kern = k_km2<CPW, DPL, STG>;
   static bool attr_set = false;  // benign race: setting the attribute twice is harmless
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1276,9 +1394,15 @@ void km2_launch_one(const Km2Args& a, int nb, size_t lds, hipStream_t st) {
   hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), lds, st, a);
 }
 
-void km2_dispatch(const Km2Args& a, int nb, size_t lds, hipStream_t st) {
+void km2_dispatch(const Km2Args& a, int nb, size_t lds, hipStream_t st, bool stg) {
   const int cpw = (a.G + kNW - 1) / kNW;
-  if (a.D <= 64) {
+  if (stg) {
+    if (cpw <= 2) km2_launch_one<2, 1, true>(a, nb, lds, st);
+    else if (cpw <= 4) km2_launch_one<4, 1, true>(a, nb, lds, st);
+    else if (cpw <= 8) km2_launch_one<8, 1, true>(a, nb, lds, st);
+    else if (cpw <= 13) km2_launch_one<13, 1, true>(a, nb, lds, st);
+    else km2_launch_one<16, 1, true>(a, nb, lds, st);
+  } else if (a.D <= 64) {
     if (cpw <= 2) km2_launch_one<2, 1>(a, nb, lds, st);
     else if (cpw <= 4) km2_launch_one<4, 1>(a, nb, lds, st);
     else if (cpw <= 8) km2_launch_one<8, 1>(a, nb, lds, st);
@@ -1293,11 +1417,11 @@ void km2_dispatch(const Km2Args& a, int nb, size_t lds, hipStream_t st) {
   }
 }
 
-template <int CPW, int DPL>
+template <int CPW, int DPL, bool STG = false>
 void km2_launch_batched_one(const Km2Args& base, const gmm_model_desc* models,
                             const BatchWorkspace& bw, const Km2Batch& kb, int grid, size_t lds,
                             hipStream_t st) {
-  auto kern = k_km2_batched<CPW, DPL>;
+  auto kern = k_km2_batched<CPW, DPL, STG>;
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1355,7 +1479,8 @@ hipError_t launch_kmeans_fast(const float* X, int64_t N, int D, int64_t ldx, int
     a.dev_status = dev_status;
     {
       ProfScope ps(kProfKmAssign, st);
-      km2_dispatch(a, nb, km2_lds_bytes(D, G, KSK), st);
+      const bool stg = km2_stage_fits(D, G);
+      km2_dispatch(a, nb, stg ? km2_stage_lds_max(D, G) : km2_lds_bytes(D, G, KSK), st, stg);
     }
     hipLaunchKernelGGL(k_km_fin_fast, dim3(G), dim3(256), 0, st, w.partials, nb, N, D, G,
                        var_floor, means, dcovs, hefts, counts, w.scalars, inertia, dev_status);
@@ -1428,12 +1553,18 @@ hipError_t launch_kmeans_batched(const gmm_model_desc* models, int n_models, int
   base.D = D;
   base.part = bw.partials;
   base.in_part = bw.sparts;
-  const size_t lds = km2_lds_bytes(D, bw.Gmax, KSK);
+  const bool stg = km2_stage_fits(D, bw.Gmax);
+  const size_t lds = stg ? km2_stage_lds_max(D, bw.Gmax) : km2_lds_bytes(D, bw.Gmax, KSK);
   const int grid = n_items_host < 256 ? (n_items_host < 1 ? 1 : n_items_host) : 256;
   {
     ProfScope ps(kProfBatched, st);
     const int cpw = (bw.Gmax + kNW - 1) / kNW;
-    if (D <= 64) {
+    if (stg) {
+      if (cpw <= 2) km2_launch_batched_one<2, 1, true>(base, models, bw, kb, grid, lds, st);
+      else if (cpw <= 4) km2_launch_batched_one<4, 1, true>(base, models, bw, kb, grid, lds, st);
+      else if (cpw <= 8) km2_launch_batched_one<8, 1, true>(base, models, bw, kb, grid, lds, st);
+      else km2_launch_batched_one<16, 1, true>(base, models, bw, kb, grid, lds, st);
+    } else if (D <= 64) {
       if (cpw <= 2) km2_launch_batched_one<2, 1>(base, models, bw, kb, grid, lds, st);
       else if (cpw <= 4) km2_launch_batched_one<4, 1>(base, models, bw, kb, grid, lds, st);
       else if (cpw <= 8) km2_launch_batched_one<8, 1>(base, models, bw, kb, grid, lds, st);
