@@ -888,8 +888,10 @@ __device__ __forceinline__ float slice_lse(const float* pd, const float* ps, int
 //           pairs) -> wD[slice][n] and the slice's sum of
 //           exp(value - M - wD) -> wS[slice][n];
 //   MODE 3  log-sum-exp M + D* + log(sum over slices of
-//           wS exp(wD - D*)), D* = max over slices of wD (Eqs. 16-18), the
-//           responsibilities and the map step of the slice's components.
+//           wS exp(wD - D*)), D* = max over slices of wD (Eqs. 16-18; the
+//           log-likelihood pass k_wll, run between MODES 2 and 3, leaves M,
+//           D* and the logarithm of each sample in slot 0 of wM, wD, wS),
+//           the responsibilities and the map step of the slice's components.
 // Near pairs are the same in MODES 2 and 3 (same bound, same M, same order)
 // and always taken in FP64: MODE 2 stores the first kCapR exact values of
 // each 16-sample group and slice (wR), MODE 3 reads them and recomputes only
@@ -1175,7 +1177,7 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
     if constexpr (MODE < 2) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) M[j] = row16_max(M[j]);
-    } else {
+    } else if constexpr (MODE == 2) {
       // the bound over all slices
 #pragma unroll
       for (int j = 0; j < 4; ++j)
@@ -1185,6 +1187,11 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
           for (int q = 0; q < a.S; ++q) m = fmaxf(m, pm[(size_t)q * a.NS]);
           M[j] = m;
         }
+    } else {
+      // MODE 3: the bound over all slices, combined into slot 0 by k_wll
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (vj[j]) M[j] = a.wM[s0 + 4 * rowq + j];
     }
     if constexpr (MODE == 1) {
       if (colc == 0) {
@@ -1356,17 +1363,13 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if constexpr (MODE == 3) {
-        // lse = M + D* + log(sum over slices in slice order)
-        double lsd = 0.0;
-        float dstar = 0.0f;
-        if (vj[j])
-          dstar = slice_lse(a.wD + s0 + 4 * rowq + j, a.wS + s0 + 4 * rowq + j, a.S, a.NS, lsd);
-        const float ls = (float)lsd;
-        const double lse = ((double)M[j] + (double)dstar) + lsd;
-        if (vj[j] && colc == 0 && g0 == 0) {
-          llacc += lse;
-          if (!isfinite(lse)) bad = 1;
-          if (a.per_sample) a.per_sample[s0 + 4 * rowq + j] = (float)lse;
+        // lse = M + D* + log(sum over slices in slice order): D* and the
+        // logarithm combined by k_wll into slot 0 (which also took the
+        // log-likelihood)
+        float dstar = 0.0f, ls = 0.0f;
+        if (vj[j]) {
+          dstar = a.wD[s0 + 4 * rowq + j];
+          ls = a.wS[s0 + 4 * rowq + j];
         }
 #pragma unroll
         for (int cb = 0; cb < RBT; ++cb) {
@@ -1646,7 +1649,7 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
   }
   if (a.n_rec && lane == 0 && nrec)
     atomicAdd((unsigned long long*)a.n_rec, (unsigned long long)nrec);
-  if (MODE == 3 && g0 != 0) return;  // the first slice holds the log-likelihood
+  if (MODE == 3) return;  // k_wll took the log-likelihood
   {
     const double v = wave_sum_d(llacc);
     if (lane == 0) L.llw[w] = v;
@@ -1685,17 +1688,18 @@ __global__ void __launch_bounds__(kThreads) k_em2s(FastArgs a) {
   em2_range<16, DPL, MODE == 3, MODE>(s, i0, i1, b, lds_raw);
 }
 
-// Log-likelihood of the sliced passes without the map step: per sample
-// lse = M + slice_lse (the arithmetic of MODE 3), the
-// workgroup's samples summed per thread and the threads in order.
+// Log-likelihood of the sliced passes: per sample lse = M + slice_lse, the
+// workgroup's samples summed per thread and the threads in order.  With comb
+// set it also leaves, in slot 0 of each array, what the map pass needs of the
+// sample: M (wM), D* (wD) and log(sum over slices of S_q exp(D_q - D*)) (wS),
+// each thread reading all slots of its sample before it writes them.
 constexpr int kWllT = 256;
-__global__ void __launch_bounds__(kWllT) k_wll(const float* __restrict__ wM,
-                                               const float* __restrict__ wD,
-                                               const float* __restrict__ wS, int S, int64_t NS,
+__global__ void __launch_bounds__(kWllT) k_wll(float* __restrict__ wM, float* __restrict__ wD,
+                                               float* __restrict__ wS, int S, int64_t NS,
                                                int64_t N, int64_t chunk,
                                                float* __restrict__ per_sample,
                                                double* __restrict__ ll_part,
-                                               int32_t* __restrict__ dev_status) {
+                                               int32_t* __restrict__ dev_status, int comb) {
   __shared__ double sh[kWllT];
   const int b = blockIdx.x;
   const int64_t i0 = (int64_t)b * chunk;
@@ -1711,6 +1715,11 @@ __global__ void __launch_bounds__(kWllT) k_wll(const float* __restrict__ wM,
     acc += lse;
     if (!isfinite(lse)) bad = 1;
     if (per_sample) per_sample[n] = (float)lse;
+    if (comb) {
+      wM[n] = m;
+      wD[n] = dstar;
+      wS[n] = (float)ls;  // a float widened: exact
+    }
   }
   sh[threadIdx.x] = acc;
   __syncthreads();
@@ -1931,19 +1940,21 @@ hipError_t launch_em_sliced(const float* X, int64_t N, int D, int64_t ldx, int G
                      w.lamg64, dev_status, n_recomputed, w.counters);
   {
     ProfScope ps(mstep ? kProfEM : kProfLoglik, st);
+    // bounds, near pairs and slice sums; the log-likelihood (and, before a
+    // map pass, each sample's combination of its slices); the map pass
     if (D <= 64) {
       launch_em2s_one<1, 1>(a, nb, st);
       launch_em2s_one<1, 2>(a, nb, st);
-      if (mstep) launch_em2s_one<1, 3>(a, nb, st);
     } else {
       launch_em2s_one<2, 1>(a, nb, st);
       launch_em2s_one<2, 2>(a, nb, st);
-      if (mstep) launch_em2s_one<2, 3>(a, nb, st);
     }
-    if (!mstep)
-      hipLaunchKernelGGL(k_wll, dim3(nb), dim3(kWllT), 0, st, (const float*)w.wM,
-                         (const float*)w.wD, (const float*)w.wS, S, N, N, a.chunk, per_sample,
-                         w.scalars, dev_status);
+    hipLaunchKernelGGL(k_wll, dim3(nb), dim3(kWllT), 0, st, w.wM, w.wD, w.wS, S, N, N, a.chunk,
+                       per_sample, w.scalars, dev_status, mstep ? 1 : 0);
+    if (mstep) {
+      if (D <= 64) launch_em2s_one<1, 3>(a, nb, st);
+      else launch_em2s_one<2, 3>(a, nb, st);
+    }
   }
   *nb_out = nb;
   return hipGetLastError();
