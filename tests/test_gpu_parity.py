@@ -97,6 +97,8 @@ EM_ONEPASS = [
     (20_000, 100, 100),
     (4097, 64, 40),
     (2000, 40, 128),
+    (50_000, 64, 16),   # per-wave map-step states, largest LDS layout
+    (20_000, 40, 9),
 ]
 
 
@@ -146,7 +148,8 @@ def test_em_step_diag_beyond_onepass(G_, oracle, N, D, G, path, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
-@pytest.mark.parametrize("N,D,G", [(777, 64, 128), (777, 64, 130), (777, 64, 200)])
+@pytest.mark.parametrize("N,D,G", [(777, 64, 128), (777, 64, 130), (777, 64, 200), (777, 64, 16),
+                                   (5000, 40, 12), (777, 40, 64)])
 def test_em_heavy_sample_after_tiny_weights(G_, oracle, N, D, G, prec):
     """Unfitted components that collapse onto one or two samples: far-off
     samples with responsibilities ~1e-11 can open a component's run in a
@@ -164,7 +167,7 @@ def test_em_heavy_sample_after_tiny_weights(G_, oracle, N, D, G, prec):
     check_em(gpu, oracle.em_iter(X, w, mu, var, 1e-10), N)
 
 
-@pytest.mark.parametrize("N,D,G", [(200_000, 100, 100), (50_000, 40, 64)])
+@pytest.mark.parametrize("N,D,G", [(200_000, 100, 100), (50_000, 40, 64), (100_000, 40, 16)])
 def test_em_forms_agree_on_fitted_model(G_, oracle, N, D, G):
     """From a k-means hand-off (the realistic regime: most samples have one
     near component), both arithmetic forms match the oracle and each other."""
@@ -339,7 +342,8 @@ def test_loglik_diag(G_, oracle, N, D, G, prec):
                                         (5000, 128, 128, True), (3001, 65, 17, False),
                                         (1025, 40, 64, False), (129, 40, 16, True),
                                         (6000, 64, 512, True), (3001, 100, 300, False),
-                                        (2000, 64, 1100, True), (1000, 300, 3, True)])
+                                        (2000, 64, 1100, True), (1000, 300, 3, True),
+                                        (50_000, 64, 16, True), (20_000, 40, 9, False)])
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
 def test_kmeans_step(G_, oracle, N, D, G, maha, prec):
     X, _ = synth.diag_gmm(300 + N, D, max(G, 2), N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
