@@ -883,7 +883,8 @@ __device__ __forceinline__ float slice_lse(const float* pd, const float* ps, int
 // than one workgroup's LDS holds, three passes over slices of them, each
 // workgroup (b, slice) screening its slice for its sample range:
 //   MODE 1  the slice's bounded maximum per sample -> wM[slice][n];
-//   MODE 2  the global bound M = max over slices, the slice's near pairs
+//   MODE 2  the global bound M = max over slices (k_wmax, run between
+//           MODES 1 and 2, leaves it in slot 0 of wM), the slice's near pairs
 //           recomputed exactly, their largest value less M (0 without near
 //           pairs) -> wD[slice][n] and the slice's sum of
 //           exp(value - M - wD) -> wS[slice][n];
@@ -1177,18 +1178,9 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
     if constexpr (MODE < 2) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) M[j] = row16_max(M[j]);
-    } else if constexpr (MODE == 2) {
-      // the bound over all slices
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (vj[j]) {
-          const float* pm = a.wM + s0 + 4 * rowq + j;
-          float m = -INFINITY;
-          for (int q = 0; q < a.S; ++q) m = fmaxf(m, pm[(size_t)q * a.NS]);
-          M[j] = m;
-        }
     } else {
-      // MODE 3: the bound over all slices, combined into slot 0 by k_wll
+      // MODES 2 and 3: the bound over all slices, combined into slot 0 (by
+      // k_wmax after MODE 1; k_wll keeps it there)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         if (vj[j]) M[j] = a.wM[s0 + 4 * rowq + j];
@@ -1688,6 +1680,17 @@ __global__ void __launch_bounds__(kThreads) k_em2s(FastArgs a) {
   em2_range<16, DPL, MODE == 3, MODE>(s, i0, i1, b, lds_raw);
 }
 
+// The bound over all slices of each sample into slot 0 of wM (in place: the
+// maximum is unchanged by it, so later passes may take it again).
+__global__ void __launch_bounds__(256) k_wmax(float* __restrict__ wM, int S, int64_t NS,
+                                              int64_t N) {
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  float m = wM[n];
+  for (int q = 1; q < S; ++q) m = fmaxf(m, wM[(size_t)q * NS + n]);
+  wM[n] = m;
+}
+
 // Log-likelihood of the sliced passes: per sample lse = M + slice_lse, the
 // workgroup's samples summed per thread and the threads in order.  With comb
 // set it also leaves, in slot 0 of each array, what the map pass needs of the
@@ -1942,13 +1945,12 @@ hipError_t launch_em_sliced(const float* X, int64_t N, int D, int64_t ldx, int G
     ProfScope ps(mstep ? kProfEM : kProfLoglik, st);
     // bounds, near pairs and slice sums; the log-likelihood (and, before a
     // map pass, each sample's combination of its slices); the map pass
-    if (D <= 64) {
-      launch_em2s_one<1, 1>(a, nb, st);
-      launch_em2s_one<1, 2>(a, nb, st);
-    } else {
-      launch_em2s_one<2, 1>(a, nb, st);
-      launch_em2s_one<2, 2>(a, nb, st);
-    }
+    if (D <= 64) launch_em2s_one<1, 1>(a, nb, st);
+    else launch_em2s_one<2, 1>(a, nb, st);
+    hipLaunchKernelGGL(k_wmax, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, w.wM, S, N,
+                       N);
+    if (D <= 64) launch_em2s_one<1, 2>(a, nb, st);
+    else launch_em2s_one<2, 2>(a, nb, st);
     hipLaunchKernelGGL(k_wll, dim3(nb), dim3(kWllT), 0, st, w.wM, w.wD, w.wS, S, N, N, a.chunk,
                        per_sample, w.scalars, dev_status, mstep ? 1 : 0);
     if (mstep) {
