@@ -1525,6 +1525,28 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
           // hoisted out of the round loop
           int wo = w;
           asm volatile("" : "+v"(wo));
+          // D <= 64, rows in global memory: the deviation row of every
+          // slot's first pair is fetched before any update, so those loads
+          // share one round trip (the rest of a slot's pairs follow as below)
+          constexpr bool kFirst = !STG && DPL == 1;
+          float yf[kFirst ? CPW : 1];
+          if constexpr (kFirst) {
+            int rowf[CPW];
+            int of = 0;
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) {
+              // an empty slot reads the round's first sample (in range)
+              rowf[c] = cnt[c] > 0 ? (os[min(of, 63)].x & 0xFF) : 0;
+              of += cnt[c];
+            }
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) {
+              const int g = g0 + wo + kNW * c;
+              const float m0 = kMuReg ? mur[kMuReg ? c : 0][0]
+                                      : a.means[(size_t)min(g, Gt - 1) * D + min(lane, D - 1)];
+              yf[c] = a.X[(base + rowf[c]) * a.ldx + min(lane, D - 1)] - m0;
+            }
+          }
 #pragma unroll
           for (int c = 0; c < CPW; ++c) {
             const int cc = cnt[c];
@@ -1536,7 +1558,23 @@ __device__ __forceinline__ void em2_range(const FastArgs& a, int64_t i0, int64_t
                 mu[jd] = kMuReg ? mur[kMuReg ? c : 0][jd]
                          : STG  ? smu[g * D + min(lane + kWave * jd, D - 1)]
                                 : a.means[(size_t)g * D + min(lane + kWave * jd, D - 1)];
-              for (int q0 = 0; q0 < cc; q0 += 4) {
+              if constexpr (kFirst) {
+                const float r = __int_as_float(os[o].y);
+                if (r != 0.0f) {
+                  const float Lo = Lc[c];
+                  const float Ln = Lo + r;
+                  const float rc = __builtin_amdgcn_rcpf(Ln);
+                  const float inv = r * rc;
+                  const float wo = Lo * rc;
+                  const float w2 = inv * Lo;
+                  const bool dom = inv > 0.5f;
+                  Lc[c] = Ln;
+                  const float dl = yf[c] - S1[c][0];
+                  S1[c][0] = dom ? fmaf(-wo, dl, yf[c]) : fmaf(inv, dl, S1[c][0]);
+                  S2[c][0] = fmaf(w2 * dl, dl, S2[c][0]);
+                }
+              }
+              for (int q0 = kFirst ? 1 : 0; q0 < cc; q0 += 4) {
                 float rq[4], y[4][DPL];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
