@@ -41,10 +41,15 @@ def gpu_em_step(gmm, X, w, mu, var, floor, prec=0, full=False, ws=None):
                 loglik=float(ll.item()), nrec=int(nrec.item()), status=int(st.item()))
 
 
-def gpu_kmeans_step(gmm, X, mu, dist, floor, gvar=None, prec=0):
+def gpu_kmeans_step(gmm, X, mu, dist, floor, gvar=None, prec=0, ldx=None):
     N, D = X.shape
     G = mu.shape[0]
-    Xd = _t(X)
+    if ldx is None or ldx == D:
+        Xd = _t(X)
+    else:  # rows ldx floats apart
+        wide = np.zeros((N, ldx), np.float32)
+        wide[:, :D] = X
+        Xd = _t(wide)[:, :D]
     m = _t(mu)
     dc = torch.zeros(G, D, device=DEV)
     h = torch.zeros(G, device=DEV)
@@ -298,22 +303,41 @@ def test_em_deterministic(G_, prec):
     assert a["loglik"] == b["loglik"]
 
 
-def test_em_row_stride(G_, oracle):
-    """X with a row stride larger than D (ldx > D)."""
-    X, _ = synth.diag_gmm(56, 5, 3, 2000, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
-    w, mu, var = _params(6, 5, 3, X)
-    wide = np.zeros((2000, 8), np.float32)
-    wide[:, :5] = X
-    Xd = _t(wide)[:, :5]
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
+@pytest.mark.parametrize("D,G,ldx", [(5, 3, 8), (40, 12, 41), (40, 40, 48)])
+def test_em_row_stride(G_, oracle, D, G, ldx, prec):
+    """X with a row stride larger than D (ldx > D); in the BF16x3 form these
+    shapes run the staged E-step (per-wave map step at G=12, owners at G=40)."""
+    N = 2000
+    X, _ = synth.diag_gmm(56 + D, D, G, N, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
+    w, mu, var = _params(6, D, G, X)
+    wide = np.zeros((N, ldx), np.float32)
+    wide[:, :D] = X
+    Xd = _t(wide)[:, :D]
     cov = G_.COV_DIAG
     h, m, c = _t(w), _t(mu), _t(var)
     ll = torch.zeros(1, dtype=torch.float64, device=DEV)
     st = torch.zeros(1, dtype=torch.int32, device=DEV)
-    ws = G_.workspace(2000, 5, 3, cov, 0, DEV)
-    G_.gmm_em_iter(Xd, cov, h, m, c, 1e-10, 0, ll, None, st, ws)
+    ws = G_.workspace(N, D, G, cov, prec, DEV)
+    G_.gmm_em_iter(Xd, cov, h, m, c, 1e-10, prec, ll, None, st, ws)
+    assert int(st.item()) == 0
     gpu = dict(hefts=h.cpu().numpy(), means=m.cpu().numpy(), covs=c.cpu().numpy(),
                loglik=float(ll.item()))
-    check_em(gpu, oracle.em_iter(X, w, mu, var, 1e-10), 2000)
+    check_em(gpu, oracle.em_iter(X, w, mu, var, 1e-10), N)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
+@pytest.mark.parametrize("D,G,ldx", [(40, 12, 41), (40, 40, 48)])
+def test_kmeans_row_stride(G_, oracle, D, G, ldx, prec):
+    """k-means on X with a row stride larger than D (the staged matrix-core
+    form in BF16x3: per-wave accumulation at G=12, owners at G=40)."""
+    X, _ = synth.diag_gmm(88 + D, D, G, 3001, "normal", 0.0, 4.0, "loguniform", 0.1, 10.0)
+    mu = synth.static_subset(X, G)
+    gv = oracle.global_stats(X)[1]
+    lam = oracle.maha_lambda(gv, 1e-10)
+    gk = gpu_kmeans_step(G_, X, mu, 1, 1e-10, gvar=gv, prec=prec, ldx=ldx)
+    assert gk["status"] == 0
+    check_kmeans(gk, oracle.kmeans_iter(X, mu, lam, 1e-10), oracle.kmeans_dists(X, mu, lam), len(X))
 
 
 # ---------------------------------------------------------------- loglik
