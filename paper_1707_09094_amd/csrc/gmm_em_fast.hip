@@ -650,12 +650,14 @@ __global__ void __launch_bounds__(256) k_pre_fast_batched(const gmm_model_desc* 
 
 // Reduce step for the Welford partials [nb][G][1 + 2D] = (L, m, Q), m being
 // the weighted mean of x - mu_old: one workgroup per component (D <= 128),
-// thread per dimension, blocks combined in order by L = La + Lb,
+// thread per dimension, blocks (or the segments k_welford_seg combined, every
+// seg-th block) combined in order by L = La + Lb,
 // m = ma + (mb - ma) Lb / L, Q = Qa + Qb + (mb - ma)^2 La Lb / L
 // (welford_combine).
 // Then Eq. 5 (w = L/N), Eq. 6 (mu = mu_old + m), Eq. 7 (sigma2 = Q/L) and the
 // floor.
 __global__ void __launch_bounds__(256) k_fin_welford(const double* __restrict__ part, int nb,
+                                                     int seg,
                                                      int64_t N, int D, int G, float var_floor,
                                                      float* __restrict__ hefts,
                                                      float* __restrict__ means,
@@ -670,7 +672,8 @@ __global__ void __launch_bounds__(256) k_fin_welford(const double* __restrict__ 
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   double m, Q;
-  const double Ltot = welford_combine<256, 32>(part + (size_t)g * P, (size_t)G * P, nb, D, S, m, Q);
+  const double Ltot = welford_combine<256, 32>(part + (size_t)g * P, (size_t)seg * G * P,
+                                               (nb + seg - 1) / seg, D, S, m, Q);
   const int d = threadIdx.x;
   if (d < D && Ltot > 0.0) {
     double v = Q / Ltot;
@@ -2061,7 +2064,13 @@ hipError_t launch_em_fast(const float* X, int64_t N, int D, int64_t ldx, int G, 
 hipError_t launch_fin_welford(int nb, int64_t N, int D, int G, float var_floor, float* hefts,
                               float* means, float* covs, double* mean_loglik, int32_t* dev_status,
                               const Workspace& w, hipStream_t st) {
-  hipLaunchKernelGGL(k_fin_welford, dim3(G), dim3(256), 0, st, w.partials, nb, N, D, G,
+  // more than 64 blocks: segments of 32 first (G x segments workgroups), so
+  // that the G final chains are short
+  const int seg = nb > 64 ? 32 : 1;
+  if (seg > 1)
+    hipLaunchKernelGGL(k_welford_seg, dim3(G, (nb + seg - 1) / seg), dim3(256), 0, st, w.partials,
+                       nb, seg, D, G);
+  hipLaunchKernelGGL(k_fin_welford, dim3(G), dim3(256), 0, st, w.partials, nb, seg, N, D, G,
                      var_floor, hefts, means, covs, w.scalars, mean_loglik, dev_status);
   return hipGetLastError();
 }

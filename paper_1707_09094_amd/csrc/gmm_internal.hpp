@@ -535,6 +535,33 @@ __device__ double welford_combine(const double* __restrict__ base, size_t stride
   return S.run;
 }
 
+namespace {
+// First level of the reduce of the Welford partials [nb][G][1 + 2D] when
+// there are many blocks: workgroup (g, s) combines blocks s seg ..
+// min((s + 1) seg, nb) - 1 of component g in order (welford_combine) and
+// leaves the segment's (L, m, Q) in place of the segment's first block, so
+// that the chains of the final reduce are nb / seg long instead of nb.
+__global__ void __launch_bounds__(256) k_welford_seg(double* __restrict__ part, int nb, int seg,
+                                                     int D, int G) {
+  __shared__ WelfordLds S;
+  const int g = blockIdx.x, b0 = blockIdx.y * seg;
+  const int n = min(seg, nb - b0);
+  if (n <= 0) return;
+  const int P = 2 * D + 1;
+  double* const base = part + (size_t)b0 * G * P + (size_t)g * P;
+  double m, Q;
+  const double L = welford_combine<256, 32>(base, (size_t)G * P, n, D, S, m, Q);
+  // welford_combine ends with a barrier: every read of the segment is done
+  const int d = threadIdx.x;
+  if (d == 0) base[0] = L;
+  if (d < D) {
+    base[1 + d] = L > 0.0 ? m : 0.0;
+    base[1 + D + d] = L > 0.0 ? Q : 0.0;
+  }
+}
+
+}  // namespace
+
 // Sum of v[0..n) in index order, by thread 0, with the values staged through
 // LDS by the whole workgroup so that their loads overlap (the same arithmetic
 // as one thread's plain loop).  Every thread must call it; the sum is valid in

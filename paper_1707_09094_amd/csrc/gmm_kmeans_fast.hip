@@ -406,7 +406,8 @@ __global__ void __launch_bounds__(256) k_km_pre_fast(const double* __restrict__ 
 // Reduce step of the k-means map: pairwise (count, mean, M2) combination in
 // block order, new means, hand-off variances/weights, counts, inertia.
 __global__ void __launch_bounds__(256) k_km_fin_fast(const double* __restrict__ part, int nb,
-                                                     int64_t N, int D, int G, float var_floor,
+                                                     int seg, int64_t N, int D, int G,
+                                                     float var_floor,
                                                      float* __restrict__ means,
                                                      float* __restrict__ dcovs,
                                                      float* __restrict__ hefts,
@@ -418,7 +419,9 @@ __global__ void __launch_bounds__(256) k_km_fin_fast(const double* __restrict__ 
   const int g = blockIdx.x;
   const int P = 2 * D + 1;
   double m, Q;
-  const double Ltot = welford_combine<256, 32>(part + (size_t)g * P, (size_t)G * P, nb, D, S, m, Q);
+  // blocks, or every seg-th block holding its segment's combination
+  const double Ltot = welford_combine<256, 32>(part + (size_t)g * P, (size_t)seg * G * P,
+                                               (nb + seg - 1) / seg, D, S, m, Q);
   const int d = threadIdx.x;
   if (d < D) {
     if (Ltot > 0.0) {
@@ -1444,6 +1447,19 @@ bool km_fast_supported(int D, int G) {
   return km_lds_bytes(D, G) <= 160 * 1024;
 }
 
+// The k-means reduce; more than 64 blocks: segments of 32 first, so that the
+// G final chains are short.
+static void launch_km_fin(int nb, int64_t N, int D, int G, float var_floor, float* means,
+                          float* dcovs, float* hefts, int64_t* counts, double* inertia,
+                          int32_t* dev_status, const Workspace& w, hipStream_t st) {
+  const int seg = nb > 64 ? 32 : 1;
+  if (seg > 1)
+    hipLaunchKernelGGL(k_welford_seg, dim3(G, (nb + seg - 1) / seg), dim3(256), 0, st, w.partials,
+                       nb, seg, D, G);
+  hipLaunchKernelGGL(k_km_fin_fast, dim3(G), dim3(256), 0, st, w.partials, nb, seg, N, D, G,
+                     var_floor, means, dcovs, hefts, counts, w.scalars, inertia, dev_status);
+}
+
 hipError_t launch_kmeans_fast(const float* X, int64_t N, int D, int64_t ldx, int G, int dist,
                               const double* gvar, float var_floor, float* means, float* dcovs,
                               float* hefts, int64_t* counts, int32_t* assign, double* inertia,
@@ -1482,8 +1498,7 @@ hipError_t launch_kmeans_fast(const float* X, int64_t N, int D, int64_t ldx, int
       const bool stg = km2_stage_fits(D, G);
       km2_dispatch(a, nb, stg ? km2_stage_lds_max(D, G) : km2_lds_bytes(D, G, KSK), st, stg);
     }
-    hipLaunchKernelGGL(k_km_fin_fast, dim3(G), dim3(256), 0, st, w.partials, nb, N, D, G,
-                       var_floor, means, dcovs, hefts, counts, w.scalars, inertia, dev_status);
+    launch_km_fin(nb, N, D, G, var_floor, means, dcovs, hefts, counts, inertia, dev_status, w, st);
     return hipGetLastError();
   }
   int64_t nb64 = (N + 2 * kT - 1) / (2 * kT);
@@ -1527,8 +1542,7 @@ hipError_t launch_kmeans_fast(const float* X, int64_t N, int D, int64_t ldx, int
       else km_launch_one<16, 2>(a, nb, lds, st);
     }
   }
-  hipLaunchKernelGGL(k_km_fin_fast, dim3(G), dim3(256), 0, st, w.partials, nb, N, D, G, var_floor,
-                     means, dcovs, hefts, counts, w.scalars, inertia, dev_status);
+  launch_km_fin(nb, N, D, G, var_floor, means, dcovs, hefts, counts, inertia, dev_status, w, st);
   return hipGetLastError();
 }
 
