@@ -17,13 +17,30 @@ namespace {
 // order within a group and a model's items stay consecutive.  A model whose
 // descriptor is unusable gets no items; if the descriptors ask for more items
 // than the host sized (`cap`), no model gets any.
+// Exclusive prefix sum over the 1024 threads of the workgroup (Hillis-Steele
+// in LDS, exact in 64-bit integers); *total receives the sum.  Every thread
+// must call it.
+__device__ long long block_scan_excl(long long v, long long* sh, long long* total) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const long long t = tid >= off ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += t;
+    __syncthreads();
+  }
+  const long long incl = sh[tid];
+  *total = sh[1023];
+  __syncthreads();  // sh is reused by the next call
+  return incl - v;
+}
+
 __global__ void __launch_bounds__(1024) k_batch_plan(const gmm_model_desc* models, int n_models,
                                                      int Gmax, int64_t chunk, int cap,
                                                      BatchItemDev* items, int2* mitems,
                                                      int* n_items) {
-  __shared__ int part_sum[1024];
-  __shared__ int overflow;
-  __shared__ int run_sh;
+  __shared__ long long scan_sh[1024];
   const int tid = threadIdx.x;
   // per-thread contiguous block of models
   const int per = (n_models + 1023) / 1024;
@@ -33,17 +50,10 @@ __global__ void __launch_bounds__(1024) k_batch_plan(const gmm_model_desc* model
   };
   int64_t local = 0;
   for (int m = m0; m < m1; ++m) local += count(m);
-  part_sum[tid] = (int)min(local, (int64_t)cap + 1);
-  __syncthreads();
-  if (tid == 0) {
-    int64_t run = 0;
-    for (int t = 0; t < 1024; ++t) run += part_sum[t];
-    overflow = run > cap;
-    *n_items = run > cap ? 0 : (int)run;
-    run_sh = 0;
-  }
-  __syncthreads();
-  const bool ovf = overflow != 0;
+  long long all = 0;
+  (void)block_scan_excl((long long)local, scan_sh, &all);
+  const bool ovf = all > cap;
+  if (tid == 0) *n_items = ovf ? 0 : (int)all;
   for (int m = m0; m < m1; ++m) {
     const gmm_model_desc& md = models[m];
     const bool ok = batch_desc_ok(md, Gmax) && !ovf;
@@ -52,24 +62,14 @@ __global__ void __launch_bounds__(1024) k_batch_plan(const gmm_model_desc* model
   }
   if (ovf) return;
   const int RBmax = (Gmax + 15) / 16;
+  int run = 0;  // items of the groups placed so far
   for (int rb = RBmax; rb >= 1; --rb) {
     auto in_group = [&](int m) { return (models[m].G + 15) / 16 == rb; };
     int mine = 0;
     for (int m = m0; m < m1; ++m)
       if (in_group(m)) mine += (int)count(m);
-    part_sum[tid] = mine;
-    __syncthreads();
-    if (tid == 0) {
-      int run = run_sh;
-      for (int t = 0; t < 1024; ++t) {
-        const int v = part_sum[t];
-        part_sum[t] = run;
-        run += v;
-      }
-      run_sh = run;
-    }
-    __syncthreads();
-    int first = part_sum[tid];
+    long long grp = 0;
+    int first = run + (int)block_scan_excl(mine, scan_sh, &grp);
     for (int m = m0; m < m1; ++m) {
       if (!in_group(m)) continue;
       const gmm_model_desc& md = models[m];
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(1024) k_batch_plan(const gmm_model_desc* model
       }
       first += cnt;
     }
-    __syncthreads();
+    run += (int)grp;
   }
 }
 
